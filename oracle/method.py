@@ -1,0 +1,198 @@
+"""The parallel rational method, step by step, in plain FP64 (oracle side).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Full matrix, f in {exp, phi1} (§1, §2, §4.3):
+  1. eta = ||A||_1 (max column sum of |a_ij|; §5 names the 1-norm as the usual
+     choice) and θ = θ(f, m, tol) from the forward bound of §3.
+  2. s = smallest integer s >= 0 with eta * 2^-s <= θ; B = A * 2^-s (exact).
+  3. For each nonzero shift c_k: LU with partial pivoting of M_k = I - c_k B
+     (LAPACK getrf) and Z_k = M_k^{-1} B (getrs).  These are the m
+     independent "processors" of §2.
+  4. Round-off form of §4.3: R = a0 I + sum_k w_k Z_k with w_k = b_k c_k; for
+     a complex-conjugate pair on real A the pair contributes 2 Re(w_k Z_k).
+  5. Undo the scaling (§1): s times { Phi <- (R + I) Phi / 2 ; R <- R R }.
+     The phi1 step is the doubling identity of §1 written for B:
+     phi1(2B) = (e^B + I) phi1(B) / 2 (the printed form drops a factor t;
+     see the design notes), and it uses R *before* it is squared.
+
+Action on a block V (n x p) (§1, §2):
+  1. eta, θ as above; N = max(1, ceil(eta / θ)) (correctly rounded quotient);
+     B = A / N entry by entry.
+  2. LU of every M_k once, reused for all N steps (§5.1, first remark).
+  3. exp:  v_0 = V, v_j = r(B) v_{j-1} for j = 1..N where
+           r(B) y = a0 y + sum_k w_k M_k^{-1} (B y)            (round-off form)
+     phi1: u_1 = phi1-approximant(B) V / N, u_{j+1} = r(B) u_j + u_1, and
+           u_N = phi1(A) V.  This is the solution u(1) of u' = A u + V,
+           u(0) = 0, stepped with h = 1/N (the linear ODE of §1).
+
+All arithmetic is numpy/scipy FP64 (complex128 where A or a shift is complex);
+the only library primitives are LAPACK getrf/getrs and matrix products.
+"""
+
+import math
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import coefficients as co
+from . import theta as th
+
+_THETA_CACHE = {}
+
+
+def norm1(A):
+    """||A||_1 = max_j sum_i |a_ij| (|z| for complex entries)."""
+    return float(np.abs(np.asarray(A)).sum(axis=0).max())
+
+
+def theta_for(funcs, m, tol):
+    """θ used by the plan.  phi1 always needs the exponential approximant as
+    well (its doubling step and its N-step recurrence both apply e^B), so a
+    request containing phi1 takes min(θ_exp, θ_phi1)."""
+    key = (tuple(sorted(funcs)), m, float(tol))
+    if key not in _THETA_CACHE:
+        need = {"exp"} | set(funcs)
+        _THETA_CACHE[key] = min(th.theta_set(f, m, tol) for f in need)
+    return _THETA_CACHE[key]
+
+
+def plan_scaling(eta, theta):
+    """Smallest s >= 0 with eta * 2^-s <= θ (§1: N = 2^s, then s squarings)."""
+    if not math.isfinite(eta):
+        raise FloatingPointError("non-finite norm")
+    s = 0
+    while math.ldexp(eta, -s) > theta:
+        s += 1
+    return s
+
+
+def plan_steps(eta, theta):
+    """N = max(1, ceil(eta / θ)) (§1: v_n = e^{A/N} v_{n-1}, n = 1..N)."""
+    if not math.isfinite(eta):
+        raise FloatingPointError("non-finite norm")
+    return max(1, math.ceil(eta / theta))
+
+
+def build_terms(funcs, m, complex_A):
+    """Solve list [(c_k, {func: w_k}, is_pair)] and the constants a0 per func.
+
+    Every requested function shares the same solves (§2: several functions
+    from one set of F_i), except m = 1, where exp and phi1 have different
+    Padé poles and so need a pair each.  For complex A a conjugate pair cannot
+    be folded into 2 Re(.), so it is expanded into its two conjugate terms.
+    """
+    need = ["exp"] + (["phi1"] if "phi1" in funcs else [])
+    a0 = {}
+    terms = []
+    if m == 1:
+        for f in need:
+            a0[f], tl = co.roundoff_terms(f, 1)
+            (c, w, _), = tl
+            if complex_A:
+                terms.append((c, {f: w}, False))
+                terms.append((c.conjugate(), {f: w.conjugate()}, False))
+            else:
+                terms.append((c, {f: w}, True))
+        return a0, terms
+    per_f = {}
+    for f in need:
+        a0[f], per_f[f] = co.roundoff_terms(f, m)
+    for k in range(len(per_f["exp"])):
+        c = per_f["exp"][k][0]
+        ws = {f: per_f[f][k][1] for f in need}
+        for f in need:
+            assert per_f[f][k][0] == c
+        terms.append((c, ws, False))
+    return a0, terms
+
+
+def _accumulate(acc, Z, w, pair):
+    if pair:
+        acc += 2.0 * (w * Z).real
+    else:
+        acc += w * Z
+
+
+def expm_full(A, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
+    """f(A) for f in ``funcs`` (subset of {"exp", "phi1"}) by the full-matrix
+    algorithm in the module docstring.  Returns a dict with the requested
+    results and the plan (s, θ, eta)."""
+    A = np.asarray(A)
+    n = A.shape[0]
+    cplx = np.iscomplexobj(A)
+    theta = theta_for(funcs, m, tol)
+    eta = norm1(A)
+    s = plan_scaling(eta, theta) if force_plan is None else int(force_plan)
+    B = np.ldexp(A.real, -s) + (1j * np.ldexp(A.imag, -s) if cplx else 0.0)
+    a0, terms = build_terms(funcs, m, cplx)
+    I = np.eye(n)
+    out_dtype = np.complex128 if cplx else np.float64
+    acc = {f: a0[f] * I.astype(out_dtype) for f in a0}
+    for c, ws, pair in terms:
+        M = I - c * B
+        lu = sla.lu_factor(M)
+        Z = sla.lu_solve(lu, B.astype(M.dtype))
+        for f, w in ws.items():
+            _accumulate(acc[f], Z, w, pair and not cplx)
+    R = acc["exp"]
+    Phi = acc.get("phi1")
+    for _ in range(s):
+        if Phi is not None:
+            Phi = 0.5 * ((R + I) @ Phi)
+        R = R @ R
+    res = {"plan": s, "theta": theta, "eta": eta}
+    if "exp" in funcs:
+        res["exp"] = R
+    if "phi1" in funcs:
+        res["phi1"] = Phi
+    return res
+
+
+def action(A, V, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
+    """f(A) V for f in ``funcs`` by the N-step recurrence of the module
+    docstring.  V is n x p.  Returns a dict with the results and the plan."""
+    A = np.asarray(A)
+    V = np.asarray(V)
+    n = A.shape[0]
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(V)
+    theta = theta_for(funcs, m, tol)
+    eta = norm1(A)
+    N = plan_steps(eta, theta) if force_plan is None else int(force_plan)
+    B = A / N
+    a0, terms = build_terms(funcs, m, np.iscomplexobj(A))
+    I = np.eye(n)
+    lus = [sla.lu_factor(I - c * B) for c, _, _ in terms]
+    real_out = not cplx
+
+    def apply_r(f, X):
+        Y = B @ X
+        out = a0[f] * X.astype(np.complex128 if cplx else np.float64)
+        for (c, ws, pair), lu in zip(terms, lus):
+            w = ws.get(f, 0.0)
+            if w == 0.0:
+                continue
+            Z = sla.lu_solve(lu, Y.astype(lu[0].dtype))
+            _accumulate(out, Z, w, pair and real_out)
+        return out
+
+    res = {"plan": N, "theta": theta, "eta": eta}
+    if "exp" in funcs:
+        v = V
+        for _ in range(N):
+            v = apply_r("exp", v)
+        res["exp"] = v
+    if "phi1" in funcs:
+        u1 = apply_r("phi1", V) / N
+        u = u1
+        for _ in range(N - 1):
+            u = apply_r("exp", u) + u1
+        res["phi1"] = u
+    return res
+
+
+def rel_fro(X, Xref):
+    """Relative Frobenius error ||X - Xref||_F / ||Xref||_F."""
+    X = np.asarray(X)
+    Xref = np.asarray(Xref)
+    return float(np.linalg.norm(X - Xref) / np.linalg.norm(Xref))
