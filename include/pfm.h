@@ -1,0 +1,169 @@
+/*
+ * pfm.h -- C ABI of libpfm: parallel fractional matrix functions on MI355X.
+ *
+ * Implements the method of S. Blanes, "Parallel computation of functions of
+ * matrices and their action on vectors" (arXiv:2210.03714):
+ *
+ *   f(B) ~ r(B) = a0 I + sum_k w_k (I - c_k B)^{-1} B,   w_k = b_k c_k,
+ *
+ * i.e. the approximant sum_i b_i (I - c_i B)^{-1} of §2 (eqs. 2 and 4) in the
+ * round-off-reducing form of §4.3, with the shifts c_k and weights b_k of the
+ * paper's sets for each solve count m.  The m shifted solves are independent
+ * (the paper's "processors") and run concurrently on the GPU.  Large norms are
+ * handled as in §1: B = A / 2^s followed by s squarings for f(A), or B = A / N
+ * followed by the recurrence v_j = r(B) v_{j-1} (N steps) for f(A) V.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: PFM_OK (0) on success; a negative PFM_ERR_* code means that
+ *   nothing was enqueued and outputs are untouched (text via pfm_last_error).
+ *   A positive return k from pfm_eval_batched means the batch ran and k
+ *   instances carry a nonzero per-instance status; all other instances are
+ *   valid.  Because results are produced asynchronously, the positive count
+ *   is only known after the stream synchronises: pfm_eval_batched itself
+ *   returns PFM_OK and the caller reads pfm_info.status.
+ * - Matrices are row-major with a leading dimension counted in elements
+ *   (ld >= n).  Complex data is interleaved (re, im) binary64, the layout of
+ *   C99 double _Complex and torch.complex128.
+ * - Device pointers are HIP device pointers on the context's device.  The
+ *   caller owns every buffer it passes; the library never frees them and never
+ *   writes to inputs.  The context owns all workspace.
+ * - All device work is enqueued on the caller's stream and the calls return
+ *   without waiting for it.  One context must not be used from two streams at
+ *   the same time (its workspace is shared between calls).
+ */
+#ifndef PFM_H
+#define PFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pfm_ctx pfm_ctx;
+typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
+
+/* functions (bit mask: EXP|PHI1 computes both from one set of solves, §2) */
+#define PFM_EXP 1
+#define PFM_PHI1 2
+
+/* element types */
+#define PFM_R64 0  /* real binary64 */
+#define PFM_C128 1 /* complex, interleaved binary64 */
+
+/* precision paths */
+#define PFM_FP64 0  /* LU, solves, combination and squaring in binary64 */
+#define PFM_MIXED 1 /* LU and solves in binary32 on MFMA with binary64
+                       iterative-refinement residuals; combination and
+                       squaring in binary64 */
+
+/* return codes */
+#define PFM_OK 0
+#define PFM_ERR_INVALID (-1)     /* null pointer, n < 1, ld < n, p < 0, tol not in (0,1), ... */
+#define PFM_ERR_UNSUPPORTED (-2) /* (f, m, dtype, prec) combination not provided */
+#define PFM_ERR_BUDGET (-3)      /* workspace would exceed the context's HBM budget */
+#define PFM_ERR_HIP (-4)         /* HIP runtime error */
+#define PFM_ERR_DEVICE (-5)      /* a device-side wait timed out (reported by pfm_check) */
+
+/* per-instance status bits (pfm_info.status) */
+#define PFM_SINGULAR_SHIFT 1 /* an exact zero pivot in I - c_k B; bad_shift = k */
+#define PFM_NONFINITE 2      /* ||A||_1 is not finite (NaN or Inf in A) */
+#define PFM_IR_STALL 4       /* mixed path: refinement did not reach the target */
+
+/* One problem instance.  p == 0: full matrix, F_exp / F_phi1 are n x n with
+ * leading dimension ldf.  p >= 1: action on the n x p block V (leading
+ * dimension ldv), F_exp / F_phi1 are n x p with leading dimension ldf.
+ * Outputs not requested by the function mask may be NULL. */
+typedef struct {
+  int32_t n;
+  int32_t p;
+  int64_t lda;
+  int64_t ldv;
+  int64_t ldf;
+  const void *A;
+  const void *V;
+  void *F_exp;
+  void *F_phi1;
+} pfm_problem;
+
+/* Per-instance report, written to device memory by pfm_eval_batched. */
+typedef struct {
+  int32_t status;    /* PFM_SINGULAR_SHIFT | PFM_NONFINITE | PFM_IR_STALL */
+  int32_t plan;      /* s (full matrix: B = A / 2^s) or N (action: B = A / N) */
+  int32_t order;     /* order of the rational approximation (eq. 3) */
+  int32_t ir_iters;  /* mixed path: refinement sweeps performed */
+  int32_t bad_shift; /* first shift index with a zero pivot, -1 if none */
+  int32_t reserved;
+  double norm1;      /* ||A||_1 */
+  double theta;      /* admissible ||B||_1 for the requested tolerance (§3) */
+  double resid;      /* mixed path: largest relative refinement residual */
+} pfm_info;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the
+ * workspace the context may allocate (0 = no cap).  Allocation happens lazily
+ * on the first call that needs it. */
+int pfm_create(pfm_ctx **ctx, int device, size_t hbm_budget_bytes);
+
+/* Destroy a context and free its workspace.  The caller must have
+ * synchronised every stream that used it. */
+int pfm_destroy(pfm_ctx *ctx);
+
+/* Text of the last error on this context (never NULL). */
+const char *pfm_last_error(const pfm_ctx *ctx);
+
+/* Host only.  Coefficients of the set used for function `f` (PFM_EXP or
+ * PFM_PHI1, not both) with m solves: the round-off form of §4.3,
+ * r(x) = a0 + sum_k w_k x / (1 - c_k x), with w_k = b_k c_k and b_k the
+ * solution of eq. (4) (§2).  m = 1: the 4th-order Padé pair of eq. (5) (exp)
+ * or eq. (6) (phi1) written in this form, one conjugate pair (the conjugate
+ * term is implied, *is_pair = 1).  m = 4: the set of §4.1 with alpha = 5;
+ * m = 5: the set of §5.1; m = 8: the set of §4.2 with alpha = 5.  phi1 weights
+ * solve eq. (4) with a_k = 1/(k+1)! on the same shifts.  Arrays must hold 8
+ * entries.  Returns PFM_ERR_UNSUPPORTED for an unknown (f, m). */
+int pfm_coeffs(int f, int m, int *n_terms, double *c_re, double *c_im,
+               double *w_re, double *w_im, double *a0, int *order,
+               int *is_pair);
+
+/* Host only.  θ(f, m, tol): the largest x with sum_k |a_k - alpha_k| x^k <=
+ * tol (forward bound of §3; absolute, any consistent norm).  For
+ * f = PFM_EXP|PFM_PHI1 the minimum of the two. */
+int pfm_theta(int f, int m, double tol, double *theta);
+
+/* Evaluate a batch of problems.
+ *   f          PFM_EXP, PFM_PHI1 or both
+ *   m          number of shifted solves: 1, 4, 5 or 8
+ *   tol        target of the forward bound per scaled step, in (0, 1)
+ *   prec       PFM_FP64 or PFM_MIXED
+ *   dtype      PFM_R64 or PFM_C128 (for A, V and outputs)
+ *   batch      number of problems, >= 1
+ *   probs      host array of `batch` problems; sizes may differ
+ *   info       device array of `batch` pfm_info records, or NULL
+ *   force_plan -1: planner (s or N from ||A||_1 and θ).  >= 0: use this s
+ *              (full matrix) or N >= 1 (action) for every instance (tests).
+ *   stream     HIP stream to enqueue on
+ * A problem with p == 0 and one with p >= 1 may not be mixed in one call. */
+int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec,
+                     int dtype, int batch, const pfm_problem *probs,
+                     pfm_info *info, int force_plan, pfm_stream_t stream);
+
+/* Block until `stream` is idle and report device-side failures of previous
+ * calls on this context (PFM_ERR_DEVICE if a bounded device wait timed out). */
+int pfm_check(pfm_ctx *ctx, pfm_stream_t stream);
+
+/* Library version string (static storage). */
+const char *pfm_version(void);
+
+/* Test hook.  Runs one v_mfma_f64_16x16x4 on device `device` with operands
+ * A[i][k] = 4 i + k + 1 and B[k][j] = 100 (k + 1) + j (i, j < 16, k < 4) and
+ * copies the 64 lanes x 4 accumulator values, lane-major, to the host array
+ * `out` (256 doubles).  Lets the tests confirm the fragment layout the
+ * kernels assume.  Synchronous; allocates and frees its own 2 KiB. */
+int pfm_selftest_mfma(int device, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFM_H */

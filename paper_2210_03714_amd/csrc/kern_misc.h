@@ -1,0 +1,143 @@
+// Norm/plan, output store, info and self-test kernels.
+#pragma once
+#include "kern_common.h"
+
+namespace pfm {
+
+// eta = ||A||_1 (max column sum of |a_ij|; |z| for complex), then the plan of
+// §1: s = smallest s >= 0 with eta 2^-s <= θ (full matrix) or
+// N = max(1, ceil(eta / θ)) (action).  Column sums run over rows in order.
+__global__ void __launch_bounds__(256)
+plan_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan, double theta,
+            int action, int force_plan, int cplx) {
+  __shared__ double red[256];
+  __shared__ int bad_s;
+  const int ii = blockIdx.x;
+  const InstDesc D = inst[ii];
+  const int n = D.n;
+  if (threadIdx.x == 0) bad_s = 0;
+  __syncthreads();
+  double mx = 0.0;
+  int bad = 0;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double s = 0.0;
+    if (cplx) {
+      for (int r = 0; r < n; ++r) {
+        const double *z = D.A + 2 * ((int64_t)r * D.lda + c);
+        s += hypot(z[0], z[1]);
+      }
+    } else {
+      for (int r = 0; r < n; ++r) s += fabs(D.A[(int64_t)r * D.lda + c]);
+    }
+    if (!isfinite(s)) bad = 1;
+    mx = fmax(mx, s);
+  }
+  red[threadIdx.x] = mx;
+  if (bad) bad_s = 1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    PlanRec P;
+    P.status = 0;
+    P.bad_shift = 0x7fffffff;
+    P.ir_iters = 0;
+    P.resid = 0.0;
+    double eta = red[0];
+    if (bad_s) {
+      eta = __builtin_nan("");
+      P.status = 2;
+    }
+    P.eta = eta;
+    int plan_v;
+    if (force_plan >= 0) {
+      plan_v = action ? (force_plan < 1 ? 1 : force_plan) : force_plan;
+    } else if (bad_s) {
+      plan_v = action ? 1 : 0;
+    } else if (action) {
+      const double q = ceil(eta / theta);
+      plan_v = q < 1.0 ? 1 : (q > 1e9 ? 1000000000 : (int)q);
+    } else {
+      int s = 0;
+      while (ldexp(eta, -s) > theta && s < 1023) ++s;
+      plan_v = s;
+    }
+    P.s = plan_v;
+    plan[ii] = P;
+  }
+}
+
+// Copy the final R / Phi (column-major, npad) to the caller's row-major
+// outputs, through a 32 x 32 LDS transpose.  Grid: x = tile, y = instance.
+__global__ void __launch_bounds__(256)
+store_full_kernel(const InstDesc *__restrict__ inst, const PlanRec *__restrict__ plan,
+                  const double *__restrict__ wsd, int want_exp, int want_phi) {
+  __shared__ double tile[32][33];
+  const int ii = blockIdx.y;
+  const InstDesc D = inst[ii];
+  const int n = D.n, np = D.npad;
+  const int tn = (n + 31) / 32;
+  const int tix = blockIdx.x;
+  if (tix >= tn * tn) return;
+  const int r0 = (tix % tn) * 32, c0 = (tix / tn) * 32;
+  const int s = plan[ii].s;
+  const int64_t nn = (int64_t)np * np;
+  const int t = threadIdx.x;
+  for (int which = 0; which < 2; ++which) {
+    if (which == 0 && !want_exp) continue;
+    if (which == 1 && !want_phi) continue;
+    const double *src = wsd + D.r_off + (which * 2 + (s & 1)) * nn;
+    double *dst = which ? D.Fp : D.Fe;
+    // read column-major: column c0 + t/8, rows r0 + (t%8)*4 + u
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + (t & 7) * 4 + u, c = c0 + (t >> 3);
+      tile[(t & 7) * 4 + u][t >> 3] = (r < n && c < n) ? src[r + (int64_t)c * np] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + (t >> 3), c = c0 + (t & 7) * 4 + u;
+      if (r < n && c < n) dst[(int64_t)r * D.ldf + c] = tile[t >> 3][(t & 7) * 4 + u];
+    }
+    __syncthreads();
+  }
+}
+
+struct InfoRec {  // mirrors pfm_info
+  int32_t status, plan, order, ir_iters, bad_shift, reserved;
+  double norm1, theta, resid;
+};
+
+__global__ void info_kernel(const PlanRec *__restrict__ plan, InfoRec *__restrict__ info, int batch,
+                            int order, double theta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const PlanRec P = plan[i];
+  InfoRec r;
+  r.status = P.status;
+  r.plan = P.s;
+  r.order = order;
+  r.ir_iters = P.ir_iters;
+  r.bad_shift = P.bad_shift == 0x7fffffff ? -1 : P.bad_shift;
+  r.reserved = 0;
+  r.norm1 = P.eta;
+  r.theta = theta;
+  r.resid = P.resid;
+  info[i] = r;
+}
+
+// One 16x16x4 FP64 MFMA on known operands: A[i][k] = 4 i + k + 1,
+// B[k][j] = 100 (k + 1) + j; lane l writes its four accumulator values.
+__global__ void selftest_mfma_kernel(double *out) {
+  const int l = threadIdx.x, i16 = l & 15, g = l >> 4;
+  const double a = 4.0 * i16 + g + 1.0;
+  const double b = 100.0 * (g + 1) + i16;
+  v4d acc = mfma16(a, b, zero4());
+#pragma unroll
+  for (int v = 0; v < 4; ++v) out[l * 4 + v] = acc[v];
+}
+
+}  // namespace pfm

@@ -1,0 +1,218 @@
+// Shifted solves fused with the linear combination (full-matrix path).
+//
+// For every nonzero shift c_k the paper needs Z_k = (I - c_k B)^{-1} B (the
+// round-off form of §4.3: the right-hand side is B, not I), and the result is
+//   R   = a0 I + sum_k w_k   Z_k      (exp,  w_k   = b_k   c_k)
+//   Phi = a0' I + sum_k w'_k Z_k      (phi1, w'_k  = b'_k  c_k)
+// from the same solves (§2: several functions from one set of F_i).
+//
+// One workgroup owns one column slab (SW columns) of one instance and loops
+// over all shifts: it loads P_k^T B[:, slab], runs the forward (unit L) and
+// backward (U) block substitutions on v_mfma_f64_16x16x4 with the 16x16
+// diagonal blocks pre-inverted by the LU kernel, and accumulates w_k Z_k in
+// registers.  No Z_k ever reaches memory; the slab of R (and Phi) is written
+// once, column-major, into the squaring buffers.
+//
+// Register layout: row block b (16 rows) belongs to wave b mod 4; each wave
+// holds RB = NPMAX/64 row blocks x CT = SW/16 column tiles of Z and of the
+// accumulators as MFMA C fragments.  After a diagonal block is finished it is
+// broadcast through a double-buffered LDS slab and every wave updates its
+// remaining row blocks with the off-diagonal blocks of L (or U) streamed from
+// the factor buffer.
+#pragma once
+#include "kern_common.h"
+
+namespace pfm {
+
+template <int NPMAX, int SW>
+__global__ void __launch_bounds__(256)
+solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
+                      int nlist, const PlanRec *__restrict__ plan, Terms T,
+                      double *__restrict__ wsd, const int *__restrict__ wsi) {
+  constexpr int RB = NPMAX / 64;
+  constexpr int CT = SW / 16;
+  constexpr int NSLAB = NPMAX / SW;
+  __shared__ double S[2][16 * SW];
+  __shared__ double Tst[4][16 * SW];
+
+  int slot, sl;
+  xcd_map(blockIdx.x, NSLAB, slot, sl);
+  if (slot >= nlist) return;
+  const int ii = ilist[slot];
+  const InstDesc D = inst[ii];
+  const int n = D.n, np = D.npad;
+  if (np > NPMAX || (np & 15) || n > np || n < 1) return;  // sizes the host never sends
+  const int c0 = sl * SW;
+  if (c0 >= np) return;
+  const int nblk = np >> 4;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int i16 = lane & 15, g = lane >> 4;
+  const int ar = arow(i16);
+  const double sc = ldexp(1.0, -plan[ii].s);
+
+  v4d Z[RB][CT], Ae[RB][CT], Ap[RB][CT];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) { Ae[rb][ct] = zero4(); Ap[rb][ct] = zero4(); }
+
+  for (int k = 0; k < T.nterms; ++k) {
+    const double *W = wsd + D.fac_off + (int64_t)k * np * np;
+    const int *perm = wsi + D.perm_ioff + (int64_t)k * np;
+    const double *dL = wsd + D.dinv_off + (int64_t)(2 * k) * nblk * 256;
+    const double *dU = dL + (int64_t)nblk * 256;
+
+    // right-hand side P^T B[:, slab], B = A 2^-s
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int b = wave + 4 * rb;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int col = c0 + 16 * ct + i16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * b + 4 * g + v;
+          double val = 0.0;
+          if (b < nblk && r < n && col < n) {
+            const int pr = perm[r];
+            if (pr < n) val = sc * D.A[(int64_t)pr * D.lda + col];
+          }
+          Z[rb][ct][v] = val;
+        }
+      }
+    }
+
+    // forward substitution with unit-lower L
+    for (int b = 0; b < nblk; ++b) {
+      double *Sb = S[b & 1];
+      if (wave == (b & 3)) {
+        const int rbo = b >> 2;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb == rbo) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Tst[wave][(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
+            wave_lds_sync();
+            v4d acc[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[ct] = zero4();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double a = dL[b * 256 + ar + 16 * (4 * q + g)];
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct)
+                acc[ct] = mfma16(a, Tst[wave][(4 * q + g) * SW + 16 * ct + i16], acc[ct]);
+            }
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              Z[rb][ct] = acc[ct];
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Sb[(4 * g + v) * SW + 16 * ct + i16] = acc[ct][v];
+            }
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int bb = wave + 4 * rb;
+        if (bb > b && bb < nblk) {
+          double a[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a[q] = W[(16 * bb + ar) + (int64_t)(16 * b + 4 * q + g) * np];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              Z[rb][ct] = mfma16(-a[q], Sb[(4 * q + g) * SW + 16 * ct + i16], Z[rb][ct]);
+        }
+      }
+    }
+
+    // backward substitution with upper U
+    for (int b = nblk - 1; b >= 0; --b) {
+      double *Sb = S[b & 1];
+      if (wave == (b & 3)) {
+        const int rbo = b >> 2;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb == rbo) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Tst[wave][(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
+            wave_lds_sync();
+            v4d acc[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[ct] = zero4();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double a = dU[b * 256 + ar + 16 * (4 * q + g)];
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct)
+                acc[ct] = mfma16(a, Tst[wave][(4 * q + g) * SW + 16 * ct + i16], acc[ct]);
+            }
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              Z[rb][ct] = acc[ct];
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Sb[(4 * g + v) * SW + 16 * ct + i16] = acc[ct][v];
+            }
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int bb = wave + 4 * rb;
+        if (bb < b) {
+          double a[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a[q] = W[(16 * bb + ar) + (int64_t)(16 * b + 4 * q + g) * np];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              Z[rb][ct] = mfma16(-a[q], Sb[(4 * q + g) * SW + 16 * ct + i16], Z[rb][ct]);
+        }
+      }
+    }
+
+    // combination in the round-off form (§4.3)
+    const double we = T.we_re[k], wp = T.wp_re[k];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Ae[rb][ct][v] = fma(we, Z[rb][ct][v], Ae[rb][ct][v]);
+          if (T.want_phi) Ap[rb][ct][v] = fma(wp, Z[rb][ct][v], Ap[rb][ct][v]);
+        }
+    __syncthreads();
+  }
+
+  // R = a0 I + sum w_k Z_k (and Phi) into the level-0 squaring buffers
+  double *R0 = wsd + D.r_off;
+  double *P0 = R0 + 2 * (int64_t)np * np;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int b = wave + 4 * rb;
+    if (b >= nblk) continue;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int col = c0 + 16 * ct + i16;
+      if (col >= np) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * b + 4 * g + v;
+        R0[r + (int64_t)col * np] = Ae[rb][ct][v] + (r == col ? T.a0e : 0.0);
+        if (T.want_phi) P0[r + (int64_t)col * np] = Ap[rb][ct][v] + (r == col ? T.a0p : 0.0);
+      }
+    }
+  }
+}
+
+}  // namespace pfm

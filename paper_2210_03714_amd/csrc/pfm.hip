@@ -1,0 +1,444 @@
+// libpfm host runtime: the C ABI of include/pfm.h on top of the gfx950 kernels.
+//
+// A call of pfm_eval_batched is planned on the host only as far as the
+// coefficient set and the workspace layout go; the per-instance plan (s or N)
+// is computed on the device from ||A||_1 and consumed there, so a call never
+// waits on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pfm.h"
+#include "pfm_internal.h"
+#include "pfm_tables.inc"
+#include "kern_common.h"
+#include "kern_lu.h"
+#include "kern_misc.h"
+#include "kern_solve.h"
+#include "kern_square.h"
+
+using namespace pfm;
+
+struct pfm_ctx {
+  int device = 0;
+  size_t budget = 0;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  int *d_err = nullptr;  // device-side error flags
+  int num_cu = 0;
+  // pinned host staging for descriptors, plans and task lists; the event
+  // marks the last upload that reads it
+  char *pin = nullptr;
+  size_t pin_bytes = 0;
+  hipEvent_t pin_ev = nullptr;
+  bool pin_pending = false;
+  // device buffer for per-level squaring task lists
+  void *tasks = nullptr;
+  size_t tasks_bytes = 0;
+  std::string err;
+};
+
+namespace {
+
+int set_err(pfm_ctx *ctx, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int set_err(pfm_ctx *ctx, int code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return set_err(ctx, PFM_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+  } while (0)
+
+const PfmSetEntry *find_set(int m, int func) {
+  for (int i = 0; i < kPfmNumSets; ++i)
+    if (kPfmSets[i].m == m && kPfmSets[i].func == func) return &kPfmSets[i];
+  return nullptr;
+}
+
+// eps(x) = sum_k d_k x^k (§3), Horner in extended precision; all d_k >= 0.
+long double bound_eval(const PfmSetEntry *e, long double x) {
+  long double s = 0.0L;
+  for (int k = PFM_KBOUND - 1; k >= 0; --k) s = s * x + (long double)e->d[k];
+  return s;
+}
+
+double theta_of(const PfmSetEntry *e, double tol) {
+  double cmax = 0.0;
+  for (int k = 0; k < e->nterms; ++k) cmax = std::max(cmax, std::hypot(e->c_re[k], e->c_im[k]));
+  long double lo = 0.0L, hi = 0.9L / (long double)cmax;
+  if (bound_eval(e, hi) <= tol) return (double)hi;
+  for (int it = 0; it < 200; ++it) {
+    const long double mid = 0.5L * (lo + hi);
+    if (bound_eval(e, mid) <= (long double)tol) lo = mid; else hi = mid;
+  }
+  double v = (double)lo;
+  if ((long double)v > lo) v = std::nextafter(v, 0.0);
+  return v;
+}
+
+inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Pinned staging area of at least `bytes`; waits until the previous upload
+// that read it has executed.
+int staging(pfm_ctx *ctx, size_t bytes, char **out) {
+  if (ctx->pin_pending) {
+    HIP_TRY(ctx, hipEventSynchronize(ctx->pin_ev));
+    ctx->pin_pending = false;
+  }
+  if (bytes > ctx->pin_bytes) {
+    if (ctx->pin) HIP_TRY(ctx, hipHostFree(ctx->pin));
+    ctx->pin = nullptr;
+    ctx->pin_bytes = 0;
+    const size_t nb = std::max<size_t>(bytes, 1 << 20);
+    HIP_TRY(ctx, hipHostMalloc((void **)&ctx->pin, nb, hipHostMallocDefault));
+    ctx->pin_bytes = nb;
+  }
+  *out = ctx->pin;
+  return PFM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pfm_version(void) { return "pfm 0.1 (gfx950; f64 full-matrix path)"; }
+
+int pfm_create(pfm_ctx **out, int device, size_t budget) {
+  if (!out) return PFM_ERR_INVALID;
+  *out = nullptr;
+  pfm_ctx *ctx = new pfm_ctx();
+  ctx->device = device;
+  ctx->budget = budget;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) { delete ctx; return PFM_ERR_HIP; }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) { delete ctx; return PFM_ERR_HIP; }
+  ctx->num_cu = prop.multiProcessorCount;
+  e = hipMalloc(&ctx->d_err, 64);
+  if (e != hipSuccess) { delete ctx; return PFM_ERR_HIP; }
+  e = hipMemset(ctx->d_err, 0, 64);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->pin_ev, hipEventDisableTiming);
+  if (e != hipSuccess) { (void)hipFree(ctx->d_err); delete ctx; return PFM_ERR_HIP; }
+  *out = ctx;
+  return PFM_OK;
+}
+
+int pfm_destroy(pfm_ctx *ctx) {
+  if (!ctx) return PFM_ERR_INVALID;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->pin_ev) {
+    (void)hipEventSynchronize(ctx->pin_ev);
+    (void)hipEventDestroy(ctx->pin_ev);
+  }
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->tasks) (void)hipFree(ctx->tasks);
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
+  if (ctx->d_err) (void)hipFree(ctx->d_err);
+  delete ctx;
+  return PFM_OK;
+}
+
+const char *pfm_last_error(const pfm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int pfm_coeffs(int f, int m, int *n_terms, double *c_re, double *c_im, double *w_re, double *w_im,
+               double *a0, int *order, int *is_pair) {
+  if (f != PFM_EXP && f != PFM_PHI1) return PFM_ERR_INVALID;
+  const PfmSetEntry *e = find_set(m, f == PFM_EXP ? 0 : 1);
+  if (!e) return PFM_ERR_UNSUPPORTED;
+  if (n_terms) *n_terms = e->nterms;
+  for (int k = 0; k < e->nterms; ++k) {
+    if (c_re) c_re[k] = e->c_re[k];
+    if (c_im) c_im[k] = e->c_im[k];
+    if (w_re) w_re[k] = e->w_re[k];
+    if (w_im) w_im[k] = e->w_im[k];
+  }
+  if (a0) *a0 = e->a0;
+  if (order) *order = e->order;
+  if (is_pair) *is_pair = e->pair;
+  return PFM_OK;
+}
+
+int pfm_theta(int f, int m, double tol, double *theta) {
+  if (!theta || !(tol > 0.0 && tol < 1.0)) return PFM_ERR_INVALID;
+  if (f < 1 || f > 3) return PFM_ERR_INVALID;
+  // phi1 always carries the exponential approximant too (its doubling and its
+  // recurrence apply e^B), so its θ is the smaller of the two.
+  const PfmSetEntry *ee = find_set(m, 0);
+  const PfmSetEntry *ep = find_set(m, 1);
+  if (!ee || !ep) return PFM_ERR_UNSUPPORTED;
+  double th = theta_of(ee, tol);
+  if (f & PFM_PHI1) th = std::min(th, theta_of(ep, tol));
+  *theta = th;
+  return PFM_OK;
+}
+
+int pfm_check(pfm_ctx *ctx, pfm_stream_t stream) {
+  if (!ctx) return PFM_ERR_INVALID;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize((hipStream_t)stream));
+  int flags[16];
+  HIP_TRY(ctx, hipMemcpy(flags, ctx->d_err, sizeof flags, hipMemcpyDeviceToHost));
+  if (flags[0]) {
+    HIP_TRY(ctx, hipMemset(ctx->d_err, 0, 64));
+    return set_err(ctx, PFM_ERR_DEVICE, "device-side wait timed out or scheduler overflow (flags 0x%x)",
+                   flags[0]);
+  }
+  return PFM_OK;
+}
+
+// Test hook: run one FP64 MFMA on known operands and copy the 64 x 4
+// accumulator values to host memory `out`.
+int pfm_selftest_mfma(int device, double *out) {
+  if (!out) return PFM_ERR_INVALID;
+  if (hipSetDevice(device) != hipSuccess) return PFM_ERR_HIP;
+  double *d = nullptr;
+  if (hipMalloc(&d, 256 * sizeof(double)) != hipSuccess) return PFM_ERR_HIP;
+  hipLaunchKernelGGL(selftest_mfma_kernel, dim3(1), dim3(64), 0, 0, d);
+  hipError_t e = hipMemcpy(out, d, 256 * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  return e == hipSuccess ? PFM_OK : PFM_ERR_HIP;
+}
+
+int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype, int batch,
+                     const pfm_problem *probs, pfm_info *info, int force_plan,
+                     pfm_stream_t stream_) {
+  if (!ctx) return PFM_ERR_INVALID;
+  if (f < 1 || f > 3) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
+  if (!(tol > 0.0 && tol < 1.0)) return set_err(ctx, PFM_ERR_INVALID, "tol must lie in (0,1)");
+  if (batch < 1 || !probs) return set_err(ctx, PFM_ERR_INVALID, "empty batch");
+  if (prec != PFM_FP64 && prec != PFM_MIXED) return set_err(ctx, PFM_ERR_INVALID, "bad prec");
+  if (dtype != PFM_R64 && dtype != PFM_C128) return set_err(ctx, PFM_ERR_INVALID, "bad dtype");
+  hipStream_t stream = (hipStream_t)stream_;
+  const bool action = probs[0].p > 0;
+  for (int i = 0; i < batch; ++i) {
+    const pfm_problem &P = probs[i];
+    if (P.n < 1 || P.p < 0 || !P.A) return set_err(ctx, PFM_ERR_INVALID, "problem %d: bad n/p/A", i);
+    if ((P.p > 0) != action) return set_err(ctx, PFM_ERR_INVALID, "mixed full/action batch");
+    if (P.lda < P.n) return set_err(ctx, PFM_ERR_INVALID, "problem %d: lda < n", i);
+    const int64_t ocols = action ? P.p : P.n;
+    if (P.ldf < ocols) return set_err(ctx, PFM_ERR_INVALID, "problem %d: ldf too small", i);
+    if ((f & PFM_EXP) && !P.F_exp) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_exp null", i);
+    if ((f & PFM_PHI1) && !P.F_phi1) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_phi1 null", i);
+    if (action && (!P.V || P.ldv < P.p)) return set_err(ctx, PFM_ERR_INVALID, "problem %d: bad V", i);
+  }
+  const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
+  if (!ee || !ep) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
+  if (dtype != PFM_R64 || prec != PFM_FP64 || action || ee->pair)
+    return set_err(ctx, PFM_ERR_UNSUPPORTED, "only the real FP64 full-matrix path with real shifts is built");
+  for (int i = 0; i < batch; ++i)
+    if (probs[i].n > 512) return set_err(ctx, PFM_ERR_UNSUPPORTED, "n > 512 not supported on this path");
+
+  double theta;
+  int rc = pfm_theta(f, m, tol, &theta);
+  if (rc) return set_err(ctx, rc, "theta failed");
+
+  Terms T;
+  memset(&T, 0, sizeof T);
+  T.nterms = ee->nterms;
+  T.pair = 0;
+  T.want_exp = (f & PFM_EXP) ? 1 : 0;
+  T.want_phi = (f & PFM_PHI1) ? 1 : 0;
+  T.a0e = ee->a0;
+  T.a0p = ep->a0;
+  for (int k = 0; k < ee->nterms; ++k) {
+    T.c_re[k] = ee->c_re[k];
+    T.c_im[k] = ee->c_im[k];
+    T.we_re[k] = ee->w_re[k];
+    T.we_im[k] = ee->w_im[k];
+    T.wp_re[k] = ep->w_re[k];
+    T.wp_im[k] = ep->w_im[k];
+  }
+  const int nterms = T.nterms;
+
+  // workspace layout
+  std::vector<InstDesc> desc(batch);
+  std::vector<int> cls_list[3];
+  int64_t dofs = 0, iofs = 0;
+  for (int i = 0; i < batch; ++i) {
+    const pfm_problem &P = probs[i];
+    InstDesc &D = desc[i];
+    D.A = (const double *)P.A;
+    D.V = (const double *)P.V;
+    D.Fe = (double *)P.F_exp;
+    D.Fp = (double *)P.F_phi1;
+    D.lda = P.lda;
+    D.ldv = P.ldv;
+    D.ldf = P.ldf;
+    D.n = P.n;
+    D.npad = (P.n + 15) / 16 * 16;
+    D.p = P.p;
+    D.cls = D.npad <= 128 ? 0 : (D.npad <= 256 ? 1 : 2);
+    const int64_t np = D.npad, nn = np * np;
+    D.fac_off = dofs;  dofs += align_up(nterms * nn, 64);
+    D.dinv_off = dofs; dofs += align_up(nterms * 2 * (np / 16) * 256, 64);
+    D.r_off = dofs;    dofs += align_up(4 * nn, 64);
+    D.x_off = 0;
+    D.perm_ioff = iofs; iofs += align_up(nterms * np, 64);
+    D.ipiv_ioff = iofs; iofs += align_up(nterms * np, 64);
+    cls_list[D.cls].push_back(i);
+  }
+  const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
+  const int64_t desc_bytes = align_up((int64_t)batch * sizeof(InstDesc), 256);
+  const int64_t list_bytes = align_up((int64_t)batch * sizeof(int), 256);
+  const int64_t need = dofs * 8 + iofs * 4 + plan_bytes + desc_bytes + list_bytes + 4096;
+  if (ctx->budget && (size_t)need > ctx->budget)
+    return set_err(ctx, PFM_ERR_BUDGET, "workspace %lld bytes exceeds budget %zu", (long long)need,
+                   ctx->budget);
+
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((size_t)need > ctx->ws_bytes) {
+    if (ctx->ws) {
+      HIP_TRY(ctx, hipStreamSynchronize(stream));
+      HIP_TRY(ctx, hipFree(ctx->ws));
+      ctx->ws = nullptr;
+      ctx->ws_bytes = 0;
+    }
+    HIP_TRY(ctx, hipMalloc(&ctx->ws, (size_t)need));
+    ctx->ws_bytes = (size_t)need;
+  }
+  char *base = (char *)ctx->ws;
+  double *wsd = (double *)base;
+  int *wsi = (int *)(base + dofs * 8);
+  char *tail = base + dofs * 8 + align_up(iofs * 4, 256);
+  PlanRec *d_plan = (PlanRec *)tail;
+  InstDesc *d_desc = (InstDesc *)(tail + plan_bytes);
+  int *d_list = (int *)(tail + plan_bytes + desc_bytes);
+
+  // descriptors and class lists (stored back to back) through pinned staging
+  char *pin = nullptr;
+  const size_t stage_bytes = desc_bytes + list_bytes + plan_bytes;
+  int rcs = staging(ctx, stage_bytes, &pin);
+  if (rcs) return rcs;
+  InstDesc *h_desc = (InstDesc *)pin;
+  int *h_list = (int *)(pin + desc_bytes);
+  PlanRec *h_plan = (PlanRec *)(pin + desc_bytes + list_bytes);
+  memcpy(h_desc, desc.data(), batch * sizeof(InstDesc));
+  int list_off[3];
+  {
+    int pos = 0;
+    for (int c = 0; c < 3; ++c) {
+      list_off[c] = pos;
+      for (int i : cls_list[c]) h_list[pos++] = i;
+    }
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(d_desc, h_desc, batch * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_list, h_list, batch * sizeof(int), hipMemcpyHostToDevice, stream));
+
+  // 1. norm and plan on the device; the host reads the plans back once (it
+  //    needs max s to size the squaring launches)
+  hipLaunchKernelGGL(plan_kernel, dim3(batch), dim3(256), 0, stream, d_desc, d_plan, theta, 0,
+                     force_plan, 0);
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipMemcpyAsync(h_plan, d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  std::vector<int> svec(batch);
+  int smax = 0;
+  for (int i = 0; i < batch; ++i) {
+    svec[i] = std::max(0, std::min(h_plan[i].s, kSCap));
+    smax = std::max(smax, svec[i]);
+  }
+  for (int i = 0; i < batch; ++i)
+    if (h_plan[i].s > kSCap) {
+      return set_err(ctx, PFM_ERR_INVALID, "instance %d needs s = %d squarings (cap %d)", i,
+                     h_plan[i].s, kSCap);
+    }
+
+  // 2. shifted LU factorisations, all (instance, shift) pairs of a size class
+  //    in one launch
+  for (int c = 0; c < 3; ++c) {
+    const int nl = (int)cls_list[c].size();
+    if (!nl) continue;
+    const int *dl = d_list + list_off[c];
+    const dim3 glu(xcd_grid(nl, nterms));
+    if (c == 0) hipLaunchKernelGGL(lu_f64_kernel<128>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, 0);
+    if (c == 1) hipLaunchKernelGGL(lu_f64_kernel<256>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, 0);
+    if (c == 2) hipLaunchKernelGGL(lu_f64_kernel<512>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, 0);
+  }
+  // 3. solves fused with the combination
+  for (int c = 0; c < 3; ++c) {
+    const int nl = (int)cls_list[c].size();
+    if (!nl) continue;
+    const int *dl = d_list + list_off[c];
+    if (c == 0) hipLaunchKernelGGL((solve_full_f64_kernel<128, 32>), dim3(xcd_grid(nl, 128 / 32)), dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi);
+    if (c == 1) hipLaunchKernelGGL((solve_full_f64_kernel<256, 32>), dim3(xcd_grid(nl, 256 / 32)), dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi);
+    if (c == 2) hipLaunchKernelGGL((solve_full_f64_kernel<512, 16>), dim3(xcd_grid(nl, 512 / 16)), dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi);
+  }
+  // 4. squaring levels: task lists built here, one launch per level
+  std::vector<SqTask> all;
+  std::vector<std::pair<int64_t, int>> lv;  // (offset, count)
+  for (int j = 1; j <= smax; ++j) {
+    std::vector<std::vector<SqTask>> qx(8);
+    int x = 0;
+    for (int i = 0; i < batch; ++i) {
+      if (svec[i] < j) continue;
+      const int tl = (desc[i].npad + kSqTile - 1) / kSqTile;
+      for (int w = 0; w < 1 + T.want_phi; ++w)
+        for (int tt = 0; tt < tl * tl; ++tt) qx[x].push_back(SqTask{i, tt + (w << 20)});
+      x = (x + 1) & 7;
+    }
+    size_t mx = 0;
+    for (auto &q : qx) mx = std::max(mx, q.size());
+    const int64_t off = (int64_t)all.size();
+    for (size_t qq = 0; qq < mx; ++qq)
+      for (int xx = 0; xx < 8; ++xx) all.push_back(qq < qx[xx].size() ? qx[xx][qq] : SqTask{-1, 0});
+    lv.emplace_back(off, (int)(mx * 8));
+  }
+  if (!all.empty()) {
+    const size_t tb = all.size() * sizeof(SqTask);
+    if (tb > ctx->tasks_bytes) {
+      if (ctx->tasks) HIP_TRY(ctx, hipFree(ctx->tasks));
+      ctx->tasks = nullptr;
+      ctx->tasks_bytes = 0;
+      HIP_TRY(ctx, hipMalloc(&ctx->tasks, tb));
+      ctx->tasks_bytes = tb;
+    }
+    // the staging area is free again: the stream was synchronised above
+    char *pin2 = nullptr;
+    rcs = staging(ctx, tb, &pin2);
+    if (rcs) return rcs;
+    memcpy(pin2, all.data(), tb);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->tasks, pin2, tb, hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
+    ctx->pin_pending = true;
+    const SqTask *dt = (const SqTask *)ctx->tasks;
+    for (int j = 1; j <= smax; ++j) {
+      const auto &e = lv[j - 1];
+      hipLaunchKernelGGL(square_level_f64_kernel, dim3(e.second), dim3(256), 0, stream, d_desc,
+                         dt + e.first, e.second, j, wsd);
+    }
+  } else {
+    HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
+    ctx->pin_pending = true;
+  }
+  // 5. results to the caller's row-major buffers, then the info records
+  int maxn = 0;
+  for (int i = 0; i < batch; ++i) maxn = std::max(maxn, probs[i].n);
+  const int tn = (maxn + 31) / 32;
+  hipLaunchKernelGGL(store_full_kernel, dim3(tn * tn, batch), dim3(256), 0, stream, d_desc, d_plan,
+                     wsd, T.want_exp, T.want_phi);
+  if (info)
+    hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_plan,
+                       (InfoRec *)info, batch, ee->order, theta);
+  HIP_TRY(ctx, hipGetLastError());
+  return PFM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,273 @@
+"""Thin ctypes binding of libpfm (include/pfm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libpfm.so.  PyTorch supplies device memory and the stream.  There
+is no fallback: if the library is missing, or a tensor is not on the GPU, the
+call raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpfm.so")
+
+EXP = 1
+PHI1 = 2
+R64 = 0
+C128 = 1
+FP64 = 0
+MIXED = 1
+
+OK = 0
+ERR_INVALID = -1
+ERR_UNSUPPORTED = -2
+ERR_BUDGET = -3
+ERR_HIP = -4
+ERR_DEVICE = -5
+
+SINGULAR_SHIFT = 1
+NONFINITE = 2
+IR_STALL = 4
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("lda", ctypes.c_int64), ("ldv", ctypes.c_int64), ("ldf", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("F_exp", ctypes.c_void_p), ("F_phi1", ctypes.c_void_p)]
+
+
+INFO_DTYPE = np.dtype([("status", "<i4"), ("plan", "<i4"), ("order", "<i4"), ("ir_iters", "<i4"),
+                       ("bad_shift", "<i4"), ("reserved", "<i4"), ("norm1", "<f8"),
+                       ("theta", "<f8"), ("resid", "<f8")])
+assert INFO_DTYPE.itemsize == 48
+
+_lib = None
+
+
+def lib():
+    """Load libpfm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpfm.so is not built: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        L.pfm_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_size_t]
+        L.pfm_destroy.argtypes = [vp]
+        L.pfm_last_error.argtypes = [vp]
+        L.pfm_last_error.restype = ctypes.c_char_p
+        L.pfm_coeffs.argtypes = [i32, i32, ip, dp, dp, dp, dp, dp, ip, ip]
+        L.pfm_theta.argtypes = [i32, i32, dbl, dp]
+        L.pfm_eval_batched.argtypes = [vp, i32, i32, dbl, i32, i32, i32, ctypes.POINTER(Problem),
+                                       vp, i32, vp]
+        L.pfm_check.argtypes = [vp, vp]
+        L.pfm_version.restype = ctypes.c_char_p
+        L.pfm_selftest_mfma.argtypes = [i32, dp]
+        _lib = L
+    return _lib
+
+
+def version():
+    return lib().pfm_version().decode()
+
+
+def coeffs(f, m):
+    """(c, w, a0, order, is_pair) of the library's set for f (EXP or PHI1)."""
+    L = lib()
+    n = ctypes.c_int()
+    arrs = [(ctypes.c_double * 8)() for _ in range(4)]
+    a0 = ctypes.c_double()
+    order = ctypes.c_int()
+    pair = ctypes.c_int()
+    rc = L.pfm_coeffs(f, m, ctypes.byref(n), *[ctypes.cast(a, ctypes.POINTER(ctypes.c_double)) for a in arrs],
+                      ctypes.byref(a0), ctypes.byref(order), ctypes.byref(pair))
+    if rc:
+        raise ValueError("pfm_coeffs(%d, %d) -> %d" % (f, m, rc))
+    k = n.value
+    c = np.array(arrs[0][:k]) + 1j * np.array(arrs[1][:k])
+    w = np.array(arrs[2][:k]) + 1j * np.array(arrs[3][:k])
+    return c, w, a0.value, order.value, bool(pair.value)
+
+
+def theta(f, m, tol):
+    out = ctypes.c_double()
+    rc = lib().pfm_theta(f, m, tol, ctypes.byref(out))
+    if rc:
+        raise ValueError("pfm_theta(%d, %d, %g) -> %d" % (f, m, tol, rc))
+    return out.value
+
+
+def selftest_mfma(device=0):
+    out = (ctypes.c_double * 256)()
+    rc = lib().pfm_selftest_mfma(device, ctypes.cast(out, ctypes.POINTER(ctypes.c_double)))
+    if rc:
+        raise RuntimeError("pfm_selftest_mfma -> %d" % rc)
+    return np.array(out[:]).reshape(64, 4)
+
+
+class PfmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("pfm error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Context:
+    """Owns one pfm_ctx (workspace) on a device."""
+
+    def __init__(self, device=0, budget=0):
+        self._h = ctypes.c_void_p()
+        rc = lib().pfm_create(ctypes.byref(self._h), device, budget)
+        if rc:
+            raise PfmError(rc, "pfm_create failed")
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().pfm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def last_error(self):
+        return lib().pfm_last_error(self._h).decode()
+
+    def check(self, stream=None):
+        rc = lib().pfm_check(self._h, _stream_ptr(stream))
+        if rc:
+            raise PfmError(rc, self.last_error())
+
+    def eval_batched(self, probs, f, m, tol, prec=FP64, dtype=R64, info=None, force_plan=-1,
+                     stream=None):
+        """Raw call: ``probs`` is a list of Problem; ``info`` a device tensor of
+        len(probs) * 48 bytes or None.  Returns the C return code."""
+        arr = (Problem * len(probs))(*probs)
+        iptr = ctypes.c_void_p(info.data_ptr()) if info is not None else ctypes.c_void_p()
+        return lib().pfm_eval_batched(self._h, f, m, tol, prec, dtype, len(probs), arr, iptr,
+                                      force_plan, _stream_ptr(stream))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _fmask(funcs):
+    m = 0
+    for f in funcs:
+        m |= {"exp": EXP, "phi1": PHI1}[f]
+    return m
+
+
+_default_ctx = {}
+
+
+def default_context(device=0):
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def _require_gpu(t):
+    if not t.is_cuda:
+        raise ValueError("pfm operates on GPU tensors only (no CPU path)")
+
+
+def expm(A, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None, stream=None,
+         out=None):
+    """f(A) for every matrix of ``A``.
+
+    ``A`` is a CUDA tensor (batch, n, n) or a list of CUDA tensors (n_i, n_i),
+    float64 or complex128, rows contiguous.  Returns (results, info) where
+    results maps each requested function to a tensor (or list) like ``A`` and
+    info is a numpy structured array (after a stream synchronisation)."""
+    import torch
+    mats = list(A) if isinstance(A, (list, tuple)) else [A[i] for i in range(A.shape[0])]
+    for a in mats:
+        _require_gpu(a)
+        if a.dim() != 2 or a.shape[0] != a.shape[1] or a.stride(1) != 1:
+            raise ValueError("each A must be square with unit column stride")
+    cplx = mats[0].is_complex()
+    fm = _fmask(funcs)
+    if out is None:
+        out = {}
+        for f in funcs:
+            if isinstance(A, (list, tuple)):
+                out[f] = [torch.empty_like(a) for a in mats]
+            else:
+                out[f] = torch.empty_like(A)
+    outs = {f: (list(out[f]) if isinstance(out[f], (list, tuple)) else [out[f][i] for i in range(len(mats))])
+            for f in funcs}
+    probs = []
+    for i, a in enumerate(mats):
+        fe = outs["exp"][i] if "exp" in funcs else None
+        fp = outs["phi1"][i] if "phi1" in funcs else None
+        ldf = (fe if fe is not None else fp).stride(0)
+        probs.append(Problem(a.shape[0], 0, a.stride(0), 0, ldf, a.data_ptr(), None,
+                             fe.data_ptr() if fe is not None else None,
+                             fp.data_ptr() if fp is not None else None))
+    ctx = ctx or default_context(mats[0].device.index or 0)
+    info = torch.empty(len(mats) * INFO_DTYPE.itemsize, dtype=torch.uint8, device=mats[0].device)
+    rc = ctx.eval_batched(probs, fm, m, tol, {"fp64": FP64, "mixed": MIXED}[prec],
+                          C128 if cplx else R64, info, force_plan, stream)
+    if rc:
+        raise PfmError(rc, ctx.last_error())
+    return out, _Info(info)
+
+
+def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None, stream=None):
+    """f(A) V for every (A, V) pair (lists or batched tensors)."""
+    import torch
+    mats = list(A) if isinstance(A, (list, tuple)) else [A[i] for i in range(A.shape[0])]
+    vecs = list(V) if isinstance(V, (list, tuple)) else [V[i] for i in range(V.shape[0])]
+    for a, v in zip(mats, vecs):
+        _require_gpu(a)
+        _require_gpu(v)
+    cplx = mats[0].is_complex() or vecs[0].is_complex()
+    fm = _fmask(funcs)
+    out = {f: [torch.empty_like(v) for v in vecs] for f in funcs}
+    probs = []
+    for i, (a, v) in enumerate(zip(mats, vecs)):
+        fe = out["exp"][i] if "exp" in funcs else None
+        fp = out["phi1"][i] if "phi1" in funcs else None
+        ldf = (fe if fe is not None else fp).stride(0)
+        probs.append(Problem(a.shape[0], v.shape[1], a.stride(0), v.stride(0), ldf, a.data_ptr(),
+                             v.data_ptr(), fe.data_ptr() if fe is not None else None,
+                             fp.data_ptr() if fp is not None else None))
+    ctx = ctx or default_context(mats[0].device.index or 0)
+    info = torch.empty(len(mats) * INFO_DTYPE.itemsize, dtype=torch.uint8, device=mats[0].device)
+    rc = ctx.eval_batched(probs, fm, m, tol, {"fp64": FP64, "mixed": MIXED}[prec],
+                          C128 if cplx else R64, info, force_plan, stream)
+    if rc:
+        raise PfmError(rc, ctx.last_error())
+    return out, _Info(info)
+
+
+class _Info:
+    """Lazily decoded per-instance info (reading it synchronises)."""
+
+    def __init__(self, buf):
+        self._buf = buf
+        self._arr = None
+
+    def get(self):
+        if self._arr is None:
+            self._arr = np.frombuffer(self._buf.cpu().numpy().tobytes(), dtype=INFO_DTYPE)
+        return self._arr
+
+    def __getitem__(self, k):
+        return self.get()[k]

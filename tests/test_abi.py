@@ -1,0 +1,85 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/pfm.h declares, and its host-only calls agree with
+the oracle -- coefficient tables to the last bit, θ to 1e-13 relative."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import coefficients as co
+from oracle import theta as th
+from paper_2210_03714_amd import pfm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(pfm.LIB_PATH):
+        from paper_2210_03714_amd import build
+        build.build()
+    return pfm.lib()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pfm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pfm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "pfm_eval_batched" in names and len(names) >= 9
+    for nm in names:
+        assert hasattr(L, nm), nm
+        assert ctypes.cast(getattr(L, nm), ctypes.c_void_p).value
+
+
+def test_version(L):
+    assert "pfm" in pfm.version()
+
+
+@pytest.mark.parametrize("m", [4, 5, 8])
+@pytest.mark.parametrize("func", ["exp", "phi1"])
+def test_coeffs_bitwise_equal_oracle(L, m, func):
+    c, w, a0, order, pair = pfm.coeffs(pfm.EXP if func == "exp" else pfm.PHI1, m)
+    a0o, terms = co.roundoff_terms(func, m)
+    assert not pair
+    assert a0 == a0o
+    assert order == co.order_of(m)
+    assert list(c.real) == [t[0] for t in terms]
+    assert list(w.real) == [t[1] for t in terms]
+    assert not np.any(c.imag) and not np.any(w.imag)
+
+
+@pytest.mark.parametrize("func", ["exp", "phi1"])
+def test_coeffs_pairs_match_oracle(L, func):
+    c, w, a0, order, pair = pfm.coeffs(pfm.EXP if func == "exp" else pfm.PHI1, 1)
+    a0o, ((co_, wo, po),) = co.roundoff_terms(func, 1)
+    assert pair and po and order == 4
+    assert abs(a0 - a0o) <= 1e-15
+    assert abs(c[0] - co_) <= 1e-16 * abs(co_)
+    assert abs(w[0] - wo) <= 1e-15 * abs(wo)
+
+
+@pytest.mark.parametrize("m", [1, 4, 5, 8])
+@pytest.mark.parametrize("tol", [2.0 ** -24, 1e-8, 1e-10, 1e-12])
+def test_theta_matches_oracle(L, m, tol):
+    for fm, funcs in ((pfm.EXP, ("exp",)), (pfm.EXP | pfm.PHI1, ("exp", "phi1"))):
+        lib_t = pfm.theta(fm, m, tol)
+        orc_t = min(th.theta_set(f, m, tol) for f in funcs)
+        assert abs(lib_t - orc_t) <= 1e-13 * orc_t, (m, tol, lib_t, orc_t)
+
+
+def test_invalid_arguments_rejected_on_host(L):
+    out = ctypes.c_double()
+    assert L.pfm_theta(1, 8, 0.0, ctypes.byref(out)) == pfm.ERR_INVALID
+    assert L.pfm_theta(1, 8, 1.5, ctypes.byref(out)) == pfm.ERR_INVALID
+    assert L.pfm_theta(1, 3, 1e-12, ctypes.byref(out)) == pfm.ERR_UNSUPPORTED
+    assert L.pfm_eval_batched(None, 1, 8, 1e-12, 0, 0, 1, None, None, -1, None) == pfm.ERR_INVALID
+    n = ctypes.c_int()
+    assert L.pfm_coeffs(3, 8, ctypes.byref(n), None, None, None, None, None, None, None) == pfm.ERR_INVALID
+    assert L.pfm_coeffs(1, 7, ctypes.byref(n), None, None, None, None, None, None, None) == pfm.ERR_UNSUPPORTED

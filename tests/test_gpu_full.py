@@ -1,0 +1,174 @@
+"""GPU parity of the full-matrix path f(A) (exp, phi1) against the CPU oracle.
+
+Every case runs the HIP kernels through the C ABI and compares element by
+element with the oracle on the same seeded inputs: relative Frobenius error
+<= 1e-12 per instance (the FP64 bar), with the plan s equal to the oracle's
+(or, where eta/θ sits within 1e-12 of a power of two, the GPU's s is passed
+to the oracle)."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import method as me
+from paper_2210_03714_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    from paper_2210_03714_amd import pfm
+    pfm.lib()
+    return torch, torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _check_instances(mats, res, info, funcs, m, tol, bar=TOL, idx=None):
+    idx = range(len(mats)) if idx is None else idx
+    worst = 0.0
+    for i in idx:
+        A = mats[i]
+        s_gpu = int(info[i]["plan"])
+        ref_own = me.expm_full(A, funcs, m, tol)
+        q = ref_own["eta"] / ref_own["theta"]
+        near_tie = q > 0 and abs(math.log2(q) - round(math.log2(q))) < 1e-12
+        if not near_tie:
+            assert s_gpu == ref_own["plan"], (i, s_gpu, ref_own["plan"])
+            ref = ref_own
+        else:
+            ref = me.expm_full(A, funcs, m, tol, force_plan=s_gpu)
+        assert abs(info[i]["norm1"] - ref_own["eta"]) <= 1e-14 * ref_own["eta"]
+        for f in funcs:
+            got = res[f][i].cpu().numpy()
+            err = me.rel_fro(got, ref[f])
+            worst = max(worst, err)
+            assert err <= bar, (i, f, A.shape[0], err)
+    return worst
+
+
+def test_mfma_fragment_layout(torch_dev):
+    from paper_2210_03714_amd import pfm
+    out = pfm.selftest_mfma(0)
+    A = np.array([[4.0 * i + k + 1 for k in range(4)] for i in range(16)])
+    B = np.array([[100.0 * (k + 1) + j for j in range(16)] for k in range(4)])
+    C = A @ B
+    # hardware layout: lane 16 g + i holds D[g + 4 v][i] in element v
+    for l in range(64):
+        i16, g = l & 15, l >> 4
+        for v in range(4):
+            assert out[l, v] == C[g + 4 * v, i16], (l, v)
+
+
+@pytest.mark.parametrize("m", [4, 5, 8])
+def test_config_small_full(torch_dev, m):
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    A, _ = wl.config_small()
+    _say("case config_small m=%d" % m)
+    res, info = pfm.expm(torch.from_numpy(A[None]).to(dev), ("exp", "phi1"), m=m, tol=1e-12)
+    torch.cuda.synchronize()
+    _check_instances([A], res, info, ("exp", "phi1"), m, 1e-12)
+    if m == 4:
+        assert info[0]["plan"] == 6
+
+
+def test_ragged_uneven_batch(torch_dev):
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    sizes = [1, 2, 15, 16, 17, 31, 33, 64, 100, 127, 128, 129, 200, 255, 256, 257, 300, 511, 512]
+    rng = np.random.default_rng(wl.SEED_BASE + 50)
+    mats = [wl.gaussian(n, float(rng.uniform(0.5, 8.0)), wl.SEED_BASE + 51 + n) for n in sizes]
+    _say("case ragged sizes", sizes)
+    At = [torch.from_numpy(a).to(dev) for a in mats]
+    res, info = pfm.expm(At, ("exp", "phi1"), m=8, tol=1e-12)
+    torch.cuda.synchronize()
+    _check_instances(mats, res, info, ("exp", "phi1"), 8, 1e-12)
+
+
+def test_config2_full_batch(torch_dev):
+    """512 matrices n = 128, ||A||_1 ~ U[0.5, 8], R8 at 1e-12: every instance."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    A, _ = wl.gaussian_batch(512, 128, 0.5, 8.0, wl.SEED_BASE + 1)
+    _say("case config2 512x128")
+    res, info = pfm.expm(torch.from_numpy(A).to(dev), ("exp",), m=8, tol=1e-12)
+    torch.cuda.synchronize()
+    w = _check_instances(list(A), res, info, ("exp",), 8, 1e-12)
+    _say("config2 worst rel err %.3e" % w)
+
+
+def test_headline_sampled(torch_dev):
+    """512 matrices n = 256 (the benchmark workload): 24 sampled instances."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    A, _ = wl.gaussian_batch(512, 256, 0.5, 8.0, wl.SEED_BASE + 10)
+    _say("case headline 512x256")
+    res, info = pfm.expm(torch.from_numpy(A).to(dev), ("exp",), m=8, tol=1e-12)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(0).choice(512, 24, replace=False)
+    w = _check_instances(list(A), res, info, ("exp",), 8, 1e-12, idx=idx)
+    _say("headline worst rel err %.3e" % w)
+    # the plan of every instance against its own norm
+    th = info[0]["theta"]
+    for i in range(512):
+        eta = np.abs(A[i]).sum(0).max()
+        assert abs(info[i]["norm1"] - eta) <= 1e-14 * eta
+        assert info[i]["status"] == 0
+
+
+def test_pivoting_forced_plan(torch_dev):
+    """force s = 0 on ||A||_1 = 60: c_k B is far from small, so partial
+    pivoting swaps rows; parity still holds (the approximant is evaluated
+    outside its accuracy range, but both sides evaluate the same thing)."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    mats = [wl.gaussian(n, 60.0, wl.SEED_BASE + 70 + n) for n in (40, 130, 256)]
+    _say("case pivoting")
+    res, info = pfm.expm([torch.from_numpy(a).to(dev) for a in mats], ("exp",), m=8, tol=1e-12,
+                         force_plan=0)
+    torch.cuda.synchronize()
+    for i, a in enumerate(mats):
+        ref = me.expm_full(a, ("exp",), 8, 1e-12, force_plan=0)
+        err = me.rel_fro(res["exp"][i].cpu().numpy(), ref["exp"])
+        assert err <= 1e-11, (i, err)
+
+
+def test_singular_shift_and_nonfinite_are_isolated(torch_dev):
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    good = wl.gaussian(48, 2.0, wl.SEED_BASE + 80)
+    sing = np.diag(np.r_[5.0, np.linspace(0.1, 0.5, 47)])   # I - (1/5) B singular at s = 0
+    bad = good.copy()
+    bad[3, 7] = np.nan
+    mats = [good, sing, bad, good]
+    _say("case singular/nonfinite")
+    res, info = pfm.expm([torch.from_numpy(a).to(dev) for a in mats], ("exp",), m=8, tol=1e-12,
+                         force_plan=0)
+    torch.cuda.synchronize()
+    assert info[1]["status"] & pfm.SINGULAR_SHIFT and info[1]["bad_shift"] == 0
+    assert info[2]["status"] & pfm.NONFINITE
+    assert info[0]["status"] == 0 and info[3]["status"] == 0
+    ref = me.expm_full(good, ("exp",), 8, 1e-12, force_plan=0)
+    for i in (0, 3):
+        assert me.rel_fro(res["exp"][i].cpu().numpy(), ref["exp"]) <= TOL
+
+
+def test_deterministic(torch_dev):
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    A, _ = wl.gaussian_batch(16, 96, 0.5, 8.0, wl.SEED_BASE + 90)
+    At = torch.from_numpy(A).to(dev)
+    r1, _ = pfm.expm(At, ("exp", "phi1"), m=8)
+    r2, _ = pfm.expm(At, ("exp", "phi1"), m=8)
+    torch.cuda.synchronize()
+    assert torch.equal(r1["exp"], r2["exp"]) and torch.equal(r1["phi1"], r2["phi1"])
