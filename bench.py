@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the GPU path on one MI355X.
+
+Workload (the headline configuration): a batch of 512 real dense FP64
+matrices, n = 256, entries N(0,1) rescaled to ||A||_1 ~ U[0.5, 8] (seeded),
+exp(A) with m = 8 shifted solves (the 8-processor set of §4.2, alpha = 5) at
+tol 1e-12.  One step = one pfm_eval_batched call over the whole batch: norm
+and plan, the 4096 shifted LU factorisations, the fused solves + combination,
+the squaring levels and the store.  Inputs are resident in HBM before timing.
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(timed live with hipEvents on the library's stream) and the CPU oracle's rate
+on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "exp(A) evals/sec, batch n=256 at 1e-12 rel err (FP64 vs mixed); p99 latency"
+PEAK_FP64 = 78.6e12   # dense FP64 MFMA, FLOP/s
+PEAK_HBM = 8.0e12     # bytes/s
+
+PROBLEM_DTYPE = None
+
+
+def _problem_array(np, A, outs, ldf):
+    """pfm_problem records for a (batch, n, n) tensor A and output tensors."""
+    dt = np.dtype([("n", "<i4"), ("p", "<i4"), ("lda", "<i8"), ("ldv", "<i8"), ("ldf", "<i8"),
+                   ("A", "<u8"), ("V", "<u8"), ("F_exp", "<u8"), ("F_phi1", "<u8")])
+    assert dt.itemsize == 64
+    b, n = A.shape[0], A.shape[1]
+    arr = np.zeros(b, dtype=dt)
+    es = A.element_size()
+    arr["n"] = n
+    arr["lda"] = A.stride(1)
+    arr["ldf"] = ldf
+    arr["A"] = A.data_ptr() + np.arange(b, dtype=np.uint64) * np.uint64(A.stride(0) * es)
+    for key, t in outs.items():
+        arr[key] = t.data_ptr() + np.arange(b, dtype=np.uint64) * np.uint64(t.stride(0) * es)
+    return arr
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2210_03714_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, fn), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return k.get("bytes_per_launch")
+
+
+def cpu_baseline(A, seconds):
+    """The oracle, untuned, on consecutive instances of the same batch until
+    ``seconds`` have elapsed."""
+    from oracle import method as me
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    me.expm_full(A[0], ("exp",), 8, 1e-12)  # warm the θ cache
+    t0 = time.perf_counter()
+    k = 0
+    while k < A.shape[0] and (time.perf_counter() - t0) < seconds:
+        me.expm_full(A[k], ("exp",), 8, 1e-12)
+        k += 1
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": "%d consecutive instances of the n=256 batch (R8 exp, tol 1e-12), one process, "
+                      "numpy/scipy LAPACK with %d BLAS threads, %.1f s" % (k, threads, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the instance batch would be split across GPUs with no communication).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": src.numel() * 8, "calib_copy_bytes_written": dst.numel() * 8}))
+        return
+
+    from paper_2210_03714_amd import pfm
+    from paper_2210_03714_amd import workloads as wl
+
+    if not os.path.exists(pfm.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    L = pfm.lib()
+
+    batch, n, m, tol = args.batch, args.n, 8, 1e-12
+    A, _ = wl.gaussian_batch(batch, n, 0.5, 8.0, wl.SEED_BASE + 10)
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(A).to(dev)
+    out = torch.empty_like(At)
+    info = torch.empty(batch * pfm.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    probs = _problem_array(np, At, {"F_exp": out}, out.stride(1))
+    import ctypes
+    pptr = ctypes.cast(probs.ctypes.data, ctypes.POINTER(pfm.Problem))
+    ctx = pfm.Context(0)
+    stream = torch.cuda.current_stream()
+    sptr = ctypes.c_void_p(stream.cuda_stream)
+    iptr = ctypes.c_void_p(info.data_ptr())
+
+    def step():
+        rc = L.pfm_eval_batched(ctx.handle, pfm.EXP, m, tol, pfm.FP64, pfm.R64, batch, pptr, iptr, -1, sptr)
+        if rc:
+            raise pfm.PfmError(rc, ctx.last_error())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check()
+    phases, calls = ctx.profile_read()
+    ctx.profile(False)
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    ms_per_step = max(wall_ms, ev_ms)
+    value = batch / (ms_per_step / 1e3)
+
+    inf = np.frombuffer(info.cpu().numpy().tobytes(), dtype=pfm.INFO_DTYPE)
+    svals = inf["plan"].astype(np.int64)
+    n3 = float(n) ** 3
+    flops = {
+        "lu": batch * m * (2.0 / 3.0) * n3,
+        "solve_combine": batch * m * 2.0 * n3,
+        "square": float(svals.sum()) * 2.0 * n3,
+    }
+    step_flops = sum(flops.values())
+    dom = max(("lu", "solve_combine", "square"), key=lambda p: phases[p][0])
+    tot_ms, launches = phases[dom]
+    per_launch_ms = tot_ms / max(1, launches)
+    flops_per_launch = flops[dom] * calls / max(1, launches)
+    achieved = flops_per_launch / (per_launch_ms * 1e-3)
+    kname = {"lu": "lu_f64_kernel<256>", "solve_combine": "solve_full_f64_kernel<256,32>",
+             "square": "square_level_f64_kernel"}[dom]
+
+    res = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batch 512 x dense n=256 FP64, N(0,1) rescaled to ||A||_1~U[0.5,8], "
+                               "exp(A), m=8 shifted solves (R8, alpha=5), tol 1e-12, FP64 path",
+                   "batch": batch, "n": n, "m": m, "tol": tol, "prec": "fp64",
+                   "seed": wl.SEED_BASE + 10, "mean_s": float(svals.mean())},
+        "roofline": {"bound": "mfma", "kernel": kname, "achieved": round(achieved / 1e12, 3),
+                     "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64, 4),
+                     "traffic": traffic_from_profile(kname)},
+        "phases_ms_per_step": {p: round(v[0] / max(1, calls), 4) for p, v in phases.items()},
+        "path_tflops": round(step_flops / (ms_per_step * 1e-3) / 1e12, 3),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(A, args.cpu_seconds)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

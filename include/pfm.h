@@ -152,6 +152,18 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec,
  * calls on this context (PFM_ERR_DEVICE if a bounded device wait timed out). */
 int pfm_check(pfm_ctx *ctx, pfm_stream_t stream);
 
+/* Phase timing.  enable != 0: every later pfm_eval_batched on this context
+ * records hipEvents on its stream around four phases -- 0: shifted LU
+ * factorisations, 1: shifted solves fused with the combination, 2: squaring
+ * levels, 3: store of the results -- and accumulates their elapsed times.
+ * Enabling or disabling resets the totals. */
+int pfm_profile(pfm_ctx *ctx, int enable);
+
+/* Totals since the last pfm_profile call: ms[4] milliseconds per phase,
+ * launches[4] kernel launches per phase (may be NULL), *calls the number of
+ * timed calls (may be NULL).  Waits for the last timed call to finish. */
+int pfm_profile_read(pfm_ctx *ctx, double *ms, int *launches, int *calls);
+
 /* Library version string (static storage). */
 const char *pfm_version(void);
 

@@ -25,6 +25,9 @@
 
 using namespace pfm;
 
+// phases timed by pfm_profile: LU, solve+combine, squaring, store
+constexpr int kNumPhases = 4;
+
 struct pfm_ctx {
   int device = 0;
   size_t budget = 0;
@@ -41,6 +44,14 @@ struct pfm_ctx {
   // device buffer for per-level squaring task lists
   void *tasks = nullptr;
   size_t tasks_bytes = 0;
+  // optional phase timing (hipEvents on the caller's stream)
+  bool prof = false;
+  bool prof_pending = false;
+  hipEvent_t pev[kNumPhases + 1] = {};
+  double prof_ms[kNumPhases] = {};
+  int prof_launches[kNumPhases] = {};
+  int prof_calls = 0;
+  int cur_launches[kNumPhases] = {};
   std::string err;
 };
 
@@ -114,9 +125,52 @@ int staging(pfm_ctx *ctx, size_t bytes, char **out) {
   return PFM_OK;
 }
 
+int prof_harvest(pfm_ctx *ctx) {
+  if (!ctx->prof_pending) return PFM_OK;
+  HIP_TRY(ctx, hipEventSynchronize(ctx->pev[kNumPhases]));
+  for (int p = 0; p < kNumPhases; ++p) {
+    float ms = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->pev[p], ctx->pev[p + 1]));
+    ctx->prof_ms[p] += ms;
+    ctx->prof_launches[p] += ctx->cur_launches[p];
+  }
+  ctx->prof_calls++;
+  ctx->prof_pending = false;
+  return PFM_OK;
+}
+
+inline void prof_mark(pfm_ctx *ctx, int idx, hipStream_t stream) {
+  if (ctx->prof) (void)hipEventRecord(ctx->pev[idx], stream);
+}
+
 }  // namespace
 
 extern "C" {
+
+int pfm_profile(pfm_ctx *ctx, int enable) {
+  if (!ctx) return PFM_ERR_INVALID;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (enable && !ctx->pev[0])
+    for (int p = 0; p <= kNumPhases; ++p) HIP_TRY(ctx, hipEventCreate(&ctx->pev[p]));
+  int rc = prof_harvest(ctx);
+  if (rc) return rc;
+  ctx->prof = enable != 0;
+  for (int p = 0; p < kNumPhases; ++p) { ctx->prof_ms[p] = 0.0; ctx->prof_launches[p] = 0; }
+  ctx->prof_calls = 0;
+  return PFM_OK;
+}
+
+int pfm_profile_read(pfm_ctx *ctx, double *ms, int *launches, int *calls) {
+  if (!ctx || !ms) return PFM_ERR_INVALID;
+  int rc = prof_harvest(ctx);
+  if (rc) return rc;
+  for (int p = 0; p < kNumPhases; ++p) {
+    ms[p] = ctx->prof_ms[p];
+    if (launches) launches[p] = ctx->prof_launches[p];
+  }
+  if (calls) *calls = ctx->prof_calls;
+  return PFM_OK;
+}
 
 const char *pfm_version(void) { return "pfm 0.1 (gfx950; f64 full-matrix path)"; }
 
@@ -144,6 +198,8 @@ int pfm_create(pfm_ctx **out, int device, size_t budget) {
 int pfm_destroy(pfm_ctx *ctx) {
   if (!ctx) return PFM_ERR_INVALID;
   (void)hipSetDevice(ctx->device);
+  for (int p = 0; p <= kNumPhases; ++p)
+    if (ctx->pev[p]) (void)hipEventDestroy(ctx->pev[p]);
   if (ctx->pin_ev) {
     (void)hipEventSynchronize(ctx->pin_ev);
     (void)hipEventDestroy(ctx->pin_ev);
@@ -349,6 +405,10 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipMemcpyAsync(h_plan, d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
+  {
+    int rcp = prof_harvest(ctx);
+    if (rcp) return rcp;
+  }
   std::vector<int> svec(batch);
   int smax = 0;
   for (int i = 0; i < batch; ++i) {
@@ -361,6 +421,8 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
                      h_plan[i].s, kSCap);
     }
 
+  for (int p = 0; p < kNumPhases; ++p) ctx->cur_launches[p] = 0;
+  prof_mark(ctx, 0, stream);
   // 2. shifted LU factorisations, all (instance, shift) pairs of a size class
   //    in one launch
   for (int c = 0; c < 3; ++c) {
@@ -371,7 +433,9 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     if (c == 0) hipLaunchKernelGGL(lu_f64_kernel<128>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, 0);
     if (c == 1) hipLaunchKernelGGL(lu_f64_kernel<256>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, 0);
     if (c == 2) hipLaunchKernelGGL(lu_f64_kernel<512>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, 0);
+    ctx->cur_launches[0]++;
   }
+  prof_mark(ctx, 1, stream);
   // 3. solves fused with the combination
   for (int c = 0; c < 3; ++c) {
     const int nl = (int)cls_list[c].size();
@@ -380,7 +444,9 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     if (c == 0) hipLaunchKernelGGL((solve_full_f64_kernel<128, 32>), dim3(xcd_grid(nl, 128 / 32)), dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi);
     if (c == 1) hipLaunchKernelGGL((solve_full_f64_kernel<256, 32>), dim3(xcd_grid(nl, 256 / 32)), dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi);
     if (c == 2) hipLaunchKernelGGL((solve_full_f64_kernel<512, 16>), dim3(xcd_grid(nl, 512 / 16)), dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi);
+    ctx->cur_launches[1]++;
   }
+  prof_mark(ctx, 2, stream);
   // 4. squaring levels: task lists built here, one launch per level
   std::vector<SqTask> all;
   std::vector<std::pair<int64_t, int>> lv;  // (offset, count)
@@ -423,17 +489,22 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
       const auto &e = lv[j - 1];
       hipLaunchKernelGGL(square_level_f64_kernel, dim3(e.second), dim3(256), 0, stream, d_desc,
                          dt + e.first, e.second, j, wsd);
+      ctx->cur_launches[2]++;
     }
   } else {
     HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
     ctx->pin_pending = true;
   }
+  prof_mark(ctx, 3, stream);
   // 5. results to the caller's row-major buffers, then the info records
   int maxn = 0;
   for (int i = 0; i < batch; ++i) maxn = std::max(maxn, probs[i].n);
   const int tn = (maxn + 31) / 32;
   hipLaunchKernelGGL(store_full_kernel, dim3(tn * tn, batch), dim3(256), 0, stream, d_desc, d_plan,
                      wsd, T.want_exp, T.want_phi);
+  ctx->cur_launches[3]++;
+  prof_mark(ctx, 4, stream);
+  if (ctx->prof) ctx->prof_pending = true;
   if (info)
     hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_plan,
                        (InfoRec *)info, batch, ee->order, theta);

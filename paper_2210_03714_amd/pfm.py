@@ -68,6 +68,8 @@ def lib():
         L.pfm_check.argtypes = [vp, vp]
         L.pfm_version.restype = ctypes.c_char_p
         L.pfm_selftest_mfma.argtypes = [i32, dp]
+        L.pfm_profile.argtypes = [vp, i32]
+        L.pfm_profile_read.argtypes = [vp, dp, ip, ip]
         _lib = L
     return _lib
 
@@ -140,6 +142,24 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def profile(self, enable=True):
+        rc = lib().pfm_profile(self._h, 1 if enable else 0)
+        if rc:
+            raise PfmError(rc, self.last_error())
+
+    PHASES = ("lu", "solve_combine", "square", "store")
+
+    def profile_read(self):
+        """{phase: (total_ms, launches)} and the number of timed calls."""
+        ms = (ctypes.c_double * 4)()
+        ln = (ctypes.c_int * 4)()
+        calls = ctypes.c_int()
+        rc = lib().pfm_profile_read(self._h, ctypes.cast(ms, ctypes.POINTER(ctypes.c_double)),
+                                    ctypes.cast(ln, ctypes.POINTER(ctypes.c_int)), ctypes.byref(calls))
+        if rc:
+            raise PfmError(rc, self.last_error())
+        return {p: (ms[i], ln[i]) for i, p in enumerate(self.PHASES)}, calls.value
 
     def last_error(self):
         return lib().pfm_last_error(self._h).decode()
