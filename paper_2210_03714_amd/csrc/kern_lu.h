@@ -16,29 +16,37 @@
 //
 // Algorithm: right-looking blocked LU with panel width 16.
 //   panel     rows j0.., 16 columns, one row per thread in registers; pivot =
-//             first index of max |x| (LAPACK idamax rule) found with wave
-//             shuffles and a 4-entry LDS reduction; 2 barriers per column.
+//             first index of max |x| (LAPACK idamax rule): a shuffle
+//             reduction per wave, then each wave posts its candidate row to a
+//             double-buffered LDS slot, so one barrier per column suffices;
 //   swaps     applied to all columns outside the panel;
 //   U12       = L11^{-1} A12, one column per thread;
-//   A22      -= L21 U12 on v_mfma_f64_16x16x4 with L21, U12 from LDS.
+//   A22      -= L21 U12 on v_mfma_f64_16x16x4 with L21, U12 from LDS, eight
+//             16x16 tiles in flight per wave.
+// Epilogue for the solve kernels: the 16x16 diagonal blocks of L and U are
+// inverted (stored separately) and every off-diagonal block is multiplied by
+// the inverse of the diagonal block of its column:
+//   L'_ij = L_ij inv(L_jj) (i > j),   U'_ij = U_ij inv(U_jj) (i < j).
+// A block substitution then runs on un-normalised blocks (the diagonal solves
+// leave the critical path; see the solve kernel).
 #pragma once
 #include "kern_common.h"
 
 namespace pfm {
 
 template <int NPMAX>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (NPMAX > 256 ? 1 : 2))
 lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
               int nlist, PlanRec *__restrict__ plan, Terms T,
               double *__restrict__ wsd, int *__restrict__ wsi, int action) {
   constexpr int H = (NPMAX + 255) / 256;
   constexpr int LDP = NPMAX + 16;  // panel column stride in LDS (== 16 mod 32)
   constexpr int LDU = NPMAX + 16;  // U12 row stride in LDS
+  constexpr int NOIDX = 0x7fffffff;
   __shared__ double panel[16 * LDP];
   __shared__ double u12[16 * LDU];
-  __shared__ double redv[4];
-  __shared__ int redi[4];
-  __shared__ double rowbuf[2][16];
+  __shared__ double cand[2][4][18];  // per column parity and wave: row, |pivot|, index
+  __shared__ double qbuf[2][16];
   __shared__ int ipiv_s[16];
   __shared__ int anyswap_s;
 
@@ -107,8 +115,9 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
 #pragma unroll
     for (int c2 = 0; c2 < 16; ++c2) {
       const int qrow = j0 + c2;
+      const int par = c2 & 1;
       double best = -1.0;
-      int bi = 0x7fffffff;
+      int bi = NOIDX;
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         const int r = j0 + t + 256 * h;
@@ -123,35 +132,41 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
         const int oi = __shfl_xor(bi, off);
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
-      if (lane == 0) { redv[wave] = best; redi[wave] = bi; }
-      __syncthreads();
-      best = redv[0];
-      bi = redi[0];
+      // the lane holding this wave's candidate posts it (row values included)
+      if (bi == NOIDX) {
+        if (lane == 0) { cand[par][wave][16] = -1.0; cand[par][wave][17] = (double)NOIDX; }
+      } else {
 #pragma unroll
-      for (int w = 1; w < 4; ++w) {
-        const double ob = redv[w];
-        const int oi = redi[w];
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      const int p = (bi == 0x7fffffff) ? qrow : bi;
-      const int po = (p - j0) & 255, ps = (p - j0) >> 8;
-      if (t == po) {
+        for (int h = 0; h < H; ++h) {
+          if (j0 + t + 256 * h == bi) {
 #pragma unroll
-        for (int h = 0; h < H; ++h)
-          if (h == ps) {
-#pragma unroll
-            for (int cc = 0; cc < 16; ++cc) rowbuf[0][cc] = pr[h][cc];
+            for (int cc = 0; cc < 16; ++cc) cand[par][wave][cc] = pr[h][cc];
+            cand[par][wave][16] = best;
+            cand[par][wave][17] = (double)bi;
           }
+        }
       }
       if (t == c2) {
 #pragma unroll
-        for (int cc = 0; cc < 16; ++cc) rowbuf[1][cc] = pr[0][cc];
+        for (int cc = 0; cc < 16; ++cc) qbuf[par][cc] = pr[0][cc];
       }
       __syncthreads();
+      best = cand[par][0][16];
+      bi = (int)cand[par][0][17];
+      int wsel = 0;
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        const double ob = cand[par][w][16];
+        const int oi = (int)cand[par][w][17];
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; wsel = w; }
+      }
+      const bool none = (bi == NOIDX);
+      const int p = none ? qrow : bi;
       double pv[16];
 #pragma unroll
-      for (int cc = 0; cc < 16; ++cc) pv[cc] = rowbuf[0][cc];
+      for (int cc = 0; cc < 16; ++cc) pv[cc] = none ? qbuf[par][cc] : cand[par][wsel][cc];
       if (p != qrow) {
+        const int po = (p - j0) & 255, ps = (p - j0) >> 8;
         if (t == c2) {
 #pragma unroll
           for (int cc = 0; cc < 16; ++cc) pr[0][cc] = pv[cc];
@@ -161,7 +176,7 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
           for (int h = 0; h < H; ++h)
             if (h == ps) {
 #pragma unroll
-              for (int cc = 0; cc < 16; ++cc) pr[h][cc] = rowbuf[1][cc];
+              for (int cc = 0; cc < 16; ++cc) pr[h][cc] = qbuf[par][cc];
             }
         }
       }
@@ -236,29 +251,26 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
     }
     __syncthreads();
 
-    // trailing update A22 -= L21 U12 (16x16 tiles, one per wave at a time)
-    // Four independent tiles per wave per round keep loads and MFMAs in flight.
+    // trailing update A22 -= L21 U12, eight 16x16 tiles in flight per wave
+    constexpr int TB = 8;
     const int nt = (np - j0 - 16) >> 4;
     const int ntt = nt * nt;
-    for (int base = wave; base < ntt; base += 16) {
-      v4d acc[4];
-      v4d *Cp[4];
-      int tr[4], tc[4];
+    for (int base = wave; base < ntt; base += 4 * TB) {
+      v4d acc[TB];
+      int tr[TB], tc[TB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < TB; ++u) {
         const int tile = base + 4 * u;
         tr[u] = tile % nt;
         tc[u] = tile / nt;
-        if (tile < ntt) {
-          Cp[u] = reinterpret_cast<v4d *>(W + (int64_t)(j0 + 16 + 16 * tc[u] + i16) * np + j0 + 16 +
-                                          16 * tr[u] + 4 * g);
-          acc[u] = *Cp[u];
-        }
+        if (tile < ntt)
+          acc[u] = *reinterpret_cast<const v4d *>(W + (int64_t)(j0 + 16 + 16 * tc[u] + i16) * np + j0 +
+                                                  16 + 16 * tr[u] + 4 * g);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < TB; ++u) {
           if (base + 4 * u < ntt) {
             const double a = panel[(16 + 16 * tr[u] + ar) + (4 * q + g) * LDP];
             const double b = u12[(4 * q + g) * LDU + 16 * tc[u] + i16];
@@ -267,8 +279,10 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (base + 4 * u < ntt) *Cp[u] = acc[u];
+      for (int u = 0; u < TB; ++u)
+        if (base + 4 * u < ntt)
+          *reinterpret_cast<v4d *>(W + (int64_t)(j0 + 16 + 16 * tc[u] + i16) * np + j0 + 16 +
+                                   16 * tr[u] + 4 * g) = acc[u];
     }
     __syncthreads();
   }
@@ -307,6 +321,39 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) dU[b * 256 + r + 16 * j] = x[r];
+  }
+  __syncthreads();
+
+  // 4. Off-diagonal blocks times the inverse of their column's diagonal block.
+  {
+    constexpr int TB = 4;
+    const int nb2 = nblk * nblk;
+    for (int base = wave; base < nb2; base += 4 * TB) {
+      v4d acc[TB];
+      int bi[TB], bj[TB];
+#pragma unroll
+      for (int u = 0; u < TB; ++u) {
+        const int id = base + 4 * u;
+        bi[u] = id % nblk;
+        bj[u] = id / nblk;
+        acc[u] = zero4();
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          if (base + 4 * u < nb2 && bi[u] != bj[u]) {
+            const double a = W[(16 * bi[u] + ar) + (int64_t)(16 * bj[u] + 4 * q + g) * np];
+            const double *inv = (bi[u] > bj[u] ? dL : dU) + bj[u] * 256;
+            acc[u] = mfma16(a, inv[(4 * q + g) + 16 * i16], acc[u]);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TB; ++u)
+        if (base + 4 * u < nb2 && bi[u] != bj[u])
+          *reinterpret_cast<v4d *>(W + (int64_t)(16 * bj[u] + i16) * np + 16 * bi[u] + 4 * g) = acc[u];
+    }
   }
 }
 

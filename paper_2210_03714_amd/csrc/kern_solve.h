@@ -7,31 +7,69 @@
 // from the same solves (§2: several functions from one set of F_i).
 //
 // One workgroup owns one column slab (SW columns) of one instance and loops
-// over all shifts: it loads P_k^T B[:, slab], runs the forward (unit L) and
-// backward (U) block substitutions on v_mfma_f64_16x16x4 with the 16x16
-// diagonal blocks pre-inverted by the LU kernel, and accumulates w_k Z_k in
-// registers.  No Z_k ever reaches memory; the slab of R (and Phi) is written
-// once, column-major, into the squaring buffers.
+// over all shifts, accumulating w_k Z_k in registers; no Z_k ever reaches
+// memory and the slab of R (and Phi) is written once, column-major, into the
+// squaring buffers.
+//
+// Block substitution without diagonal solves on the critical path: with the
+// LU kernel's L'_ij = L_ij inv(L_jj), the forward recurrence
+//   Y_i <- Y_i - sum_{j<i} L'_ij Y_j      (Y = P^T B[:, slab] initially)
+// runs on un-normalised blocks, and Z_i = inv(L_ii) Y_i afterwards, for all i
+// at once (the same algebra as Z_i = inv(L_ii)(Y_i - sum_j L_ij Z_j)).  The
+// backward pass with U'_ij = U_ij inv(U_jj) is the mirror image.  Each step is
+// then: the owner wave posts its finished block to a double-buffered LDS slab,
+// one barrier, and every wave updates its own blocks below (MFMA, A operand
+// from the factor buffer, loaded before the barrier).
 //
 // Register layout: row block b (16 rows) belongs to wave b mod 4; each wave
 // holds RB = NPMAX/64 row blocks x CT = SW/16 column tiles of Z and of the
-// accumulators as MFMA C fragments.  After a diagonal block is finished it is
-// broadcast through a double-buffered LDS slab and every wave updates its
-// remaining row blocks with the off-diagonal blocks of L (or U) streamed from
-// the factor buffer.
+// accumulators as MFMA C fragments.
 #pragma once
 #include "kern_common.h"
 
 namespace pfm {
 
-template <int NPMAX, int SW>
-__global__ void __launch_bounds__(256)
+// Z[rb] <- inv(D_b) Z[rb] for the row blocks this wave owns (D = L or U
+// diagonal blocks, stored inverted, column-major 16 x 16).
+template <int RB, int CT, int SW>
+__device__ __forceinline__ void diag_pass(v4d (&Z)[RB][CT], const double *__restrict__ dinv,
+                                          double *__restrict__ st, int wave, int nblk, int ar,
+                                          int g, int i16) {
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int b = wave + 4 * rb;
+    if (b >= nblk) continue;
+    double a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = dinv[b * 256 + ar + 16 * (4 * q + g)];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) st[(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
+    wave_lds_sync();
+    v4d acc[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = zero4();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        acc[ct] = mfma16(a[q], st[(4 * q + g) * SW + 16 * ct + i16], acc[ct]);
+    wave_lds_sync();
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) Z[rb][ct] = acc[ct];
+  }
+}
+
+template <int NPMAX, int SW, bool PHI>
+__global__ void __launch_bounds__(256, (NPMAX > 256 ? 1 : 2))
 solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
                       int nlist, const PlanRec *__restrict__ plan, Terms T,
                       double *__restrict__ wsd, const int *__restrict__ wsi) {
   constexpr int RB = NPMAX / 64;
   constexpr int CT = SW / 16;
   constexpr int NSLAB = NPMAX / SW;
+  constexpr int PRB = PHI ? RB : 1;
   __shared__ double S[2][16 * SW];
   __shared__ double Tst[4][16 * SW];
 
@@ -50,12 +88,17 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
   const int ar = arow(i16);
   const double sc = ldexp(1.0, -plan[ii].s);
 
-  v4d Z[RB][CT], Ae[RB][CT], Ap[RB][CT];
+  v4d Z[RB][CT], Ae[RB][CT], Ap[PRB][CT];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) { Ae[rb][ct] = zero4(); Ap[rb][ct] = zero4(); }
+    for (int ct = 0; ct < CT; ++ct) Ae[rb][ct] = zero4();
+#pragma unroll
+  for (int rb = 0; rb < PRB; ++rb)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) Ap[rb][ct] = zero4();
 
+#pragma unroll 1
   for (int k = 0; k < T.nterms; ++k) {
     const double *W = wsd + D.fac_off + (int64_t)k * np * np;
     const int *perm = wsi + D.perm_ioff + (int64_t)k * np;
@@ -82,115 +125,97 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
       }
     }
 
-    // forward substitution with unit-lower L
+    // forward recurrence with L'
+#pragma unroll 1
     for (int b = 0; b < nblk; ++b) {
       double *Sb = S[b & 1];
+      double a[RB][4];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int bb = wave + 4 * rb;
+        if (bb > b && bb < nblk) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a[rb][q] = W[(16 * bb + ar) + (int64_t)(16 * b + 4 * q + g) * np];
+        }
+      }
       if (wave == (b & 3)) {
         const int rbo = b >> 2;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
+        for (int rb = 0; rb < RB; ++rb)
           if (rb == rbo) {
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-              for (int v = 0; v < 4; ++v) Tst[wave][(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
-            wave_lds_sync();
-            v4d acc[CT];
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) acc[ct] = zero4();
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const double a = dL[b * 256 + ar + 16 * (4 * q + g)];
-#pragma unroll
-              for (int ct = 0; ct < CT; ++ct)
-                acc[ct] = mfma16(a, Tst[wave][(4 * q + g) * SW + 16 * ct + i16], acc[ct]);
-            }
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-              Z[rb][ct] = acc[ct];
-#pragma unroll
-              for (int v = 0; v < 4; ++v) Sb[(4 * g + v) * SW + 16 * ct + i16] = acc[ct][v];
-            }
+              for (int v = 0; v < 4; ++v) Sb[(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
           }
-        }
       }
       __syncthreads();
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         const int bb = wave + 4 * rb;
         if (bb > b && bb < nblk) {
-          double a[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) a[q] = W[(16 * bb + ar) + (int64_t)(16 * b + 4 * q + g) * np];
 #pragma unroll
           for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
-              Z[rb][ct] = mfma16(-a[q], Sb[(4 * q + g) * SW + 16 * ct + i16], Z[rb][ct]);
+              Z[rb][ct] = mfma16(-a[rb][q], Sb[(4 * q + g) * SW + 16 * ct + i16], Z[rb][ct]);
         }
       }
     }
+    diag_pass<RB, CT, SW>(Z, dL, Tst[wave], wave, nblk, ar, g, i16);
 
-    // backward substitution with upper U
+    // backward recurrence with U'
+#pragma unroll 1
     for (int b = nblk - 1; b >= 0; --b) {
       double *Sb = S[b & 1];
+      double a[RB][4];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int bb = wave + 4 * rb;
+        if (bb < b) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a[rb][q] = W[(16 * bb + ar) + (int64_t)(16 * b + 4 * q + g) * np];
+        }
+      }
       if (wave == (b & 3)) {
         const int rbo = b >> 2;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
+        for (int rb = 0; rb < RB; ++rb)
           if (rb == rbo) {
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-              for (int v = 0; v < 4; ++v) Tst[wave][(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
-            wave_lds_sync();
-            v4d acc[CT];
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) acc[ct] = zero4();
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const double a = dU[b * 256 + ar + 16 * (4 * q + g)];
-#pragma unroll
-              for (int ct = 0; ct < CT; ++ct)
-                acc[ct] = mfma16(a, Tst[wave][(4 * q + g) * SW + 16 * ct + i16], acc[ct]);
-            }
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-              Z[rb][ct] = acc[ct];
-#pragma unroll
-              for (int v = 0; v < 4; ++v) Sb[(4 * g + v) * SW + 16 * ct + i16] = acc[ct][v];
-            }
+              for (int v = 0; v < 4; ++v) Sb[(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
           }
-        }
       }
       __syncthreads();
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         const int bb = wave + 4 * rb;
         if (bb < b) {
-          double a[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) a[q] = W[(16 * bb + ar) + (int64_t)(16 * b + 4 * q + g) * np];
 #pragma unroll
           for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
-              Z[rb][ct] = mfma16(-a[q], Sb[(4 * q + g) * SW + 16 * ct + i16], Z[rb][ct]);
+              Z[rb][ct] = mfma16(-a[rb][q], Sb[(4 * q + g) * SW + 16 * ct + i16], Z[rb][ct]);
         }
       }
     }
+    diag_pass<RB, CT, SW>(Z, dU, Tst[wave], wave, nblk, ar, g, i16);
 
     // combination in the round-off form (§4.3)
     const double we = T.we_re[k], wp = T.wp_re[k];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
+      for (int ct = 0; ct < CT; ++ct) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          Ae[rb][ct][v] = fma(we, Z[rb][ct][v], Ae[rb][ct][v]);
-          if (T.want_phi) Ap[rb][ct][v] = fma(wp, Z[rb][ct][v], Ap[rb][ct][v]);
+        for (int v = 0; v < 4; ++v) Ae[rb][ct][v] = fma(we, Z[rb][ct][v], Ae[rb][ct][v]);
+        if constexpr (PHI) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Ap[rb][ct][v] = fma(wp, Z[rb][ct][v], Ap[rb][ct][v]);
         }
+      }
     __syncthreads();
   }
 
@@ -205,11 +230,16 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
     for (int ct = 0; ct < CT; ++ct) {
       const int col = c0 + 16 * ct + i16;
       if (col >= np) continue;
+      const int r = 16 * b + 4 * g;
+      v4d o = Ae[rb][ct];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * b + 4 * g + v;
-        R0[r + (int64_t)col * np] = Ae[rb][ct][v] + (r == col ? T.a0e : 0.0);
-        if (T.want_phi) P0[r + (int64_t)col * np] = Ap[rb][ct][v] + (r == col ? T.a0p : 0.0);
+      for (int v = 0; v < 4; ++v) o[v] += (r + v == col ? T.a0e : 0.0);
+      *reinterpret_cast<v4d *>(R0 + r + (int64_t)col * np) = o;
+      if constexpr (PHI) {
+        v4d op = Ap[rb][ct];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) op[v] += (r + v == col ? T.a0p : 0.0);
+        *reinterpret_cast<v4d *>(P0 + r + (int64_t)col * np) = op;
       }
     }
   }

@@ -441,9 +441,20 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     const int nl = (int)cls_list[c].size();
     if (!nl) continue;
     const int *dl = d_list + list_off[c];
-    if (c == 0) hipLaunchKernelGGL((solve_full_f64_kernel<128, 32>), dim3(xcd_grid(nl, 128 / 32)), dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi);
-    if (c == 1) hipLaunchKernelGGL((solve_full_f64_kernel<256, 32>), dim3(xcd_grid(nl, 256 / 32)), dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi);
-    if (c == 2) hipLaunchKernelGGL((solve_full_f64_kernel<512, 16>), dim3(xcd_grid(nl, 512 / 16)), dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi);
+#define PFM_SOLVE(NPM, SWW)                                                                      \
+  do {                                                                                           \
+    const dim3 gs(xcd_grid(nl, NPM / SWW));                                                      \
+    if (T.want_phi)                                                                              \
+      hipLaunchKernelGGL((solve_full_f64_kernel<NPM, SWW, true>), gs, dim3(256), 0, stream,     \
+                         d_desc, dl, nl, d_plan, T, wsd, wsi);                                   \
+    else                                                                                         \
+      hipLaunchKernelGGL((solve_full_f64_kernel<NPM, SWW, false>), gs, dim3(256), 0, stream,    \
+                         d_desc, dl, nl, d_plan, T, wsd, wsi);                                   \
+  } while (0)
+    if (c == 0) PFM_SOLVE(128, 32);
+    if (c == 1) PFM_SOLVE(256, 16);
+    if (c == 2) PFM_SOLVE(512, 16);
+#undef PFM_SOLVE
     ctx->cur_launches[1]++;
   }
   prof_mark(ctx, 2, stream);
