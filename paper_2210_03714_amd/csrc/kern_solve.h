@@ -61,6 +61,95 @@ __device__ __forceinline__ void diag_pass(v4d (&Z)[RB][CT], const double *__rest
   }
 }
 
+// Z <- M^{-1} Z for one shift, Z = P^T (right-hand side) on entry: forward
+// recurrence with L', diagonal pass, backward recurrence with U', diagonal pass.
+// All waves of the workgroup must call it together.
+template <int RB, int CT, int SW>
+__device__ __forceinline__ void lu_solve_slab(v4d (&Z)[RB][CT], const double *__restrict__ W,
+                                              const double *__restrict__ dL,
+                                              const double *__restrict__ dU, double (*S)[16 * SW],
+                                              double *__restrict__ st, int np, int nblk, int wave,
+                                              int ar, int g, int i16) {
+    // forward recurrence with L'
+#pragma unroll 1
+  for (int b = 0; b < nblk; ++b) {
+    double *Sb = S[b & 1];
+    double a[RB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int bb = wave + 4 * rb;
+      if (bb > b && bb < nblk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[rb][q] = W[(16 * bb + ar) + (int64_t)(16 * b + 4 * q + g) * np];
+      }
+    }
+    if (wave == (b & 3)) {
+      const int rbo = b >> 2;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+        if (rb == rbo) {
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Sb[(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int bb = wave + 4 * rb;
+      if (bb > b && bb < nblk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+            Z[rb][ct] = mfma16(-a[rb][q], Sb[(4 * q + g) * SW + 16 * ct + i16], Z[rb][ct]);
+      }
+    }
+  }
+  diag_pass<RB, CT, SW>(Z, dL, st, wave, nblk, ar, g, i16);
+
+  // backward recurrence with U'
+#pragma unroll 1
+  for (int b = nblk - 1; b >= 0; --b) {
+    double *Sb = S[b & 1];
+    double a[RB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int bb = wave + 4 * rb;
+      if (bb < b) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[rb][q] = W[(16 * bb + ar) + (int64_t)(16 * b + 4 * q + g) * np];
+      }
+    }
+    if (wave == (b & 3)) {
+      const int rbo = b >> 2;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+        if (rb == rbo) {
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Sb[(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int bb = wave + 4 * rb;
+      if (bb < b) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+            Z[rb][ct] = mfma16(-a[rb][q], Sb[(4 * q + g) * SW + 16 * ct + i16], Z[rb][ct]);
+      }
+    }
+  }
+  diag_pass<RB, CT, SW>(Z, dU, st, wave, nblk, ar, g, i16);
+
+}
+
 template <int NPMAX, int SW, bool PHI>
 __global__ void __launch_bounds__(256, (NPMAX > 256 ? 1 : 2))
 solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
@@ -125,83 +214,7 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
       }
     }
 
-    // forward recurrence with L'
-#pragma unroll 1
-    for (int b = 0; b < nblk; ++b) {
-      double *Sb = S[b & 1];
-      double a[RB][4];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int bb = wave + 4 * rb;
-        if (bb > b && bb < nblk) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) a[rb][q] = W[(16 * bb + ar) + (int64_t)(16 * b + 4 * q + g) * np];
-        }
-      }
-      if (wave == (b & 3)) {
-        const int rbo = b >> 2;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-          if (rb == rbo) {
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) Sb[(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
-          }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int bb = wave + 4 * rb;
-        if (bb > b && bb < nblk) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-              Z[rb][ct] = mfma16(-a[rb][q], Sb[(4 * q + g) * SW + 16 * ct + i16], Z[rb][ct]);
-        }
-      }
-    }
-    diag_pass<RB, CT, SW>(Z, dL, Tst[wave], wave, nblk, ar, g, i16);
-
-    // backward recurrence with U'
-#pragma unroll 1
-    for (int b = nblk - 1; b >= 0; --b) {
-      double *Sb = S[b & 1];
-      double a[RB][4];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int bb = wave + 4 * rb;
-        if (bb < b) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) a[rb][q] = W[(16 * bb + ar) + (int64_t)(16 * b + 4 * q + g) * np];
-        }
-      }
-      if (wave == (b & 3)) {
-        const int rbo = b >> 2;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-          if (rb == rbo) {
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) Sb[(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
-          }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int bb = wave + 4 * rb;
-        if (bb < b) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-              Z[rb][ct] = mfma16(-a[rb][q], Sb[(4 * q + g) * SW + 16 * ct + i16], Z[rb][ct]);
-        }
-      }
-    }
-    diag_pass<RB, CT, SW>(Z, dU, Tst[wave], wave, nblk, ar, g, i16);
+    lu_solve_slab<RB, CT, SW>(Z, W, dL, dU, S, Tst[wave], np, nblk, wave, ar, g, i16);
 
     // combination in the round-off form (§4.3)
     const double we = T.we_re[k], wp = T.wp_re[k];

@@ -22,6 +22,7 @@
 #include "kern_misc.h"
 #include "kern_solve.h"
 #include "kern_square.h"
+#include "kern_action.h"
 
 using namespace pfm;
 
@@ -297,8 +298,8 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   }
   const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
   if (!ee || !ep) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
-  if (dtype != PFM_R64 || prec != PFM_FP64 || action || ee->pair)
-    return set_err(ctx, PFM_ERR_UNSUPPORTED, "only the real FP64 full-matrix path with real shifts is built");
+  if (dtype != PFM_R64 || prec != PFM_FP64 || ee->pair)
+    return set_err(ctx, PFM_ERR_UNSUPPORTED, "only the real FP64 path with real shifts is built");
   for (int i = 0; i < batch; ++i)
     if (probs[i].n > 512) return set_err(ctx, PFM_ERR_UNSUPPORTED, "n > 512 not supported on this path");
 
@@ -400,8 +401,8 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
 
   // 1. norm and plan on the device; the host reads the plans back once (it
   //    needs max s to size the squaring launches)
-  hipLaunchKernelGGL(plan_kernel, dim3(batch), dim3(256), 0, stream, d_desc, d_plan, theta, 0,
-                     force_plan, 0);
+  hipLaunchKernelGGL(plan_kernel, dim3(batch), dim3(256), 0, stream, d_desc, d_plan, theta,
+                     action ? 1 : 0, force_plan, 0);
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipMemcpyAsync(h_plan, d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
@@ -415,11 +416,17 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     svec[i] = std::max(0, std::min(h_plan[i].s, kSCap));
     smax = std::max(smax, svec[i]);
   }
-  for (int i = 0; i < batch; ++i)
-    if (h_plan[i].s > kSCap) {
-      return set_err(ctx, PFM_ERR_INVALID, "instance %d needs s = %d squarings (cap %d)", i,
-                     h_plan[i].s, kSCap);
-    }
+  if (action)
+    for (int i = 0; i < batch; ++i)
+      if (h_plan[i].s > kNCap)
+        return set_err(ctx, PFM_ERR_INVALID, "instance %d needs N = %d steps (cap %d)", i,
+                       h_plan[i].s, kNCap);
+  if (!action)
+    for (int i = 0; i < batch; ++i)
+      if (h_plan[i].s > kSCap) {
+        return set_err(ctx, PFM_ERR_INVALID, "instance %d needs s = %d squarings (cap %d)", i,
+                       h_plan[i].s, kSCap);
+      }
 
   for (int p = 0; p < kNumPhases; ++p) ctx->cur_launches[p] = 0;
   prof_mark(ctx, 0, stream);
@@ -430,12 +437,55 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     if (!nl) continue;
     const int *dl = d_list + list_off[c];
     const dim3 glu(xcd_grid(nl, nterms));
-    if (c == 0) hipLaunchKernelGGL(lu_f64_kernel<128>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, 0);
-    if (c == 1) hipLaunchKernelGGL(lu_f64_kernel<256>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, 0);
-    if (c == 2) hipLaunchKernelGGL(lu_f64_kernel<512>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, 0);
+    const int am = action ? 1 : 0;
+    if (c == 0) hipLaunchKernelGGL(lu_f64_kernel<128>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, am);
+    if (c == 1) hipLaunchKernelGGL(lu_f64_kernel<256>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, am);
+    if (c == 2) hipLaunchKernelGGL(lu_f64_kernel<512>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, am);
     ctx->cur_launches[0]++;
   }
   prof_mark(ctx, 1, stream);
+  if (action) {
+    // 3'. B = A / N column-major, then the N-step recurrence per column slab
+    int maxn = 0, maxp = 0;
+    for (int i = 0; i < batch; ++i) {
+      maxn = std::max(maxn, desc[i].npad);
+      maxp = std::max(maxp, probs[i].p);
+    }
+    const int tnb = (maxn + 31) / 32;
+    hipLaunchKernelGGL(prep_bt_kernel, dim3(tnb * tnb, batch), dim3(256), 0, stream, d_desc, d_plan, wsd);
+    for (int c = 0; c < 3; ++c) {
+      const int nl = (int)cls_list[c].size();
+      if (!nl) continue;
+      const int *dl = d_list + list_off[c];
+#define PFM_ACT(NPM, SWW)                                                                       \
+  do {                                                                                          \
+    const int ns = (maxp + SWW - 1) / SWW;                                                      \
+    const dim3 ga(xcd_grid(nl, ns));                                                            \
+    if (T.want_exp)                                                                             \
+      hipLaunchKernelGGL((action_f64_kernel<NPM, SWW, false>), ga, dim3(256), 0, stream, d_desc, \
+                         dl, nl, ns, d_plan, T, wsd, wsi);                                      \
+    if (T.want_phi)                                                                             \
+      hipLaunchKernelGGL((action_f64_kernel<NPM, SWW, true>), ga, dim3(256), 0, stream, d_desc,  \
+                         dl, nl, ns, d_plan, T, wsd, wsi);                                      \
+  } while (0)
+      if (c == 0) PFM_ACT(128, 16);
+      if (c == 1) PFM_ACT(256, 16);
+      if (c == 2) PFM_ACT(512, 16);
+#undef PFM_ACT
+      ctx->cur_launches[1] += T.want_exp + T.want_phi;
+    }
+    prof_mark(ctx, 2, stream);
+    prof_mark(ctx, 3, stream);
+    prof_mark(ctx, 4, stream);
+    if (ctx->prof) ctx->prof_pending = true;
+    HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
+    ctx->pin_pending = true;
+    if (info)
+      hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_plan,
+                         (InfoRec *)info, batch, ee->order, theta);
+    HIP_TRY(ctx, hipGetLastError());
+    return PFM_OK;
+  }
   // 3. solves fused with the combination
   for (int c = 0; c < 3; ++c) {
     const int nl = (int)cls_list[c].size();

@@ -6,6 +6,7 @@ namespace pfm {
 
 constexpr int kMaxTerms = 16;   // nonzero-shift solves per call
 constexpr int kSCap = 1000;     // largest squaring count accepted
+constexpr int kNCap = 1 << 20;  // largest action step count accepted
 constexpr int kSqTile = 64;     // squaring GEMM tile edge
 
 // One problem instance as the kernels see it.  Offsets index the context's
