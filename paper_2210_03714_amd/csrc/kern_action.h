@@ -78,6 +78,7 @@ action_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ili
   const int N = plan[ii].s;
   const double Nd = (double)N;
   const double *Bt = wsd + D.r_off;
+  const int hn = D.hn, emb = D.emb, cin = D.cin;
 
   v4d u[RB][CT], acc[RB][CT], Z[RB][CT];
   v4d u1[PHI ? RB : 1][CT];
@@ -90,7 +91,16 @@ action_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ili
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * b + 4 * g + v;
-        u[rb][ct][v] = (b < nblk && r < n && col < p) ? D.V[(int64_t)r * D.ldv + col] : 0.0;
+        double x = 0.0;
+        if (b < nblk && r < n && col < p) {
+          if (!emb)
+            x = D.V[(int64_t)r * D.ldv + col];
+          else if (r < hn)  // emb(V) first block column: [Re V; Im V]
+            x = cin ? D.V[2 * ((int64_t)r * D.ldv + col)] : D.V[(int64_t)r * D.ldv + col];
+          else
+            x = cin ? D.V[2 * ((int64_t)(r - hn) * D.ldv + col) + 1] : 0.0;
+        }
+        u[rb][ct][v] = x;
       }
     }
   }
@@ -149,7 +159,11 @@ action_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ili
       for (int ct = 0; ct < CT; ++ct) acc[rb][ct] = zero4();
 #pragma unroll 1
     for (int k = 0; k < T.nterms; ++k) {
-      const double w = first_phi ? T.wp_re[k] : T.we_re[k];
+      const int fold = T.fold[k];
+      if (fold && T.fn[k] != (first_phi ? 1 : 0)) continue;  // a pair of the other function
+      const double w = fold ? 1.0 : (first_phi ? T.wp_re[k] : T.we_re[k]);
+      const double fre = fold ? (T.fn[k] ? T.wp_re[k] : T.we_re[k]) : 1.0;
+      const double fim = fold ? (T.fn[k] ? T.wp_im[k] : T.we_im[k]) : 0.0;
       if (w == 0.0) continue;
       const double *W = wsd + D.fac_off + (int64_t)k * np * np;
       const int *perm = wsi + D.perm_ioff + (int64_t)k * np;
@@ -163,16 +177,30 @@ action_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ili
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int r = 16 * b + 4 * g + v;
-            Z[rb][ct][v] = (b < nblk) ? Ybuf[perm[r] * SW + 16 * ct + i16] : 0.0;
+            double z = 0.0;
+            if (b < nblk) {
+              const int q = perm[r];
+              z = Ybuf[q * SW + 16 * ct + i16];
+              if (fold) {  // emb(w Y) = w_re Y + w_im J Y
+                const double yj = q < hn ? -Ybuf[(q + hn) * SW + 16 * ct + i16] : Ybuf[(q - hn) * SW + 16 * ct + i16];
+                z = fre * z + fim * yj;
+              }
+            }
+            Z[rb][ct][v] = z;
           }
       }
       lu_solve_slab<RB, CT, SW>(Z, W, dL, dU, S, Tst[wave], np, nblk, wave, ar, g, i16);
+      const double fsc = (fold && T.pair_real) ? 2.0 : 1.0;
+      const int frows = (fold && T.pair_real) ? hn : np;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
+        for (int ct = 0; ct < CT; ++ct) {
+          const int r0 = 16 * (wave + 4 * rb) + 4 * g;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[rb][ct][v] = fma(w, Z[rb][ct][v], acc[rb][ct][v]);
+          for (int v = 0; v < 4; ++v)
+            if (r0 + v < frows) acc[rb][ct][v] = fma(fsc * w, Z[rb][ct][v], acc[rb][ct][v]);
+        }
     }
     // next state
 #pragma unroll
@@ -204,7 +232,14 @@ action_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ili
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * b + 4 * g + v;
-        if (b < nblk && r < n && col < p) F[(int64_t)r * D.ldf + col] = u[rb][ct][v];
+        if (b < nblk && r < n && col < p) {
+          if (!emb)
+            F[(int64_t)r * D.ldf + col] = u[rb][ct][v];
+          else if (cin)
+            F[2 * ((int64_t)(r < hn ? r : r - hn) * D.ldf + col) + (r < hn ? 0 : 1)] = u[rb][ct][v];
+          else if (r < hn)
+            F[(int64_t)r * D.ldf + col] = u[rb][ct][v];
+        }
       }
     }
   }

@@ -75,16 +75,29 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
 
   if (t == 0) anyswap_s = 0;
 
-  // 1. W = I - c B, B = A 2^-s (or A / N), transposed from row-major A.
+  // 1. W = I - c B, B = A 2^-s (or A / N), transposed from row-major A.  For
+  //    a complex shift on an embedded instance, c B = c_re B + c_im J B with
+  //    (J B)[r] = -B[r + hn] (r < hn), B[r - hn] (r >= hn).
   {
-    double *tile = panel;  // 32 x 33 staging tile
+    const double ci = T.c_im[k];
+    const bool jterm = D.emb && ci != 0.0;
+    const double csi = ldexp(ci, -P.s);
+    double *tile = panel;          // 32 x 33 staging tile
+    double *tilej = panel + 1056;  // J B staging tile
     for (int tr = 0; tr < np; tr += 32) {
       for (int tc = 0; tc < np; tc += 32) {
         const int rl = t >> 3, cl = (t & 7) * 4;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int r = tr + rl, cc = tc + cl + u;
-          tile[rl * 33 + cl + u] = (r < n && cc < n) ? D.A[(int64_t)r * D.lda + cc] : 0.0;
+          const bool ok = r < n && cc < n;
+          tile[rl * 33 + cl + u] = ok ? D.A[(int64_t)r * D.lda + cc] : 0.0;
+          if (jterm) {
+            const int hn = D.hn;
+            tilej[rl * 33 + cl + u] =
+                ok ? (r < hn ? -D.A[(int64_t)(r + hn) * D.lda + cc] : D.A[(int64_t)(r - hn) * D.lda + cc])
+                   : 0.0;
+          }
         }
         __syncthreads();
         const int cc = tc + rl;
@@ -93,7 +106,11 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
           const int r = tr + cl + u;
           if (r < np && cc < np) {
             const double a = tile[(cl + u) * 33 + rl];
-            const double cb = action ? c * (a / Nd) : cs * a;
+            double cb = action ? c * (a / Nd) : cs * a;
+            if (jterm) {
+              const double aj = tilej[(cl + u) * 33 + rl];
+              cb += action ? ci * (aj / Nd) : csi * aj;
+            }
             W[r + (int64_t)cc * np] = (r == cc ? 1.0 : 0.0) - cb;
           }
         }

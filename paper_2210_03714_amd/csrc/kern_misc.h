@@ -9,12 +9,13 @@ namespace pfm {
 // N = max(1, ceil(eta / θ)) (action).  Column sums run over rows in order.
 __global__ void __launch_bounds__(256)
 plan_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan, double theta,
-            int action, int force_plan, int cplx) {
+            int action, int force_plan) {
   __shared__ double red[256];
   __shared__ int bad_s;
   const int ii = blockIdx.x;
   const InstDesc D = inst[ii];
-  const int n = D.n;
+  const int n = D.emb ? D.hn : D.n;  // the caller's matrix
+  const int cplx = D.cin;
   if (threadIdx.x == 0) bad_s = 0;
   __syncthreads();
   double mx = 0.0;
@@ -23,11 +24,11 @@ plan_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan, doubl
     double s = 0.0;
     if (cplx) {
       for (int r = 0; r < n; ++r) {
-        const double *z = D.A + 2 * ((int64_t)r * D.lda + c);
+        const double *z = D.Ain + 2 * ((int64_t)r * D.ldin + c);
         s += hypot(z[0], z[1]);
       }
     } else {
-      for (int r = 0; r < n; ++r) s += fabs(D.A[(int64_t)r * D.lda + c]);
+      for (int r = 0; r < n; ++r) s += fabs(D.Ain[(int64_t)r * D.ldin + c]);
     }
     if (!isfinite(s)) bad = 1;
     mx = fmax(mx, s);
@@ -70,14 +71,18 @@ plan_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan, doubl
 }
 
 // Copy the final R / Phi (column-major, npad) to the caller's row-major
-// outputs, through a 32 x 32 LDS transpose.  Grid: x = tile, y = instance.
+// outputs, through a 32 x 32 LDS transpose.  Embedded instances: the first
+// block column holds [Re R; Im R]; complex outputs are interleaved, a real
+// output (conjugate pair on real A) takes the top half.  Grid: x = tile,
+// y = instance.
 __global__ void __launch_bounds__(256)
 store_full_kernel(const InstDesc *__restrict__ inst, const PlanRec *__restrict__ plan,
                   const double *__restrict__ wsd, int want_exp, int want_phi) {
-  __shared__ double tile[32][33];
+  __shared__ double tile[2][32][33];
   const int ii = blockIdx.y;
   const InstDesc D = inst[ii];
-  const int n = D.n, np = D.npad;
+  const int np = D.npad;
+  const int n = D.emb ? D.hn : D.n;
   const int tn = (n + 31) / 32;
   const int tix = blockIdx.x;
   if (tix >= tn * tn) return;
@@ -85,24 +90,66 @@ store_full_kernel(const InstDesc *__restrict__ inst, const PlanRec *__restrict__
   const int s = plan[ii].s;
   const int64_t nn = (int64_t)np * np;
   const int t = threadIdx.x;
+  const bool cplx_out = D.emb && D.cin;
   for (int which = 0; which < 2; ++which) {
     if (which == 0 && !want_exp) continue;
     if (which == 1 && !want_phi) continue;
     const double *src = wsd + D.r_off + (which * 2 + (s & 1)) * nn;
     double *dst = which ? D.Fp : D.Fe;
-    // read column-major: column c0 + t/8, rows r0 + (t%8)*4 + u
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int r = r0 + (t & 7) * 4 + u, c = c0 + (t >> 3);
-      tile[(t & 7) * 4 + u][t >> 3] = (r < n && c < n) ? src[r + (int64_t)c * np] : 0.0;
+      const bool ok = r < n && c < n;
+      tile[0][(t & 7) * 4 + u][t >> 3] = ok ? src[r + (int64_t)c * np] : 0.0;
+      if (cplx_out) tile[1][(t & 7) * 4 + u][t >> 3] = ok ? src[r + D.hn + (int64_t)c * np] : 0.0;
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int r = r0 + (t >> 3), c = c0 + (t & 7) * 4 + u;
-      if (r < n && c < n) dst[(int64_t)r * D.ldf + c] = tile[t >> 3][(t & 7) * 4 + u];
+      if (r < n && c < n) {
+        if (cplx_out) {
+          dst[2 * ((int64_t)r * D.ldf + c)] = tile[0][t >> 3][(t & 7) * 4 + u];
+          dst[2 * ((int64_t)r * D.ldf + c) + 1] = tile[1][t >> 3][(t & 7) * 4 + u];
+        } else {
+          dst[(int64_t)r * D.ldf + c] = tile[0][t >> 3][(t & 7) * 4 + u];
+        }
+      }
     }
     __syncthreads();
+  }
+}
+
+// E = emb(A) = [[Re A, -Im A], [Im A, Re A]] row-major (2 hn)^2 for embedded
+// instances (a real A has Im A = 0).  Grid: x = 32x32 tile of E, y = instance.
+__global__ void __launch_bounds__(256)
+embed_kernel(const InstDesc *__restrict__ inst, double *__restrict__ wsd) {
+  const int ii = blockIdx.y;
+  const InstDesc D = inst[ii];
+  if (!D.emb) return;
+  const int n = D.n, hn = D.hn;
+  const int tn = (n + 31) / 32;
+  const int tix = blockIdx.x;
+  if (tix >= tn * tn) return;
+  const int r0 = (tix / tn) * 32, c0 = (tix % tn) * 32;
+  double *E = wsd + D.e_off;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = r0 + (t >> 3), c = c0 + (t & 7) * 4 + u;
+    if (r < n && c < n) {
+      const int rb = r >= hn, cb = c >= hn;
+      const int ri = r - rb * hn, ci = c - cb * hn;
+      double x, y;
+      if (D.cin) {
+        x = D.Ain[2 * ((int64_t)ri * D.ldin + ci)];
+        y = D.Ain[2 * ((int64_t)ri * D.ldin + ci) + 1];
+      } else {
+        x = D.Ain[(int64_t)ri * D.ldin + ci];
+        y = 0.0;
+      }
+      E[(int64_t)r * n + c] = (rb == cb) ? x : (rb ? y : -y);
+    }
   }
 }
 

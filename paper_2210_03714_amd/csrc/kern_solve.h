@@ -170,12 +170,14 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
   const int n = D.n, np = D.npad;
   if (np > NPMAX || (np & 15) || n > np || n < 1) return;  // sizes the host never sends
   const int c0 = sl * SW;
-  if (c0 >= np) return;
+  const int ncol = D.ncol;
+  if (c0 >= ncol) return;
   const int nblk = np >> 4;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int i16 = lane & 15, g = lane >> 4;
   const int ar = arow(i16);
   const double sc = ldexp(1.0, -plan[ii].s);
+  const int hn = D.hn;
 
   v4d Z[RB][CT], Ae[RB][CT], Ap[PRB][CT];
 #pragma unroll
@@ -194,7 +196,11 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
     const double *dL = wsd + D.dinv_off + (int64_t)(2 * k) * nblk * 256;
     const double *dU = dL + (int64_t)nblk * 256;
 
-    // right-hand side P^T B[:, slab], B = A 2^-s
+    // right-hand side P^T B[:, slab], B = A 2^-s; with a folded complex weight
+    // P^T emb(w B)[:, slab] = P^T (w_re B + w_im J B)[:, slab]
+    const int fold = T.fold[k];
+    const double fre = fold ? (T.fn[k] ? T.wp_re[k] : T.we_re[k]) : 1.0;
+    const double fim = fold ? (T.fn[k] ? T.wp_im[k] : T.we_im[k]) : 0.0;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const int b = wave + 4 * rb;
@@ -205,9 +211,17 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
         for (int v = 0; v < 4; ++v) {
           const int r = 16 * b + 4 * g + v;
           double val = 0.0;
-          if (b < nblk && r < n && col < n) {
+          if (b < nblk && r < n && col < ncol) {
             const int pr = perm[r];
-            if (pr < n) val = sc * D.A[(int64_t)pr * D.lda + col];
+            if (pr < n) {
+              val = D.A[(int64_t)pr * D.lda + col];
+              if (fold) {
+                const double aj = pr < hn ? -D.A[(int64_t)(pr + hn) * D.lda + col]
+                                          : D.A[(int64_t)(pr - hn) * D.lda + col];
+                val = fre * val + fim * aj;
+              }
+              val *= sc;
+            }
           }
           Z[rb][ct][v] = val;
         }
@@ -216,17 +230,24 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
 
     lu_solve_slab<RB, CT, SW>(Z, W, dL, dU, S, Tst[wave], np, nblk, wave, ar, g, i16);
 
-    // combination in the round-off form (§4.3)
-    const double we = T.we_re[k], wp = T.wp_re[k];
+    // combination in the round-off form (§4.3); folded terms already carry
+    // their weight, a conjugate pair on real A adds twice the real (top) half
+    const double we = fold ? 0.0 : T.we_re[k];
+    const double wp = fold ? 0.0 : T.wp_re[k];
+    const double fsc = T.pair_real ? 2.0 : 1.0;
+    const int frows = T.pair_real ? hn : np;
+    const bool fe = fold && T.fn[k] == 0, fp = fold && T.fn[k] == 1;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
+        const int r0 = 16 * (wave + 4 * rb) + 4 * g;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Ae[rb][ct][v] = fma(we, Z[rb][ct][v], Ae[rb][ct][v]);
-        if constexpr (PHI) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) Ap[rb][ct][v] = fma(wp, Z[rb][ct][v], Ap[rb][ct][v]);
+        for (int v = 0; v < 4; ++v) {
+          const double z = Z[rb][ct][v];
+          const double zf = (r0 + v < frows) ? fsc * z : 0.0;
+          Ae[rb][ct][v] = fold ? (fe ? Ae[rb][ct][v] + zf : Ae[rb][ct][v]) : fma(we, z, Ae[rb][ct][v]);
+          if constexpr (PHI) Ap[rb][ct][v] = fold ? (fp ? Ap[rb][ct][v] + zf : Ap[rb][ct][v]) : fma(wp, z, Ap[rb][ct][v]);
         }
       }
     __syncthreads();
@@ -242,7 +263,7 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       const int col = c0 + 16 * ct + i16;
-      if (col >= np) continue;
+      if (col >= ncol) continue;
       const int r = 16 * b + 4 * g;
       v4d o = Ae[rb][ct];
 #pragma unroll

@@ -8,6 +8,9 @@
 // instance land on one XCD (workgroup b runs on XCD b mod 8) and share its L2.
 // Buffers ping-pong: level j reads buffer (j-1) mod 2 and writes j mod 2.
 // Stream order separates the levels, so no workgroup ever waits on another.
+// Embedded (complex) instances store only the first block column
+// [Re R; Im R] of emb(R); the A operand's other block column is rebuilt on
+// load, emb(R)[:, hn + j] = J emb(R)[:, j], and only hn columns are produced.
 #pragma once
 #include "kern_common.h"
 
@@ -29,7 +32,7 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
   const SqTask tk = tasks[q];
   if (tk.inst < 0) return;
   const InstDesc D = inst[tk.inst];
-  const int np = D.npad;
+  const int np = D.npad, nr = D.n, ncol = D.ncol, hn = D.hn, emb = D.emb;
   const int which = tk.tile >> 20;
   const int lt = tk.tile & ((1 << 20) - 1);
   const int tl = (np + kSqTile - 1) / kSqTile;
@@ -54,11 +57,17 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int r = m0 + ar0 + u, kc = k0 + ak;
-      double a = (r < np) ? Asrc[r + (int64_t)kc * np] : 0.0;
+      double a = 0.0;
+      if (r < nr && kc < nr) {
+        if (!emb || kc < hn)
+          a = Asrc[r + (int64_t)kc * np];
+        else
+          a = r < hn ? -Asrc[(r + hn) + (int64_t)(kc - hn) * np] : Asrc[(r - hn) + (int64_t)(kc - hn) * np];
+      }
       if (which && r == kc) a += 1.0;  // (R + I) for the phi1 doubling
       ra[u] = a;
       const int c = n0 + bc;
-      rbv[u] = (c < np) ? Bsrc[(k0 + bk0 + u) + (int64_t)c * np] : 0.0;
+      rbv[u] = (c < ncol) ? Bsrc[(k0 + bk0 + u) + (int64_t)c * np] : 0.0;
     }
   };
 
@@ -98,7 +107,7 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
     for (int b = 0; b < 2; ++b) {
       const int c = n0 + 32 * wn + 16 * b + i16;
       const int r = m0 + 32 * wm + 16 * a + 4 * g;
-      if (c < np && r < np) {
+      if (c < ncol && r < np) {
         v4d o = acc[a][b] * scl;
         *reinterpret_cast<v4d *>(Cdst + r + (int64_t)c * np) = o;
       }

@@ -298,10 +298,17 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   }
   const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
   if (!ee || !ep) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
-  if (dtype != PFM_R64 || prec != PFM_FP64 || ee->pair)
-    return set_err(ctx, PFM_ERR_UNSUPPORTED, "only the real FP64 path with real shifts is built");
-  for (int i = 0; i < batch; ++i)
-    if (probs[i].n > 512) return set_err(ctx, PFM_ERR_UNSUPPORTED, "n > 512 not supported on this path");
+  if (prec != PFM_FP64)
+    return set_err(ctx, PFM_ERR_UNSUPPORTED, "requested precision path is not built");
+  const bool cplx = dtype == PFM_C128;
+  const bool pairs = ee->pair != 0;
+  const bool emb = cplx || pairs;  // complex arithmetic runs on the real embedding
+  for (int i = 0; i < batch; ++i) {
+    const int nk = emb ? 2 * probs[i].n : probs[i].n;
+    if (nk > 512)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED, "problem %d: n = %d exceeds this path (%s)", i, probs[i].n,
+                     emb ? "complex: n <= 256" : "n <= 512");
+  }
 
   double theta;
   int rc = pfm_theta(f, m, tol, &theta);
@@ -309,19 +316,37 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
 
   Terms T;
   memset(&T, 0, sizeof T);
-  T.nterms = ee->nterms;
-  T.pair = 0;
   T.want_exp = (f & PFM_EXP) ? 1 : 0;
   T.want_phi = (f & PFM_PHI1) ? 1 : 0;
   T.a0e = ee->a0;
   T.a0p = ep->a0;
-  for (int k = 0; k < ee->nterms; ++k) {
-    T.c_re[k] = ee->c_re[k];
-    T.c_im[k] = ee->c_im[k];
-    T.we_re[k] = ee->w_re[k];
-    T.we_im[k] = ee->w_im[k];
-    T.wp_re[k] = ep->w_re[k];
-    T.wp_im[k] = ep->w_im[k];
+  if (!pairs) {
+    // one real shift set shared by both functions (§2)
+    T.nterms = ee->nterms;
+    for (int k = 0; k < ee->nterms; ++k) {
+      T.c_re[k] = ee->c_re[k];
+      T.we_re[k] = ee->w_re[k];
+      T.wp_re[k] = ep->w_re[k];
+    }
+  } else {
+    // one conjugate pair per function (the Padé poles of exp and phi1
+    // differ); the exponential's pair is always needed (squaring/recurrence)
+    int k = 0;
+    for (int fn = 0; fn < 1 + T.want_phi; ++fn) {
+      const PfmSetEntry *e = fn ? ep : ee;
+      for (int cj = 0; cj < (cplx ? 2 : 1); ++cj) {  // complex A: both members
+        const double sg = cj ? -1.0 : 1.0;
+        T.c_re[k] = e->c_re[0];
+        T.c_im[k] = sg * e->c_im[0];
+        if (fn) { T.wp_re[k] = e->w_re[0]; T.wp_im[k] = sg * e->w_im[0]; }
+        else { T.we_re[k] = e->w_re[0]; T.we_im[k] = sg * e->w_im[0]; }
+        T.fold[k] = 1;
+        T.fn[k] = fn;
+        ++k;
+      }
+    }
+    T.nterms = k;
+    T.pair_real = cplx ? 0 : 1;
   }
   const int nterms = T.nterms;
 
@@ -332,22 +357,33 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   for (int i = 0; i < batch; ++i) {
     const pfm_problem &P = probs[i];
     InstDesc &D = desc[i];
-    D.A = (const double *)P.A;
+    memset(&D, 0, sizeof D);
+    D.Ain = (const double *)P.A;
+    D.ldin = P.lda;
+    D.cin = cplx ? 1 : 0;
     D.V = (const double *)P.V;
     D.Fe = (double *)P.F_exp;
     D.Fp = (double *)P.F_phi1;
-    D.lda = P.lda;
     D.ldv = P.ldv;
     D.ldf = P.ldf;
-    D.n = P.n;
-    D.npad = (P.n + 15) / 16 * 16;
+    D.emb = emb ? 1 : 0;
+    D.hn = P.n;
+    D.n = emb ? 2 * P.n : P.n;
+    D.ncol = P.n;
+    D.npad = (D.n + 15) / 16 * 16;
     D.p = P.p;
     D.cls = D.npad <= 128 ? 0 : (D.npad <= 256 ? 1 : 2);
     const int64_t np = D.npad, nn = np * np;
     D.fac_off = dofs;  dofs += align_up(nterms * nn, 64);
     D.dinv_off = dofs; dofs += align_up(nterms * 2 * (np / 16) * 256, 64);
     D.r_off = dofs;    dofs += align_up(4 * nn, 64);
-    D.x_off = 0;
+    if (emb) {
+      D.e_off = dofs;  dofs += align_up((int64_t)D.n * D.n, 64);
+      D.lda = D.n;     // A is set once the workspace base is known
+    } else {
+      D.A = (const double *)P.A;
+      D.lda = P.lda;
+    }
     D.perm_ioff = iofs; iofs += align_up(nterms * np, 64);
     D.ipiv_ioff = iofs; iofs += align_up(nterms * np, 64);
     cls_list[D.cls].push_back(i);
@@ -379,6 +415,9 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   InstDesc *d_desc = (InstDesc *)(tail + plan_bytes);
   int *d_list = (int *)(tail + plan_bytes + desc_bytes);
 
+  for (int i = 0; i < batch; ++i)
+    if (desc[i].emb) desc[i].A = wsd + desc[i].e_off;
+
   // descriptors and class lists (stored back to back) through pinned staging
   char *pin = nullptr;
   const size_t stage_bytes = desc_bytes + list_bytes + plan_bytes;
@@ -399,10 +438,16 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   HIP_TRY(ctx, hipMemcpyAsync(d_desc, h_desc, batch * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
   HIP_TRY(ctx, hipMemcpyAsync(d_list, h_list, batch * sizeof(int), hipMemcpyHostToDevice, stream));
 
+  if (emb) {
+    int maxk = 0;
+    for (int i = 0; i < batch; ++i) maxk = std::max(maxk, desc[i].n);
+    const int te = (maxk + 31) / 32;
+    hipLaunchKernelGGL(embed_kernel, dim3(te * te, batch), dim3(256), 0, stream, d_desc, wsd);
+  }
   // 1. norm and plan on the device; the host reads the plans back once (it
   //    needs max s to size the squaring launches)
   hipLaunchKernelGGL(plan_kernel, dim3(batch), dim3(256), 0, stream, d_desc, d_plan, theta,
-                     action ? 1 : 0, force_plan, 0);
+                     action ? 1 : 0, force_plan);
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipMemcpyAsync(h_plan, d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
@@ -516,9 +561,10 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     int x = 0;
     for (int i = 0; i < batch; ++i) {
       if (svec[i] < j) continue;
-      const int tl = (desc[i].npad + kSqTile - 1) / kSqTile;
+      const int tlm = (desc[i].npad + kSqTile - 1) / kSqTile;
+      const int tln = (desc[i].ncol + kSqTile - 1) / kSqTile;
       for (int w = 0; w < 1 + T.want_phi; ++w)
-        for (int tt = 0; tt < tl * tl; ++tt) qx[x].push_back(SqTask{i, tt + (w << 20)});
+        for (int tt = 0; tt < tlm * tln; ++tt) qx[x].push_back(SqTask{i, tt + (w << 20)});
       x = (x + 1) & 7;
     }
     size_t mx = 0;
@@ -560,7 +606,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   // 5. results to the caller's row-major buffers, then the info records
   int maxn = 0;
   for (int i = 0; i < batch; ++i) maxn = std::max(maxn, probs[i].n);
-  const int tn = (maxn + 31) / 32;
+  const int tn = (maxn + 31) / 32;  // stores run over the caller's n
   hipLaunchKernelGGL(store_full_kernel, dim3(tn * tn, batch), dim3(256), 0, stream, d_desc, d_plan,
                      wsd, T.want_exp, T.want_phi);
   ctx->cur_launches[3]++;

@@ -11,17 +11,30 @@ constexpr int kSqTile = 64;     // squaring GEMM tile edge
 
 // One problem instance as the kernels see it.  Offsets index the context's
 // workspace (doubles for *_off in the double region, ints for *_ioff).
+//
+// Complex problems run on the real embedding of a complex matrix,
+// emb(X + iY) = [[X, -Y], [Y, X]] (size 2n): emb(f(A)) = f(emb(A)) for the
+// real-coefficient functions here, and a complex scalar c acts as
+// c_re I + c_im J with J = emb(i I).  For such instances (emb = 1) A points at
+// the embedded matrix built in the workspace, n = 2 hn, and only the first
+// block column (hn columns) of every n x n result is computed.
 struct InstDesc {
-  const double *A;   // caller's A (row-major; complex: interleaved)
+  const double *A;   // row-major real matrix the kernels read (embedded if emb)
+  const double *Ain; // caller's A (the norm is taken on it; complex: interleaved)
   const double *V;   // caller's V (action), else null
   double *Fe;        // caller's outputs (row-major)
   double *Fp;
   int64_t lda, ldv, ldf;
+  int64_t ldin;      // leading dimension of Ain
   int32_t n, npad, p, cls;
+  int32_t emb;       // 1: complex embedding, A is 2 hn x 2 hn
+  int32_t hn;        // emb: size of the original problem
+  int32_t cin;       // 1: caller's data are complex (interleaved)
+  int32_t ncol;      // columns of the result that are computed (n, or hn if emb)
   int64_t fac_off;   // nterms * npad^2 (complex: 2x) : LU factors, column-major
   int64_t dinv_off;  // nterms * 2 * (npad/16) * 256   : inverted 16x16 diagonal blocks of L and U
   int64_t r_off;     // 4 * npad^2 : R ping-pong buffers, then phi1 ping-pong buffers
-  int64_t x_off;     // action: npad * p-sized state vectors
+  int64_t e_off;     // emb: the embedded matrix, row-major n x n
   int64_t perm_ioff; // nterms * npad : row permutation of each factorisation
   int64_t ipiv_ioff; // nterms * npad : LAPACK-style pivot sequence
 };
@@ -37,14 +50,22 @@ struct PlanRec {
 };
 
 // The shift/weight list of a call (passed by value to kernels).
+// Real weights (fold = 0): Z_k is accumulated as we_k Z_k and wp_k Z_k.
+// Complex weight (fold = 1, embedded instances): the weight of function fn_k
+// is folded into the right-hand side, M_k^{-1} emb(w_k B), since M_k^{-1}
+// commutes with J; the solve returns emb(w_k Z_k) directly.
+// pair_real: the set is one conjugate pair per function on a real A, so the
+// pair contributes 2 Re(w_k Z_k) = twice the top half of emb(w_k Z_k).
 struct Terms {
   int32_t nterms;
-  int32_t pair;        // 1: real A with complex-conjugate pairs -> combine 2 Re(w Z)
+  int32_t pair_real;
   int32_t want_exp, want_phi;
   double a0e, a0p;
   double c_re[kMaxTerms], c_im[kMaxTerms];
   double we_re[kMaxTerms], we_im[kMaxTerms];
   double wp_re[kMaxTerms], wp_im[kMaxTerms];
+  int32_t fold[kMaxTerms];
+  int32_t fn[kMaxTerms];
 };
 
 }  // namespace pfm
