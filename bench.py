@@ -188,7 +188,7 @@ def main():
     per_launch_ms = tot_ms / max(1, launches)
     flops_per_launch = flops[dom] * calls / max(1, launches)
     achieved = flops_per_launch / (per_launch_ms * 1e-3)
-    kname = {"lu": "lu_f64_kernel<256>", "solve_combine": "solve_full_f64_kernel<256,32>",
+    kname = {"lu": "lu_kernel<256,double>", "solve_combine": "solve_full_f64_kernel<256,16>",
              "square": "square_level_f64_kernel"}[dom]
 
     res = {
@@ -215,6 +215,38 @@ def main():
         "phases_ms_per_step": {p: round(v[0] / max(1, calls), 4) for p, v in phases.items()},
         "path_tflops": round(step_flops / (ms_per_step * 1e-3) / 1e12, 3),
     }
+    # mixed-precision leg: the same batch at tol 1e-10, against the FP64 path
+    # on the same GPU at the same tolerance
+    outm = torch.empty_like(At)
+    outd = torch.empty_like(At)
+    pm = _problem_array(np, At, {"F_exp": outm}, outm.stride(1))
+    pd = _problem_array(np, At, {"F_exp": outd}, outd.stride(1))
+    pmp = ctypes.cast(pm.ctypes.data, ctypes.POINTER(pfm.Problem))
+    pdp = ctypes.cast(pd.ctypes.data, ctypes.POINTER(pfm.Problem))
+    infom = torch.empty_like(info)
+
+    def step_mixed(prec, pp):
+        rc = L.pfm_eval_batched(ctx.handle, pfm.EXP, m, 1e-10, prec, pfm.R64, batch, pp,
+                                ctypes.c_void_p(infom.data_ptr()), -1, sptr)
+        if rc:
+            raise pfm.PfmError(rc, ctx.last_error())
+
+    legs = {}
+    for name, prec, pp in (("mixed", pfm.MIXED, pmp), ("fp64", pfm.FP64, pdp)):
+        for _ in range(args.warmup):
+            step_mixed(prec, pp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.steps // 2)):
+            step_mixed(prec, pp)
+        torch.cuda.synchronize()
+        legs[name] = (time.perf_counter() - t0) * 1e3 / max(1, args.steps // 2)
+    ctx.check()
+    rel = ((outm - outd).flatten(1).norm(dim=1) / outd.flatten(1).norm(dim=1)).max().item()
+    res["mixed_tol1e-10"] = {"value": round(batch / (legs["mixed"] / 1e3), 2), "unit": "evals/s",
+                             "ms_per_step": round(legs["mixed"], 4),
+                             "fp64_same_tol_value": round(batch / (legs["fp64"] / 1e3), 2),
+                             "max_rel_err_vs_fp64_gpu": rel}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(A, args.cpu_seconds)
     print(json.dumps(res))

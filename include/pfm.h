@@ -170,8 +170,9 @@ const char *pfm_version(void);
 /* Test hook.  Runs one v_mfma_f64_16x16x4 on device `device` with operands
  * A[i][k] = 4 i + k + 1 and B[k][j] = 100 (k + 1) + j (i, j < 16, k < 4) and
  * copies the 64 lanes x 4 accumulator values, lane-major, to the host array
- * `out` (256 doubles).  Lets the tests confirm the fragment layout the
- * kernels assume.  Synchronous; allocates and frees its own 2 KiB. */
+ * `out[0..255]`; then the same for v_mfma_f32_16x16x4 into `out[256..511]`
+ * (512 doubles in all).  Lets the tests confirm the fragment layouts the
+ * kernels assume.  Synchronous; allocates and frees its own 4 KiB. */
 int pfm_selftest_mfma(int device, double *out);
 
 #ifdef __cplusplus

@@ -22,11 +22,13 @@
 
 namespace pfm {
 
-// Bt = A / N, column-major npad x npad, zero padded; into the instance's
-// (otherwise unused) squaring buffer.  Grid: x = 32x32 tile, y = instance.
+// B column-major npad x npad, zero padded.  action != 0: B = A / N into the
+// instance's (otherwise unused) squaring buffer; action == 0: B = A 2^-s into
+// the e_off buffer (residual products of the mixed path).
+// Grid: x = 32x32 tile, y = instance.
 __global__ void __launch_bounds__(256)
 prep_bt_kernel(const InstDesc *__restrict__ inst, const PlanRec *__restrict__ plan,
-               double *__restrict__ wsd) {
+               double *__restrict__ wsd, int action) {
   __shared__ double tile[32][33];
   const int ii = blockIdx.y;
   const InstDesc D = inst[ii];
@@ -36,12 +38,17 @@ prep_bt_kernel(const InstDesc *__restrict__ inst, const PlanRec *__restrict__ pl
   if (tix >= tn * tn) return;
   const int r0 = (tix % tn) * 32, c0 = (tix / tn) * 32;
   const double Nd = (double)plan[ii].s;
-  double *Bt = wsd + D.r_off;
+  double *Bt = wsd + (action ? D.r_off : D.e_off);
   const int t = threadIdx.x;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {  // row-major read
     const int r = r0 + (t >> 3), c = c0 + (t & 7) * 4 + u;
-    tile[t >> 3][(t & 7) * 4 + u] = (r < n && c < n) ? D.A[(int64_t)r * D.lda + c] / Nd : 0.0;
+    double a = 0.0;
+    if (r < n && c < n) {
+      a = D.A[(int64_t)r * D.lda + c];
+      a = action ? a / Nd : ldexp(a, -plan[ii].s);
+    }
+    tile[t >> 3][(t & 7) * 4 + u] = a;
   }
   __syncthreads();
 #pragma unroll
@@ -189,7 +196,7 @@ action_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ili
             Z[rb][ct][v] = z;
           }
       }
-      lu_solve_slab<RB, CT, SW>(Z, W, dL, dU, S, Tst[wave], np, nblk, wave, ar, g, i16);
+      lu_solve_slab<RB, CT, SW, double>(Z, W, dL, dU, S, Tst[wave], np, nblk, wave, ar, g, i16);
       const double fsc = (fold && T.pair_real) ? 2.0 : 1.0;
       const int frows = (fold && T.pair_real) ? hn : np;
 #pragma unroll

@@ -31,6 +31,28 @@ __device__ __forceinline__ v4d zero4() {
   return z;
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// v_mfma_f32_16x16x4_f32 (binary32 path).  Operand layout as above; element v
+// of lane (g, i) holds D[4 g + v][i] (checked by pfm_selftest_mfma32), so the
+// A operand is fed unpermuted.
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Element-type traits shared by the templated LU and substitution kernels.
+template <class S> struct MT;
+template <> struct MT<double> {
+  typedef v4d v4;
+  static __device__ __forceinline__ int arow_(int i16) { return arow(i16); }
+  static __device__ __forceinline__ v4 zero() { return zero4(); }
+};
+template <> struct MT<float> {
+  typedef v4f v4;
+  static __device__ __forceinline__ int arow_(int i16) { return i16; }
+  static __device__ __forceinline__ v4 zero() { v4f z = {0.f, 0.f, 0.f, 0.f}; return z; }
+};
+
 // Order LDS traffic of one wave (write then read by other lanes of it).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

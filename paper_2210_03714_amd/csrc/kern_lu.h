@@ -34,19 +34,26 @@
 
 namespace pfm {
 
-template <int NPMAX>
+template <int NPMAX, class S>
 __global__ void __launch_bounds__(256, (NPMAX > 256 ? 1 : 2))
-lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
+lu_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
               int nlist, PlanRec *__restrict__ plan, Terms T,
               double *__restrict__ wsd, int *__restrict__ wsi, int action) {
   constexpr int H = (NPMAX + 255) / 256;
   constexpr int LDP = NPMAX + 16;  // panel column stride in LDS (== 16 mod 32)
   constexpr int LDU = NPMAX + 16;  // U12 row stride in LDS
   constexpr int NOIDX = 0x7fffffff;
-  __shared__ double panel[16 * LDP];
-  __shared__ double u12[16 * LDU];
-  __shared__ double cand[2][4][18];  // per column parity and wave: row, |pivot|, index
-  __shared__ double qbuf[2][16];
+  typedef typename MT<S>::v4 v4;
+  // panel and U12 share one LDS block with the load phase's two 32x33
+  // binary64 staging tiles (2 x 1056 doubles, smaller than panel + U12)
+  constexpr int kPanelBytes = 16 * LDP * (int)sizeof(S);
+  constexpr int kSmemBytes = 2 * kPanelBytes;
+  static_assert(kSmemBytes >= 2 * 1056 * 8, "staging tiles must fit");
+  __shared__ __align__(16) char smem[kSmemBytes];
+  S *panel = reinterpret_cast<S *>(smem);
+  S *u12 = reinterpret_cast<S *>(smem + kPanelBytes);
+  __shared__ S cand[2][4][18];  // per column parity and wave: row, |pivot|, index
+  __shared__ S qbuf[2][16];
   __shared__ int ipiv_s[16];
   __shared__ int anyswap_s;
 
@@ -59,14 +66,14 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
   if (np > NPMAX || (np & 15) || n > np || n < 1) return;  // sizes the host never sends
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int i16 = lane & 15, g = lane >> 4;
-  const int ar = arow(i16);
+  const int ar = MT<S>::arow_(i16);
 
-  double *W = wsd + D.fac_off + (int64_t)k * np * np;
+  S *W = reinterpret_cast<S *>(wsd + D.fac_off) + (int64_t)k * np * np;
   int *ipiv = wsi + D.ipiv_ioff + (int64_t)k * np;
   int *perm = wsi + D.perm_ioff + (int64_t)k * np;
   const int nblk = np >> 4;
-  double *dL = wsd + D.dinv_off + (int64_t)(2 * k) * nblk * 256;
-  double *dU = dL + (int64_t)nblk * 256;
+  S *dL = reinterpret_cast<S *>(wsd + D.dinv_off) + (int64_t)(2 * k) * nblk * 256;
+  S *dU = dL + (int64_t)nblk * 256;
 
   const PlanRec P = plan[ii];
   const double c = T.c_re[k];
@@ -82,8 +89,8 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
     const double ci = T.c_im[k];
     const bool jterm = D.emb && ci != 0.0;
     const double csi = ldexp(ci, -P.s);
-    double *tile = panel;          // 32 x 33 staging tile
-    double *tilej = panel + 1056;  // J B staging tile
+    double *tile = reinterpret_cast<double *>(smem);   // 32 x 33 staging tile
+    double *tilej = tile + 1056;                        // J B staging tile
     for (int tr = 0; tr < np; tr += 32) {
       for (int tc = 0; tc < np; tc += 32) {
         const int rl = t >> 3, cl = (t & 7) * 4;
@@ -111,7 +118,7 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
               const double aj = tilej[(cl + u) * 33 + rl];
               cb += action ? ci * (aj / Nd) : csi * aj;
             }
-            W[r + (int64_t)cc * np] = (r == cc ? 1.0 : 0.0) - cb;
+            W[r + (int64_t)cc * np] = (S)((r == cc ? 1.0 : 0.0) - cb);
           }
         }
         __syncthreads();
@@ -121,7 +128,7 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
 
   // 2. Blocked right-looking factorisation.
   for (int j0 = 0; j0 < np; j0 += 16) {
-    double pr[H][16];
+    S pr[H][16];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       const int r = j0 + t + 256 * h;
@@ -133,25 +140,25 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
     for (int c2 = 0; c2 < 16; ++c2) {
       const int qrow = j0 + c2;
       const int par = c2 & 1;
-      double best = -1.0;
+      S best = -1;
       int bi = NOIDX;
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         const int r = j0 + t + 256 * h;
         if (r >= qrow && r < np) {
-          const double a = fabs(pr[h][c2]);
+          const S a = fabs(pr[h][c2]);
           if (a > best) { best = a; bi = r; }
         }
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
+        const S ob = __shfl_xor(best, off);
         const int oi = __shfl_xor(bi, off);
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
       // the lane holding this wave's candidate posts it (row values included)
       if (bi == NOIDX) {
-        if (lane == 0) { cand[par][wave][16] = -1.0; cand[par][wave][17] = (double)NOIDX; }
+        if (lane == 0) { cand[par][wave][16] = -1; cand[par][wave][17] = (S)-1; }
       } else {
 #pragma unroll
         for (int h = 0; h < H; ++h) {
@@ -159,7 +166,7 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
 #pragma unroll
             for (int cc = 0; cc < 16; ++cc) cand[par][wave][cc] = pr[h][cc];
             cand[par][wave][16] = best;
-            cand[par][wave][17] = (double)bi;
+            cand[par][wave][17] = (S)bi;
           }
         }
       }
@@ -169,17 +176,17 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
       }
       __syncthreads();
       best = cand[par][0][16];
-      bi = (int)cand[par][0][17];
+      bi = cand[par][0][17] < 0 ? NOIDX : (int)cand[par][0][17];
       int wsel = 0;
 #pragma unroll
       for (int w = 1; w < 4; ++w) {
-        const double ob = cand[par][w][16];
-        const int oi = (int)cand[par][w][17];
+        const S ob = cand[par][w][16];
+        const int oi = cand[par][w][17] < 0 ? NOIDX : (int)cand[par][w][17];
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; wsel = w; }
       }
       const bool none = (bi == NOIDX);
       const int p = none ? qrow : bi;
-      double pv[16];
+      S pv[16];
 #pragma unroll
       for (int cc = 0; cc < 16; ++cc) pv[cc] = none ? qbuf[par][cc] : cand[par][wsel][cc];
       if (p != qrow) {
@@ -197,14 +204,14 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
             }
         }
       }
-      const double d = pv[c2];
-      if (d != 0.0) {
-        const double rd = 1.0 / d;
+      const S d = pv[c2];
+      if (d != (S)0) {
+        const S rd = (S)1 / d;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
           const int r = j0 + t + 256 * h;
           if (r > qrow && r < np) {
-            const double l = pr[h][c2] * rd;
+            const S l = pr[h][c2] * rd;
             pr[h][c2] = l;
 #pragma unroll
             for (int cc = c2 + 1; cc < 16; ++cc) pr[h][cc] = fma(-l, pv[cc], pr[h][cc]);
@@ -240,19 +247,19 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
     for (int c2 = 0; c2 < 16; ++c2) sw |= (ipiv_s[c2] != j0 + c2);
     for (int col = t; col < np; col += 256) {
       if (col >= j0 && col < j0 + 16) continue;
-      double *Wc = W + (int64_t)col * np;
+      S *Wc = W + (int64_t)col * np;
       if (sw) {
         for (int c2 = 0; c2 < 16; ++c2) {
           const int p = ipiv_s[c2];
           if (p != j0 + c2) {
-            const double a = Wc[j0 + c2];
+            const S a = Wc[j0 + c2];
             Wc[j0 + c2] = Wc[p];
             Wc[p] = a;
           }
         }
       }
       if (col >= j0 + 16) {
-        double u[16];
+        S u[16];
 #pragma unroll
         for (int cc = 0; cc < 16; ++cc) u[cc] = Wc[j0 + cc];
 #pragma unroll
@@ -273,7 +280,7 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
     const int nt = (np - j0 - 16) >> 4;
     const int ntt = nt * nt;
     for (int base = wave; base < ntt; base += 4 * TB) {
-      v4d acc[TB];
+      v4 acc[TB];
       int tr[TB], tc[TB];
 #pragma unroll
       for (int u = 0; u < TB; ++u) {
@@ -281,7 +288,7 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
         tr[u] = tile % nt;
         tc[u] = tile / nt;
         if (tile < ntt)
-          acc[u] = *reinterpret_cast<const v4d *>(W + (int64_t)(j0 + 16 + 16 * tc[u] + i16) * np + j0 +
+          acc[u] = *reinterpret_cast<const v4 *>(W + (int64_t)(j0 + 16 + 16 * tc[u] + i16) * np + j0 +
                                                   16 + 16 * tr[u] + 4 * g);
       }
 #pragma unroll
@@ -289,8 +296,8 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
 #pragma unroll
         for (int u = 0; u < TB; ++u) {
           if (base + 4 * u < ntt) {
-            const double a = panel[(16 + 16 * tr[u] + ar) + (4 * q + g) * LDP];
-            const double b = u12[(4 * q + g) * LDU + 16 * tc[u] + i16];
+            const S a = panel[(16 + 16 * tr[u] + ar) + (4 * q + g) * LDP];
+            const S b = u12[(4 * q + g) * LDU + 16 * tc[u] + i16];
             acc[u] = mfma16(-a, b, acc[u]);
           }
         }
@@ -298,7 +305,7 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
 #pragma unroll
       for (int u = 0; u < TB; ++u)
         if (base + 4 * u < ntt)
-          *reinterpret_cast<v4d *>(W + (int64_t)(j0 + 16 + 16 * tc[u] + i16) * np + j0 + 16 +
+          *reinterpret_cast<v4 *>(W + (int64_t)(j0 + 16 + 16 * tc[u] + i16) * np + j0 + 16 +
                                    16 * tr[u] + 4 * g) = acc[u];
     }
     __syncthreads();
@@ -318,10 +325,10 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
   }
   for (int idx = t; idx < nblk * 16; idx += 256) {
     const int b = idx >> 4, j = idx & 15;
-    const double *Wb = W + (int64_t)(16 * b) * np + 16 * b;
-    double x[16];
+    const S *Wb = W + (int64_t)(16 * b) * np + 16 * b;
+    S x[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = (r == j) ? 1.0 : 0.0;
+    for (int r = 0; r < 16; ++r) x[r] = (r == j) ? (S)1 : (S)0;
 #pragma unroll
     for (int a = 0; a < 16; ++a)
 #pragma unroll
@@ -329,7 +336,7 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
 #pragma unroll
     for (int r = 0; r < 16; ++r) dL[b * 256 + r + 16 * j] = x[r];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = (r == j) ? 1.0 : 0.0;
+    for (int r = 0; r < 16; ++r) x[r] = (r == j) ? (S)1 : (S)0;
 #pragma unroll
     for (int a = 15; a >= 0; --a) {
       x[a] = x[a] / Wb[a + (int64_t)a * np];
@@ -346,22 +353,22 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
     constexpr int TB = 4;
     const int nb2 = nblk * nblk;
     for (int base = wave; base < nb2; base += 4 * TB) {
-      v4d acc[TB];
+      v4 acc[TB];
       int bi[TB], bj[TB];
 #pragma unroll
       for (int u = 0; u < TB; ++u) {
         const int id = base + 4 * u;
         bi[u] = id % nblk;
         bj[u] = id / nblk;
-        acc[u] = zero4();
+        acc[u] = MT<S>::zero();
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
 #pragma unroll
         for (int u = 0; u < TB; ++u) {
           if (base + 4 * u < nb2 && bi[u] != bj[u]) {
-            const double a = W[(16 * bi[u] + ar) + (int64_t)(16 * bj[u] + 4 * q + g) * np];
-            const double *inv = (bi[u] > bj[u] ? dL : dU) + bj[u] * 256;
+            const S a = W[(16 * bi[u] + ar) + (int64_t)(16 * bj[u] + 4 * q + g) * np];
+            const S *inv = (bi[u] > bj[u] ? dL : dU) + bj[u] * 256;
             acc[u] = mfma16(a, inv[(4 * q + g) + 16 * i16], acc[u]);
           }
         }
@@ -369,7 +376,7 @@ lu_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
 #pragma unroll
       for (int u = 0; u < TB; ++u)
         if (base + 4 * u < nb2 && bi[u] != bj[u])
-          *reinterpret_cast<v4d *>(W + (int64_t)(16 * bj[u] + i16) * np + 16 * bi[u] + 4 * g) = acc[u];
+          *reinterpret_cast<v4 *>(W + (int64_t)(16 * bj[u] + i16) * np + 16 * bi[u] + 4 * g) = acc[u];
     }
   }
 }

@@ -187,4 +187,15 @@ __global__ void selftest_mfma_kernel(double *out) {
   for (int v = 0; v < 4; ++v) out[l * 4 + v] = acc[v];
 }
 
+// The same check for v_mfma_f32_16x16x4_f32.
+__global__ void selftest_mfma32_kernel(double *out) {
+  const int l = threadIdx.x, i16 = l & 15, g = l >> 4;
+  const float a = 4.0f * i16 + g + 1.0f;
+  const float b = 100.0f * (g + 1) + i16;
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+  acc = mfma16(a, b, acc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) out[l * 4 + v] = acc[v];
+}
+
 }  // namespace pfm

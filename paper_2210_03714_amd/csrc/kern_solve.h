@@ -31,15 +31,16 @@ namespace pfm {
 
 // Z[rb] <- inv(D_b) Z[rb] for the row blocks this wave owns (D = L or U
 // diagonal blocks, stored inverted, column-major 16 x 16).
-template <int RB, int CT, int SW>
-__device__ __forceinline__ void diag_pass(v4d (&Z)[RB][CT], const double *__restrict__ dinv,
-                                          double *__restrict__ st, int wave, int nblk, int ar,
+template <int RB, int CT, int SW, class S>
+__device__ __forceinline__ void diag_pass(typename MT<S>::v4 (&Z)[RB][CT], const S *__restrict__ dinv,
+                                          S *__restrict__ st, int wave, int nblk, int ar,
                                           int g, int i16) {
+  typedef typename MT<S>::v4 v4;
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     const int b = wave + 4 * rb;
     if (b >= nblk) continue;
-    double a[4];
+    S a[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[q] = dinv[b * 256 + ar + 16 * (4 * q + g)];
 #pragma unroll
@@ -47,9 +48,9 @@ __device__ __forceinline__ void diag_pass(v4d (&Z)[RB][CT], const double *__rest
 #pragma unroll
       for (int v = 0; v < 4; ++v) st[(4 * g + v) * SW + 16 * ct + i16] = Z[rb][ct][v];
     wave_lds_sync();
-    v4d acc[CT];
+    v4 acc[CT];
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) acc[ct] = zero4();
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = MT<S>::zero();
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -64,17 +65,17 @@ __device__ __forceinline__ void diag_pass(v4d (&Z)[RB][CT], const double *__rest
 // Z <- M^{-1} Z for one shift, Z = P^T (right-hand side) on entry: forward
 // recurrence with L', diagonal pass, backward recurrence with U', diagonal pass.
 // All waves of the workgroup must call it together.
-template <int RB, int CT, int SW>
-__device__ __forceinline__ void lu_solve_slab(v4d (&Z)[RB][CT], const double *__restrict__ W,
-                                              const double *__restrict__ dL,
-                                              const double *__restrict__ dU, double (*S)[16 * SW],
-                                              double *__restrict__ st, int np, int nblk, int wave,
+template <int RB, int CT, int SW, class T_>
+__device__ __forceinline__ void lu_solve_slab(typename MT<T_>::v4 (&Z)[RB][CT], const T_ *__restrict__ W,
+                                              const T_ *__restrict__ dL,
+                                              const T_ *__restrict__ dU, T_ (*S)[16 * SW],
+                                              T_ *__restrict__ st, int np, int nblk, int wave,
                                               int ar, int g, int i16) {
     // forward recurrence with L'
 #pragma unroll 1
   for (int b = 0; b < nblk; ++b) {
-    double *Sb = S[b & 1];
-    double a[RB][4];
+    T_ *Sb = S[b & 1];
+    T_ a[RB][4];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const int bb = wave + 4 * rb;
@@ -107,13 +108,13 @@ __device__ __forceinline__ void lu_solve_slab(v4d (&Z)[RB][CT], const double *__
       }
     }
   }
-  diag_pass<RB, CT, SW>(Z, dL, st, wave, nblk, ar, g, i16);
+  diag_pass<RB, CT, SW, T_>(Z, dL, st, wave, nblk, ar, g, i16);
 
   // backward recurrence with U'
 #pragma unroll 1
   for (int b = nblk - 1; b >= 0; --b) {
-    double *Sb = S[b & 1];
-    double a[RB][4];
+    T_ *Sb = S[b & 1];
+    T_ a[RB][4];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const int bb = wave + 4 * rb;
@@ -146,7 +147,7 @@ __device__ __forceinline__ void lu_solve_slab(v4d (&Z)[RB][CT], const double *__
       }
     }
   }
-  diag_pass<RB, CT, SW>(Z, dU, st, wave, nblk, ar, g, i16);
+  diag_pass<RB, CT, SW, T_>(Z, dU, st, wave, nblk, ar, g, i16);
 
 }
 
@@ -228,7 +229,7 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
       }
     }
 
-    lu_solve_slab<RB, CT, SW>(Z, W, dL, dU, S, Tst[wave], np, nblk, wave, ar, g, i16);
+    lu_solve_slab<RB, CT, SW, double>(Z, W, dL, dU, S, Tst[wave], np, nblk, wave, ar, g, i16);
 
     // combination in the round-off form (§4.3); folded terms already carry
     // their weight, a conjugate pair on real A adds twice the real (top) half

@@ -23,6 +23,7 @@
 #include "kern_solve.h"
 #include "kern_square.h"
 #include "kern_action.h"
+#include "kern_mixed.h"
 
 using namespace pfm;
 
@@ -267,9 +268,10 @@ int pfm_selftest_mfma(int device, double *out) {
   if (!out) return PFM_ERR_INVALID;
   if (hipSetDevice(device) != hipSuccess) return PFM_ERR_HIP;
   double *d = nullptr;
-  if (hipMalloc(&d, 256 * sizeof(double)) != hipSuccess) return PFM_ERR_HIP;
+  if (hipMalloc(&d, 512 * sizeof(double)) != hipSuccess) return PFM_ERR_HIP;
   hipLaunchKernelGGL(selftest_mfma_kernel, dim3(1), dim3(64), 0, 0, d);
-  hipError_t e = hipMemcpy(out, d, 256 * sizeof(double), hipMemcpyDeviceToHost);
+  hipLaunchKernelGGL(selftest_mfma32_kernel, dim3(1), dim3(64), 0, 0, d + 256);
+  hipError_t e = hipMemcpy(out, d, 512 * sizeof(double), hipMemcpyDeviceToHost);
   (void)hipFree(d);
   return e == hipSuccess ? PFM_OK : PFM_ERR_HIP;
 }
@@ -298,10 +300,12 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   }
   const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
   if (!ee || !ep) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
-  if (prec != PFM_FP64)
-    return set_err(ctx, PFM_ERR_UNSUPPORTED, "requested precision path is not built");
   const bool cplx = dtype == PFM_C128;
   const bool pairs = ee->pair != 0;
+  const bool mixed = prec == PFM_MIXED;
+  if (mixed && (cplx || pairs || action))
+    return set_err(ctx, PFM_ERR_UNSUPPORTED,
+                   "the mixed path is built for real full-matrix problems with real shift sets");
   const bool emb = cplx || pairs;  // complex arithmetic runs on the real embedding
   for (int i = 0; i < batch; ++i) {
     const int nk = emb ? 2 * probs[i].n : probs[i].n;
@@ -377,8 +381,10 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     D.fac_off = dofs;  dofs += align_up(nterms * nn, 64);
     D.dinv_off = dofs; dofs += align_up(nterms * 2 * (np / 16) * 256, 64);
     D.r_off = dofs;    dofs += align_up(4 * nn, 64);
+    if (emb || mixed) {
+      D.e_off = dofs;  dofs += align_up((int64_t)std::max(D.n, D.npad) * D.npad, 64);
+    }
     if (emb) {
-      D.e_off = dofs;  dofs += align_up((int64_t)D.n * D.n, 64);
       D.lda = D.n;     // A is set once the workspace base is known
     } else {
       D.A = (const double *)P.A;
@@ -483,9 +489,19 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     const int *dl = d_list + list_off[c];
     const dim3 glu(xcd_grid(nl, nterms));
     const int am = action ? 1 : 0;
-    if (c == 0) hipLaunchKernelGGL(lu_f64_kernel<128>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, am);
-    if (c == 1) hipLaunchKernelGGL(lu_f64_kernel<256>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, am);
-    if (c == 2) hipLaunchKernelGGL(lu_f64_kernel<512>, glu, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, wsi, am);
+#define PFM_LU(NPM)                                                                            \
+  do {                                                                                         \
+    if (mixed)                                                                                 \
+      hipLaunchKernelGGL((lu_kernel<NPM, float>), glu, dim3(256), 0, stream, d_desc, dl, nl,  \
+                         d_plan, T, wsd, wsi, am);                                             \
+    else                                                                                       \
+      hipLaunchKernelGGL((lu_kernel<NPM, double>), glu, dim3(256), 0, stream, d_desc, dl, nl, \
+                         d_plan, T, wsd, wsi, am);                                             \
+  } while (0)
+    if (c == 0) PFM_LU(128);
+    if (c == 1) PFM_LU(256);
+    if (c == 2) PFM_LU(512);
+#undef PFM_LU
     ctx->cur_launches[0]++;
   }
   prof_mark(ctx, 1, stream);
@@ -497,7 +513,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
       maxp = std::max(maxp, probs[i].p);
     }
     const int tnb = (maxn + 31) / 32;
-    hipLaunchKernelGGL(prep_bt_kernel, dim3(tnb * tnb, batch), dim3(256), 0, stream, d_desc, d_plan, wsd);
+    hipLaunchKernelGGL(prep_bt_kernel, dim3(tnb * tnb, batch), dim3(256), 0, stream, d_desc, d_plan, wsd, 1);
     for (int c = 0; c < 3; ++c) {
       const int nl = (int)cls_list[c].size();
       if (!nl) continue;
@@ -532,7 +548,37 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     return PFM_OK;
   }
   // 3. solves fused with the combination
-  for (int c = 0; c < 3; ++c) {
+  if (mixed) {
+    int maxn = 0;
+    for (int i = 0; i < batch; ++i) maxn = std::max(maxn, desc[i].npad);
+    const int tnb = (maxn + 31) / 32;
+    hipLaunchKernelGGL(prep_bt_kernel, dim3(tnb * tnb, batch), dim3(256), 0, stream, d_desc, d_plan, wsd, 0);
+    double sw = 0.0, swp = 0.0;
+    for (int k = 0; k < nterms; ++k) { sw += std::fabs(T.we_re[k]); swp += std::fabs(T.wp_re[k]); }
+    const double irtol = tol / (4.0 * std::max(sw, T.want_phi ? swp : 0.0));
+    const int maxit = 3;
+    for (int c = 0; c < 3; ++c) {
+      const int nl = (int)cls_list[c].size();
+      if (!nl) continue;
+      const int *dl = d_list + list_off[c];
+#define PFM_MIX(NPM, SWW)                                                                         \
+  do {                                                                                            \
+    const dim3 gs(xcd_grid(nl, NPM / SWW));                                                       \
+    if (T.want_phi)                                                                               \
+      hipLaunchKernelGGL((solve_mixed_kernel<NPM, SWW, true>), gs, dim3(256), 0, stream, d_desc, \
+                         dl, nl, d_plan, T, wsd, wsi, maxit, irtol);                              \
+    else                                                                                          \
+      hipLaunchKernelGGL((solve_mixed_kernel<NPM, SWW, false>), gs, dim3(256), 0, stream, d_desc,\
+                         dl, nl, d_plan, T, wsd, wsi, maxit, irtol);                              \
+  } while (0)
+      if (c == 0) PFM_MIX(128, 16);
+      if (c == 1) PFM_MIX(256, 16);
+      if (c == 2) PFM_MIX(512, 16);
+#undef PFM_MIX
+      ctx->cur_launches[1]++;
+    }
+  }
+  for (int c = 0; c < 3 && !mixed; ++c) {
     const int nl = (int)cls_list[c].size();
     if (!nl) continue;
     const int *dl = d_list + list_off[c];

@@ -105,11 +105,13 @@ def theta(f, m, tol):
 
 
 def selftest_mfma(device=0):
-    out = (ctypes.c_double * 256)()
+    """(f64 accumulators, f32 accumulators), each 64 lanes x 4."""
+    out = (ctypes.c_double * 512)()
     rc = lib().pfm_selftest_mfma(device, ctypes.cast(out, ctypes.POINTER(ctypes.c_double)))
     if rc:
         raise RuntimeError("pfm_selftest_mfma -> %d" % rc)
-    return np.array(out[:]).reshape(64, 4)
+    a = np.array(out[:])
+    return a[:256].reshape(64, 4), a[256:].reshape(64, 4)
 
 
 class PfmError(RuntimeError):

@@ -58,7 +58,7 @@ def _check_instances(mats, res, info, funcs, m, tol, bar=TOL, idx=None):
 
 def test_mfma_fragment_layout(torch_dev):
     from paper_2210_03714_amd import pfm
-    out = pfm.selftest_mfma(0)
+    out, out32 = pfm.selftest_mfma(0)
     A = np.array([[4.0 * i + k + 1 for k in range(4)] for i in range(16)])
     B = np.array([[100.0 * (k + 1) + j for j in range(16)] for k in range(4)])
     C = A @ B
@@ -67,6 +67,11 @@ def test_mfma_fragment_layout(torch_dev):
         i16, g = l & 15, l >> 4
         for v in range(4):
             assert out[l, v] == C[g + 4 * v, i16], (l, v)
+    # binary32 MFMA: lane 16 g + i holds D[4 g + v][i] (all values exact in f32)
+    for l in range(64):
+        i16, g = l & 15, l >> 4
+        for v in range(4):
+            assert out32[l, v] == C[4 * g + v, i16], ("f32", l, v)
 
 
 @pytest.mark.parametrize("m", [4, 5, 8])
