@@ -1,0 +1,270 @@
+// Shifted inverses X_k = (I - c_k B)^{-1} by block Gauss-Jordan, for
+// instances where partial pivoting provably performs no interchange.
+//
+// With |c_k| ||B||_1 < 1, M_k = I - c_k B is strictly column diagonally
+// dominant (|1 - c_k b_jj| >= 1 - |c_k| |b_jj| > |c_k| sum_{i != j} |b_ij|), and
+// elimination keeps it so: every multiplier has |l_ij| < 1 and the partial
+// pivoting choice (largest |.| in the column, first index on ties) is always
+// the diagonal.  The host sends an instance here only if |c_k| ||B||_1 <= 1/2
+// for every shift (the planner's ||B||_1 <= θ gives |c_k| ||B||_1 < 0.06 on
+// the paper's sets); anything else takes the pivoting LU path.  The inverse
+// then serves §2's "inverse" form of each processor, (I - c_k B)^{-1}, and the
+// round-off combination of §4.3 becomes
+//   R = a0 I + (sum_k w_k X_k) B,
+// one product per instance instead of one solve per shift.
+//
+// Algorithm (in place, column-major, npad a multiple of 64, blocks of 64):
+//   for each block J:  D = W[J,J];  Dinv = D^{-1} (Gauss-Jordan in LDS)
+//     W[J,c] <- Dinv W[J,c]            (c != J)   MFMA, Dinv from LDS
+//     W[I,c] <- W[I,c] - W[I,J] W[J,c] (I,c != J) MFMA rank-64 update
+//     W[I,J] <- -W[I,J] Dinv           (I != J)
+//     W[J,J] <- Dinv
+// Each wave keeps its 16-row strips of W[I,J] in registers (MFMA A operand)
+// for the whole step; each 64-column chunk of the transformed row block is
+// staged once in LDS and is the B operand of the update, so the inner loops
+// read only registers and LDS.
+#pragma once
+#include "kern_common.h"
+
+namespace pfm {
+
+constexpr int kGJ = 64;
+
+// Loads M = I - c B (B = A 2^-s, or A / N) column-major into W: the same
+// transposed load as the LU kernel, for a real non-embedded instance.
+__device__ __forceinline__ void load_shifted(const InstDesc &D, double c, int s_or_n, int action,
+                                             double *__restrict__ W, double *tile) {
+  const int n = D.n, np = D.npad, t = threadIdx.x;
+  const double cs = ldexp(c, -s_or_n);
+  const double Nd = (double)s_or_n;
+  for (int tr = 0; tr < np; tr += 32) {
+    for (int tc = 0; tc < np; tc += 32) {
+      const int rl = t >> 3, cl = (t & 7) * 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = tr + rl, cc = tc + cl + u;
+        tile[rl * 33 + cl + u] = (r < n && cc < n) ? D.A[(int64_t)r * D.lda + cc] : 0.0;
+      }
+      __syncthreads();
+      const int cc = tc + rl;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = tr + cl + u;
+        if (r < np && cc < np) {
+          const double a = tile[(cl + u) * 33 + rl];
+          const double cb = action ? c * (a / Nd) : cs * a;
+          W[r + (int64_t)cc * np] = (r == cc ? 1.0 : 0.0) - cb;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int NPMAX>
+__global__ void __launch_bounds__(256, 2)
+gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nlist,
+              const PlanRec *__restrict__ plan, Terms T, double *__restrict__ wsd, int action) {
+  constexpr int LDD = kGJ + 1;
+  __shared__ double Dl[kGJ * LDD];      // D, then D^{-1} (row-major, padded)
+  __shared__ double Cl[kGJ * LDD];      // staging for the row-block product
+
+  int slot, k;
+  xcd_map(blockIdx.x, T.nterms, slot, k);
+  if (slot >= nlist) return;
+  const int ii = ilist[slot];
+  const InstDesc D = inst[ii];
+  const int np = D.npad;
+  if (np > NPMAX || (np % kGJ) || D.n > np || D.n < 1 || D.emb) return;  // never sent
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int i16 = lane & 15, g = lane >> 4;
+  const int ar = arow(i16);
+  double *W = wsd + D.fac_off + (int64_t)k * np * np;
+  const int nJ = np / kGJ;
+
+  load_shifted(D, T.c_re[k], plan[ii].s, action, W, Cl);
+
+  // this thread's 4 x 4 patch of a 64 x 64 block
+  const int pr0 = (t >> 4) * 4, pc0 = (t & 15) * 4;
+
+#pragma unroll 1
+  for (int J = 0; J < nJ; ++J) {
+    const int j0 = J * kGJ;
+    // 1. Dinv in LDS by Gauss-Jordan without interchanges
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        Dl[(pr0 + a) * LDD + pc0 + b] = W[(j0 + pr0 + a) + (int64_t)(j0 + pc0 + b) * np];
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < kGJ; ++c) {
+      const double p = 1.0 / Dl[c * LDD + c];
+      double colc[4], rowc[4], cur[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) colc[a] = Dl[(pr0 + a) * LDD + c];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) rowc[b] = Dl[c * LDD + pc0 + b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cur[a][b] = Dl[(pr0 + a) * LDD + pc0 + b];
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int i = pr0 + a;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int j = pc0 + b;
+          double v;
+          if (i == c && j == c) v = p;
+          else if (i == c) v = rowc[b] * p;
+          else if (j == c) v = -colc[a] * p;
+          else v = fma(-colc[a] * p, rowc[b], cur[a][b]);
+          Dl[i * LDD + j] = v;
+        }
+      }
+      __syncthreads();
+    }
+
+    // The rows of W[I, J] (I outside block J): 16-row strips, strip w + 4 m
+    // to wave w, held as MFMA A fragments through steps 3 and 4, MSG strips
+    // per wave at a time (NG groups).  The first group transforms the row
+    // block (step 2) chunk by chunk; later groups read it back.
+    constexpr int MSW = NPMAX / 64 - 1 > 0 ? NPMAX / 64 - 1 : 1;  // strips per wave, at most
+    constexpr int MSG = MSW < 3 ? MSW : 3;
+    constexpr int NG = (MSW + MSG - 1) / MSG;
+    const int nstrip = (np - kGJ) / 16;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+#pragma unroll 1
+    for (int grp = 0; grp < NG; ++grp) {
+      double aI[MSG][kGJ / 4];
+      int srow[MSG];
+#pragma unroll
+      for (int m = 0; m < MSG; ++m) {
+        const int sidx = wave + 4 * (grp * MSG + m);
+        srow[m] = -1;
+        if (sidx < nstrip) {
+          const int r0 = sidx * 16 + (sidx * 16 >= j0 ? kGJ : 0);
+          srow[m] = r0;
+#pragma unroll
+          for (int q = 0; q < kGJ / 4; ++q) aI[m][q] = W[(r0 + ar) + (int64_t)(j0 + 4 * q + g) * np];
+        }
+      }
+
+      // 2+3. per 64-column chunk C != J: new = Dinv W[J, C] (to LDS and W),
+      //      then W[I, C] -= W[I, J] new for this wave's strips
+#pragma unroll 1
+      for (int C = 0; C < nJ; ++C) {
+        if (C == J) continue;
+        const int c0 = C * kGJ;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            Cl[(pr0 + a) * LDD + pc0 + b] = W[(j0 + pr0 + a) + (int64_t)(c0 + pc0 + b) * np];
+        __syncthreads();
+        if (grp == 0) {
+          v4d acc[2][2];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = zero4();
+#pragma unroll 4
+          for (int q = 0; q < kGJ / 4; ++q) {
+            const int kk = 4 * q + g;
+            double av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = Dl[(wr + 16 * a + ar) * LDD + kk];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Cl[kk * LDD + wc + 16 * b + i16];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+              for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+          }
+          __syncthreads();  // every wave has read the old chunk
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              const int rr = wr + 16 * a + 4 * g, cc = wc + 16 * b + i16;
+              *reinterpret_cast<v4d *>(W + (j0 + rr) + (int64_t)(c0 + cc) * np) = acc[a][b];
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Cl[(rr + v) * LDD + cc] = acc[a][b][v];
+            }
+          __syncthreads();  // the new chunk is in LDS
+        }
+#pragma unroll
+        for (int m = 0; m < MSG; ++m) {
+          if (srow[m] < 0) continue;
+          const int r0 = srow[m];
+          v4d cacc[4];
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            cacc[b] = *reinterpret_cast<const v4d *>(W + (r0 + 4 * g) + (int64_t)(c0 + 16 * b + i16) * np);
+#pragma unroll
+          for (int q = 0; q < kGJ / 4; ++q)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              cacc[b] = mfma16(-aI[m][q], Cl[(4 * q + g) * LDD + 16 * b + i16], cacc[b]);
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            *reinterpret_cast<v4d *>(W + (r0 + 4 * g) + (int64_t)(c0 + 16 * b + i16) * np) = cacc[b];
+        }
+        __syncthreads();  // before the next chunk overwrites Cl
+      }
+
+      // 4. W[I, J] <- -W[I, J] Dinv from the register-held rows
+#pragma unroll
+      for (int m = 0; m < MSG; ++m) {
+        if (srow[m] < 0) continue;
+        const int r0 = srow[m];
+        v4d acc[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = zero4();
+#pragma unroll
+        for (int q = 0; q < kGJ / 4; ++q)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[b] = mfma16(-aI[m][q], Dl[(4 * q + g) * LDD + 16 * b + i16], acc[b]);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          *reinterpret_cast<v4d *>(W + (r0 + 4 * g) + (int64_t)(j0 + 16 * b + i16) * np) = acc[b];
+      }
+    }
+    // 5. W[J, J] <- Dinv
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        W[(j0 + pr0 + a) + (int64_t)(j0 + pc0 + b) * np] = Dl[(pr0 + a) * LDD + pc0 + b];
+    __syncthreads();
+  }
+}
+
+// S_e = sum_k we_k X_k, S_p = sum_k wp_k X_k (binary64, fixed order k = 0..),
+// into the level-1 squaring buffers (free at this point).  Grid: x = chunk of
+// 4 * 256 elements, y = instance.
+__global__ void __launch_bounds__(256)
+combine_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, Terms T,
+                   double *__restrict__ wsd) {
+  const InstDesc D = inst[ilist[blockIdx.y]];
+  const int64_t nn = (int64_t)D.npad * D.npad;
+  const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (e0 >= nn) return;
+  const double *X = wsd + D.fac_off;
+  v4d se = zero4(), sp = zero4();
+  for (int k = 0; k < T.nterms; ++k) {
+    const v4d x = *reinterpret_cast<const v4d *>(X + (int64_t)k * nn + e0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      se[v] = fma(T.we_re[k], x[v], se[v]);
+      sp[v] = fma(T.wp_re[k], x[v], sp[v]);
+    }
+  }
+  double *base = wsd + D.r_off;
+  *reinterpret_cast<v4d *>(base + nn + e0) = se;                    // R buffer 1
+  if (T.want_phi) *reinterpret_cast<v4d *>(base + 3 * nn + e0) = sp;  // Phi buffer 1
+}
+
+}  // namespace pfm

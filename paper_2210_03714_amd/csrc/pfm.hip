@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,7 @@
 #include "kern_square.h"
 #include "kern_action.h"
 #include "kern_mixed.h"
+#include "kern_gj.h"
 
 using namespace pfm;
 
@@ -46,6 +48,9 @@ struct pfm_ctx {
   // device buffer for per-level squaring task lists
   void *tasks = nullptr;
   size_t tasks_bytes = 0;
+  // Gauss-Jordan route for diagonally dominant shifted matrices (PFM_GJ=0
+  // disables it, for comparisons)
+  int gj = 1;
   // optional phase timing (hipEvents on the caller's stream)
   bool prof = false;
   bool prof_pending = false;
@@ -188,6 +193,7 @@ int pfm_create(pfm_ctx **out, int device, size_t budget) {
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) { delete ctx; return PFM_ERR_HIP; }
   ctx->num_cu = prop.multiProcessorCount;
+  if (const char *ev = getenv("PFM_GJ")) ctx->gj = atoi(ev) != 0;
   e = hipMalloc(&ctx->d_err, 64);
   if (e != hipSuccess) { delete ctx; return PFM_ERR_HIP; }
   e = hipMemset(ctx->d_err, 0, 64);
@@ -354,6 +360,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   }
   const int nterms = T.nterms;
 
+  const bool gj_call = ctx->gj && !action && !emb && !mixed;
   // workspace layout
   std::vector<InstDesc> desc(batch);
   std::vector<int> cls_list[3];
@@ -374,7 +381,9 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     D.hn = P.n;
     D.n = emb ? 2 * P.n : P.n;
     D.ncol = P.n;
-    D.npad = (D.n + 15) / 16 * 16;
+    // real FP64 full-matrix instances may take the Gauss-Jordan path, whose
+    // blocks are 64 wide
+    D.npad = gj_call ? (D.n + 63) / 64 * 64 : (D.n + 15) / 16 * 16;
     D.p = P.p;
     D.cls = D.npad <= 128 ? 0 : (D.npad <= 256 ? 1 : 2);
     const int64_t np = D.npad, nn = np * np;
@@ -396,7 +405,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   }
   const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
   const int64_t desc_bytes = align_up((int64_t)batch * sizeof(InstDesc), 256);
-  const int64_t list_bytes = align_up((int64_t)batch * sizeof(int), 256);
+  const int64_t list_bytes = align_up((int64_t)2 * batch * sizeof(int), 256);
   const int64_t need = dofs * 8 + iofs * 4 + plan_bytes + desc_bytes + list_bytes + 4096;
   if (ctx->budget && (size_t)need > ctx->budget)
     return set_err(ctx, PFM_ERR_BUDGET, "workspace %lld bytes exceeds budget %zu", (long long)need,
@@ -424,25 +433,14 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   for (int i = 0; i < batch; ++i)
     if (desc[i].emb) desc[i].A = wsd + desc[i].e_off;
 
-  // descriptors and class lists (stored back to back) through pinned staging
+  // descriptors through pinned staging
   char *pin = nullptr;
-  const size_t stage_bytes = desc_bytes + list_bytes + plan_bytes;
-  int rcs = staging(ctx, stage_bytes, &pin);
+  int rcs = staging(ctx, desc_bytes + plan_bytes, &pin);
   if (rcs) return rcs;
   InstDesc *h_desc = (InstDesc *)pin;
-  int *h_list = (int *)(pin + desc_bytes);
-  PlanRec *h_plan = (PlanRec *)(pin + desc_bytes + list_bytes);
+  PlanRec *h_plan = (PlanRec *)(pin + desc_bytes);
   memcpy(h_desc, desc.data(), batch * sizeof(InstDesc));
-  int list_off[3];
-  {
-    int pos = 0;
-    for (int c = 0; c < 3; ++c) {
-      list_off[c] = pos;
-      for (int i : cls_list[c]) h_list[pos++] = i;
-    }
-  }
   HIP_TRY(ctx, hipMemcpyAsync(d_desc, h_desc, batch * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
-  HIP_TRY(ctx, hipMemcpyAsync(d_list, h_list, batch * sizeof(int), hipMemcpyHostToDevice, stream));
 
   if (emb) {
     int maxk = 0;
@@ -451,7 +449,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     hipLaunchKernelGGL(embed_kernel, dim3(te * te, batch), dim3(256), 0, stream, d_desc, wsd);
   }
   // 1. norm and plan on the device; the host reads the plans back once (it
-  //    needs max s to size the squaring launches)
+  //    needs max s to size the squaring launches and routes each instance)
   hipLaunchKernelGGL(plan_kernel, dim3(batch), dim3(256), 0, stream, d_desc, d_plan, theta,
                      action ? 1 : 0, force_plan);
   HIP_TRY(ctx, hipGetLastError());
@@ -479,14 +477,96 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
                        h_plan[i].s, kSCap);
       }
 
+  // Routing: with |c_k| ||B||_1 <= 1/2 every M_k is strictly column diagonally
+  // dominant, partial pivoting would never interchange rows, and the inverse
+  // is formed by Gauss-Jordan; everything else takes the pivoting LU path.
+  double cmax = 0.0;
+  for (int k = 0; k < nterms; ++k) cmax = std::max(cmax, std::hypot(T.c_re[k], T.c_im[k]));
+  std::vector<int> fast_list[3], slow_list[3];
+  std::vector<char> is_fast(batch, 0);
+  for (int c = 0; c < 3; ++c)
+    for (int i : cls_list[c]) {
+      const bool fast = gj_call && (desc[i].npad % kGJ) == 0 && !(h_plan[i].status & 2) &&
+                        cmax * std::ldexp(h_plan[i].eta, -svec[i]) <= 0.5;
+      (fast ? fast_list : slow_list)[c].push_back(i);
+      is_fast[i] = fast;
+    }
+  int fast_off[3], slow_off[3];
+  std::vector<int> lists;
+  for (int c = 0; c < 3; ++c) {
+    fast_off[c] = (int)lists.size();
+    lists.insert(lists.end(), fast_list[c].begin(), fast_list[c].end());
+  }
+  for (int c = 0; c < 3; ++c) {
+    slow_off[c] = (int)lists.size();
+    lists.insert(lists.end(), slow_list[c].begin(), slow_list[c].end());
+  }
+  bool any_fast = false;
+  for (int i = 0; i < batch; ++i) any_fast |= is_fast[i] != 0;
+
+  // GEMM task lists: level 0 = R = a0 I + S B for the Gauss-Jordan instances,
+  // levels 1..smax = squarings.  All tiles of one instance go to one XCD.
+  std::vector<SqTask> all;
+  std::vector<std::pair<int64_t, int>> lv;  // (offset, count) per level
+  for (int j = 0; j <= smax; ++j) {
+    std::vector<std::vector<SqTask>> qx(8);
+    int x = 0;
+    for (int i = 0; i < batch; ++i) {
+      if (j == 0 ? !is_fast[i] : svec[i] < j) continue;
+      const int tlm = (desc[i].npad + kSqTile - 1) / kSqTile;
+      const int tln = (desc[i].ncol + kSqTile - 1) / kSqTile;
+      for (int w = 0; w < 1 + T.want_phi; ++w)
+        for (int tt = 0; tt < tlm * tln; ++tt) qx[x].push_back(SqTask{i, tt + (w << 20)});
+      x = (x + 1) & 7;
+    }
+    size_t mx = 0;
+    for (auto &q : qx) mx = std::max(mx, q.size());
+    const int64_t off = (int64_t)all.size();
+    for (size_t qq = 0; qq < mx; ++qq)
+      for (int xx = 0; xx < 8; ++xx) all.push_back(qq < qx[xx].size() ? qx[xx][qq] : SqTask{-1, 0});
+    lv.emplace_back(off, (int)(mx * 8));
+  }
+  const size_t tb = all.size() * sizeof(SqTask);
+  if (tb > ctx->tasks_bytes) {
+    if (ctx->tasks) HIP_TRY(ctx, hipFree(ctx->tasks));
+    ctx->tasks = nullptr;
+    ctx->tasks_bytes = 0;
+    HIP_TRY(ctx, hipMalloc(&ctx->tasks, std::max<size_t>(tb, 256)));
+    ctx->tasks_bytes = std::max<size_t>(tb, 256);
+  }
+  {
+    // the staging area is free again: the stream was synchronised above
+    const size_t lb = align_up((int64_t)lists.size() * sizeof(int), 256);
+    char *pin2 = nullptr;
+    rcs = staging(ctx, lb + tb + 256, &pin2);
+    if (rcs) return rcs;
+    memcpy(pin2, lists.data(), lists.size() * sizeof(int));
+    if (tb) memcpy(pin2 + lb, all.data(), tb);
+    HIP_TRY(ctx, hipMemcpyAsync(d_list, pin2, lists.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+    if (tb) HIP_TRY(ctx, hipMemcpyAsync(ctx->tasks, pin2 + lb, tb, hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
+    ctx->pin_pending = true;
+  }
+  const SqTask *dt = (const SqTask *)ctx->tasks;
+
   for (int p = 0; p < kNumPhases; ++p) ctx->cur_launches[p] = 0;
   prof_mark(ctx, 0, stream);
-  // 2. shifted LU factorisations, all (instance, shift) pairs of a size class
-  //    in one launch
+  // 2. shifted factorisations: Gauss-Jordan inverses (fast instances) and
+  //    pivoting LU (the rest), all (instance, shift) pairs of a class per launch
   for (int c = 0; c < 3; ++c) {
-    const int nl = (int)cls_list[c].size();
+    const int nl = (int)fast_list[c].size();
     if (!nl) continue;
-    const int *dl = d_list + list_off[c];
+    const int *dl = d_list + fast_off[c];
+    const dim3 gg(xcd_grid(nl, nterms));
+    if (c == 0) hipLaunchKernelGGL(gj_inv_kernel<128>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0);
+    if (c == 1) hipLaunchKernelGGL(gj_inv_kernel<256>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0);
+    if (c == 2) hipLaunchKernelGGL(gj_inv_kernel<512>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0);
+    ctx->cur_launches[0]++;
+  }
+  for (int c = 0; c < 3; ++c) {
+    const int nl = (int)slow_list[c].size();
+    if (!nl) continue;
+    const int *dl = d_list + slow_off[c];
     const dim3 glu(xcd_grid(nl, nterms));
     const int am = action ? 1 : 0;
 #define PFM_LU(NPM)                                                                            \
@@ -515,9 +595,9 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     const int tnb = (maxn + 31) / 32;
     hipLaunchKernelGGL(prep_bt_kernel, dim3(tnb * tnb, batch), dim3(256), 0, stream, d_desc, d_plan, wsd, 1);
     for (int c = 0; c < 3; ++c) {
-      const int nl = (int)cls_list[c].size();
+      const int nl = (int)slow_list[c].size();
       if (!nl) continue;
-      const int *dl = d_list + list_off[c];
+      const int *dl = d_list + slow_off[c];
 #define PFM_ACT(NPM, SWW)                                                                       \
   do {                                                                                          \
     const int ns = (maxp + SWW - 1) / SWW;                                                      \
@@ -539,8 +619,6 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     prof_mark(ctx, 3, stream);
     prof_mark(ctx, 4, stream);
     if (ctx->prof) ctx->prof_pending = true;
-    HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
-    ctx->pin_pending = true;
     if (info)
       hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_plan,
                          (InfoRec *)info, batch, ee->order, theta);
@@ -558,9 +636,9 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     const double irtol = tol / (4.0 * std::max(sw, T.want_phi ? swp : 0.0));
     const int maxit = 3;
     for (int c = 0; c < 3; ++c) {
-      const int nl = (int)cls_list[c].size();
+      const int nl = (int)slow_list[c].size();
       if (!nl) continue;
-      const int *dl = d_list + list_off[c];
+      const int *dl = d_list + slow_off[c];
 #define PFM_MIX(NPM, SWW)                                                                         \
   do {                                                                                            \
     const dim3 gs(xcd_grid(nl, NPM / SWW));                                                       \
@@ -578,10 +656,28 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
       ctx->cur_launches[1]++;
     }
   }
+  if (any_fast) {
+    // S = sum_k w_k X_k, then R = a0 I + S B (and Phi) for the Gauss-Jordan instances
+    int maxnp = 0;
+    for (int i = 0; i < batch; ++i)
+      if (is_fast[i]) maxnp = std::max(maxnp, desc[i].npad);
+    const int chunks = (int)(((int64_t)maxnp * maxnp / 4 + 255) / 256);
+    for (int c = 0; c < 3; ++c) {
+      const int nl = (int)fast_list[c].size();
+      if (!nl) continue;
+      hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nl), dim3(256), 0, stream, d_desc,
+                         d_list + fast_off[c], T, wsd);
+    }
+    const auto &e = lv[0];
+    if (e.second)
+      hipLaunchKernelGGL(square_level_f64_kernel<1>, dim3(e.second), dim3(256), 0, stream, d_desc,
+                         dt + e.first, e.second, 0, wsd, d_plan, T.a0e, T.a0p);
+    ctx->cur_launches[1] += 2;
+  }
   for (int c = 0; c < 3 && !mixed; ++c) {
-    const int nl = (int)cls_list[c].size();
+    const int nl = (int)slow_list[c].size();
     if (!nl) continue;
-    const int *dl = d_list + list_off[c];
+    const int *dl = d_list + slow_off[c];
 #define PFM_SOLVE(NPM, SWW)                                                                      \
   do {                                                                                           \
     const dim3 gs(xcd_grid(nl, NPM / SWW));                                                      \
@@ -599,54 +695,13 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     ctx->cur_launches[1]++;
   }
   prof_mark(ctx, 2, stream);
-  // 4. squaring levels: task lists built here, one launch per level
-  std::vector<SqTask> all;
-  std::vector<std::pair<int64_t, int>> lv;  // (offset, count)
+  // 4. squaring levels, one launch per level
   for (int j = 1; j <= smax; ++j) {
-    std::vector<std::vector<SqTask>> qx(8);
-    int x = 0;
-    for (int i = 0; i < batch; ++i) {
-      if (svec[i] < j) continue;
-      const int tlm = (desc[i].npad + kSqTile - 1) / kSqTile;
-      const int tln = (desc[i].ncol + kSqTile - 1) / kSqTile;
-      for (int w = 0; w < 1 + T.want_phi; ++w)
-        for (int tt = 0; tt < tlm * tln; ++tt) qx[x].push_back(SqTask{i, tt + (w << 20)});
-      x = (x + 1) & 7;
-    }
-    size_t mx = 0;
-    for (auto &q : qx) mx = std::max(mx, q.size());
-    const int64_t off = (int64_t)all.size();
-    for (size_t qq = 0; qq < mx; ++qq)
-      for (int xx = 0; xx < 8; ++xx) all.push_back(qq < qx[xx].size() ? qx[xx][qq] : SqTask{-1, 0});
-    lv.emplace_back(off, (int)(mx * 8));
-  }
-  if (!all.empty()) {
-    const size_t tb = all.size() * sizeof(SqTask);
-    if (tb > ctx->tasks_bytes) {
-      if (ctx->tasks) HIP_TRY(ctx, hipFree(ctx->tasks));
-      ctx->tasks = nullptr;
-      ctx->tasks_bytes = 0;
-      HIP_TRY(ctx, hipMalloc(&ctx->tasks, tb));
-      ctx->tasks_bytes = tb;
-    }
-    // the staging area is free again: the stream was synchronised above
-    char *pin2 = nullptr;
-    rcs = staging(ctx, tb, &pin2);
-    if (rcs) return rcs;
-    memcpy(pin2, all.data(), tb);
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->tasks, pin2, tb, hipMemcpyHostToDevice, stream));
-    HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
-    ctx->pin_pending = true;
-    const SqTask *dt = (const SqTask *)ctx->tasks;
-    for (int j = 1; j <= smax; ++j) {
-      const auto &e = lv[j - 1];
-      hipLaunchKernelGGL(square_level_f64_kernel, dim3(e.second), dim3(256), 0, stream, d_desc,
-                         dt + e.first, e.second, j, wsd);
-      ctx->cur_launches[2]++;
-    }
-  } else {
-    HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
-    ctx->pin_pending = true;
+    const auto &e = lv[j];
+    if (!e.second) continue;
+    hipLaunchKernelGGL(square_level_f64_kernel<0>, dim3(e.second), dim3(256), 0, stream, d_desc,
+                       dt + e.first, e.second, j, wsd, d_plan, 0.0, 0.0);
+    ctx->cur_launches[2]++;
   }
   prof_mark(ctx, 3, stream);
   // 5. results to the caller's row-major buffers, then the info records
