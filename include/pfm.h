@@ -59,6 +59,10 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
                        iterative-refinement residuals; combination and
                        squaring in binary64 */
 
+/* routes of the full-matrix FP64 path (pfm_set_route) */
+#define PFM_ROUTE_AUTO 0
+#define PFM_ROUTE_LU 1
+
 /* return codes */
 #define PFM_OK 0
 #define PFM_ERR_INVALID (-1)     /* null pointer, n < 1, ld < n, p < 0, tol not in (0,1), ... */
@@ -71,6 +75,12 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
 #define PFM_SINGULAR_SHIFT 1 /* an exact zero pivot in I - c_k B; bad_shift = k */
 #define PFM_NONFINITE 2      /* ||A||_1 is not finite (NaN or Inf in A) */
 #define PFM_IR_STALL 4       /* mixed path: refinement did not reach the target */
+#define PFM_NOT_COMPUTED 8   /* n > 512 (complex: > 256): the instance was not
+                                computed and its outputs were not written,
+                                because A is not finite or some shifted matrix
+                                I - c_k B is not diagonally dominant enough for
+                                the large-instance route (|c_k| ||B||_1 <= 1/2;
+                                the planner's B always is, a forced plan may not) */
 
 /* One problem instance.  p == 0: full matrix, F_exp / F_phi1 are n x n with
  * leading dimension ldf.  p >= 1: action on the n x p block V (leading
@@ -90,12 +100,15 @@ typedef struct {
 
 /* Per-instance report, written to device memory by pfm_eval_batched. */
 typedef struct {
-  int32_t status;    /* PFM_SINGULAR_SHIFT | PFM_NONFINITE | PFM_IR_STALL */
+  int32_t status;    /* PFM_SINGULAR_SHIFT | PFM_NONFINITE | PFM_IR_STALL | PFM_NOT_COMPUTED */
   int32_t plan;      /* s (full matrix: B = A / 2^s) or N (action: B = A / N) */
   int32_t order;     /* order of the rational approximation (eq. 3) */
   int32_t ir_iters;  /* mixed path: refinement sweeps performed */
   int32_t bad_shift; /* first shift index with a zero pivot, -1 if none */
-  int32_t reserved;
+  int32_t route;     /* 1: shifted inverses by Gauss-Jordan without interchanges
+                        (every |c_k| ||B||_1 <= 1/2); 2: the same for a large
+                        instance (n > 512, complex n > 256), spread over many
+                        workgroups; 0: pivoting LU route */
   double norm1;      /* ||A||_1 */
   double theta;      /* admissible ||B||_1 for the requested tolerance (§3) */
   double resid;      /* mixed path: largest relative refinement residual */
@@ -158,6 +171,20 @@ int pfm_check(pfm_ctx *ctx, pfm_stream_t stream);
  * levels, 3: store of the results -- and accumulates their elapsed times.
  * Enabling or disabling resets the totals. */
 int pfm_profile(pfm_ctx *ctx, int enable);
+
+/* Route of the full-matrix FP64 path on real A.
+ *   PFM_ROUTE_AUTO (default): an instance whose shifts all satisfy
+ *     |c_k| ||B||_1 <= 1/2 has strictly column diagonally dominant
+ *     I - c_k B, on which partial pivoting performs no interchange; its
+ *     shifted inverses (I - c_k B)^{-1} (§2) are formed by Gauss-Jordan
+ *     and R = a0 I + (sum_k w_k (I - c_k B)^{-1}) B (§4.3).  Every other
+ *     instance takes the pivoting LU route.
+ *   PFM_ROUTE_LU: every instance takes the pivoting LU route: M_k = P L U,
+ *     Z_k = M_k^{-1} B by substitution, R = a0 I + sum_k w_k Z_k.
+ * Both routes evaluate the same r(B) up to rounding; pfm_info.route reports
+ * the one taken.  Returns PFM_ERR_INVALID for another value.  Takes effect
+ * on the next pfm_eval_batched call. */
+int pfm_set_route(pfm_ctx *ctx, int route);
 
 /* Totals since the last pfm_profile call: ms[4] milliseconds per phase,
  * launches[4] kernel launches per phase (may be NULL), *calls the number of

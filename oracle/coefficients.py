@@ -32,7 +32,7 @@ def taylor_coeffs(func, K):
     exp:    a_k = 1/k!
     phiJ:   phi_J(x) = (e^x - sum_{j<J} x^j/j!) / x^J, so a_k = 1/(k+J)!  (§1;
             the subtracted polynomial has degree J-1, otherwise phi_J(0) would
-            vanish -- reading stated in the design notes)
+            vanish)
     log1m:  log(1 - x) = -sum_{k>=1} x^k / k                         (§2)
     """
     if func == "exp":

@@ -13,8 +13,8 @@ Full matrix, f in {exp, phi1} (§1, §2, §4.3):
      a complex-conjugate pair on real A the pair contributes 2 Re(w_k Z_k).
   5. Undo the scaling (§1): s times { Phi <- (R + I) Phi / 2 ; R <- R R }.
      The phi1 step is the doubling identity of §1 written for B:
-     phi1(2B) = (e^B + I) phi1(B) / 2 (the printed form drops a factor t;
-     see the design notes), and it uses R *before* it is squared.
+     phi1(2B) = (e^B + I) phi1(B) / 2 (the form printed in §1 lacks the
+     factor t that phi1(tA) carries), and it uses R *before* it is squared.
 
 Action on a block V (n x p) (§1, §2):
   1. eta, θ as above; N = max(1, ceil(eta / θ)) (correctly rounded quotient);
@@ -188,6 +188,81 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
         for _ in range(N - 1):
             u = apply_r("exp", u) + u1
         res["phi1"] = u
+    return res
+
+
+def r_scalar(func, m, x):
+    """The approximant of ``func`` on the m-solve set at scalars x (array),
+    in the round-off form of §4.3: a0 + sum_k w_k x / (1 - c_k x)."""
+    x = np.asarray(x, dtype=np.complex128)
+    a0, terms = co.roundoff_terms(func, m)
+    out = np.full(x.shape, a0, dtype=np.complex128)
+    for c, w, pair in terms:
+        t = w * x / (1 - c * x)
+        out += t + np.conj(w) * x / (1 - np.conj(c) * x) if pair else t
+    return out
+
+
+def _r_mp(func, m, xs, N, geo):
+    """r(x)^N (geo=False) or rho(x) / N * sum_{j<N} r(x)^j (geo=True, rho the
+    phi1 approximant) at 40 digits, from the binary64 coefficients the
+    method uses; returned as complex128."""
+    import mpmath
+    a0e, te = co.roundoff_terms("exp", m)
+    a0p, tp = co.roundoff_terms("phi1", m)
+    out = np.empty(len(xs), dtype=np.complex128)
+    with mpmath.workdps(40):
+        def rat(a0, terms, x):
+            v = mpmath.mpc(a0)
+            for c, w, pair in terms:
+                v += mpmath.mpc(w) * x / (1 - mpmath.mpc(c) * x)
+                if pair:
+                    v += mpmath.conj(mpmath.mpc(w)) * x / (1 - mpmath.conj(mpmath.mpc(c)) * x)
+            return v
+        for i, x in enumerate(xs):
+            xm = mpmath.mpc(complex(x))
+            r = rat(a0e, te, xm)
+            if not geo:
+                v = r ** N
+            else:
+                s = mpmath.mpf(N) if r == 1 else (1 - r ** N) / (1 - r)
+                v = rat(a0p, tp, xm) / N * s
+            out[i] = complex(v)
+    return out
+
+
+def action_normal(mu, U, V, funcs=("exp",), m=8, N=1, exact_scalars=False):
+    """The N-step action of ``action`` for a normal A = U diag(mu) U^H
+    (U unitary), evaluated per eigenvalue instead of by solves: with
+    x = mu / N, the steps act on U^H V as multiplication by r(x), so
+      exp:  U diag(r(x)^N) U^H V
+      phi1: U diag(rho(x) / N * sum_{j<N} r(x)^j) U^H V,
+    rho the phi1 approximant (u_1 = rho(B) V / N, u_{j+1} = r(B) u_j + u_1).
+    Exact up to rounding for any n, so it serves as the reference at sizes
+    where the step-by-step oracle is too slow.
+
+    With exact_scalars the per-eigenvalue factors are evaluated at 40 digits
+    (from the same binary64 coefficients): in binary64 their rounding,
+    about sum_k |w_k x / (1 - c_k x)| u, is amplified N times by the power,
+    which at N in the hundreds reaches 1e-12."""
+    mu = np.asarray(mu)
+    x = mu / N
+    W = U.conj().T @ V
+    res = {}
+    if exact_scalars:
+        if "exp" in funcs:
+            res["exp"] = U @ (_r_mp("exp", m, x, N, False)[:, None] * W)
+        if "phi1" in funcs:
+            res["phi1"] = U @ (_r_mp("phi1", m, x, N, True)[:, None] * W)
+        return res
+    r = r_scalar("exp", m, x)
+    if "exp" in funcs:
+        res["exp"] = U @ ((r ** N)[:, None] * W)
+    if "phi1" in funcs:
+        geo = np.zeros_like(r)
+        for _ in range(N):
+            geo = geo * r + 1.0
+        res["phi1"] = U @ ((r_scalar("phi1", m, x) / N * geo)[:, None] * W)
     return res
 
 

@@ -64,7 +64,7 @@ __device__ __forceinline__ void load_shifted(const InstDesc &D, double c, int s_
 template <int NPMAX>
 __global__ void __launch_bounds__(256, 2)
 gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nlist,
-              const PlanRec *__restrict__ plan, Terms T, double *__restrict__ wsd, int action) {
+              PlanRec *__restrict__ plan, Terms T, double *__restrict__ wsd, int action) {
   constexpr int LDD = kGJ + 1;
   __shared__ double Dl[kGJ * LDD];      // D, then D^{-1} (row-major, padded)
   __shared__ double Cl[kGJ * LDD];      // staging for the row-block product
@@ -81,6 +81,7 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   const int ar = arow(i16);
   double *W = wsd + D.fac_off + (int64_t)k * np * np;
   const int nJ = np / kGJ;
+  if (k == 0 && t == 0) plan[ii].route = 1;
 
   load_shifted(D, T.c_re[k], plan[ii].s, action, W, Cl);
 
@@ -243,8 +244,10 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
 }
 
 // S_e = sum_k we_k X_k, S_p = sum_k wp_k X_k (binary64, fixed order k = 0..),
-// into the level-1 squaring buffers (free at this point).  Grid: x = chunk of
-// 4 * 256 elements, y = instance.
+// into the level-1 squaring buffers (free at this point).  Large instances
+// (class 3) take the weights w_k c_k instead: T = sum_k w_k c_k X_k for the
+// form R = a0 I + alpha1 B + B T B (see square_level_f64_kernel).  Grid:
+// x = chunk of 4 * 256 elements, y = instance.
 __global__ void __launch_bounds__(256)
 combine_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, Terms T,
                    double *__restrict__ wsd) {
@@ -253,13 +256,16 @@ combine_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ il
   const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
   if (e0 >= nn) return;
   const double *X = wsd + D.fac_off;
+  const bool q1 = D.cls == 3;
   v4d se = zero4(), sp = zero4();
   for (int k = 0; k < T.nterms; ++k) {
     const v4d x = *reinterpret_cast<const v4d *>(X + (int64_t)k * nn + e0);
+    const double we = q1 ? T.we_re[k] * T.c_re[k] : T.we_re[k];
+    const double wp = q1 ? T.wp_re[k] * T.c_re[k] : T.wp_re[k];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      se[v] = fma(T.we_re[k], x[v], se[v]);
-      sp[v] = fma(T.wp_re[k], x[v], sp[v]);
+      se[v] = fma(we, x[v], se[v]);
+      sp[v] = fma(wp, x[v], sp[v]);
     }
   }
   double *base = wsd + D.r_off;

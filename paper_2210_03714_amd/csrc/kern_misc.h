@@ -1,6 +1,7 @@
 // Norm/plan, output store, info and self-test kernels.
 #pragma once
 #include "kern_common.h"
+#include "pfm.h"
 
 namespace pfm {
 
@@ -45,6 +46,8 @@ plan_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan, doubl
     P.status = 0;
     P.bad_shift = 0x7fffffff;
     P.ir_iters = 0;
+    P.route = 0;
+    P.pad_ = 0;
     P.resid = 0.0;
     double eta = red[0];
     if (bad_s) {
@@ -88,6 +91,7 @@ store_full_kernel(const InstDesc *__restrict__ inst, const PlanRec *__restrict__
   if (tix >= tn * tn) return;
   const int r0 = (tix % tn) * 32, c0 = (tix / tn) * 32;
   const int s = plan[ii].s;
+  if (plan[ii].status & PFM_NOT_COMPUTED) return;
   const int64_t nn = (int64_t)np * np;
   const int t = threadIdx.x;
   const bool cplx_out = D.emb && D.cin;
@@ -153,8 +157,17 @@ embed_kernel(const InstDesc *__restrict__ inst, double *__restrict__ wsd) {
   }
 }
 
+// status |= bits, and route = route (if >= 0), for the listed instances
+__global__ void mark_status_kernel(PlanRec *__restrict__ plan, const int *__restrict__ list, int n, int bits,
+                                   int route) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  plan[list[i]].status |= bits;
+  if (route >= 0) plan[list[i]].route = route;
+}
+
 struct InfoRec {  // mirrors pfm_info
-  int32_t status, plan, order, ir_iters, bad_shift, reserved;
+  int32_t status, plan, order, ir_iters, bad_shift, route;
   double norm1, theta, resid;
 };
 
@@ -169,7 +182,7 @@ __global__ void info_kernel(const PlanRec *__restrict__ plan, InfoRec *__restric
   r.order = order;
   r.ir_iters = P.ir_iters;
   r.bad_shift = P.bad_shift == 0x7fffffff ? -1 : P.bad_shift;
-  r.reserved = 0;
+  r.route = P.route;
   r.norm1 = P.eta;
   r.theta = theta;
   r.resid = P.resid;

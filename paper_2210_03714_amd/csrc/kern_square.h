@@ -23,13 +23,24 @@ struct SqTask {
 
 // MODE 0: squaring level `level` as described above.
 // MODE 1: the combination's product for the Gauss-Jordan path,
-//         R = a0 I + S B (S in buffer 1, B = A 2^-s read from the caller's
-//         row-major A), written to buffer 0 (and the same for Phi).
+//         R = a0 I + S B (S in buffer 1, B read from the row-major A: A 2^-s,
+//         or A / N when `level` is 1 (action)), written to buffer 0 (and the
+//         same for Phi).  Large instances (class 3) use the equivalent
+//         R = a0 I + alpha1 B + (B T) B, T = sum_k w_k c_k X_k, with B T
+//         from MODE 2 in the (no longer needed) factor buffer: since
+//         X_k = I + c_k B X_k, sum_k w_k X_k B = alpha1 B + B T B with
+//         alpha1 = sum_k w_k.  The identity parts of the X_k, whose
+//         rounding the weights (sum |w_k| in the hundreds) would amplify,
+//         drop out; what remains of the X_k is damped by B twice.
+// MODE 2: B T for the large instances: T from buffer 1 (3), B from the
+//         row-major A as in MODE 1, output in the factor buffer slot 0 (1),
+//         all npad columns.
 template <int MODE>
 __global__ void __launch_bounds__(256)
 square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restrict__ tasks,
                         int ntasks, int level, double *__restrict__ wsd,
-                        const PlanRec *__restrict__ plan, double a0e, double a0p) {
+                        const PlanRec *__restrict__ plan, double a0e, double a0p,
+                        double a1e = 0.0, double a1p = 0.0) {
   constexpr int LDA = 80, LDB = 80;  // == 16 mod 32 doubles: conflict-free fragment reads
   __shared__ double As[16 * LDA];
   __shared__ double Bs[16 * LDB];
@@ -53,30 +64,46 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
   const double *Asrc, *Bsrc;
   double *Cdst;
   int sdiv = 0;
+  const bool act = MODE != 0 && level == 1;
+  const bool q1 = MODE == 1 && D.cls == 3;
+  double *facb = wsd + D.fac_off + (which ? nn : 0);
   if (MODE == 0) {
     Asrc = base + ((level - 1) & 1) * nn;   // R_{j-1}
     Bsrc = which ? base + (2 + ((level - 1) & 1)) * nn : Asrc;
     Cdst = which ? base + (2 + (level & 1)) * nn : base + (level & 1) * nn;
-  } else {
-    Asrc = base + (which ? 3 : 1) * nn;     // S_e or S_p
+  } else if (MODE == 1) {
+    Asrc = q1 ? facb : base + (which ? 3 : 1) * nn;  // B T, or S_e / S_p
     Bsrc = nullptr;
     Cdst = base + (which ? 2 : 0) * nn;
     sdiv = plan[tk.inst].s;
+  } else {
+    Asrc = nullptr;
+    Bsrc = base + (which ? 3 : 1) * nn;     // T_e or T_p
+    Cdst = facb;
+    sdiv = plan[tk.inst].s;
   }
+  auto bval = [&](int r, int c) -> double {  // B = A 2^-s or A / N, zero padded
+    const double a = (r < nr && c < nr) ? D.A[(int64_t)r * D.lda + c] : 0.0;
+    return act ? a / (double)sdiv : ldexp(a, -sdiv);
+  };
 
   // per-thread staging: A tile 64x16 (4 consecutive rows of one k column),
   // B tile 16x64 (4 consecutive k of one column)
   const int ak = t >> 4, ar0 = (t & 15) * 4;
   const int bc = t >> 2, bk0 = (t & 3) * 4;
   double ra[4], rbv[4];
-  // MODE 1 reads B row-major: 4 consecutive columns of one row per thread
+  // MODE 1 reads B row-major: 4 consecutive columns of one row per thread;
+  // MODE 2 reads its A operand (B) row-major: 4 consecutive k of one row
   const int bk1 = t >> 4, bc1 = (t & 15) * 4;
+  const int ar2 = t >> 2, ak2 = (t & 3) * 4;
   auto load = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int r = m0 + ar0 + u, kc = k0 + ak;
       double a = 0.0;
-      if (MODE == 1) {
+      if (MODE == 2) {
+        a = bval(m0 + ar2, k0 + ak2 + u);
+      } else if (MODE == 1) {
         a = (r < np) ? Asrc[r + (int64_t)kc * np] : 0.0;
       } else if (r < nr && kc < nr) {
         if (!emb || kc < hn)
@@ -89,9 +116,11 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
       if (MODE == 0) {
         const int c = n0 + bc;
         rbv[u] = (c < ncol) ? Bsrc[(k0 + bk0 + u) + (int64_t)c * np] : 0.0;
+      } else if (MODE == 2) {
+        const int c = n0 + bc;
+        rbv[u] = Bsrc[(k0 + bk0 + u) + (int64_t)c * np];
       } else {
-        const int kr = k0 + bk1, c = n0 + bc1 + u;
-        rbv[u] = (kr < nr && c < nr) ? ldexp(D.A[(int64_t)kr * D.lda + c], -sdiv) : 0.0;
+        rbv[u] = bval(k0 + bk1, n0 + bc1 + u);
       }
     }
   };
@@ -106,8 +135,9 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
   for (int k0 = 0; k0 < np; k0 += 16) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      As[ar0 + u + ak * LDA] = ra[u];
-      if (MODE == 0) Bs[(bk0 + u) * LDB + bc] = rbv[u];
+      if (MODE == 2) As[ar2 + (ak2 + u) * LDA] = ra[u];
+      else As[ar0 + u + ak * LDA] = ra[u];
+      if (MODE != 1) Bs[(bk0 + u) * LDB + bc] = rbv[u];
       else Bs[bk1 * LDB + bc1 + u] = rbv[u];
     }
     __syncthreads();
@@ -128,17 +158,22 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
   }
   const double scl = (MODE == 0 && which) ? 0.5 : 1.0;
   const double dia = MODE == 1 ? (which ? a0p : a0e) : 0.0;
+  const double lin = q1 ? (which ? a1p : a1e) : 0.0;
+  const int oc = MODE == 2 ? np : ncol;  // computed columns
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int c = n0 + 32 * wn + 16 * b + i16;
       const int r = m0 + 32 * wm + 16 * a + 4 * g;
-      if (c < ncol && r < np) {
+      if (c < oc && r < np) {
         v4d o = acc[a][b] * scl;
         if (MODE == 1) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) o[v] += (r + v == c) ? dia : 0.0;
+          for (int v = 0; v < 4; ++v) {
+            o[v] += (r + v == c) ? dia : 0.0;
+            if (q1) o[v] = fma(lin, bval(r + v, c), o[v]);
+          }
         }
         *reinterpret_cast<v4d *>(Cdst + r + (int64_t)c * np) = o;
       }

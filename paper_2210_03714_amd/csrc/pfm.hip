@@ -1,9 +1,10 @@
 // libpfm host runtime: the C ABI of include/pfm.h on top of the gfx950 kernels.
 //
-// A call of pfm_eval_batched is planned on the host only as far as the
-// coefficient set and the workspace layout go; the per-instance plan (s or N)
-// is computed on the device from ||A||_1 and consumed there, so a call never
-// waits on the GPU.
+// A call of pfm_eval_batched validates on the host, lays out the workspace,
+// computes the per-instance plan (s or N) on the device from ||A||_1, reads
+// the plans back once (one stream synchronisation per call: the host sizes
+// the squaring / step launches and routes each instance from them), then
+// enqueues the rest of the path without further waits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +27,7 @@
 #include "kern_action.h"
 #include "kern_mixed.h"
 #include "kern_gj.h"
+#include "kern_large.h"
 
 using namespace pfm;
 
@@ -48,8 +50,8 @@ struct pfm_ctx {
   // device buffer for per-level squaring task lists
   void *tasks = nullptr;
   size_t tasks_bytes = 0;
-  // Gauss-Jordan route for diagonally dominant shifted matrices (PFM_GJ=0
-  // disables it, for comparisons)
+  // Gauss-Jordan route for diagonally dominant shifted matrices
+  // (pfm_set_route(PFM_ROUTE_LU) disables it)
   int gj = 1;
   // optional phase timing (hipEvents on the caller's stream)
   bool prof = false;
@@ -154,6 +156,14 @@ inline void prof_mark(pfm_ctx *ctx, int idx, hipStream_t stream) {
 
 extern "C" {
 
+int pfm_set_route(pfm_ctx *ctx, int route) {
+  if (!ctx) return PFM_ERR_INVALID;
+  if (route != PFM_ROUTE_AUTO && route != PFM_ROUTE_LU)
+    return set_err(ctx, PFM_ERR_INVALID, "pfm_set_route: unknown route %d", route);
+  ctx->gj = route == PFM_ROUTE_AUTO;
+  return PFM_OK;
+}
+
 int pfm_profile(pfm_ctx *ctx, int enable) {
   if (!ctx) return PFM_ERR_INVALID;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -193,7 +203,6 @@ int pfm_create(pfm_ctx **out, int device, size_t budget) {
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) { delete ctx; return PFM_ERR_HIP; }
   ctx->num_cu = prop.multiProcessorCount;
-  if (const char *ev = getenv("PFM_GJ")) ctx->gj = atoi(ev) != 0;
   e = hipMalloc(&ctx->d_err, 64);
   if (e != hipSuccess) { delete ctx; return PFM_ERR_HIP; }
   e = hipMemset(ctx->d_err, 0, 64);
@@ -315,9 +324,17 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   const bool emb = cplx || pairs;  // complex arithmetic runs on the real embedding
   for (int i = 0; i < batch; ++i) {
     const int nk = emb ? 2 * probs[i].n : probs[i].n;
-    if (nk > 512)
-      return set_err(ctx, PFM_ERR_UNSUPPORTED, "problem %d: n = %d exceeds this path (%s)", i, probs[i].n,
-                     emb ? "complex: n <= 256" : "n <= 512");
+    if (nk <= 512) continue;
+    // large instances: Gauss-Jordan route only (real shift sets, binary64)
+    if (mixed || pairs)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED,
+                     "problem %d: n = %d needs the large-instance route, which has no %s", i, probs[i].n,
+                     mixed ? "mixed-precision variant" : "conjugate-pair (m = 1) variant");
+    if (nk > kLargeMax)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED, "problem %d: n = %d exceeds the largest size (%s%d)", i,
+                     probs[i].n, emb ? "complex: n <= " : "n <= ", emb ? kLargeMax / 2 : kLargeMax);
+    if (action && probs[i].p > 64)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED, "problem %d: p = %d > 64 at n > 512 (split V)", i, probs[i].p);
   }
 
   double theta;
@@ -363,7 +380,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   const bool gj_call = ctx->gj && !action && !emb && !mixed;
   // workspace layout
   std::vector<InstDesc> desc(batch);
-  std::vector<int> cls_list[3];
+  std::vector<int> cls_list[4];
   int64_t dofs = 0, iofs = 0;
   for (int i = 0; i < batch; ++i) {
     const pfm_problem &P = probs[i];
@@ -382,13 +399,22 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     D.n = emb ? 2 * P.n : P.n;
     D.ncol = P.n;
     // real FP64 full-matrix instances may take the Gauss-Jordan path, whose
-    // blocks are 64 wide
-    D.npad = gj_call ? (D.n + 63) / 64 * 64 : (D.n + 15) / 16 * 16;
+    // blocks are 64 wide; so do all large instances (class 3)
+    const bool large = D.n > 512;
+    D.npad = (gj_call || large) ? (D.n + 63) / 64 * 64 : (D.n + 15) / 16 * 16;
     D.p = P.p;
-    D.cls = D.npad <= 128 ? 0 : (D.npad <= 256 ? 1 : 2);
+    D.cls = large ? 3 : (D.npad <= 128 ? 0 : (D.npad <= 256 ? 1 : 2));
     const int64_t np = D.npad, nn = np * np;
     D.fac_off = dofs;  dofs += align_up(nterms * nn, 64);
-    D.dinv_off = dofs; dofs += align_up(nterms * 2 * (np / 16) * 256, 64);
+    if (large) {
+      D.ln_off = dofs; dofs += align_up(nterms * ln_stride(D.npad), 64);
+      if (action) {
+        D.v_off = dofs;
+        dofs += align_up(2 * ln_vchain(D.npad, D.p) + (int64_t)ln_ks(D.n) * np * ln_pp(D.p), 64);
+      }
+    } else {
+      D.dinv_off = dofs; dofs += align_up(nterms * 2 * (np / 16) * 256, 64);
+    }
     D.r_off = dofs;    dofs += align_up(4 * nn, 64);
     if (emb || mixed) {
       D.e_off = dofs;  dofs += align_up((int64_t)std::max(D.n, D.npad) * D.npad, 64);
@@ -399,8 +425,10 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
       D.A = (const double *)P.A;
       D.lda = P.lda;
     }
-    D.perm_ioff = iofs; iofs += align_up(nterms * np, 64);
-    D.ipiv_ioff = iofs; iofs += align_up(nterms * np, 64);
+    if (!large) {
+      D.perm_ioff = iofs; iofs += align_up(nterms * np, 64);
+      D.ipiv_ioff = iofs; iofs += align_up(nterms * np, 64);
+    }
     cls_list[D.cls].push_back(i);
   }
   const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
@@ -459,6 +487,9 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     int rcp = prof_harvest(ctx);
     if (rcp) return rcp;
   }
+  // the pinned staging area is reused below for the lists: keep a copy
+  std::vector<PlanRec> hplan(h_plan, h_plan + batch);
+  h_plan = hplan.data();
   std::vector<int> svec(batch);
   int smax = 0;
   for (int i = 0; i < batch; ++i) {
@@ -501,6 +532,23 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     slow_off[c] = (int)lists.size();
     lists.insert(lists.end(), slow_list[c].begin(), slow_list[c].end());
   }
+  // large instances: the multi-workgroup Gauss-Jordan route when the same
+  // dominance test holds for the real matrix the kernels see
+  // (||emb(B)||_1 <= sqrt(2) ||B||_1); otherwise they are not computed
+  std::vector<int> ln_list, skip_list;
+  std::vector<char> skip(batch, 0);
+  for (int i : cls_list[3]) {
+    const double bn = action ? h_plan[i].eta / (double)std::max(1, h_plan[i].s)
+                             : std::ldexp(h_plan[i].eta, -svec[i]);
+    const bool ok = !(h_plan[i].status & 2) && cmax * bn * (desc[i].emb ? std::sqrt(2.0) : 1.0) <= 0.5;
+    (ok ? ln_list : skip_list).push_back(i);
+    is_fast[i] = ok;
+    skip[i] = !ok;
+  }
+  const int ln_off_l = (int)lists.size();
+  lists.insert(lists.end(), ln_list.begin(), ln_list.end());
+  const int skip_off_l = (int)lists.size();
+  lists.insert(lists.end(), skip_list.begin(), skip_list.end());
   bool any_fast = false;
   for (int i = 0; i < batch; ++i) any_fast |= is_fast[i] != 0;
 
@@ -508,11 +556,12 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   // levels 1..smax = squarings.  All tiles of one instance go to one XCD.
   std::vector<SqTask> all;
   std::vector<std::pair<int64_t, int>> lv;  // (offset, count) per level
-  for (int j = 0; j <= smax; ++j) {
+  const int jtop = action ? 0 : smax;  // the action has no squarings
+  for (int j = 0; j <= jtop; ++j) {
     std::vector<std::vector<SqTask>> qx(8);
     int x = 0;
     for (int i = 0; i < batch; ++i) {
-      if (j == 0 ? !is_fast[i] : svec[i] < j) continue;
+      if (skip[i] || (j == 0 ? !is_fast[i] : svec[i] < j)) continue;
       const int tlm = (desc[i].npad + kSqTile - 1) / kSqTile;
       const int tln = (desc[i].ncol + kSqTile - 1) / kSqTile;
       for (int w = 0; w < 1 + T.want_phi; ++w)
@@ -525,6 +574,32 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     for (size_t qq = 0; qq < mx; ++qq)
       for (int xx = 0; xx < 8; ++xx) all.push_back(qq < qx[xx].size() ? qx[xx][qq] : SqTask{-1, 0});
     lv.emplace_back(off, (int)(mx * 8));
+  }
+  // B T products (all npad columns) of the large instances, before level 0
+  std::pair<int64_t, int> lvbt(0, 0);
+  {
+    std::vector<std::vector<SqTask>> qx(8);
+    int x = 0;
+    for (int i : ln_list) {
+      const int tl = desc[i].npad / kSqTile;
+      for (int w = 0; w < 1 + T.want_phi; ++w)
+        for (int tt = 0; tt < tl * tl; ++tt) qx[x].push_back(SqTask{i, tt + (w << 20)});
+      x = (x + 1) & 7;
+    }
+    size_t mx = 0;
+    for (auto &q : qx) mx = std::max(mx, q.size());
+    lvbt.first = (int64_t)all.size();
+    for (size_t qq = 0; qq < mx; ++qq)
+      for (int xx = 0; xx < 8; ++xx) all.push_back(qq < qx[xx].size() ? qx[xx][qq] : SqTask{-1, 0});
+    lvbt.second = (int)(mx * 8);
+  }
+  // alpha1 = sum_k w_k of the binary64 weights, summed in extended precision
+  double a1e = 0.0, a1p = 0.0;
+  {
+    long double se = 0.0L, sp = 0.0L;
+    for (int k = 0; k < nterms; ++k) { se += (long double)T.we_re[k]; sp += (long double)T.wp_re[k]; }
+    a1e = (double)se;
+    a1p = (double)sp;
   }
   const size_t tb = all.size() * sizeof(SqTask);
   if (tb > ctx->tasks_bytes) {
@@ -548,6 +623,18 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     ctx->pin_pending = true;
   }
   const SqTask *dt = (const SqTask *)ctx->tasks;
+  if (!skip_list.empty())
+    hipLaunchKernelGGL(mark_status_kernel, dim3(((int)skip_list.size() + 255) / 256), dim3(256), 0, stream,
+                       d_plan, d_list + skip_off_l, (int)skip_list.size(), PFM_NOT_COMPUTED, -1);
+  const int nln = (int)ln_list.size();
+  if (nln)
+    hipLaunchKernelGGL(mark_status_kernel, dim3((nln + 255) / 256), dim3(256), 0, stream, d_plan,
+                       d_list + ln_off_l, nln, 0, 2);
+  int ln_npm = 0, ln_nmax = 0;
+  for (int i : ln_list) {
+    ln_npm = std::max(ln_npm, desc[i].npad);
+    ln_nmax = std::max(ln_nmax, action ? h_plan[i].s : 0);
+  }
 
   for (int p = 0; p < kNumPhases; ++p) ctx->cur_launches[p] = 0;
   prof_mark(ctx, 0, stream);
@@ -584,6 +671,22 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
 #undef PFM_LU
     ctx->cur_launches[0]++;
   }
+  if (nln) {
+    // large instances: W_k = I - c_k B, then one (row, update) launch pair
+    // per 64-column block step, every (instance, shift) in each launch
+    const int nslot = nln * nterms;
+    const int t1 = ln_npm / kLB, nR = (ln_npm + kLRows - 1) / kLRows;
+    const int *dl = d_list + ln_off_l;
+    hipLaunchKernelGGL(ln_load_kernel, dim3(xcd_grid(nslot, t1 * t1)), dim3(256), 0, stream, d_desc, dl,
+                       nslot, t1, d_plan, T, wsd, action ? 1 : 0);
+    for (int J = 0; J < t1; ++J) {
+      hipLaunchKernelGGL(ln_row_kernel, dim3(xcd_grid(nslot, t1)), dim3(256), 0, stream, d_desc, dl, nslot,
+                         t1, T, wsd, J);
+      hipLaunchKernelGGL(ln_upd_kernel, dim3(xcd_grid(nslot, t1 * nR)), dim3(256), 0, stream, d_desc, dl,
+                         nslot, t1, nR, T, wsd, J);
+    }
+    ctx->cur_launches[0] += 1 + 2 * t1;
+  }
   prof_mark(ctx, 1, stream);
   if (action) {
     // 3'. B = A / N column-major, then the N-step recurrence per column slab
@@ -614,6 +717,46 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
       if (c == 2) PFM_ACT(512, 16);
 #undef PFM_ACT
       ctx->cur_launches[1] += T.want_exp + T.want_phi;
+    }
+    if (nln) {
+      // large instances: S = sum_k w_k X_k, R = a0 I + S B and P (phi1),
+      // then the N steps U <- R U (+ U1) as K-split GEMMs
+      const int chunks = (int)(((int64_t)ln_npm * ln_npm / 4 + 255) / 256);
+      const int *dl = d_list + ln_off_l;
+      hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nln), dim3(256), 0, stream, d_desc, dl, T, wsd);
+      if (lvbt.second)  // level argument 1: B = A / N
+        hipLaunchKernelGGL(square_level_f64_kernel<2>, dim3(lvbt.second), dim3(256), 0, stream, d_desc,
+                           dt + lvbt.first, lvbt.second, 1, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);
+      const auto &e = lv[0];
+      if (e.second)
+        hipLaunchKernelGGL(square_level_f64_kernel<1>, dim3(e.second), dim3(256), 0, stream, d_desc,
+                           dt + e.first, e.second, 1, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);
+      const int nchain = T.want_exp + T.want_phi;
+      hipLaunchKernelGGL(ln_vprep_kernel, dim3(ln_npm / 64, nln), dim3(256), 0, stream, d_desc, dl, nchain, wsd);
+      int ppmask = 0, ksmax = 1;
+      for (int i : ln_list) {
+        ppmask |= 1 << (ln_pp(desc[i].p) / 16 - 1);
+        ksmax = std::max(ksmax, ln_ks(desc[i].n));
+      }
+      const int nsub = (ln_npm / 64) * ksmax;
+      const dim3 gv(xcd_grid(nln, nsub));
+      for (int j = 1; j <= ln_nmax; ++j) {
+        for (int ch = 0; ch < nchain; ++ch) {
+          const int phi = (ch == 1 || !T.want_exp) ? 1 : 0;
+          const int use_p = phi && j == 1;
+          const int inb = (j - 1) & 1, outb = j & 1;
+#define PFM_GEMV(PPV)                                                                              \
+  if (ppmask & (1 << (PPV / 16 - 1)))                                                            \
+    hipLaunchKernelGGL(ln_gemv_kernel<PPV>, gv, dim3(256), 0, stream, d_desc, dl, nln, nsub, d_plan, \
+                       wsd, j, ch, use_p, inb);
+          PFM_GEMV(16) PFM_GEMV(32) PFM_GEMV(48) PFM_GEMV(64)
+#undef PFM_GEMV
+          hipLaunchKernelGGL(ln_vreduce_kernel, dim3(ln_npm / 64, nln), dim3(256), 0, stream, d_desc, dl,
+                             d_plan, wsd, j, ch, outb, 1.0, phi);
+          ctx->cur_launches[1] += 2;
+        }
+      }
+      ctx->cur_launches[1] += 3;
     }
     prof_mark(ctx, 2, stream);
     prof_mark(ctx, 3, stream);
@@ -668,10 +811,16 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
       hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nl), dim3(256), 0, stream, d_desc,
                          d_list + fast_off[c], T, wsd);
     }
+    if (nln)
+      hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nln), dim3(256), 0, stream, d_desc,
+                         d_list + ln_off_l, T, wsd);
+    if (lvbt.second)
+      hipLaunchKernelGGL(square_level_f64_kernel<2>, dim3(lvbt.second), dim3(256), 0, stream, d_desc,
+                         dt + lvbt.first, lvbt.second, 0, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);
     const auto &e = lv[0];
     if (e.second)
       hipLaunchKernelGGL(square_level_f64_kernel<1>, dim3(e.second), dim3(256), 0, stream, d_desc,
-                         dt + e.first, e.second, 0, wsd, d_plan, T.a0e, T.a0p);
+                         dt + e.first, e.second, 0, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);
     ctx->cur_launches[1] += 2;
   }
   for (int c = 0; c < 3 && !mixed; ++c) {

@@ -8,6 +8,7 @@ constexpr int kMaxTerms = 16;   // nonzero-shift solves per call
 constexpr int kSCap = 1000;     // largest squaring count accepted
 constexpr int kNCap = 1 << 20;  // largest action step count accepted
 constexpr int kSqTile = 64;     // squaring GEMM tile edge
+constexpr int kLargeMax = 16384; // largest real dimension (2n for complex) of a large instance
 
 // One problem instance as the kernels see it.  Offsets index the context's
 // workspace (doubles for *_off in the double region, ints for *_ioff).
@@ -35,6 +36,8 @@ struct InstDesc {
   int64_t dinv_off;  // nterms * 2 * (npad/16) * 256   : inverted 16x16 diagonal blocks of L and U
   int64_t r_off;     // 4 * npad^2 : R ping-pong buffers, then phi1 ping-pong buffers
   int64_t e_off;     // emb: the embedded matrix, row-major n x n
+  int64_t ln_off;    // large instances: nterms * ln_stride(npad) (colbuf, dinv)
+  int64_t v_off;     // large action instances: step vectors and partial products
   int64_t perm_ioff; // nterms * npad : row permutation of each factorisation
   int64_t ipiv_ioff; // nterms * npad : LAPACK-style pivot sequence
 };
@@ -45,6 +48,8 @@ struct PlanRec {
   int32_t status;     // PFM_* status bits
   int32_t bad_shift;  // smallest shift index with a zero pivot (0x7fffffff: none)
   int32_t ir_iters;
+  int32_t route;      // 1: Gauss-Jordan inverse route, 0: pivoting LU route
+  int32_t pad_;
   double eta;         // ||A||_1
   double resid;
 };

@@ -20,6 +20,8 @@ R64 = 0
 C128 = 1
 FP64 = 0
 MIXED = 1
+ROUTE_AUTO = 0
+ROUTE_LU = 1
 
 OK = 0
 ERR_INVALID = -1
@@ -31,6 +33,7 @@ ERR_DEVICE = -5
 SINGULAR_SHIFT = 1
 NONFINITE = 2
 IR_STALL = 4
+NOT_COMPUTED = 8
 
 
 class Problem(ctypes.Structure):
@@ -41,7 +44,7 @@ class Problem(ctypes.Structure):
 
 
 INFO_DTYPE = np.dtype([("status", "<i4"), ("plan", "<i4"), ("order", "<i4"), ("ir_iters", "<i4"),
-                       ("bad_shift", "<i4"), ("reserved", "<i4"), ("norm1", "<f8"),
+                       ("bad_shift", "<i4"), ("route", "<i4"), ("norm1", "<f8"),
                        ("theta", "<f8"), ("resid", "<f8")])
 assert INFO_DTYPE.itemsize == 48
 
@@ -69,6 +72,7 @@ def lib():
         L.pfm_version.restype = ctypes.c_char_p
         L.pfm_selftest_mfma.argtypes = [i32, dp]
         L.pfm_profile.argtypes = [vp, i32]
+        L.pfm_set_route.argtypes = [vp, i32]
         L.pfm_profile_read.argtypes = [vp, dp, ip, ip]
         _lib = L
     return _lib
@@ -144,6 +148,13 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def set_route(self, route):
+        """ROUTE_AUTO (Gauss-Jordan where pivoting provably never swaps) or
+        ROUTE_LU (pivoting LU for every instance)."""
+        rc = lib().pfm_set_route(self._h, int(route))
+        if rc:
+            raise PfmError(rc, self.last_error())
 
     def profile(self, enable=True):
         rc = lib().pfm_profile(self._h, 1 if enable else 0)
@@ -260,6 +271,9 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx
         _require_gpu(a)
         _require_gpu(v)
     cplx = mats[0].is_complex() or vecs[0].is_complex()
+    if cplx:  # one element type per call: complex A and V (interleaved)
+        mats = [a if a.is_complex() else a.to(torch.complex128) for a in mats]
+        vecs = [v if v.is_complex() else v.to(torch.complex128) for v in vecs]
     fm = _fmask(funcs)
     out = {f: [torch.empty_like(v) for v in vecs] for f in funcs}
     probs = []

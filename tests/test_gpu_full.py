@@ -129,6 +129,38 @@ def test_headline_sampled(torch_dev):
         eta = np.abs(A[i]).sum(0).max()
         assert abs(info[i]["norm1"] - eta) <= 1e-14 * eta
         assert info[i]["status"] == 0
+        # |c_k| ||B||_1 <= max|c| θ < 1/2 on planned inputs: inverse route
+        assert info[i]["route"] == 1
+
+
+@pytest.mark.parametrize("funcs", [("exp",), ("exp", "phi1")])
+def test_lu_route_matches_oracle(torch_dev, funcs):
+    """The pivoting LU route forced on planned inputs (the route every
+    instance takes when the dominance test fails): ragged sizes, parity
+    against the oracle, and agreement with the inverse route."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    sizes = [3, 16, 47, 64, 128, 190, 256, 320, 512]
+    rng = np.random.default_rng(wl.SEED_BASE + 55)
+    mats = [wl.gaussian(n, float(rng.uniform(0.5, 8.0)), wl.SEED_BASE + 56 + n) for n in sizes]
+    _say("case lu route", sizes, funcs)
+    At = [torch.from_numpy(a).to(dev) for a in mats]
+    ctx = pfm.Context(0)
+    ctx.set_route(pfm.ROUTE_LU)
+    res, info = pfm.expm(At, funcs, m=8, tol=1e-12, ctx=ctx)
+    torch.cuda.synchronize()
+    assert all(info[i]["route"] == 0 for i in range(len(mats)))
+    _check_instances(mats, res, info, funcs, 8, 1e-12)
+    ctx.set_route(pfm.ROUTE_AUTO)
+    res2, info2 = pfm.expm(At, funcs, m=8, tol=1e-12, ctx=ctx)
+    torch.cuda.synchronize()
+    for i, n in enumerate(sizes):
+        assert info2[i]["route"] == 1
+        for f in funcs:
+            d = me.rel_fro(res2[f][i].cpu().numpy(), res[f][i].cpu().numpy())
+            assert d <= 1e-12, (n, f, d)
+    with pytest.raises(pfm.PfmError):
+        ctx.set_route(7)
 
 
 def test_pivoting_forced_plan(torch_dev):
@@ -146,6 +178,7 @@ def test_pivoting_forced_plan(torch_dev):
         ref = me.expm_full(a, ("exp",), 8, 1e-12, force_plan=0)
         err = me.rel_fro(res["exp"][i].cpu().numpy(), ref["exp"])
         assert err <= 1e-11, (i, err)
+        assert info[i]["route"] == 0
 
 
 def test_singular_shift_and_nonfinite_are_isolated(torch_dev):

@@ -86,7 +86,7 @@ def test_pade_pair_phi1_reproduces_printed_form(golden):
 
 def test_printed_r22_pole_form_needs_sqrt3_reading():
     """eq. (5) prints the numerator as 6 + i 6 sqrt(6); only 6 + 6 sqrt(3) i
-    makes the pole form equal r_22 (reading recorded in the design notes)."""
+    makes the pole form equal r_22."""
     xs = sp.symbols("xs", real=True)
     r22 = (1 + xs / 2 + xs ** 2 / 12) / (1 - xs / 2 + xs ** 2 / 12)
     pole = 3 - sp.I * sp.sqrt(3)

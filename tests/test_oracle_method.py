@@ -300,3 +300,44 @@ def test_planted_squaring_order_error_is_caught(monkeypatch):
     assert me.rel_fro(good["phi1"], want) < 1e-12
     assert me.rel_fro(Phi, want) > 1e-3
     del res
+
+
+@pytest.mark.parametrize("kind", ["iH", "negL"])
+def test_action_normal_matches_step_by_step(kind):
+    """The per-eigenvalue form of the N-step action equals the step-by-step
+    oracle (LU solves every step) for normal A: iH (complex) and -L (real)."""
+    n, p = 40, 3
+    if kind == "iH":
+        H = wl.ih_matrix(n, wl.SEED_BASE + 300) / 1j
+        lam, U = np.linalg.eigh(H)
+        mu, A = 1j * lam, 1j * H
+        V = wl.vectors(n, p, wl.SEED_BASE + 301, complex_=True)
+    else:
+        A = wl.neg_laplacian(n, 1.0)
+        mu, U = np.linalg.eigh(A)
+        V = wl.vectors(n, p, wl.SEED_BASE + 302)
+    ref = me.action(A, V, ("exp", "phi1"), 8, 1e-12)
+    got = me.action_normal(mu, U, V, ("exp", "phi1"), 8, ref["plan"])
+    got_x = me.action_normal(mu, U, V, ("exp", "phi1"), 8, ref["plan"], exact_scalars=True)
+    for f in ("exp", "phi1"):
+        assert me.rel_fro(got[f], ref[f]) <= 1e-13, (kind, f)
+        assert me.rel_fro(got_x[f], ref[f]) <= 1e-13, (kind, f)
+    # and both meet the exact functions within the bound (N steps, each <= tol)
+    ex = U @ (np.exp(mu)[:, None] * (U.conj().T @ V))
+    assert me.rel_fro(got["exp"], ex) <= ref["plan"] * 1e-12 * 10
+
+
+def test_r_scalar_is_the_rational():
+    """r_scalar in the round-off form equals sum b_k / (1 - c_k x) summed
+    exactly at rational points (the partial-fraction form of eq. 2)."""
+    from fractions import Fraction as Fr
+    c, b = co.real_set("exp", 8)
+    for xq in (Fr(1, 7), Fr(-3, 10), Fr(1, 4)):
+        exact = sum((bi / (1 - ci * xq) for ci, bi in zip(c, b)), Fr(0))
+        got = me.r_scalar("exp", 8, np.array([float(xq)]))[0]
+        # rounding bound of the round-off form: each term w x / (1 - c x)
+        # within ~3u, their sum within m u, scaled by sum_k |term_k|
+        a0, terms = co.roundoff_terms("exp", 8)
+        mag = sum(abs(w * float(xq) / (1 - c * float(xq))) for c, w, _ in terms)
+        u = 2.0 ** -53
+        assert abs(got - float(exact)) <= (len(terms) + 4) * u * (mag + abs(a0))
