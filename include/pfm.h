@@ -28,9 +28,12 @@
  * - Device pointers are HIP device pointers on the context's device.  The
  *   caller owns every buffer it passes; the library never frees them and never
  *   writes to inputs.  The context owns all workspace.
- * - All device work is enqueued on the caller's stream and the calls return
- *   without waiting for it.  One context must not be used from two streams at
- *   the same time (its workspace is shared between calls).
+ * - All device work is enqueued on the caller's stream.  pfm_eval_batched
+ *   waits once on that stream, right after the norm/plan kernel, to read the
+ *   per-instance plans (it sizes the squaring and step launches and routes
+ *   each instance from them); the rest of the call is asynchronous.  One
+ *   context must not be used from two streams at the same time (its
+ *   workspace is shared between calls).
  */
 #ifndef PFM_H
 #define PFM_H
@@ -190,6 +193,70 @@ int pfm_set_route(pfm_ctx *ctx, int route);
  * launches[4] kernel launches per phase (may be NULL), *calls the number of
  * timed calls (may be NULL).  Waits for the last timed call to finish. */
 int pfm_profile_read(pfm_ctx *ctx, double *ms, int *launches, int *calls);
+
+/* Upper bound of the workspace bytes pfm_eval_batched would allocate for
+ * this batch (host only; probs may hold NULL data pointers).  Returns 0 for
+ * an invalid or unsupported batch. */
+size_t pfm_workspace_bytes(int f, int m, int prec, int dtype, int batch, const pfm_problem *probs);
+
+/* ------------------------------------------------------------------------
+ * Serving: a scheduler thread with continuous batching over the calls above.
+ *
+ * Requests are submitted one at a time with their own function, solve count,
+ * tolerance, precision and element type.  The scheduler admits a pending
+ * request when its resident bytes (copies of A and V, its outputs) fit in the
+ * resident share of the HBM budget, copies A (and V) into library-owned
+ * device buffers, and groups admitted requests that can share one
+ * pfm_eval_batched call (same f, m, tol, prec, dtype and mode) into batches
+ * whose workspace fits one lane's share of the budget.  Each lane is a
+ * stream with its own workspace; up to `lanes` batches run concurrently,
+ * and requests arriving meanwhile are admitted and batched as lanes free up.
+ * A request's results stay in library memory until fetched or released.
+ *
+ * Latency is measured by the library from pfm_srv_submit to the host seeing
+ * the batch's completion event (host steady clock).
+ * ------------------------------------------------------------------------ */
+typedef struct pfm_server pfm_server;
+
+/* Start a server on `device`.  lanes in [1, 16]; hbm_budget_bytes > 0 is
+ * split half for resident request data, half across the lanes' workspaces;
+ * max_batch caps the requests per call. */
+int pfm_srv_start(pfm_server **srv, int device, int lanes, size_t hbm_budget_bytes, int max_batch);
+
+/* Finish every submitted request, stop the thread and free all memory
+ * (unfetched results are lost). */
+int pfm_srv_stop(pfm_server *srv);
+
+/* Queue one request.  pr holds device pointers A (and V for p >= 1); they
+ * must stay valid and unchanged until the request is done (the copy into
+ * resident memory happens at dispatch).  pr->F_exp / F_phi1 / ldf are
+ * ignored: results go to library memory.  Returns PFM_ERR_INVALID /
+ * PFM_ERR_UNSUPPORTED for a request pfm_eval_batched would reject, and
+ * PFM_ERR_BUDGET for one that can never fit the budget. */
+int pfm_srv_submit(pfm_server *srv, const pfm_problem *pr, int f, int m, double tol, int prec, int dtype,
+                   uint64_t *ticket);
+
+/* State of a request: 0 done (info and latency filled, may be NULL),
+ * 1 queued or running, PFM_ERR_INVALID for an unknown ticket, PFM_ERR_HIP if
+ * its batch failed. */
+int pfm_srv_poll(pfm_server *srv, uint64_t ticket, pfm_info *info, double *latency_s);
+
+/* Up to max completed requests not reported before: tickets, latencies (s)
+ * and per-instance status.  Returns the count. */
+int pfm_srv_drain(pfm_server *srv, int max, uint64_t *tickets, double *latency_s, int32_t *status);
+
+/* Copy a done request's result for function `which` (PFM_EXP or PFM_PHI1)
+ * to the device buffer dst (row-major, leading dimension ldd, the request's
+ * element type), synchronously.  The result stays until released. */
+int pfm_srv_fetch(pfm_server *srv, uint64_t ticket, int which, void *dst, int64_t ldd);
+
+/* Free a done request's results and forget the ticket. */
+int pfm_srv_release(pfm_server *srv, uint64_t ticket);
+
+/* Counters: submitted, done, batches launched, bytes resident now, peak
+ * resident bytes. */
+int pfm_srv_stats(pfm_server *srv, uint64_t *submitted, uint64_t *done, uint64_t *batches,
+                  uint64_t *resident_bytes, uint64_t *peak_resident_bytes);
 
 /* Library version string (static storage). */
 const char *pfm_version(void);

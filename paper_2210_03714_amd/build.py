@@ -1,8 +1,8 @@
 """Build libpfm.so for gfx950 in-tree (hipcc cross-compiles; no GPU needed).
 
 Steps: generate the coefficient/θ tables with csrc/gen_tables.py, then one
-hipcc invocation compiles the kernels and the C-ABI runtime into
-paper_2210_03714_amd/libpfm.so.
+hipcc invocation compiles the kernels and the C-ABI runtime (pfm.hip) and
+the serving runtime (serve.hip) into paper_2210_03714_amd/libpfm.so.
 """
 
 import os
@@ -34,7 +34,8 @@ def build(verbose=False):
     subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_tables.py"), tables])
     tmp = LIB + ".tmp"
     cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
-                                      os.path.join(CSRC, "pfm.hip"), "-o", tmp]
+                                      os.path.join(CSRC, "pfm.hip"), os.path.join(CSRC, "serve.hip"),
+                                      "-o", tmp]
     if verbose:
         print(" ".join(cmd))
     r = subprocess.run(cmd, capture_output=True, text=True)

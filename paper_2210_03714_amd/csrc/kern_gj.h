@@ -245,18 +245,19 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
 
 // S_e = sum_k we_k X_k, S_p = sum_k wp_k X_k (binary64, fixed order k = 0..),
 // into the level-1 squaring buffers (free at this point).  Large instances
-// (class 3) take the weights w_k c_k instead: T = sum_k w_k c_k X_k for the
+// (route 2) take the weights w_k c_k instead: T = sum_k w_k c_k X_k for the
 // form R = a0 I + alpha1 B + B T B (see square_level_f64_kernel).  Grid:
 // x = chunk of 4 * 256 elements, y = instance.
 __global__ void __launch_bounds__(256)
 combine_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, Terms T,
-                   double *__restrict__ wsd) {
-  const InstDesc D = inst[ilist[blockIdx.y]];
+                   double *__restrict__ wsd, const PlanRec *__restrict__ plan) {
+  const int ii = ilist[blockIdx.y];
+  const InstDesc D = inst[ii];
   const int64_t nn = (int64_t)D.npad * D.npad;
   const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
   if (e0 >= nn) return;
   const double *X = wsd + D.fac_off;
-  const bool q1 = D.cls == 3;
+  const bool q1 = plan[ii].route == 2;
   v4d se = zero4(), sp = zero4();
   for (int k = 0; k < T.nterms; ++k) {
     const v4d x = *reinterpret_cast<const v4d *>(X + (int64_t)k * nn + e0);

@@ -8,9 +8,11 @@
 // and Gauss-Jordan without interchanges is what partial pivoting would do.
 //
 // Block step J (64-column blocks, W column-major npad x npad per shift):
-//   ln_row_kernel  (one workgroup per column block C):
+//   ln_dinv_kernel (one workgroup per (instance, shift)):
 //       Dinv = D^{-1}, D = W[J, J] taken from colbuf (the column block J as
-//       it was before the step); C == J: Dinv -> dinv buffer and W[J, J];
+//       it was before the step), into the dinv buffer.
+//   ln_row_kernel  (one workgroup per column block C):
+//       C == J: W[J, J] <- Dinv;
 //       C != J: W[J, C] <- Dinv W[J, C]; for C == J + 1 also into the next
 //       colbuf.
 //   ln_upd_kernel  (one workgroup per 128 rows x column block C):
@@ -115,6 +117,35 @@ __device__ __forceinline__ void ln_gj64(double *Dl, int pr0, int pc0) {
 }
 
 __global__ void __launch_bounds__(256)
+ln_dinv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nslot, Terms T,
+               double *__restrict__ wsd, int J) {
+  constexpr int LDD = kLB + 1;
+  __shared__ double Dl[kLB * LDD];
+  const int slot = blockIdx.x;
+  if (slot >= nslot) return;
+  const int li = slot / T.nterms, k = slot % T.nterms;
+  const InstDesc D = inst[ilist[li]];
+  const int np = D.npad, nJ = np / kLB;
+  if (J >= nJ) return;
+  const int t = threadIdx.x;
+  const double *side = wsd + D.ln_off + (int64_t)k * ln_stride(np);
+  const double *colJ = side + (int64_t)(J & 1) * np * kLB;
+  double *dinv = wsd + D.ln_off + (int64_t)k * ln_stride(np) + 2 * (int64_t)np * kLB;
+  const int j0 = J * kLB;
+  const int pr0 = (t >> 4) * 4, pc0 = (t & 15) * 4;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Dl[(pr0 + a) * LDD + pc0 + b] = colJ[(j0 + pr0 + a) + (int64_t)(pc0 + b) * np];
+  __syncthreads();
+  ln_gj64<LDD>(Dl, pr0, pc0);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dinv[(pr0 + a) + (pc0 + b) * kLB] = Dl[(pr0 + a) * LDD + pc0 + b];
+}
+
+__global__ void __launch_bounds__(256)
 ln_row_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nslot, int nJmax,
               Terms T, double *__restrict__ wsd, int J) {
   constexpr int LDD = kLB + 1;
@@ -132,32 +163,25 @@ ln_row_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   const int ar = arow(i16);
   double *W = wsd + D.fac_off + (int64_t)k * np * np;
   double *side = wsd + D.ln_off + (int64_t)k * ln_stride(np);
-  const double *colJ = side + (int64_t)(J & 1) * np * kLB;
   double *colN = side + (int64_t)((J + 1) & 1) * np * kLB;
-  double *dinv = side + 2 * (int64_t)np * kLB;
+  const double *dinv = side + 2 * (int64_t)np * kLB;
   const int j0 = J * kLB, c0 = C * kLB;
   const int pr0 = (t >> 4) * 4, pc0 = (t & 15) * 4;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) Dl[(pr0 + a) * LDD + pc0 + b] = colJ[(j0 + pr0 + a) + (int64_t)(pc0 + b) * np];
-  __syncthreads();
-  ln_gj64<LDD>(Dl, pr0, pc0);
   if (C == J) {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const double v = Dl[(pr0 + a) * LDD + pc0 + b];
-        dinv[(pr0 + a) + (pc0 + b) * kLB] = v;
-        W[(j0 + pr0 + a) + (int64_t)(j0 + pc0 + b) * np] = v;
-      }
+      for (int b = 0; b < 4; ++b)
+        W[(j0 + pr0 + a) + (int64_t)(j0 + pc0 + b) * np] = dinv[(pr0 + a) + (pc0 + b) * kLB];
     return;
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) Cl[(pr0 + a) * LDD + pc0 + b] = W[(j0 + pr0 + a) + (int64_t)(c0 + pc0 + b) * np];
+    for (int b = 0; b < 4; ++b) {
+      Dl[(pr0 + a) * LDD + pc0 + b] = dinv[(pr0 + a) + (pc0 + b) * kLB];
+      Cl[(pr0 + a) * LDD + pc0 + b] = W[(j0 + pr0 + a) + (int64_t)(c0 + pc0 + b) * np];
+    }
   __syncthreads();
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
   v4d acc[2][2];

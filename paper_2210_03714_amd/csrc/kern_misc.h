@@ -7,70 +7,93 @@ namespace pfm {
 
 // eta = ||A||_1 (max column sum of |a_ij|; |z| for complex), then the plan of
 // §1: s = smallest s >= 0 with eta 2^-s <= θ (full matrix) or
-// N = max(1, ceil(eta / θ)) (action).  Column sums run over rows in order.
+// N = max(1, ceil(eta / θ)) (action).  Three launches:
+//   plan_init_kernel   (batch / 256 blocks): clear the plan records;
+//   norm_kernel        (64-column chunk x instance): each column's sum in
+//                      four row partitions (rows congruent mod 4, in order),
+//                      combined in a fixed order, then the chunk's max folded
+//                      into eta with an integer atomicMax on the bit pattern
+//                      (eta >= 0, and NaN patterns order above +inf), so the
+//                      result does not depend on scheduling;
+//   plan_finish_kernel (batch / 256 blocks): s or N from eta.
 __global__ void __launch_bounds__(256)
-plan_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan, double theta,
-            int action, int force_plan) {
-  __shared__ double red[256];
-  __shared__ int bad_s;
-  const int ii = blockIdx.x;
+plan_init_kernel(PlanRec *__restrict__ plan, int batch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  PlanRec P;
+  P.s = 0;
+  P.status = 0;
+  P.bad_shift = 0x7fffffff;
+  P.ir_iters = 0;
+  P.route = 0;
+  P.pad_ = 0;
+  P.eta = 0.0;
+  P.resid = 0.0;
+  plan[i] = P;
+}
+
+__global__ void __launch_bounds__(256)
+norm_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan) {
+  __shared__ double part[4][64];
+  const int ii = blockIdx.y;
   const InstDesc D = inst[ii];
   const int n = D.emb ? D.hn : D.n;  // the caller's matrix
-  const int cplx = D.cin;
-  if (threadIdx.x == 0) bad_s = 0;
-  __syncthreads();
-  double mx = 0.0;
-  int bad = 0;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    double s = 0.0;
-    if (cplx) {
-      for (int r = 0; r < n; ++r) {
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= n) return;
+  const int t = threadIdx.x, cl = t & 63, g = t >> 6;
+  const int c = c0 + cl;
+  double s = 0.0;
+  if (c < n) {
+    if (D.cin) {
+      for (int r = g; r < n; r += 4) {
         const double *z = D.Ain + 2 * ((int64_t)r * D.ldin + c);
         s += hypot(z[0], z[1]);
       }
     } else {
-      for (int r = 0; r < n; ++r) s += fabs(D.Ain[(int64_t)r * D.ldin + c]);
+      for (int r = g; r < n; r += 4) s += fabs(D.Ain[(int64_t)r * D.ldin + c]);
     }
-    if (!isfinite(s)) bad = 1;
-    mx = fmax(mx, s);
   }
-  red[threadIdx.x] = mx;
-  if (bad) bad_s = 1;
+  part[g][cl] = s;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    PlanRec P;
-    P.status = 0;
-    P.bad_shift = 0x7fffffff;
-    P.ir_iters = 0;
-    P.route = 0;
-    P.pad_ = 0;
-    P.resid = 0.0;
-    double eta = red[0];
-    if (bad_s) {
-      eta = __builtin_nan("");
-      P.status = 2;
+  if (t < 64) {
+    double v = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+    if (isnan(v)) v = __builtin_nan("");  // one canonical NaN
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v, off);
+      v = (isnan(o) || o > v) ? o : v;
     }
-    P.eta = eta;
-    int plan_v;
-    if (force_plan >= 0) {
-      plan_v = action ? (force_plan < 1 ? 1 : force_plan) : force_plan;
-    } else if (bad_s) {
-      plan_v = action ? 1 : 0;
-    } else if (action) {
-      const double q = ceil(eta / theta);
-      plan_v = q < 1.0 ? 1 : (q > 1e9 ? 1000000000 : (int)q);
-    } else {
-      int s = 0;
-      while (ldexp(eta, -s) > theta && s < 1023) ++s;
-      plan_v = s;
-    }
-    P.s = plan_v;
-    plan[ii] = P;
+    if (t == 0)
+      atomicMax(reinterpret_cast<unsigned long long *>(&plan[ii].eta), (unsigned long long)__double_as_longlong(v));
   }
+}
+
+__global__ void __launch_bounds__(256)
+plan_finish_kernel(PlanRec *__restrict__ plan, int batch, double theta, int action, int force_plan) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  PlanRec P = plan[i];
+  const double eta = P.eta;
+  const bool bad = !isfinite(eta);
+  if (bad) {
+    P.eta = __builtin_nan("");
+    P.status = 2;
+  }
+  int plan_v;
+  if (force_plan >= 0) {
+    plan_v = action ? (force_plan < 1 ? 1 : force_plan) : force_plan;
+  } else if (bad) {
+    plan_v = action ? 1 : 0;
+  } else if (action) {
+    const double q = ceil(eta / theta);
+    plan_v = q < 1.0 ? 1 : (q > 1e9 ? 1000000000 : (int)q);
+  } else {
+    int s = 0;
+    while (ldexp(eta, -s) > theta && s < 1023) ++s;
+    plan_v = s;
+  }
+  P.s = plan_v;
+  plan[i] = P;
 }
 
 // Copy the final R / Phi (column-major, npad) to the caller's row-major

@@ -25,7 +25,7 @@ struct SqTask {
 // MODE 1: the combination's product for the Gauss-Jordan path,
 //         R = a0 I + S B (S in buffer 1, B read from the row-major A: A 2^-s,
 //         or A / N when `level` is 1 (action)), written to buffer 0 (and the
-//         same for Phi).  Large instances (class 3) use the equivalent
+//         same for Phi).  Multi-workgroup-route instances use the equivalent
 //         R = a0 I + alpha1 B + (B T) B, T = sum_k w_k c_k X_k, with B T
 //         from MODE 2 in the (no longer needed) factor buffer: since
 //         X_k = I + c_k B X_k, sum_k w_k X_k B = alpha1 B + B T B with
@@ -65,7 +65,7 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
   double *Cdst;
   int sdiv = 0;
   const bool act = MODE != 0 && level == 1;
-  const bool q1 = MODE == 1 && D.cls == 3;
+  const bool q1 = MODE == 1 && plan[tk.inst].route == 2;
   double *facb = wsd + D.fac_off + (which ? nn : 0);
   if (MODE == 0) {
     Asrc = base + ((level - 1) & 1) * nn;   // R_{j-1}

@@ -189,7 +189,37 @@ int pfm_profile_read(pfm_ctx *ctx, double *ms, int *launches, int *calls) {
   return PFM_OK;
 }
 
-const char *pfm_version(void) { return "pfm 0.1 (gfx950; f64 full-matrix path)"; }
+size_t pfm_workspace_bytes(int f, int m, int prec, int dtype, int batch, const pfm_problem *probs) {
+  if (f < 1 || f > 3 || batch < 1 || !probs) return 0;
+  const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
+  if (!ee || !ep) return 0;
+  const bool cplx = dtype == PFM_C128, pairs = ee->pair != 0, mixed = prec == PFM_MIXED;
+  const bool emb = cplx || pairs;
+  const bool phi = (f & PFM_PHI1) != 0;
+  if (prec != PFM_FP64 && prec != PFM_MIXED) return 0;
+  if (dtype != PFM_R64 && dtype != PFM_C128) return 0;
+  const bool act = probs[0].p > 0;
+  if (mixed && (cplx || pairs || act)) return 0;
+  const int64_t nterms = pairs ? (int64_t)(cplx ? 2 : 1) * (1 + (phi ? 1 : 0)) : ee->nterms;
+  int64_t d = 4096 / 8, ints = 0;
+  for (int i = 0; i < batch; ++i) {
+    const pfm_problem &P = probs[i];
+    if (P.n < 1 || P.p < 0 || (P.p > 0) != act) return 0;
+    const int64_t nk = emb ? 2 * (int64_t)P.n : P.n;
+    if (nk > 512 && (mixed || pairs || nk > kLargeMax || P.p > 64)) return 0;
+    const int64_t np = (nk + 63) / 64 * 64, nn = np * np;
+    const bool large = nk > 512;
+    d += nterms * nn + 4 * nn + 6 * 64;
+    d += large ? nterms * ln_stride((int)np) : nterms * 2 * (np / 16) * 256;
+    if (emb || mixed) d += nn;
+    if (large && P.p > 0) d += 2 * ln_vchain((int)np, P.p) + (int64_t)ln_ks((int)nk) * np * ln_pp(P.p);
+    ints += large ? 0 : 2 * nterms * np + 128;
+    d += (sizeof(PlanRec) + sizeof(InstDesc) + 2 * sizeof(int) + 7) / 8;
+  }
+  return (size_t)(d * 8 + ints * 4 + 3 * 256);
+}
+
+const char *pfm_version(void) { return "pfm 0.2 (gfx950)"; }
 
 int pfm_create(pfm_ctx **out, int device, size_t budget) {
   if (!out) return PFM_ERR_INVALID;
@@ -381,6 +411,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   // workspace layout
   std::vector<InstDesc> desc(batch);
   std::vector<int> cls_list[4];
+  std::vector<char> may_ln_v(batch, 0);
   int64_t dofs = 0, iofs = 0;
   for (int i = 0; i < batch; ++i) {
     const pfm_problem &P = probs[i];
@@ -398,21 +429,27 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     D.hn = P.n;
     D.n = emb ? 2 * P.n : P.n;
     D.ncol = P.n;
-    // real FP64 full-matrix instances may take the Gauss-Jordan path, whose
-    // blocks are 64 wide; so do all large instances (class 3)
+    // Routes: real FP64 full-matrix instances may take the single-workgroup
+    // Gauss-Jordan path (64-wide blocks); instances above 512 must take the
+    // multi-workgroup one (class 3); action and complex instances above 128
+    // take it when the shifted matrices are dominant and keep the pivoting
+    // LU route otherwise, so both workspaces are laid out for them.
     const bool large = D.n > 512;
-    D.npad = (gj_call || large) ? (D.n + 63) / 64 * 64 : (D.n + 15) / 16 * 16;
+    const bool may_ln = large || (!mixed && !pairs && D.n > kLnMin && (action || emb));
+    may_ln_v[i] = may_ln;
+    D.npad = (gj_call || may_ln) ? (D.n + 63) / 64 * 64 : (D.n + 15) / 16 * 16;
     D.p = P.p;
     D.cls = large ? 3 : (D.npad <= 128 ? 0 : (D.npad <= 256 ? 1 : 2));
     const int64_t np = D.npad, nn = np * np;
     D.fac_off = dofs;  dofs += align_up(nterms * nn, 64);
-    if (large) {
+    if (may_ln) {
       D.ln_off = dofs; dofs += align_up(nterms * ln_stride(D.npad), 64);
       if (action) {
         D.v_off = dofs;
         dofs += align_up(2 * ln_vchain(D.npad, D.p) + (int64_t)ln_ks(D.n) * np * ln_pp(D.p), 64);
       }
-    } else {
+    }
+    if (!large) {
       D.dinv_off = dofs; dofs += align_up(nterms * 2 * (np / 16) * 256, 64);
     }
     D.r_off = dofs;    dofs += align_up(4 * nn, 64);
@@ -478,8 +515,15 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   }
   // 1. norm and plan on the device; the host reads the plans back once (it
   //    needs max s to size the squaring launches and routes each instance)
-  hipLaunchKernelGGL(plan_kernel, dim3(batch), dim3(256), 0, stream, d_desc, d_plan, theta,
-                     action ? 1 : 0, force_plan);
+  {
+    int maxc = 0;
+    for (int i = 0; i < batch; ++i) maxc = std::max(maxc, probs[i].n);
+    const int nb = (batch + 255) / 256;
+    hipLaunchKernelGGL(plan_init_kernel, dim3(nb), dim3(256), 0, stream, d_plan, batch);
+    hipLaunchKernelGGL(norm_kernel, dim3((maxc + 63) / 64, batch), dim3(256), 0, stream, d_desc, d_plan);
+    hipLaunchKernelGGL(plan_finish_kernel, dim3(nb), dim3(256), 0, stream, d_plan, batch, theta,
+                       action ? 1 : 0, force_plan);
+  }
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipMemcpyAsync(h_plan, d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
@@ -515,8 +559,22 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   for (int k = 0; k < nterms; ++k) cmax = std::max(cmax, std::hypot(T.c_re[k], T.c_im[k]));
   std::vector<int> fast_list[3], slow_list[3];
   std::vector<char> is_fast(batch, 0);
+  // the dominance test of the multi-workgroup route (||emb(B)||_1 <=
+  // sqrt(2) ||B||_1 for the real matrix the kernels see)
+  auto ln_dominant = [&](int i) {
+    const double bn = action ? h_plan[i].eta / (double)std::max(1, h_plan[i].s)
+                             : std::ldexp(h_plan[i].eta, -svec[i]);
+    return !(h_plan[i].status & 2) && cmax * bn * (desc[i].emb ? std::sqrt(2.0) : 1.0) <= 0.5;
+  };
+  std::vector<int> ln_list, skip_list;
+  std::vector<char> skip(batch, 0);
   for (int c = 0; c < 3; ++c)
     for (int i : cls_list[c]) {
+      if (may_ln_v[i] && ln_dominant(i)) {
+        ln_list.push_back(i);
+        is_fast[i] = 1;
+        continue;
+      }
       const bool fast = gj_call && (desc[i].npad % kGJ) == 0 && !(h_plan[i].status & 2) &&
                         cmax * std::ldexp(h_plan[i].eta, -svec[i]) <= 0.5;
       (fast ? fast_list : slow_list)[c].push_back(i);
@@ -532,15 +590,9 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     slow_off[c] = (int)lists.size();
     lists.insert(lists.end(), slow_list[c].begin(), slow_list[c].end());
   }
-  // large instances: the multi-workgroup Gauss-Jordan route when the same
-  // dominance test holds for the real matrix the kernels see
-  // (||emb(B)||_1 <= sqrt(2) ||B||_1); otherwise they are not computed
-  std::vector<int> ln_list, skip_list;
-  std::vector<char> skip(batch, 0);
+  // instances above 512 have no other route: not computed if not dominant
   for (int i : cls_list[3]) {
-    const double bn = action ? h_plan[i].eta / (double)std::max(1, h_plan[i].s)
-                             : std::ldexp(h_plan[i].eta, -svec[i]);
-    const bool ok = !(h_plan[i].status & 2) && cmax * bn * (desc[i].emb ? std::sqrt(2.0) : 1.0) <= 0.5;
+    const bool ok = ln_dominant(i);
     (ok ? ln_list : skip_list).push_back(i);
     is_fast[i] = ok;
     skip[i] = !ok;
@@ -680,12 +732,13 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     hipLaunchKernelGGL(ln_load_kernel, dim3(xcd_grid(nslot, t1 * t1)), dim3(256), 0, stream, d_desc, dl,
                        nslot, t1, d_plan, T, wsd, action ? 1 : 0);
     for (int J = 0; J < t1; ++J) {
+      hipLaunchKernelGGL(ln_dinv_kernel, dim3(nslot), dim3(256), 0, stream, d_desc, dl, nslot, T, wsd, J);
       hipLaunchKernelGGL(ln_row_kernel, dim3(xcd_grid(nslot, t1)), dim3(256), 0, stream, d_desc, dl, nslot,
                          t1, T, wsd, J);
       hipLaunchKernelGGL(ln_upd_kernel, dim3(xcd_grid(nslot, t1 * nR)), dim3(256), 0, stream, d_desc, dl,
                          nslot, t1, nR, T, wsd, J);
     }
-    ctx->cur_launches[0] += 1 + 2 * t1;
+    ctx->cur_launches[0] += 1 + 3 * t1;
   }
   prof_mark(ctx, 1, stream);
   if (action) {
@@ -723,7 +776,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
       // then the N steps U <- R U (+ U1) as K-split GEMMs
       const int chunks = (int)(((int64_t)ln_npm * ln_npm / 4 + 255) / 256);
       const int *dl = d_list + ln_off_l;
-      hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nln), dim3(256), 0, stream, d_desc, dl, T, wsd);
+      hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nln), dim3(256), 0, stream, d_desc, dl, T, wsd, d_plan);
       if (lvbt.second)  // level argument 1: B = A / N
         hipLaunchKernelGGL(square_level_f64_kernel<2>, dim3(lvbt.second), dim3(256), 0, stream, d_desc,
                            dt + lvbt.first, lvbt.second, 1, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);
@@ -809,11 +862,11 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
       const int nl = (int)fast_list[c].size();
       if (!nl) continue;
       hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nl), dim3(256), 0, stream, d_desc,
-                         d_list + fast_off[c], T, wsd);
+                         d_list + fast_off[c], T, wsd, d_plan);
     }
     if (nln)
       hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nln), dim3(256), 0, stream, d_desc,
-                         d_list + ln_off_l, T, wsd);
+                         d_list + ln_off_l, T, wsd, d_plan);
     if (lvbt.second)
       hipLaunchKernelGGL(square_level_f64_kernel<2>, dim3(lvbt.second), dim3(256), 0, stream, d_desc,
                          dt + lvbt.first, lvbt.second, 0, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);

@@ -9,6 +9,7 @@ constexpr int kSCap = 1000;     // largest squaring count accepted
 constexpr int kNCap = 1 << 20;  // largest action step count accepted
 constexpr int kSqTile = 64;     // squaring GEMM tile edge
 constexpr int kLargeMax = 16384; // largest real dimension (2n for complex) of a large instance
+constexpr int kLnMin = 128;      // action / complex instances above this may take the multi-workgroup route
 
 // One problem instance as the kernels see it.  Offsets index the context's
 // workspace (doubles for *_off in the double region, ints for *_ioff).

@@ -73,6 +73,17 @@ def lib():
         L.pfm_selftest_mfma.argtypes = [i32, dp]
         L.pfm_profile.argtypes = [vp, i32]
         L.pfm_set_route.argtypes = [vp, i32]
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.pfm_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(Problem)]
+        L.pfm_workspace_bytes.restype = ctypes.c_size_t
+        L.pfm_srv_start.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.c_size_t, i32]
+        L.pfm_srv_stop.argtypes = [vp]
+        L.pfm_srv_submit.argtypes = [vp, ctypes.POINTER(Problem), i32, i32, dbl, i32, i32, u64p]
+        L.pfm_srv_poll.argtypes = [vp, ctypes.c_uint64, vp, dp]
+        L.pfm_srv_drain.argtypes = [vp, i32, u64p, dp, ip]
+        L.pfm_srv_fetch.argtypes = [vp, ctypes.c_uint64, i32, vp, ctypes.c_int64]
+        L.pfm_srv_release.argtypes = [vp, ctypes.c_uint64]
+        L.pfm_srv_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p]
         L.pfm_profile_read.argtypes = [vp, dp, ip, ip]
         _lib = L
     return _lib
@@ -307,3 +318,111 @@ class _Info:
 
     def __getitem__(self, k):
         return self.get()[k]
+
+
+def workspace_bytes(funcs, m, prec, dtype, probs):
+    """Upper bound of the workspace bytes a pfm_eval_batched call would use
+    (host only; 0 for an unsupported batch)."""
+    arr = (Problem * len(probs))(*probs)
+    return lib().pfm_workspace_bytes(_fmask(funcs), m, {"fp64": FP64, "mixed": MIXED}[prec], dtype,
+                                     len(probs), arr)
+
+
+class Server:
+    """Continuous-batching server (pfm_srv_* in pfm.h) on one device.
+
+    submit() queues one request and returns its ticket; the library's
+    scheduler thread admits, batches and runs requests on ``lanes``
+    concurrent streams.  Inputs must stay alive until the request is done
+    (the server keeps a reference); results live in library memory until
+    fetch() or release()."""
+
+    def __init__(self, device=0, lanes=4, budget_bytes=32 << 30, max_batch=64):
+        h = ctypes.c_void_p()
+        rc = lib().pfm_srv_start(ctypes.byref(h), device, lanes, budget_bytes, max_batch)
+        if rc:
+            raise PfmError(rc, "pfm_srv_start failed")
+        self._h = h
+        self._keep = {}
+        self._meta = {}
+
+    def submit(self, A, V=None, func="exp", m=8, tol=1e-12, prec="fp64"):
+        import torch
+        _require_gpu(A)
+        cplx = A.is_complex() or (V is not None and V.is_complex())
+        if cplx:
+            A = A if A.is_complex() else A.to(torch.complex128)
+            if V is not None and not V.is_complex():
+                V = V.to(torch.complex128)
+        n = A.shape[0]
+        p = 0 if V is None else V.shape[1]
+        pr = Problem(n, p, A.stride(0), 0 if V is None else V.stride(0), 0, A.data_ptr(),
+                     None if V is None else V.data_ptr(), None, None)
+        t = ctypes.c_uint64()
+        fm = _fmask((func,) if isinstance(func, str) else func)
+        rc = lib().pfm_srv_submit(self._h, ctypes.byref(pr), fm, m, tol, {"fp64": FP64, "mixed": MIXED}[prec],
+                                  C128 if cplx else R64, ctypes.byref(t))
+        if rc:
+            raise PfmError(rc, "pfm_srv_submit rejected the request")
+        self._keep[t.value] = (A, V)
+        self._meta[t.value] = (n, p, cplx, fm)
+        return t.value
+
+    def poll(self, ticket):
+        """(state, info, latency_s): state 0 done, 1 pending."""
+        inf = np.zeros(1, dtype=INFO_DTYPE)
+        lat = ctypes.c_double()
+        rc = lib().pfm_srv_poll(self._h, ticket, inf.ctypes.data, ctypes.byref(lat))
+        if rc < 0:
+            raise PfmError(rc, "pfm_srv_poll")
+        return rc, (inf[0] if rc == 0 else None), (lat.value if rc == 0 else None)
+
+    def drain(self, max_items=4096):
+        """Completed requests not reported before: list of (ticket, latency_s, status)."""
+        tk = (ctypes.c_uint64 * max_items)()
+        lat = (ctypes.c_double * max_items)()
+        st = (ctypes.c_int * max_items)()
+        k = lib().pfm_srv_drain(self._h, max_items, tk, lat, st)
+        if k < 0:
+            raise PfmError(k, "pfm_srv_drain")
+        out = [(tk[i], lat[i], st[i]) for i in range(k)]
+        for t, _, _ in out:
+            self._keep.pop(t, None)
+        return out
+
+    def fetch(self, ticket, func="exp"):
+        """The result as a new CUDA tensor (the request keeps it until release)."""
+        import torch
+        n, p, cplx, _ = self._meta[ticket]
+        out = torch.empty((n, p if p else n), dtype=torch.complex128 if cplx else torch.float64, device="cuda")
+        rc = lib().pfm_srv_fetch(self._h, ticket, {"exp": EXP, "phi1": PHI1}[func], out.data_ptr(), out.stride(0))
+        if rc:
+            raise PfmError(rc, "pfm_srv_fetch")
+        return out
+
+    def release(self, ticket):
+        rc = lib().pfm_srv_release(self._h, ticket)
+        if rc:
+            raise PfmError(rc, "pfm_srv_release")
+        self._keep.pop(ticket, None)
+        self._meta.pop(ticket, None)
+
+    def stats(self):
+        v = [ctypes.c_uint64() for _ in range(5)]
+        rc = lib().pfm_srv_stats(self._h, *[ctypes.byref(x) for x in v])
+        keys = ("submitted", "done", "batches", "resident_bytes", "peak_resident_bytes")
+        d = {k: x.value for k, x in zip(keys, v)}
+        d["error"] = rc
+        return d
+
+    def stop(self):
+        if self._h:
+            lib().pfm_srv_stop(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

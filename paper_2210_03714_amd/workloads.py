@@ -136,3 +136,50 @@ def request_inputs(req):
     if req["mode"] == "action":
         V = vectors(n, req["p"], req["seed"] + 1, complex_=np.iscomplexobj(A))
     return A, V
+
+
+def serving_pool(seed, per_kind=64, n_lo=16, n_hi=1024):
+    """Matrices the serving stream draws from: per matrix type, ``per_kind``
+    matrices with n log-uniform in [n_lo, n_hi] (Gaussian: ||A||_1 uniform in
+    [0.5, 8]; iH; -L with tau = 1), and per type one n_hi x 32 block of
+    right-hand sides (complex for iH)."""
+    rng = np.random.default_rng(seed)
+    pool, vpool = {}, {}
+    for kind in ("gauss", "ih", "lap"):
+        mats = []
+        for _ in range(per_kind):
+            n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+            s = int(rng.integers(2**62))
+            if kind == "gauss":
+                mats.append(gaussian(n, float(rng.uniform(0.5, 8.0)), s))
+            elif kind == "ih":
+                mats.append(ih_matrix(n, s))
+            else:
+                mats.append(neg_laplacian(n, 1.0))
+        pool[kind] = mats
+        vpool[kind] = vectors(n_hi, 32, int(rng.integers(2**62)), complex_=(kind == "ih"))
+    return pool, vpool
+
+
+def serving_stream(rate, duration, seed, pool):
+    """Open-loop Poisson arrivals at ``rate`` per second for ``duration``
+    seconds over a ``serving_pool``: each request draws a matrix type, a pool
+    matrix of that type, a function (exp or phi1), a mode (full matrix, or
+    action on the first p in [1, 32] columns of the type's block) and a
+    tolerance (1e-8 or 1e-12), all uniformly."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    kinds = ("gauss", "ih", "lap")
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        kind = kinds[rng.integers(3)]
+        idx = int(rng.integers(len(pool[kind])))
+        reqs.append({"t": t, "kind": kind, "idx": idx, "n": pool[kind][idx].shape[0],
+                     "func": ("exp", "phi1")[rng.integers(2)],
+                     "mode": ("full", "action")[rng.integers(2)],
+                     "p": int(rng.integers(1, 33)),
+                     "tol": (1e-8, 1e-12)[rng.integers(2)]})
+    return reqs

@@ -83,3 +83,18 @@ def test_invalid_arguments_rejected_on_host(L):
     n = ctypes.c_int()
     assert L.pfm_coeffs(3, 8, ctypes.byref(n), None, None, None, None, None, None, None) == pfm.ERR_INVALID
     assert L.pfm_coeffs(1, 7, ctypes.byref(n), None, None, None, None, None, None, None) == pfm.ERR_UNSUPPORTED
+
+
+def test_workspace_bytes_host(L):
+    """pfm_workspace_bytes is host-only: grows with n, covers the inverses
+    of every shift, and is 0 for unsupported combinations."""
+    P = pfm.Problem
+    def ws(n, p=0, m=8, dtype=pfm.R64, prec="fp64", funcs=("exp",)):
+        return pfm.workspace_bytes(funcs, m, prec, dtype, [P(n, p, n, max(p, 0), n, None, None, None, None)])
+    assert 0 < ws(64) < ws(256) < ws(1024)
+    assert ws(256) >= 8 * 256 * 256 * 8
+    assert ws(300, dtype=pfm.C128) >= ws(600)
+    assert ws(64, m=3) == 0
+    assert ws(600, prec="mixed") == 0          # large instances: FP64 only
+    assert ws(64, p=4, prec="mixed") == 0      # mixed: full matrix only
+    assert ws(600, p=65) == 0                   # large action: p <= 64

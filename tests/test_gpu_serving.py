@@ -1,0 +1,138 @@
+"""GPU tests of the serving runtime (pfm_srv_* through pfm.Server):
+continuous batching gives each request the same result as evaluating it
+alone, results meet the oracle, HBM-budget admission holds, and bad
+requests are rejected at submit."""
+
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import method as me
+from paper_2210_03714_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    from paper_2210_03714_amd import pfm
+    pfm.lib()
+    return torch, torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _alone(pfm, torch, A, V, func, tol):
+    if V is None:
+        res, info = pfm.expm([A], (func,), m=8, tol=tol)
+    else:
+        res, info = pfm.action([A], [V], (func,), m=8, tol=tol)
+    torch.cuda.synchronize()
+    return res[func][0]
+
+
+def test_mix_equals_alone_and_oracle(torch_dev):
+    """A Poisson mix of 48 requests (every type, mode, function and
+    tolerance; n from 16 to 700, large instances included) served with 3
+    lanes: every result equals the same request evaluated alone, bit for
+    bit, and a sample meets the oracle."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm, serving
+    pool, vpool = wl.serving_pool(wl.SEED_BASE + 500, per_kind=8, n_lo=16, n_hi=700)
+    reqs = wl.serving_stream(400.0, 0.12, wl.SEED_BASE + 501, pool)
+    assert len(reqs) >= 30
+    dpool, dvpool = serving.to_device(pool, vpool)
+    srv = pfm.Server(0, lanes=3, budget_bytes=8 << 30, max_batch=16)
+    _say("case serving mix: %d requests" % len(reqs))
+    res = serving.run_stream(srv, reqs, dpool, dvpool, keep=range(len(reqs)))
+    st = srv.stats()
+    _say("  stats", st, "p99 ms %.2f" % (np.percentile(res["latency"], 99) * 1e3))
+    assert st["error"] == 0 and st["done"] == len(reqs)
+    assert (res["status"] == 0).all()
+    rng = np.random.default_rng(0)
+    oracle_idx = set(rng.choice(len(reqs), 8, replace=False).tolist())
+    for i, r in enumerate(reqs):
+        A = dpool[r["kind"]][r["idx"]]
+        V = dvpool[r["kind"]][: r["n"], : r["p"]] if r["mode"] == "action" else None
+        got = srv.fetch(res["tickets"][i], r["func"])
+        alone = _alone(pfm, torch, A, V if V is None else V.contiguous(), r["func"], r["tol"])
+        assert torch.equal(got, alone), (i, r)
+        if i in oracle_idx:
+            An = pool[r["kind"]][r["idx"]]
+            if r["mode"] == "full":
+                ref = me.expm_full(An, (r["func"],), 8, r["tol"])
+            else:
+                Vn = vpool[r["kind"]][: r["n"], : r["p"]]
+                ref = me.action(An, Vn, (r["func"],), 8, r["tol"])
+            err = me.rel_fro(got.cpu().numpy(), ref[r["func"]])
+            _say("  oracle %s n=%d %s %s tol %g: %.2e" % (r["kind"], r["n"], r["mode"], r["func"], r["tol"], err))
+            assert err <= 1e-12, (i, r, err)
+        srv.release(res["tickets"][i])
+    srv.stop()
+
+
+def test_budget_admission(torch_dev):
+    """Resident-budget admission: with room for about 11 requests' resident
+    data and results that are not released, the rest wait; releasing
+    results admits them.  Resident bytes never exceed the resident share."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    n, total = 200, 28
+    mats = [torch.from_numpy(wl.gaussian(n, 3.0, wl.SEED_BASE + 510 + i)).to(dev) for i in range(total)]
+    per_ws = pfm.workspace_bytes(("exp",), 8, "fp64", pfm.R64,
+                                 [pfm.Problem(n, 0, n, 0, n, None, None, None, None)])
+    budget = int(2 * per_ws * 1.05)  # one lane: lane share == resident share
+    # admission needs A's copy and the result (2 n^2 doubles); the copy is
+    # freed at completion and the result stays until released, so without
+    # releases the k-th admission needs (k - 1) n^2 + 2 n^2 doubles
+    mat = n * n * 8
+    fits = (budget // 2 - 2 * mat) // mat + 1
+    assert 4 <= fits < total
+    srv = pfm.Server(0, lanes=1, budget_bytes=budget, max_batch=64)
+    tks = [srv.submit(a, None, "exp", 8, 1e-12) for a in mats]
+
+    def wait_done(k):
+        t0 = time.time()
+        while srv.stats()["done"] < k:
+            assert time.time() - t0 < 60, srv.stats()
+            time.sleep(0.005)
+
+    wait_done(fits)
+    time.sleep(0.3)
+    st = srv.stats()
+    _say("  budget stats", st, "budget", budget, "fits", fits)
+    assert st["done"] == fits  # the rest wait for resident memory
+    for i in range(fits):      # keep results correct, then release them
+        assert torch.equal(srv.fetch(tks[i]), _alone(pfm, torch, mats[i], None, "exp", 1e-12))
+        srv.release(tks[i])
+    wait_done(total)
+    st = srv.stats()
+    assert st["peak_resident_bytes"] <= budget // 2 and st["error"] == 0
+    for i in range(fits, total):
+        assert srv.poll(tks[i])[0] == 0
+        assert torch.equal(srv.fetch(tks[i]), _alone(pfm, torch, mats[i], None, "exp", 1e-12))
+        srv.release(tks[i])
+    srv.stop()
+
+
+def test_rejections(torch_dev):
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    srv = pfm.Server(0, lanes=1, budget_bytes=64 << 20, max_batch=4)
+    big = torch.zeros((2000, 2000), dtype=torch.float64, device=dev)
+    with pytest.raises(pfm.PfmError):  # cannot fit the budget
+        srv.submit(big, None, "exp", 8, 1e-12)
+    a = torch.eye(8, dtype=torch.float64, device=dev)
+    with pytest.raises(pfm.PfmError):  # tol outside (0, 1)
+        srv.submit(a, None, "exp", 8, 2.0)
+    with pytest.raises(pfm.PfmError):  # no coefficient set for m = 3
+        srv.submit(a, None, "exp", 3, 1e-12)
+    with pytest.raises(pfm.PfmError):
+        srv.poll(123456)
+    srv.stop()
