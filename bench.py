@@ -94,6 +94,36 @@ def cpu_baseline(A, seconds):
                       "numpy/scipy LAPACK with %d BLAS threads, %.1f s" % (k, threads, dt)}
 
 
+def serving_leg(rate, seconds):
+    """The serving stream: open-loop Poisson arrivals at ``rate`` per second
+    for ``seconds``; each request draws n log-uniform in [16, 1024] (from a
+    pool of 48 matrices per type), exp or phi1, full matrix or action on 1-32
+    vectors, tol 1e-8 or 1e-12, and a Gaussian (||A||_1 in [0.5, 8]), iH or
+    -L matrix; m = 8, FP64.  Latency is from the scheduled arrival to the
+    host seeing the request's batch complete."""
+    from paper_2210_03714_amd import pfm, serving
+    from paper_2210_03714_amd import workloads as wl
+    pool, vpool = wl.serving_pool(wl.SEED_BASE + 5, per_kind=48)
+    dpool, dvpool = serving.to_device(pool, vpool)
+    lanes, max_batch = 4, 256
+    srv = pfm.Server(0, lanes=lanes, budget_bytes=96 << 30, max_batch=max_batch)
+    warm = wl.serving_stream(200.0, 0.5, wl.SEED_BASE + 7, pool)
+    serving.run_stream(srv, warm, dpool, dvpool)
+    reqs = wl.serving_stream(rate, seconds, wl.SEED_BASE + 6, pool)
+    out = serving.run_stream(srv, reqs, dpool, dvpool,
+                             progress=lambda s: print("serving: " + s, file=sys.stderr, flush=True))
+    st = srv.stats()
+    srv.stop()
+    summ = serving.summarize(out, reqs)
+    summ.update({"offered_req_s": rate, "duration_s": seconds, "lanes": lanes, "max_batch": max_batch,
+                 "batches": st["batches"], "peak_resident_gb": round(st["peak_resident_bytes"] / 1e9, 3),
+                 "workload": "Poisson %g req/s for %g s; n log-uniform [16,1024]; exp|phi1; full|action "
+                             "(p 1-32); tol 1e-8|1e-12; Gaussian|iH|-L; m=8 FP64" % (rate, seconds)})
+    for k in ("p50_ms", "p99_ms", "max_ms", "throughput_req_s", "max_submit_lag_ms", "wall_s"):
+        summ[k] = round(summ[k], 3)
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +134,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="duration of the serving stream (0 skips the serving leg)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -230,6 +263,8 @@ def main():
     # mixed-precision leg: the same batch at tol 1e-10, against the FP64 path
     # on the same GPU at the same tolerance
     if args.no_mixed:
+        if args.serve_seconds > 0:
+            res["serving"] = serving_leg(args.serve_rate, args.serve_seconds)
         if not args.no_cpu_baseline:
             res["cpu_baseline"] = cpu_baseline(A, args.cpu_seconds)
         print(json.dumps(res))
@@ -264,6 +299,8 @@ def main():
                              "ms_per_step": round(legs["mixed"], 4),
                              "fp64_same_tol_value": round(batch / (legs["fp64"] / 1e3), 2),
                              "max_rel_err_vs_fp64_gpu": rel}
+    if args.serve_seconds > 0:
+        res["serving"] = serving_leg(args.serve_rate, args.serve_seconds)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(A, args.cpu_seconds)
     print(json.dumps(res))

@@ -207,7 +207,8 @@ size_t pfm_workspace_bytes(int f, int m, int prec, int dtype, int batch, const p
  * request when its resident bytes (copies of A and V, its outputs) fit in the
  * resident share of the HBM budget, copies A (and V) into library-owned
  * device buffers, and groups admitted requests that can share one
- * pfm_eval_batched call (same f, m, tol, prec, dtype and mode) into batches
+ * pfm_eval_batched call (same f, m, tol, prec, dtype, mode and size bucket:
+ * real dimension <= 128, <= 512 or larger, counting 2n for complex) into batches
  * whose workspace fits one lane's share of the budget.  Each lane is a
  * stream with its own workspace; up to `lanes` batches run concurrently,
  * and requests arriving meanwhile are admitted and batched as lanes free up.

@@ -64,7 +64,7 @@ __device__ __forceinline__ void load_shifted(const InstDesc &D, double c, int s_
 template <int NPMAX>
 __global__ void __launch_bounds__(256, 2)
 gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nlist,
-              PlanRec *__restrict__ plan, Terms T, double *__restrict__ wsd, int action) {
+              PlanRec *__restrict__ plan, Terms T, double *__restrict__ wsd, int action, int route_val) {
   constexpr int LDD = kGJ + 1;
   __shared__ double Dl[kGJ * LDD];      // D, then D^{-1} (row-major, padded)
   __shared__ double Cl[kGJ * LDD];      // staging for the row-block product
@@ -75,13 +75,13 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   const int ii = ilist[slot];
   const InstDesc D = inst[ii];
   const int np = D.npad;
-  if (np > NPMAX || (np % kGJ) || D.n > np || D.n < 1 || D.emb) return;  // never sent
+  if (np > NPMAX || (np % kGJ) || D.n > np || D.n < 1) return;  // never sent
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int i16 = lane & 15, g = lane >> 4;
   const int ar = arow(i16);
   double *W = wsd + D.fac_off + (int64_t)k * np * np;
   const int nJ = np / kGJ;
-  if (k == 0 && t == 0) plan[ii].route = 1;
+  if (route_val >= 0 && k == 0 && t == 0) plan[ii].route = route_val;
 
   load_shifted(D, T.c_re[k], plan[ii].s, action, W, Cl);
 

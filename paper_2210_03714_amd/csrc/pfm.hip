@@ -597,6 +597,13 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     is_fast[i] = ok;
     skip[i] = !ok;
   }
+  // multi-workgroup-route instances, ordered by size class: those with
+  // npad <= 512 are inverted by the single-workgroup Gauss-Jordan kernel of
+  // their class, the rest block step by block step
+  std::stable_sort(ln_list.begin(), ln_list.end(), [&](int a, int b) { return desc[a].cls < desc[b].cls; });
+  int ln_cls_off[5] = {0, 0, 0, 0, 0};
+  for (int i : ln_list) ln_cls_off[desc[i].cls + 1]++;
+  for (int c = 0; c < 4; ++c) ln_cls_off[c + 1] += ln_cls_off[c];
   const int ln_off_l = (int)lists.size();
   lists.insert(lists.end(), ln_list.begin(), ln_list.end());
   const int skip_off_l = (int)lists.size();
@@ -682,10 +689,11 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   if (nln)
     hipLaunchKernelGGL(mark_status_kernel, dim3((nln + 255) / 256), dim3(256), 0, stream, d_plan,
                        d_list + ln_off_l, nln, 0, 2);
-  int ln_npm = 0, ln_nmax = 0;
+  int ln_npm = 0, ln_nmax = 0, ln_big_npm = 0;
   for (int i : ln_list) {
     ln_npm = std::max(ln_npm, desc[i].npad);
     ln_nmax = std::max(ln_nmax, action ? h_plan[i].s : 0);
+    if (desc[i].cls == 3) ln_big_npm = std::max(ln_big_npm, desc[i].npad);
   }
 
   for (int p = 0; p < kNumPhases; ++p) ctx->cur_launches[p] = 0;
@@ -697,9 +705,9 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     if (!nl) continue;
     const int *dl = d_list + fast_off[c];
     const dim3 gg(xcd_grid(nl, nterms));
-    if (c == 0) hipLaunchKernelGGL(gj_inv_kernel<128>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0);
-    if (c == 1) hipLaunchKernelGGL(gj_inv_kernel<256>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0);
-    if (c == 2) hipLaunchKernelGGL(gj_inv_kernel<512>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0);
+    if (c == 0) hipLaunchKernelGGL(gj_inv_kernel<128>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0, 1);
+    if (c == 1) hipLaunchKernelGGL(gj_inv_kernel<256>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0, 1);
+    if (c == 2) hipLaunchKernelGGL(gj_inv_kernel<512>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0, 1);
     ctx->cur_launches[0]++;
   }
   for (int c = 0; c < 3; ++c) {
@@ -723,12 +731,26 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
 #undef PFM_LU
     ctx->cur_launches[0]++;
   }
-  if (nln) {
-    // large instances: W_k = I - c_k B, then one (row, update) launch pair
-    // per 64-column block step, every (instance, shift) in each launch
-    const int nslot = nln * nterms;
-    const int t1 = ln_npm / kLB, nR = (ln_npm + kLRows - 1) / kLRows;
-    const int *dl = d_list + ln_off_l;
+  for (int c = 0; c < 3; ++c) {
+    // multi-workgroup-route instances of a small class: one launch
+    const int nl = ln_cls_off[c + 1] - ln_cls_off[c];
+    if (!nl) continue;
+    const int *dl = d_list + ln_off_l + ln_cls_off[c];
+    const dim3 gg(xcd_grid(nl, nterms));
+    const int am = action ? 1 : 0;
+    if (c == 0) hipLaunchKernelGGL(gj_inv_kernel<128>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, am, -1);
+    if (c == 1) hipLaunchKernelGGL(gj_inv_kernel<256>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, am, -1);
+    if (c == 2) hipLaunchKernelGGL(gj_inv_kernel<512>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, am, -1);
+    ctx->cur_launches[0]++;
+  }
+  if (ln_cls_off[4] > ln_cls_off[3]) {
+    // class 3: W_k = I - c_k B, then one (pivot inverse, row, update)
+    // launch triple per 64-column block step, every (instance, shift) in
+    // each launch
+    const int nbig = ln_cls_off[4] - ln_cls_off[3];
+    const int nslot = nbig * nterms;
+    const int t1 = ln_big_npm / kLB, nR = (ln_big_npm + kLRows - 1) / kLRows;
+    const int *dl = d_list + ln_off_l + ln_cls_off[3];
     hipLaunchKernelGGL(ln_load_kernel, dim3(xcd_grid(nslot, t1 * t1)), dim3(256), 0, stream, d_desc, dl,
                        nslot, t1, d_plan, T, wsd, action ? 1 : 0);
     for (int J = 0; J < t1; ++J) {

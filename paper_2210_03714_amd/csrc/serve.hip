@@ -11,10 +11,10 @@
 //      (A, V, outputs) fit the resident share of the budget, allocating the
 //      buffers from a device pool;
 //   3. for every idle lane, takes the group of the oldest admitted request
-//      (requests of one group share f, m, tol, prec, dtype and mode), fills a
-//      batch in arrival order up to max_batch requests and the lane's
-//      workspace share, copies the inputs into the resident buffers on the
-//      lane's stream and calls pfm_eval_batched on the lane.
+//      (requests of one group share f, m, tol, prec, dtype, mode and size
+//      bucket), fills a batch in arrival order up to max_batch requests and
+//      the lane's workspace share, copies the inputs into the resident
+//      buffers on the lane's stream and calls pfm_eval_batched on the lane.
 // Submitting only appends to the pending queue under the lock; the
 // scheduler drops the lock while it launches, so submissions never wait on
 // the GPU.
@@ -109,7 +109,6 @@ struct Req {
   double t_submit = 0.0, t_done = 0.0;
   pfm_info info{};
   bool reported = false;
-  uint64_t key = 0;                   // batching group
 };
 
 struct Lane {
@@ -123,16 +122,17 @@ struct Lane {
   std::vector<uint64_t> reqs;
 };
 
-uint64_t group_key(const Req &r) {
-  uint64_t tb;
-  std::memcpy(&tb, &r.tol, 8);
-  return (tb * 1000003ull) ^ ((uint64_t)r.f << 1) ^ ((uint64_t)r.m << 8) ^ ((uint64_t)r.prec << 16) ^
-         ((uint64_t)r.dtype << 20) ^ ((uint64_t)(r.prob.p > 0) << 24);
+// size bucket of the real dimension the kernels see (2n for complex): a
+// batch runs as long as its largest member, so small requests are never
+// batched with large ones
+int size_bucket(const Req &r) {
+  const int nk = r.dtype == PFM_C128 ? 2 * r.prob.n : r.prob.n;
+  return nk <= 128 ? 0 : (nk <= 512 ? 1 : 2);
 }
 
 bool same_group(const Req &a, const Req &b) {
   return a.f == b.f && a.m == b.m && a.tol == b.tol && a.prec == b.prec && a.dtype == b.dtype &&
-         (a.prob.p > 0) == (b.prob.p > 0);
+         (a.prob.p > 0) == (b.prob.p > 0) && size_bucket(a) == size_bucket(b);
 }
 
 }  // namespace
@@ -389,7 +389,6 @@ int pfm_srv_submit(pfm_server *S, const pfm_problem *pr, int f, int m, double to
   if (r.ws == 0) return PFM_ERR_UNSUPPORTED;
   const size_t need = r.a_bytes + r.v_bytes + 2 * r.o_bytes;
   if (r.ws > S->lane_budget || need > S->res_budget) return PFM_ERR_BUDGET;
-  r.key = group_key(r);
   r.t_submit = now_s();
   {
     std::lock_guard<std::mutex> g(S->mu);

@@ -337,7 +337,7 @@ class Server:
     (the server keeps a reference); results live in library memory until
     fetch() or release()."""
 
-    def __init__(self, device=0, lanes=4, budget_bytes=32 << 30, max_batch=64):
+    def __init__(self, device=0, lanes=4, budget_bytes=32 << 30, max_batch=256):
         h = ctypes.c_void_p()
         rc = lib().pfm_srv_start(ctypes.byref(h), device, lanes, budget_bytes, max_batch)
         if rc:
