@@ -194,6 +194,41 @@ int pfm_set_route(pfm_ctx *ctx, int route);
  * timed calls (may be NULL).  Waits for the last timed call to finish. */
 int pfm_profile_read(pfm_ctx *ctx, double *ms, int *launches, int *calls);
 
+/* Launch-sequence reuse.  After the plan read-back, the rest of a call is a
+ * fixed sequence of kernel launches determined by the descriptors, plans and
+ * task lists.  With graphs enabled (the default), a call whose sequence
+ * repeats the previous call's exactly (same pointers, sizes, plans, routes,
+ * function, tolerance and stream) has it captured as a hipGraph on the
+ * second occurrence and replayed from the third on; a new sequence runs
+ * eagerly.  Never on the null stream, and not while pfm_profile is on.
+ * The graph holds no memset nodes.  Takes effect on the next call. */
+int pfm_set_graphs(pfm_ctx *ctx, int enable);
+
+/* Graph captures and replays since the context was created. */
+int pfm_graph_stats(pfm_ctx *ctx, int *captures, int *replays);
+
+/* Autotuner.  Runs the batch (same arguments as pfm_eval_batched, outputs
+ * written) under each route policy that can make a difference for it --
+ * real full matrices: single-workgroup Gauss-Jordan inverses vs the pivoting
+ * LU route; action or complex: the multi-workgroup route for sizes above
+ * 128 vs only above 512 -- timing `reps` calls of each with hipEvents on
+ * `stream` after one warm-up call, and keeps the fastest for the batch's key
+ * (mode, complex, precision, size bucket of the largest instance, batch-size
+ * bucket).  Later calls with the same key use it (an explicit
+ * PFM_ROUTE_LU still wins).  Synchronises the stream.  *policy and *ms (may
+ * be NULL) receive the choice (0..3) and its time per call. */
+int pfm_tune(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype, int batch, const pfm_problem *probs,
+             int reps, pfm_stream_t stream, int *policy, double *ms);
+
+/* The tuned table as text, one "key policy" line per entry, into buf
+ * (truncated to size, NUL-terminated; buf may be NULL).  Returns the bytes
+ * needed including the NUL. */
+int pfm_tune_export(const pfm_ctx *ctx, char *buf, size_t size);
+
+/* Replace the tuned table with one produced by pfm_tune_export.  Returns
+ * PFM_ERR_INVALID (table unchanged) for unreadable text. */
+int pfm_tune_import(pfm_ctx *ctx, const char *text);
+
 /* Upper bound of the workspace bytes pfm_eval_batched would allocate for
  * this batch (host only; probs may hold NULL data pointers).  Returns 0 for
  * an invalid or unsupported batch. */

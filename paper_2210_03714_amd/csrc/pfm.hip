@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -51,8 +52,20 @@ struct pfm_ctx {
   void *tasks = nullptr;
   size_t tasks_bytes = 0;
   // Gauss-Jordan route for diagonally dominant shifted matrices
-  // (pfm_set_route(PFM_ROUTE_LU) disables it)
+  // (pfm_set_route(PFM_ROUTE_LU) disables it), and the size above which
+  // action / complex instances may take the multi-workgroup route
   int gj = 1;
+  int ln_min = kLnMin;
+  // autotuned policies per batch key (pfm_tune); force_policy >= 0 while
+  // tuning
+  std::map<uint64_t, int> tuned;
+  int force_policy = -1;
+  // hipGraph reuse of repeated launch sequences (pfm_set_graphs)
+  bool graphs = true;
+  uint64_t gsig = 0, gseen = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_captures = 0, graph_replays = 0;
   // optional phase timing (hipEvents on the caller's stream)
   bool prof = false;
   bool prof_pending = false;
@@ -148,6 +161,25 @@ int prof_harvest(pfm_ctx *ctx) {
   return PFM_OK;
 }
 
+// Route policies the autotuner chooses between.
+struct Policy {
+  int gj;      // single-workgroup Gauss-Jordan route for dominant real full matrices
+  int ln_min;  // action / complex instances above this size may take the multi-workgroup route
+};
+constexpr Policy kPolicies[] = {{1, kLnMin}, {0, kLnMin}, {1, 512}, {0, 512}};
+constexpr int kNumPolicies = 4;
+
+// Tuning key of a batch: mode, complex, precision, size bucket of its
+// largest real dimension (2n for complex), batch-size bucket.
+uint64_t batch_key(bool action, bool emb, bool mixed, int batch, const pfm_problem *probs) {
+  int nmax = 0;
+  for (int i = 0; i < batch; ++i) nmax = std::max(nmax, emb ? 2 * probs[i].n : probs[i].n);
+  const int sb = nmax <= 64 ? 0 : nmax <= 128 ? 1 : nmax <= 256 ? 2 : nmax <= 512 ? 3 : 4;
+  const int bb = batch <= 1 ? 0 : batch <= 7 ? 1 : batch <= 63 ? 2 : 3;
+  return (uint64_t)action | ((uint64_t)emb << 1) | ((uint64_t)mixed << 2) | ((uint64_t)sb << 4) |
+         ((uint64_t)bb << 8);
+}
+
 inline void prof_mark(pfm_ctx *ctx, int idx, hipStream_t stream) {
   if (ctx->prof) (void)hipEventRecord(ctx->pev[idx], stream);
 }
@@ -161,6 +193,7 @@ int pfm_set_route(pfm_ctx *ctx, int route) {
   if (route != PFM_ROUTE_AUTO && route != PFM_ROUTE_LU)
     return set_err(ctx, PFM_ERR_INVALID, "pfm_set_route: unknown route %d", route);
   ctx->gj = route == PFM_ROUTE_AUTO;
+  ctx->ln_min = route == PFM_ROUTE_AUTO ? kLnMin : 512;
   return PFM_OK;
 }
 
@@ -251,6 +284,8 @@ int pfm_destroy(pfm_ctx *ctx) {
     (void)hipEventSynchronize(ctx->pin_ev);
     (void)hipEventDestroy(ctx->pin_ev);
   }
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->tasks) (void)hipFree(ctx->tasks);
   if (ctx->pin) (void)hipHostFree(ctx->pin);
@@ -407,7 +442,20 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   }
   const int nterms = T.nterms;
 
-  const bool gj_call = ctx->gj && !action && !emb && !mixed;
+  // route policy: the context's, unless a tuned one exists for this batch
+  int pol_gj = ctx->gj, pol_ln = ctx->ln_min;
+  {
+    const int pidx = ctx->force_policy >= 0 ? ctx->force_policy
+                                            : [&] {
+                                                auto it = ctx->tuned.find(batch_key(action, emb, mixed, batch, probs));
+                                                return it == ctx->tuned.end() ? -1 : it->second;
+                                              }();
+    if (pidx >= 0 && ctx->gj) {  // an explicit PFM_ROUTE_LU stays authoritative
+      pol_gj = kPolicies[pidx].gj;
+      pol_ln = kPolicies[pidx].ln_min;
+    }
+  }
+  const bool gj_call = pol_gj && !action && !emb && !mixed;
   // workspace layout
   std::vector<InstDesc> desc(batch);
   std::vector<int> cls_list[4];
@@ -435,7 +483,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     // take it when the shifted matrices are dominant and keep the pivoting
     // LU route otherwise, so both workspaces are laid out for them.
     const bool large = D.n > 512;
-    const bool may_ln = large || (!mixed && !pairs && D.n > kLnMin && (action || emb));
+    const bool may_ln = large || (!mixed && !pairs && D.n > pol_ln && (action || emb));
     may_ln_v[i] = may_ln;
     D.npad = (gj_call || may_ln) ? (D.n + 63) / 64 * 64 : (D.n + 15) / 16 * 16;
     D.p = P.p;
@@ -682,13 +730,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     ctx->pin_pending = true;
   }
   const SqTask *dt = (const SqTask *)ctx->tasks;
-  if (!skip_list.empty())
-    hipLaunchKernelGGL(mark_status_kernel, dim3(((int)skip_list.size() + 255) / 256), dim3(256), 0, stream,
-                       d_plan, d_list + skip_off_l, (int)skip_list.size(), PFM_NOT_COMPUTED, -1);
   const int nln = (int)ln_list.size();
-  if (nln)
-    hipLaunchKernelGGL(mark_status_kernel, dim3((nln + 255) / 256), dim3(256), 0, stream, d_plan,
-                       d_list + ln_off_l, nln, 0, 2);
   int ln_npm = 0, ln_nmax = 0, ln_big_npm = 0;
   for (int i : ln_list) {
     ln_npm = std::max(ln_npm, desc[i].npad);
@@ -696,6 +738,16 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     if (desc[i].cls == 3) ln_big_npm = std::max(ln_big_npm, desc[i].npad);
   }
 
+  // Everything from here on depends only on what the host has decided (the
+  // descriptors, plans, lists and task lists); a call that repeats all of it
+  // replays a captured graph of this sequence.
+  auto enqueue = [&]() -> int {
+  if (!skip_list.empty())
+    hipLaunchKernelGGL(mark_status_kernel, dim3(((int)skip_list.size() + 255) / 256), dim3(256), 0, stream,
+                       d_plan, d_list + skip_off_l, (int)skip_list.size(), PFM_NOT_COMPUTED, -1);
+  if (nln)
+    hipLaunchKernelGGL(mark_status_kernel, dim3((nln + 255) / 256), dim3(256), 0, stream, d_plan,
+                       d_list + ln_off_l, nln, 0, 2);
   for (int p = 0; p < kNumPhases; ++p) ctx->cur_launches[p] = 0;
   prof_mark(ctx, 0, stream);
   // 2. shifted factorisations: Gauss-Jordan inverses (fast instances) and
@@ -941,6 +993,161 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_plan,
                        (InfoRec *)info, batch, ee->order, theta);
   HIP_TRY(ctx, hipGetLastError());
+  return PFM_OK;
+  };
+
+  // hipGraph reuse: eager the first time a launch sequence is seen; captured
+  // and instantiated when the same sequence comes a second time in a row;
+  // replayed from then on.  Not on the null stream (it cannot be captured)
+  // or while phase timing is on.
+  if (!ctx->graphs || ctx->prof || stream == nullptr) return enqueue();
+  uint64_t sig = 1469598103934665603ull;
+  auto mix = [&](const void *p, size_t nbytes) {  // 64-bit words, then the tail bytes
+    const unsigned char *b = (const unsigned char *)p;
+    size_t q = 0;
+    for (; q + 8 <= nbytes; q += 8) {
+      uint64_t w;
+      memcpy(&w, b + q, 8);
+      sig = (sig ^ w) * 1099511628211ull;
+      sig ^= sig >> 29;
+    }
+    for (; q < nbytes; ++q) sig = (sig ^ b[q]) * 1099511628211ull;
+  };
+  const void *ptrs[6] = {ctx->ws, ctx->tasks, info, stream, d_desc, d_list};
+  const int64_t ints[10] = {f, m, prec, dtype, batch, force_plan, pol_gj, smax, ln_nmax, (int64_t)lists.size()};
+  const double dbls[5] = {tol, theta, a1e, a1p, T.a0e};
+  mix(ptrs, sizeof ptrs);
+  mix(ints, sizeof ints);
+  mix(dbls, sizeof dbls);
+  mix(&T, sizeof T);
+  mix(desc.data(), desc.size() * sizeof(InstDesc));
+  mix(lists.data(), lists.size() * sizeof(int));
+  mix(all.data(), all.size() * sizeof(SqTask));
+  mix(svec.data(), svec.size() * sizeof(int));
+  if (ctx->gexec && sig == ctx->gsig) {
+    HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, stream));
+    ++ctx->graph_replays;
+    return PFM_OK;
+  }
+  if (sig != ctx->gseen) {  // first sighting: run eagerly, remember it
+    ctx->gseen = sig;
+    return enqueue();
+  }
+  HIP_TRY(ctx, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  const int rce = enqueue();
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(stream, &g);
+  if (rce) {
+    if (g) (void)hipGraphDestroy(g);
+    return rce;
+  }
+  if (ec != hipSuccess) return set_err(ctx, PFM_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ec));
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->gexec = nullptr;
+  ctx->graph = g;
+  ctx->gsig = 0;
+  HIP_TRY(ctx, hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+  ctx->gsig = sig;
+  HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, stream));
+  ++ctx->graph_captures;
+  return PFM_OK;
+}
+
+int pfm_set_graphs(pfm_ctx *ctx, int enable) {
+  if (!ctx) return PFM_ERR_INVALID;
+  ctx->graphs = enable != 0;
+  return PFM_OK;
+}
+
+int pfm_graph_stats(pfm_ctx *ctx, int *captures, int *replays) {
+  if (!ctx) return PFM_ERR_INVALID;
+  if (captures) *captures = ctx->graph_captures;
+  if (replays) *replays = ctx->graph_replays;
+  return PFM_OK;
+}
+
+int pfm_tune(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype, int batch, const pfm_problem *probs,
+             int reps, pfm_stream_t stream_, int *policy, double *ms) {
+  if (!ctx || !probs || batch < 1 || reps < 1) return PFM_ERR_INVALID;
+  const PfmSetEntry *ee = find_set(m, 0);
+  if (!ee) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
+  hipStream_t stream = (hipStream_t)stream_;
+  const bool action = probs[0].p > 0;
+  const bool emb = dtype == PFM_C128 || ee->pair != 0;
+  const bool mixed = prec == PFM_MIXED;
+  // candidates that can differ for this kind of batch
+  std::vector<int> cand;
+  if (!action && !emb) cand = {0, 1};  // Gauss-Jordan vs LU
+  else cand = {0, 2};                  // multi-workgroup route above 128 vs above 512
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  const bool graphs = ctx->graphs;
+  ctx->graphs = false;
+  int best = -1;
+  double best_ms = 0.0;
+  int rc = PFM_OK;
+  for (int pi : cand) {
+    ctx->force_policy = pi;
+    rc = pfm_eval_batched(ctx, f, m, tol, prec, dtype, batch, probs, nullptr, -1, stream);  // warm-up
+    if (rc) break;
+    (void)hipEventRecord(e0, stream);
+    for (int r = 0; r < reps && !rc; ++r) rc = pfm_eval_batched(ctx, f, m, tol, prec, dtype, batch, probs, nullptr, -1, stream);
+    (void)hipEventRecord(e1, stream);
+    if (rc) break;
+    (void)hipEventSynchronize(e1);
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    const double per = t / reps;
+    if (best < 0 || per < best_ms) {
+      best = pi;
+      best_ms = per;
+    }
+  }
+  ctx->force_policy = -1;
+  ctx->graphs = graphs;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  ctx->tuned[batch_key(action, emb, mixed, batch, probs)] = best;
+  if (policy) *policy = best;
+  if (ms) *ms = best_ms;
+  return PFM_OK;
+}
+
+int pfm_tune_export(const pfm_ctx *ctx, char *buf, size_t size) {
+  if (!ctx) return PFM_ERR_INVALID;
+  std::string s;
+  for (const auto &kv : ctx->tuned) {
+    char line[64];
+    snprintf(line, sizeof line, "%llu %d\n", (unsigned long long)kv.first, kv.second);
+    s += line;
+  }
+  if (buf && size > 0) {
+    const size_t k = std::min(size - 1, s.size());
+    memcpy(buf, s.data(), k);
+    buf[k] = 0;
+  }
+  return (int)s.size() + 1;
+}
+
+int pfm_tune_import(pfm_ctx *ctx, const char *text) {
+  if (!ctx || !text) return PFM_ERR_INVALID;
+  std::map<uint64_t, int> t;
+  const char *p = text;
+  while (*p) {
+    unsigned long long key;
+    int pol, used = 0;
+    if (sscanf(p, "%llu %d%n", &key, &pol, &used) != 2) break;
+    if (pol < 0 || pol >= kNumPolicies) return set_err(ctx, PFM_ERR_INVALID, "tuning table: bad policy %d", pol);
+    t[(uint64_t)key] = pol;
+    p += used;
+    while (*p == '\n' || *p == ' ' || *p == '\r') ++p;
+  }
+  if (*p) return set_err(ctx, PFM_ERR_INVALID, "tuning table: unreadable line");
+  ctx->tuned = t;
   return PFM_OK;
 }
 

@@ -330,7 +330,7 @@ int pfm_srv_start(pfm_server **out, int device, int lanes, size_t budget, int ma
   S->pool = new DevicePool(device);
   S->lanes.resize(lanes);
   for (Lane &L : S->lanes) {
-    if (pfm_create(&L.ctx, device, S->lane_budget) != PFM_OK ||
+    if (pfm_create(&L.ctx, device, S->lane_budget) != PFM_OK || pfm_set_graphs(L.ctx, 0) != PFM_OK ||
         hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) {
       pfm_srv_stop(S);

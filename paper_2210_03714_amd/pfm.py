@@ -73,6 +73,11 @@ def lib():
         L.pfm_selftest_mfma.argtypes = [i32, dp]
         L.pfm_profile.argtypes = [vp, i32]
         L.pfm_set_route.argtypes = [vp, i32]
+        L.pfm_set_graphs.argtypes = [vp, i32]
+        L.pfm_tune.argtypes = [vp, i32, i32, dbl, i32, i32, i32, ctypes.POINTER(Problem), i32, vp, ip, dp]
+        L.pfm_tune_export.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+        L.pfm_tune_import.argtypes = [vp, ctypes.c_char_p]
+        L.pfm_graph_stats.argtypes = [vp, ip, ip]
         u64p = ctypes.POINTER(ctypes.c_uint64)
         L.pfm_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(Problem)]
         L.pfm_workspace_bytes.restype = ctypes.c_size_t
@@ -167,6 +172,40 @@ class Context:
         if rc:
             raise PfmError(rc, self.last_error())
 
+    def tune_raw(self, probs, f, m, tol, prec=FP64, dtype=R64, reps=3, stream=None):
+        """pfm_tune on a list of Problem: returns (policy, ms per call)."""
+        arr = (Problem * len(probs))(*probs)
+        pol, ms = ctypes.c_int(), ctypes.c_double()
+        rc = lib().pfm_tune(self._h, f, m, tol, prec, dtype, len(probs), arr, reps, _stream_ptr(stream),
+                            ctypes.byref(pol), ctypes.byref(ms))
+        if rc:
+            raise PfmError(rc, self.last_error())
+        return pol.value, ms.value
+
+    def tune_export(self):
+        """The tuned policy table as text ("key policy" lines)."""
+        n = lib().pfm_tune_export(self._h, None, 0)
+        buf = ctypes.create_string_buffer(n)
+        lib().pfm_tune_export(self._h, buf, n)
+        return buf.value.decode()
+
+    def tune_import(self, text):
+        rc = lib().pfm_tune_import(self._h, text.encode())
+        if rc:
+            raise PfmError(rc, self.last_error())
+
+    def set_graphs(self, enable):
+        """Capture and replay repeated launch sequences as hipGraphs."""
+        rc = lib().pfm_set_graphs(self._h, 1 if enable else 0)
+        if rc:
+            raise PfmError(rc, self.last_error())
+
+    def graph_stats(self):
+        """(captures, replays) since the context was created."""
+        c, r = ctypes.c_int(), ctypes.c_int()
+        lib().pfm_graph_stats(self._h, ctypes.byref(c), ctypes.byref(r))
+        return c.value, r.value
+
     def profile(self, enable=True):
         rc = lib().pfm_profile(self._h, 1 if enable else 0)
         if rc:
@@ -232,7 +271,7 @@ def _require_gpu(t):
 
 
 def expm(A, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None, stream=None,
-         out=None):
+         out=None, info_out=None):
     """f(A) for every matrix of ``A``.
 
     ``A`` is a CUDA tensor (batch, n, n) or a list of CUDA tensors (n_i, n_i),
@@ -265,7 +304,7 @@ def expm(A, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None
                              fe.data_ptr() if fe is not None else None,
                              fp.data_ptr() if fp is not None else None))
     ctx = ctx or default_context(mats[0].device.index or 0)
-    info = torch.empty(len(mats) * INFO_DTYPE.itemsize, dtype=torch.uint8, device=mats[0].device)
+    info = _info_buffer(info_out, len(mats), mats[0].device)
     rc = ctx.eval_batched(probs, fm, m, tol, {"fp64": FP64, "mixed": MIXED}[prec],
                           C128 if cplx else R64, info, force_plan, stream)
     if rc:
@@ -273,8 +312,20 @@ def expm(A, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None
     return out, _Info(info)
 
 
-def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None, stream=None):
-    """f(A) V for every (A, V) pair (lists or batched tensors)."""
+def _info_buffer(info_out, count, device):
+    import torch
+    nbytes = count * INFO_DTYPE.itemsize
+    if info_out is None:
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+    if info_out.dtype != torch.uint8 or info_out.numel() < nbytes or not info_out.is_cuda:
+        raise ValueError("info_out must be a CUDA uint8 tensor of at least %d bytes" % nbytes)
+    return info_out
+
+
+def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None, stream=None,
+           out=None, info_out=None):
+    """f(A) V for every (A, V) pair (lists or batched tensors).  ``out`` may
+    map each function to a list of output tensors shaped like the V's."""
     import torch
     mats = list(A) if isinstance(A, (list, tuple)) else [A[i] for i in range(A.shape[0])]
     vecs = list(V) if isinstance(V, (list, tuple)) else [V[i] for i in range(V.shape[0])]
@@ -286,7 +337,8 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx
         mats = [a if a.is_complex() else a.to(torch.complex128) for a in mats]
         vecs = [v if v.is_complex() else v.to(torch.complex128) for v in vecs]
     fm = _fmask(funcs)
-    out = {f: [torch.empty_like(v) for v in vecs] for f in funcs}
+    if out is None:
+        out = {f: [torch.empty_like(v) for v in vecs] for f in funcs}
     probs = []
     for i, (a, v) in enumerate(zip(mats, vecs)):
         fe = out["exp"][i] if "exp" in funcs else None
@@ -296,7 +348,7 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx
                              v.data_ptr(), fe.data_ptr() if fe is not None else None,
                              fp.data_ptr() if fp is not None else None))
     ctx = ctx or default_context(mats[0].device.index or 0)
-    info = torch.empty(len(mats) * INFO_DTYPE.itemsize, dtype=torch.uint8, device=mats[0].device)
+    info = _info_buffer(info_out, len(mats), mats[0].device)
     rc = ctx.eval_batched(probs, fm, m, tol, {"fp64": FP64, "mixed": MIXED}[prec],
                           C128 if cplx else R64, info, force_plan, stream)
     if rc:
@@ -426,3 +478,27 @@ class Server:
             self.stop()
         except Exception:
             pass
+
+
+def tune(A, V=None, funcs=("exp",), m=8, tol=1e-12, prec="fp64", reps=3, ctx=None, stream=None):
+    """Autotune the route policy for batches like (A, V) (lists of CUDA
+    tensors; V None for f(A)).  Returns (policy, ms per call); later calls
+    on ``ctx`` with batches of the same key use the chosen policy."""
+    import torch
+    mats = list(A)
+    cplx = mats[0].is_complex() or (V is not None and V[0].is_complex())
+    outs, probs = [], []
+    for i, a in enumerate(mats):
+        v = None if V is None else V[i]
+        like = a if v is None else v
+        fe = torch.empty_like(like) if "exp" in funcs else None
+        fp = torch.empty_like(like) if "phi1" in funcs else None
+        outs.append((fe, fp))
+        probs.append(Problem(a.shape[0], 0 if v is None else v.shape[1], a.stride(0),
+                             0 if v is None else v.stride(0), like.stride(0), a.data_ptr(),
+                             None if v is None else v.data_ptr(),
+                             fe.data_ptr() if fe is not None else None,
+                             fp.data_ptr() if fp is not None else None))
+    ctx = ctx or default_context(mats[0].device.index or 0)
+    return ctx.tune_raw(probs, _fmask(funcs), m, tol, {"fp64": FP64, "mixed": MIXED}[prec],
+                        C128 if cplx else R64, reps, stream)
