@@ -61,6 +61,68 @@ __device__ __forceinline__ void load_shifted(const InstDesc &D, double c, int s_
   }
 }
 
+// 64 x 64 Gauss-Jordan inverse without interchanges of the block held
+// row-major in LDS (leading dimension LDD), in place.  Each of the 256
+// threads keeps its 4 x 4 patch (rows pr0.., columns pc0..) in registers for
+// all 64 columns; the current pivot column and row are broadcast through the
+// double-buffered bcc / bcr arrays (2 x 64 each), one barrier per column.
+// The caller synchronises before reading Dl afterwards.
+template <int LDD>
+__device__ __forceinline__ void gj64_regs(double *Dl, double *bcc, double *bcr, int pr0, int pc0) {
+  double x[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) x[a][b] = Dl[(pr0 + a) * LDD + pc0 + b];
+  if (pc0 == 0)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) bcc[pr0 + a] = x[a][0];
+  if (pr0 == 0)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bcr[pc0 + b] = x[0][b];
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < 64; ++c) {
+    const double *cc = bcc + (c & 1) * 64, *cr = bcr + (c & 1) * 64;
+    const double p = 1.0 / cc[c];
+    double colc[4], rowc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) colc[a] = cc[pr0 + a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rowc[b] = cr[pc0 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = pr0 + a;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = pc0 + b;
+        double v;
+        if (i == c && j == c) v = p;
+        else if (i == c) v = rowc[b] * p;
+        else if (j == c) v = -colc[a] * p;
+        else v = fma(-colc[a] * p, rowc[b], x[a][b]);
+        x[a][b] = v;
+      }
+    }
+    const int cn = c + 1;  // owners of column / row c + 1 broadcast it
+    if (cn < 64) {
+      double *nc = bcc + (cn & 1) * 64, *nr = bcr + (cn & 1) * 64;
+      const int q = cn & 3;
+      if ((cn >> 2) == (pc0 >> 2))
+#pragma unroll
+        for (int a = 0; a < 4; ++a) nc[pr0 + a] = q == 0 ? x[a][0] : q == 1 ? x[a][1] : q == 2 ? x[a][2] : x[a][3];
+      if ((cn >> 2) == (pr0 >> 2))
+#pragma unroll
+        for (int b = 0; b < 4; ++b) nr[pc0 + b] = q == 0 ? x[0][b] : q == 1 ? x[1][b] : q == 2 ? x[2][b] : x[3][b];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Dl[(pr0 + a) * LDD + pc0 + b] = x[a][b];
+}
+
 template <int NPMAX>
 __global__ void __launch_bounds__(256, 2)
 gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nlist,
@@ -68,6 +130,7 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   constexpr int LDD = kGJ + 1;
   __shared__ double Dl[kGJ * LDD];      // D, then D^{-1} (row-major, padded)
   __shared__ double Cl[kGJ * LDD];      // staging for the row-block product
+  __shared__ double bcc[2 * kGJ], bcr[2 * kGJ];  // pivot column / row broadcast
 
   int slot, k;
   xcd_map(blockIdx.x, T.nterms, slot, k);
@@ -85,48 +148,21 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
 
   load_shifted(D, T.c_re[k], plan[ii].s, action, W, Cl);
 
-  // this thread's 4 x 4 patch of a 64 x 64 block
+  // this thread's 4 x 4 patch of a 64 x 64 block, and its place in
+  // coalesced block copies (one row per lane, columns (t >> 6) + 4 u)
   const int pr0 = (t >> 4) * 4, pc0 = (t & 15) * 4;
+  const int cr = t & 63, cc0 = t >> 6;
 
 #pragma unroll 1
   for (int J = 0; J < nJ; ++J) {
     const int j0 = J * kGJ;
     // 1. Dinv in LDS by Gauss-Jordan without interchanges
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        Dl[(pr0 + a) * LDD + pc0 + b] = W[(j0 + pr0 + a) + (int64_t)(j0 + pc0 + b) * np];
+    for (int u = 0; u < 16; ++u)
+      Dl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (int64_t)(j0 + cc0 + 4 * u) * np];
     __syncthreads();
-#pragma unroll 1
-    for (int c = 0; c < kGJ; ++c) {
-      const double p = 1.0 / Dl[c * LDD + c];
-      double colc[4], rowc[4], cur[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) colc[a] = Dl[(pr0 + a) * LDD + c];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) rowc[b] = Dl[c * LDD + pc0 + b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) cur[a][b] = Dl[(pr0 + a) * LDD + pc0 + b];
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int i = pr0 + a;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int j = pc0 + b;
-          double v;
-          if (i == c && j == c) v = p;
-          else if (i == c) v = rowc[b] * p;
-          else if (j == c) v = -colc[a] * p;
-          else v = fma(-colc[a] * p, rowc[b], cur[a][b]);
-          Dl[i * LDD + j] = v;
-        }
-      }
-      __syncthreads();
-    }
+    gj64_regs<LDD>(Dl, bcc, bcr, pr0, pc0);
+    __syncthreads();
 
     // The rows of W[I, J] (I outside block J): 16-row strips, strip w + 4 m
     // to wave w, held as MFMA A fragments through steps 3 and 4, MSG strips
@@ -160,10 +196,8 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
         if (C == J) continue;
         const int c0 = C * kGJ;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            Cl[(pr0 + a) * LDD + pc0 + b] = W[(j0 + pr0 + a) + (int64_t)(c0 + pc0 + b) * np];
+        for (int u = 0; u < 16; ++u)
+          Cl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (int64_t)(c0 + cc0 + 4 * u) * np];
         __syncthreads();
         if (grp == 0) {
           v4d acc[2][2];
@@ -235,10 +269,8 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
     }
     // 5. W[J, J] <- Dinv
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        W[(j0 + pr0 + a) + (int64_t)(j0 + pc0 + b) * np] = Dl[(pr0 + a) * LDD + pc0 + b];
+    for (int u = 0; u < 16; ++u)
+      W[(j0 + cr) + (int64_t)(j0 + cc0 + 4 * u) * np] = Dl[cr * LDD + cc0 + 4 * u];
     __syncthreads();
   }
 }
