@@ -85,35 +85,52 @@ __device__ __forceinline__ void gj64_regs(double *Dl, double *bcc, double *bcr, 
   for (int c = 0; c < 64; ++c) {
     const double *cc = bcc + (c & 1) * 64, *cr = bcr + (c & 1) * 64;
     const double p = 1.0 / cc[c];
-    double colc[4], rowc[4];
+    double colc[4], rp[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) colc[a] = cc[pr0 + a];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) rowc[b] = cr[pc0 + b];
+    for (int b = 0; b < 4; ++b) rp[b] = cr[pc0 + b] * p;  // the pivot row scaled
+    // every element as if outside the pivot row and column ...
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int i = pr0 + a;
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int j = pc0 + b;
-        double v;
-        if (i == c && j == c) v = p;
-        else if (i == c) v = rowc[b] * p;
-        else if (j == c) v = -colc[a] * p;
-        else v = fma(-colc[a] * p, rowc[b], x[a][b]);
-        x[a][b] = v;
-      }
+      for (int b = 0; b < 4; ++b) x[a][b] = fma(-colc[a], rp[b], x[a][b]);
+    // ... then the pivot row (scaled), column (-colc p) and element (p)
+    // rewritten by their owners; c & 3 is the same in every lane
+    const bool own_r = pr0 == (c & ~3), own_c = pc0 == (c & ~3);
+#define PFM_GJ_FIX(Q)                                                         \
+  {                                                                           \
+    if (own_r)                                                                \
+      for (int b = 0; b < 4; ++b) x[Q][b] = rp[b];                            \
+    if (own_c)                                                                \
+      for (int a = 0; a < 4; ++a) x[a][Q] = -colc[a] * p;                     \
+    if (own_r && own_c) x[Q][Q] = p;                                          \
+  }
+    switch (c & 3) {
+      case 0: PFM_GJ_FIX(0) break;
+      case 1: PFM_GJ_FIX(1) break;
+      case 2: PFM_GJ_FIX(2) break;
+      default: PFM_GJ_FIX(3) break;
     }
+#undef PFM_GJ_FIX
     const int cn = c + 1;  // owners of column / row c + 1 broadcast it
     if (cn < 64) {
       double *nc = bcc + (cn & 1) * 64, *nr = bcr + (cn & 1) * 64;
-      const int q = cn & 3;
-      if ((cn >> 2) == (pc0 >> 2))
-#pragma unroll
-        for (int a = 0; a < 4; ++a) nc[pr0 + a] = q == 0 ? x[a][0] : q == 1 ? x[a][1] : q == 2 ? x[a][2] : x[a][3];
-      if ((cn >> 2) == (pr0 >> 2))
-#pragma unroll
-        for (int b = 0; b < 4; ++b) nr[pc0 + b] = q == 0 ? x[0][b] : q == 1 ? x[1][b] : q == 2 ? x[2][b] : x[3][b];
+      const bool on_c = (cn >> 2) == (pc0 >> 2), on_r = (cn >> 2) == (pr0 >> 2);
+#define PFM_GJ_BC(Q)                                                          \
+  {                                                                           \
+    if (on_c)                                                                 \
+      for (int a = 0; a < 4; ++a) nc[pr0 + a] = x[a][Q];                      \
+    if (on_r)                                                                 \
+      for (int b = 0; b < 4; ++b) nr[pc0 + b] = x[Q][b];                      \
+  }
+      switch (cn & 3) {
+        case 0: PFM_GJ_BC(0) break;
+        case 1: PFM_GJ_BC(1) break;
+        case 2: PFM_GJ_BC(2) break;
+        default: PFM_GJ_BC(3) break;
+      }
+#undef PFM_GJ_BC
     }
     __syncthreads();
   }
@@ -142,7 +159,7 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int i16 = lane & 15, g = lane >> 4;
   const int ar = arow(i16);
-  double *W = wsd + D.fac_off + (int64_t)k * np * np;
+  double *W = wsd + D.fac_off + (int64_t)k * np * np;  // 32-bit offsets below: npad <= 512
   const int nJ = np / kGJ;
   if (route_val >= 0 && k == 0 && t == 0) plan[ii].route = route_val;
 
@@ -159,13 +176,13 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
     // 1. Dinv in LDS by Gauss-Jordan without interchanges
 #pragma unroll
     for (int u = 0; u < 16; ++u)
-      Dl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (int64_t)(j0 + cc0 + 4 * u) * np];
+      Dl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (j0 + cc0 + 4 * u) * np];
     __syncthreads();
     gj64_regs<LDD>(Dl, bcc, bcr, pr0, pc0);
     __syncthreads();
 
     // The rows of W[I, J] (I outside block J): 16-row strips, strip w + 4 m
-    // to wave w, held as MFMA A fragments through steps 3 and 4, MSG strips
+    // to wave w, held negated as MFMA A fragments through steps 3 and 4, MSG strips
     // per wave at a time (NG groups).  The first group transforms the row
     // block (step 2) chunk by chunk; later groups read it back.
     constexpr int MSW = NPMAX / 64 - 1 > 0 ? NPMAX / 64 - 1 : 1;  // strips per wave, at most
@@ -185,7 +202,7 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
           const int r0 = sidx * 16 + (sidx * 16 >= j0 ? kGJ : 0);
           srow[m] = r0;
 #pragma unroll
-          for (int q = 0; q < kGJ / 4; ++q) aI[m][q] = W[(r0 + ar) + (int64_t)(j0 + 4 * q + g) * np];
+          for (int q = 0; q < kGJ / 4; ++q) aI[m][q] = -W[(r0 + ar) + (j0 + 4 * q + g) * np];
         }
       }
 
@@ -197,7 +214,7 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
         const int c0 = C * kGJ;
 #pragma unroll
         for (int u = 0; u < 16; ++u)
-          Cl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (int64_t)(c0 + cc0 + 4 * u) * np];
+          Cl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (c0 + cc0 + 4 * u) * np];
         __syncthreads();
         if (grp == 0) {
           v4d acc[2][2];
@@ -224,7 +241,7 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
               const int rr = wr + 16 * a + 4 * g, cc = wc + 16 * b + i16;
-              *reinterpret_cast<v4d *>(W + (j0 + rr) + (int64_t)(c0 + cc) * np) = acc[a][b];
+              *reinterpret_cast<v4d *>(W + (j0 + rr) + (c0 + cc) * np) = acc[a][b];
 #pragma unroll
               for (int v = 0; v < 4; ++v) Cl[(rr + v) * LDD + cc] = acc[a][b][v];
             }
@@ -237,15 +254,15 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
           v4d cacc[4];
 #pragma unroll
           for (int b = 0; b < 4; ++b)
-            cacc[b] = *reinterpret_cast<const v4d *>(W + (r0 + 4 * g) + (int64_t)(c0 + 16 * b + i16) * np);
+            cacc[b] = *reinterpret_cast<const v4d *>(W + (r0 + 4 * g) + (c0 + 16 * b + i16) * np);
 #pragma unroll
           for (int q = 0; q < kGJ / 4; ++q)
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-              cacc[b] = mfma16(-aI[m][q], Cl[(4 * q + g) * LDD + 16 * b + i16], cacc[b]);
+              cacc[b] = mfma16(aI[m][q], Cl[(4 * q + g) * LDD + 16 * b + i16], cacc[b]);
 #pragma unroll
           for (int b = 0; b < 4; ++b)
-            *reinterpret_cast<v4d *>(W + (r0 + 4 * g) + (int64_t)(c0 + 16 * b + i16) * np) = cacc[b];
+            *reinterpret_cast<v4d *>(W + (r0 + 4 * g) + (c0 + 16 * b + i16) * np) = cacc[b];
         }
         __syncthreads();  // before the next chunk overwrites Cl
       }
@@ -261,16 +278,16 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
 #pragma unroll
         for (int q = 0; q < kGJ / 4; ++q)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[b] = mfma16(-aI[m][q], Dl[(4 * q + g) * LDD + 16 * b + i16], acc[b]);
+          for (int b = 0; b < 4; ++b) acc[b] = mfma16(aI[m][q], Dl[(4 * q + g) * LDD + 16 * b + i16], acc[b]);
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          *reinterpret_cast<v4d *>(W + (r0 + 4 * g) + (int64_t)(j0 + 16 * b + i16) * np) = acc[b];
+          *reinterpret_cast<v4d *>(W + (r0 + 4 * g) + (j0 + 16 * b + i16) * np) = acc[b];
       }
     }
     // 5. W[J, J] <- Dinv
 #pragma unroll
     for (int u = 0; u < 16; ++u)
-      W[(j0 + cr) + (int64_t)(j0 + cc0 + 4 * u) * np] = Dl[cr * LDD + cc0 + 4 * u];
+      W[(j0 + cr) + (j0 + cc0 + 4 * u) * np] = Dl[cr * LDD + cc0 + 4 * u];
     __syncthreads();
   }
 }
