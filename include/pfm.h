@@ -164,6 +164,15 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec,
                      int dtype, int batch, const pfm_problem *probs,
                      pfm_info *info, int force_plan, pfm_stream_t stream);
 
+/* pfm_eval_batched with one tolerance per instance (host array tols[batch],
+ * each in (0,1)); the scalar tol is ignored when tols is not NULL.  Each
+ * instance is planned with its own θ(f, m, tol_i) and reports it in
+ * pfm_info.theta; everything else is shared, so instances of different
+ * tolerances batch together.  (The mixed path refines to the smallest.) */
+int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int prec, int dtype,
+                          int batch, const pfm_problem *probs, pfm_info *info, int force_plan,
+                          pfm_stream_t stream);
+
 /* Block until `stream` is idle and report device-side failures of previous
  * calls on this context (PFM_ERR_DEVICE if a bounded device wait timed out). */
 int pfm_check(pfm_ctx *ctx, pfm_stream_t stream);
@@ -242,7 +251,7 @@ size_t pfm_workspace_bytes(int f, int m, int prec, int dtype, int batch, const p
  * request when its resident bytes (copies of A and V, its outputs) fit in the
  * resident share of the HBM budget, copies A (and V) into library-owned
  * device buffers, and groups admitted requests that can share one
- * pfm_eval_batched call (same f, m, tol, prec, dtype, mode and size bucket:
+ * pfm_eval_batched_tols call (same f, m, prec, dtype, mode and size bucket:
  * real dimension <= 128, <= 512 or larger, counting 2n for complex) into batches
  * whose workspace fits one lane's share of the budget.  Each lane is a
  * stream with its own workspace; up to `lanes` batches run concurrently,

@@ -69,9 +69,11 @@ norm_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan) {
 }
 
 __global__ void __launch_bounds__(256)
-plan_finish_kernel(PlanRec *__restrict__ plan, int batch, double theta, int action, int force_plan) {
+plan_finish_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan, int batch, int action,
+                   int force_plan) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= batch) return;
+  const double theta = inst[i].theta;
   PlanRec P = plan[i];
   const double eta = P.eta;
   const bool bad = !isfinite(eta);
@@ -194,8 +196,8 @@ struct InfoRec {  // mirrors pfm_info
   double norm1, theta, resid;
 };
 
-__global__ void info_kernel(const PlanRec *__restrict__ plan, InfoRec *__restrict__ info, int batch,
-                            int order, double theta) {
+__global__ void info_kernel(const InstDesc *__restrict__ inst, const PlanRec *__restrict__ plan,
+                            InfoRec *__restrict__ info, int batch, int order) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= batch) return;
   const PlanRec P = plan[i];
@@ -207,7 +209,7 @@ __global__ void info_kernel(const PlanRec *__restrict__ plan, InfoRec *__restric
   r.bad_shift = P.bad_shift == 0x7fffffff ? -1 : P.bad_shift;
   r.route = P.route;
   r.norm1 = P.eta;
-  r.theta = theta;
+  r.theta = inst[i].theta;
   r.resid = P.resid;
   info[i] = r;
 }

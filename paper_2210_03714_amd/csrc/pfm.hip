@@ -357,10 +357,23 @@ int pfm_selftest_mfma(int device, double *out) {
 }
 
 int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype, int batch,
-                     const pfm_problem *probs, pfm_info *info, int force_plan,
-                     pfm_stream_t stream_) {
+                     const pfm_problem *probs, pfm_info *info, int force_plan, pfm_stream_t stream) {
+  return pfm_eval_batched_tols(ctx, f, m, nullptr, tol, prec, dtype, batch, probs, info, force_plan, stream);
+}
+
+int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int prec, int dtype,
+                          int batch, const pfm_problem *probs, pfm_info *info, int force_plan,
+                          pfm_stream_t stream_) {
   if (!ctx) return PFM_ERR_INVALID;
   if (f < 1 || f > 3) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
+  if (tols) {  // per-instance tolerances: the scalar is their minimum
+    if (batch < 1) return set_err(ctx, PFM_ERR_INVALID, "empty batch");
+    tol = tols[0];
+    for (int i = 0; i < batch; ++i) {
+      if (!(tols[i] > 0.0 && tols[i] < 1.0)) return set_err(ctx, PFM_ERR_INVALID, "tol must lie in (0,1)");
+      tol = std::min(tol, tols[i]);
+    }
+  }
   if (!(tol > 0.0 && tol < 1.0)) return set_err(ctx, PFM_ERR_INVALID, "tol must lie in (0,1)");
   if (batch < 1 || !probs) return set_err(ctx, PFM_ERR_INVALID, "empty batch");
   if (prec != PFM_FP64 && prec != PFM_MIXED) return set_err(ctx, PFM_ERR_INVALID, "bad prec");
@@ -405,6 +418,19 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   double theta;
   int rc = pfm_theta(f, m, tol, &theta);
   if (rc) return set_err(ctx, rc, "theta failed");
+  std::vector<double> thetas(batch, theta);
+  if (tols) {
+    std::map<double, double> seen;
+    for (int i = 0; i < batch; ++i) {
+      auto it = seen.find(tols[i]);
+      if (it == seen.end()) {
+        double th;
+        if (pfm_theta(f, m, tols[i], &th)) return set_err(ctx, PFM_ERR_INVALID, "theta failed");
+        it = seen.emplace(tols[i], th).first;
+      }
+      thetas[i] = it->second;
+    }
+  }
 
   Terms T;
   memset(&T, 0, sizeof T);
@@ -474,6 +500,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     D.ldv = P.ldv;
     D.ldf = P.ldf;
     D.emb = emb ? 1 : 0;
+    D.theta = thetas[i];
     D.hn = P.n;
     D.n = emb ? 2 * P.n : P.n;
     D.ncol = P.n;
@@ -569,7 +596,7 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     const int nb = (batch + 255) / 256;
     hipLaunchKernelGGL(plan_init_kernel, dim3(nb), dim3(256), 0, stream, d_plan, batch);
     hipLaunchKernelGGL(norm_kernel, dim3((maxc + 63) / 64, batch), dim3(256), 0, stream, d_desc, d_plan);
-    hipLaunchKernelGGL(plan_finish_kernel, dim3(nb), dim3(256), 0, stream, d_plan, batch, theta,
+    hipLaunchKernelGGL(plan_finish_kernel, dim3(nb), dim3(256), 0, stream, d_desc, d_plan, batch,
                        action ? 1 : 0, force_plan);
   }
   HIP_TRY(ctx, hipGetLastError());
@@ -890,8 +917,8 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
     prof_mark(ctx, 4, stream);
     if (ctx->prof) ctx->prof_pending = true;
     if (info)
-      hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_plan,
-                         (InfoRec *)info, batch, ee->order, theta);
+      hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_desc, d_plan,
+                         (InfoRec *)info, batch, ee->order);
     HIP_TRY(ctx, hipGetLastError());
     return PFM_OK;
   }
@@ -990,8 +1017,8 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   prof_mark(ctx, 4, stream);
   if (ctx->prof) ctx->prof_pending = true;
   if (info)
-    hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_plan,
-                       (InfoRec *)info, batch, ee->order, theta);
+    hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_desc, d_plan,
+                       (InfoRec *)info, batch, ee->order);
   HIP_TRY(ctx, hipGetLastError());
   return PFM_OK;
   };

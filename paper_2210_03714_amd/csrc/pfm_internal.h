@@ -37,6 +37,7 @@ struct InstDesc {
   int64_t dinv_off;  // nterms * 2 * (npad/16) * 256   : inverted 16x16 diagonal blocks of L and U
   int64_t r_off;     // 4 * npad^2 : R ping-pong buffers, then phi1 ping-pong buffers
   int64_t e_off;     // emb: the embedded matrix, row-major n x n
+  double theta;      // admissible ||B||_1 for this instance's tolerance (§3)
   int64_t ln_off;    // large instances: nterms * ln_stride(npad) (colbuf, dinv)
   int64_t v_off;     // large action instances: step vectors and partial products
   int64_t perm_ioff; // nterms * npad : row permutation of each factorisation

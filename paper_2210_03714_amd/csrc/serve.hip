@@ -11,8 +11,8 @@
 //      (A, V, outputs) fit the resident share of the budget, allocating the
 //      buffers from a device pool;
 //   3. for every idle lane, takes the group of the oldest admitted request
-//      (requests of one group share f, m, tol, prec, dtype, mode and size
-//      bucket), fills a batch in arrival order up to max_batch requests and
+//      (requests of one group share f, m, prec, dtype, mode and size bucket;
+//      tolerances may differ), fills a batch in arrival order up to max_batch requests and
 //      the lane's workspace share, copies the inputs into the resident
 //      buffers on the lane's stream and calls pfm_eval_batched on the lane.
 // Submitting only appends to the pending queue under the lock; the
@@ -130,8 +130,10 @@ int size_bucket(const Req &r) {
   return nk <= 128 ? 0 : (nk <= 512 ? 1 : 2);
 }
 
+// requests that can share one call: tolerances may differ (each instance
+// is planned with its own θ)
 bool same_group(const Req &a, const Req &b) {
-  return a.f == b.f && a.m == b.m && a.tol == b.tol && a.prec == b.prec && a.dtype == b.dtype &&
+  return a.f == b.f && a.m == b.m && a.prec == b.prec && a.dtype == b.dtype &&
          (a.prob.p > 0) == (b.prob.p > 0) && size_bucket(a) == size_bucket(b);
 }
 
@@ -203,6 +205,7 @@ bool admit_one(pfm_server *S, Req &r) {
 int launch(pfm_server *S, Lane &L, std::vector<Req *> &batch) {
   const int nb = (int)batch.size();
   std::vector<pfm_problem> probs(nb);
+  std::vector<double> tols(nb);
   for (int i = 0; i < nb; ++i) {
     Req &r = *batch[i];
     const int n = r.prob.n, p = r.prob.p;
@@ -213,6 +216,7 @@ int launch(pfm_server *S, Lane &L, std::vector<Req *> &batch) {
     if (p > 0 && hipMemcpy2DAsync(r.rV, (size_t)p * r.esz, r.prob.V, (size_t)r.prob.ldv * r.esz,
                                   (size_t)p * r.esz, n, hipMemcpyDeviceToDevice, L.stream) != hipSuccess)
       return PFM_ERR_HIP;
+    tols[i] = r.tol;
     pfm_problem &q = probs[i];
     q.n = n;
     q.p = p;
@@ -236,8 +240,8 @@ int launch(pfm_server *S, Lane &L, std::vector<Req *> &batch) {
     L.cap = S->max_batch;
   }
   const Req &r0 = *batch[0];
-  int rc = pfm_eval_batched(L.ctx, r0.f, r0.m, r0.tol, r0.prec, r0.dtype, nb, probs.data(),
-                            (pfm_info *)L.d_info, -1, L.stream);
+  int rc = pfm_eval_batched_tols(L.ctx, r0.f, r0.m, tols.data(), r0.tol, r0.prec, r0.dtype, nb, probs.data(),
+                                 (pfm_info *)L.d_info, -1, L.stream);
   if (rc) return rc;
   if (hipMemcpyAsync(L.h_info, L.d_info, sizeof(pfm_info) * nb, hipMemcpyDeviceToHost, L.stream) != hipSuccess)
     return PFM_ERR_HIP;

@@ -74,6 +74,8 @@ def lib():
         L.pfm_profile.argtypes = [vp, i32]
         L.pfm_set_route.argtypes = [vp, i32]
         L.pfm_set_graphs.argtypes = [vp, i32]
+        L.pfm_eval_batched_tols.argtypes = [vp, i32, i32, dp, dbl, i32, i32, i32, ctypes.POINTER(Problem), vp,
+                                            i32, vp]
         L.pfm_tune.argtypes = [vp, i32, i32, dbl, i32, i32, i32, ctypes.POINTER(Problem), i32, vp, ip, dp]
         L.pfm_tune_export.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
         L.pfm_tune_import.argtypes = [vp, ctypes.c_char_p]
@@ -235,9 +237,14 @@ class Context:
     def eval_batched(self, probs, f, m, tol, prec=FP64, dtype=R64, info=None, force_plan=-1,
                      stream=None):
         """Raw call: ``probs`` is a list of Problem; ``info`` a device tensor of
-        len(probs) * 48 bytes or None.  Returns the C return code."""
+        len(probs) * 48 bytes or None; ``tol`` a float, or one per problem.
+        Returns the C return code."""
         arr = (Problem * len(probs))(*probs)
         iptr = ctypes.c_void_p(info.data_ptr()) if info is not None else ctypes.c_void_p()
+        if isinstance(tol, (list, tuple, np.ndarray)):
+            tarr = (ctypes.c_double * len(probs))(*[float(x) for x in tol])
+            return lib().pfm_eval_batched_tols(self._h, f, m, tarr, 0.5, prec, dtype, len(probs), arr, iptr,
+                                               force_plan, _stream_ptr(stream))
         return lib().pfm_eval_batched(self._h, f, m, tol, prec, dtype, len(probs), arr, iptr,
                                       force_plan, _stream_ptr(stream))
 

@@ -210,3 +210,24 @@ def test_deterministic(torch_dev):
     r2, _ = pfm.expm(At, ("exp", "phi1"), m=8)
     torch.cuda.synchronize()
     assert torch.equal(r1["exp"], r2["exp"]) and torch.equal(r1["phi1"], r2["phi1"])
+
+
+def test_per_instance_tolerances(torch_dev):
+    """One call with a tolerance per instance equals the per-tolerance
+    calls bit for bit, and each instance reports its own θ and plan."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    A, _ = wl.gaussian_batch(12, 80, 0.5, 8.0, wl.SEED_BASE + 95)
+    tols = [1e-8, 1e-12, 1e-10] * 4
+    At = torch.from_numpy(A).to(dev)
+    _say("case per-instance tolerances")
+    res, info = pfm.expm(At, ("exp",), m=8, tol=tols)
+    torch.cuda.synchronize()
+    for t in set(tols):
+        idx = [i for i, x in enumerate(tols) if x == t]
+        r1, i1 = pfm.expm(At[idx], ("exp",), m=8, tol=t)
+        torch.cuda.synchronize()
+        for j, i in enumerate(idx):
+            assert torch.equal(res["exp"][i], r1["exp"][j])
+            assert info[i]["theta"] == i1[j]["theta"] == pfm.theta(pfm.EXP, 8, t)
+            assert info[i]["plan"] == i1[j]["plan"]
