@@ -254,12 +254,17 @@ size_t pfm_workspace_bytes(int f, int m, int prec, int dtype, int batch, const p
  * pfm_eval_batched_tols call (same f, m, prec, dtype, mode and size bucket:
  * real dimension <= 128, <= 512 or larger, counting 2n for complex) into batches
  * whose workspace fits one lane's share of the budget.  Each lane is a
- * stream with its own workspace; up to `lanes` batches run concurrently,
- * and requests arriving meanwhile are admitted and batched as lanes free up.
+ * stream with its own workspace; up to `lanes` batches run concurrently.
+ * With two or more lanes, a third of them (at least one) are express lanes
+ * that take only requests of real dimension <= 512 (2n for complex), so
+ * small requests never queue behind batches of large ones.  Requests
+ * arriving meanwhile are admitted and batched as lanes free up.
  * A request's results stay in library memory until fetched or released.
  *
  * Latency is measured by the library from pfm_srv_submit to the host seeing
- * the batch's completion event (host steady clock).
+ * the batch's completion event (host steady clock).  Each lane has a launch
+ * thread (the calls wait on their own stream for the plan read-back), so a
+ * lane waiting for the GPU never delays the dispatch to another.
  * ------------------------------------------------------------------------ */
 typedef struct pfm_server pfm_server;
 
@@ -299,9 +304,10 @@ int pfm_srv_fetch(pfm_server *srv, uint64_t ticket, int which, void *dst, int64_
 int pfm_srv_release(pfm_server *srv, uint64_t ticket);
 
 /* Counters: submitted, done, batches launched, bytes resident now, peak
- * resident bytes. */
+ * resident bytes, host seconds spent launching batches (summed over the
+ * lanes' launch threads).  Any pointer may be NULL. */
 int pfm_srv_stats(pfm_server *srv, uint64_t *submitted, uint64_t *done, uint64_t *batches,
-                  uint64_t *resident_bytes, uint64_t *peak_resident_bytes);
+                  uint64_t *resident_bytes, uint64_t *peak_resident_bytes, double *launch_s);
 
 /* Library version string (static storage). */
 const char *pfm_version(void);

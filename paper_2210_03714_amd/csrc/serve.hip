@@ -11,6 +11,7 @@
 //      (A, V, outputs) fit the resident share of the budget, allocating the
 //      buffers from a device pool;
 //   3. for every idle lane, takes the group of the oldest admitted request
+//      (for an express lane: the oldest of real dimension <= 512)
 //      (requests of one group share f, m, prec, dtype, mode and size bucket;
 //      tolerances may differ), fills a batch in arrival order up to max_batch requests and
 //      the lane's workspace share, copies the inputs into the resident
@@ -112,6 +113,13 @@ struct Req {
 };
 
 struct Lane {
+  bool express = false;        // serves only requests of size bucket <= 1
+  // a batch handed to the lane's launch thread, and its outcome
+  std::vector<Req *> todo;
+  bool has_todo = false, launched = false;
+  int launch_rc = 0;
+  std::thread th;
+  std::condition_variable cv;
   pfm_ctx *ctx = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
@@ -150,11 +158,12 @@ struct pfm_server {
   std::deque<uint64_t> pending;     // arrival order, not yet admitted
   std::deque<uint64_t> admitted;    // admitted, not yet dispatched (arrival order)
   std::unordered_map<uint64_t, Req> reqs;
-  std::vector<Lane> lanes;
+  std::deque<Lane> lanes;  // lanes hold threads and condition variables: built in place
   DevicePool *pool = nullptr;
   std::thread th;
   bool stop = false;
   int fatal = 0;
+  double launch_s = 0.0;  // host time spent launching batches (all lanes)
 };
 
 namespace {
@@ -249,6 +258,30 @@ int launch(pfm_server *S, Lane &L, std::vector<Req *> &batch) {
   return PFM_OK;
 }
 
+// One thread per lane: launches the batches the scheduler hands over, so
+// that one lane waiting for its plan read-back (the GPU may be busy with
+// other lanes' work) never holds up the dispatch of the others.
+void lane_main(pfm_server *S, Lane *L) {
+  (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    L->cv.wait(lk, [&] { return L->has_todo || (S->stop && !L->busy); });
+    if (!L->has_todo) break;
+    std::vector<Req *> batch;
+    batch.swap(L->todo);
+    lk.unlock();
+    const double t0 = now_s();
+    const int rc = launch(S, *L, batch);
+    const double t1 = now_s();
+    lk.lock();
+    S->launch_s += t1 - t0;
+    L->has_todo = false;
+    L->launch_rc = rc;
+    L->launched = true;
+    S->cv.notify_all();
+  }
+}
+
 void scheduler(pfm_server *S) {
   (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
@@ -256,7 +289,13 @@ void scheduler(pfm_server *S) {
     bool progress = false;
     // 1. completions
     for (Lane &L : S->lanes) {
-      if (!L.busy) continue;
+      if (!L.busy || !L.launched) continue;
+      if (L.launch_rc) {
+        retire(S, L, false);
+        S->fatal = L.launch_rc;
+        progress = true;
+        continue;
+      }
       const hipError_t q = hipEventQuery(L.done);
       if (q == hipSuccess) {
         retire(S, L, true);
@@ -275,11 +314,21 @@ void scheduler(pfm_server *S) {
       S->pending.pop_front();
       progress = true;
     }
-    // 3. dispatch to idle lanes
+    // 3. dispatch to idle lanes: the group of the oldest admitted request
+    //    (express lanes: of the oldest admitted request of size bucket <= 1)
     for (Lane &L : S->lanes) {
       if (L.busy || S->admitted.empty()) continue;
+      const Req *hp = nullptr;
+      for (uint64_t id : S->admitted) {
+        const Req &r = S->reqs[id];
+        if (!L.express || size_bucket(r) <= 1) {
+          hp = &r;
+          break;
+        }
+      }
+      if (!hp) continue;
       std::vector<Req *> batch;
-      const Req &head = S->reqs[S->admitted.front()];
+      const Req &head = *hp;
       size_t ws = 0;
       std::deque<uint64_t> rest;
       for (uint64_t id : S->admitted) {
@@ -295,19 +344,19 @@ void scheduler(pfm_server *S) {
       }
       S->admitted.swap(rest);
       L.busy = true;
+      L.launched = false;
+      L.todo.swap(batch);
+      L.has_todo = true;
       ++S->n_batches;
-      lk.unlock();
-      const int rc = launch(S, L, batch);
-      lk.lock();
-      if (rc) {
-        retire(S, L, false);
-        S->fatal = rc;
-      }
+      L.cv.notify_one();
       progress = true;
     }
     bool busy = false;
     for (Lane &L : S->lanes) busy |= L.busy;
-    if (S->stop && S->pending.empty() && S->admitted.empty() && !busy) break;
+    if (S->stop && S->pending.empty() && S->admitted.empty() && !busy) {
+      for (Lane &L : S->lanes) L.cv.notify_one();
+      break;
+    }
     if (!progress) {
       // idle: wake on a submission, or poll the lanes again shortly
       S->cv.wait_for(lk, std::chrono::microseconds(busy ? 20 : 2000));
@@ -332,7 +381,12 @@ int pfm_srv_start(pfm_server **out, int device, int lanes, size_t budget, int ma
   S->res_budget = budget / 2;
   S->lane_budget = budget / 2 / lanes;
   S->pool = new DevicePool(device);
-  S->lanes.resize(lanes);
+  for (int l = 0; l < lanes; ++l) S->lanes.emplace_back();
+  // with two or more lanes, a third of them (at least one) are express
+  // lanes for requests of real dimension <= 512, so that those never wait
+  // behind batches of large ones
+  const int nexp = lanes >= 2 ? std::max(1, lanes / 3) : 0;
+  for (int l = 0; l < nexp; ++l) S->lanes[l].express = true;
   for (Lane &L : S->lanes) {
     if (pfm_create(&L.ctx, device, S->lane_budget) != PFM_OK || pfm_set_graphs(L.ctx, 0) != PFM_OK ||
         hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -341,6 +395,7 @@ int pfm_srv_start(pfm_server **out, int device, int lanes, size_t budget, int ma
       return PFM_ERR_HIP;
     }
   }
+  for (Lane &L : S->lanes) L.th = std::thread(lane_main, S, &L);
   S->th = std::thread(scheduler, S);
   *out = S;
   return PFM_OK;
@@ -354,6 +409,12 @@ int pfm_srv_stop(pfm_server *S) {
   }
   S->cv.notify_all();
   if (S->th.joinable()) S->th.join();
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    for (Lane &L : S->lanes) L.cv.notify_all();
+  }
+  for (Lane &L : S->lanes)
+    if (L.th.joinable()) L.th.join();
   (void)hipSetDevice(S->device);
   for (Lane &L : S->lanes) {
     if (L.stream) (void)hipStreamSynchronize(L.stream);
@@ -474,9 +535,10 @@ int pfm_srv_release(pfm_server *S, uint64_t ticket) {
 }
 
 int pfm_srv_stats(pfm_server *S, uint64_t *submitted, uint64_t *done, uint64_t *batches, uint64_t *resident,
-                  uint64_t *peak) {
+                  uint64_t *peak, double *launch_s) {
   if (!S) return PFM_ERR_INVALID;
   std::lock_guard<std::mutex> g(S->mu);
+  if (launch_s) *launch_s = S->launch_s;
   if (submitted) *submitted = S->n_submitted;
   if (done) *done = S->n_done;
   if (batches) *batches = S->n_batches;

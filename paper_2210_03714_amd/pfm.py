@@ -90,7 +90,7 @@ def lib():
         L.pfm_srv_drain.argtypes = [vp, i32, u64p, dp, ip]
         L.pfm_srv_fetch.argtypes = [vp, ctypes.c_uint64, i32, vp, ctypes.c_int64]
         L.pfm_srv_release.argtypes = [vp, ctypes.c_uint64]
-        L.pfm_srv_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p]
+        L.pfm_srv_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p, dp]
         L.pfm_profile_read.argtypes = [vp, dp, ip, ip]
         _lib = L
     return _lib
@@ -468,9 +468,11 @@ class Server:
 
     def stats(self):
         v = [ctypes.c_uint64() for _ in range(5)]
-        rc = lib().pfm_srv_stats(self._h, *[ctypes.byref(x) for x in v])
+        ls = ctypes.c_double()
+        rc = lib().pfm_srv_stats(self._h, *[ctypes.byref(x) for x in v], ctypes.byref(ls))
         keys = ("submitted", "done", "batches", "resident_bytes", "peak_resident_bytes")
         d = {k: x.value for k, x in zip(keys, v)}
+        d["launch_s"] = ls.value
         d["error"] = rc
         return d
 
