@@ -181,33 +181,53 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
     gj64_regs<LDD>(Dl, bcc, bcr, pr0, pc0);
     __syncthreads();
 
-    // The rows of W[I, J] (I outside block J): 16-row strips, strip w + 4 m
-    // to wave w, held negated as MFMA A fragments through steps 3 and 4, MSG strips
-    // per wave at a time (NG groups).  The first group transforms the row
-    // block (step 2) chunk by chunk; later groups read it back.
+    // Strips of 16 rows outside block J, strip w + 4 m to wave w, MSG per
+    // wave at a time (NG groups).  With G = W[I, J] Dinv, the step is
+    //   W[I, C] <- W[I, C] - G W_old[J, C]   (C != J)
+    //   W[J, C] <- Dinv W_old[J, C]          (C != J)
+    //   W[I, J] <- -G,  W[J, J] <- Dinv,
+    // so the transform of the row block and the update of the other rows
+    // read the same staged old chunk and are independent of each other.
+    // G comes out of G^T = Dinv^T W[I, J]^T, whose accumulator layout is
+    // the MFMA A-fragment layout the update needs: lane (g, i) holds
+    // G[row ar(i)][16 t + 4 g + v] in element v of tile t, which is the A
+    // operand of k-step q = 4 t + v when the B operand supplies chunk row
+    // 16 t + 4 g + v.  With several groups, only the last transforms the row
+    // block, so earlier groups still see the old chunk.
     constexpr int MSW = NPMAX / 64 - 1 > 0 ? NPMAX / 64 - 1 : 1;  // strips per wave, at most
-    constexpr int MSG = MSW < 3 ? MSW : 3;
+    constexpr int MSG = MSW < 3 ? MSW : (NPMAX >= 512 ? 2 : 3);    // register budget
     constexpr int NG = (MSW + MSG - 1) / MSG;
     const int nstrip = (np - kGJ) / 16;
     const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int wu = __builtin_amdgcn_readfirstlane(wave);
 #pragma unroll 1
     for (int grp = 0; grp < NG; ++grp) {
-      double aI[MSG][kGJ / 4];
+      v4d Gt[MSG][4];  // G of each strip, 4 tiles of 16 columns
       int srow[MSG];
 #pragma unroll
       for (int m = 0; m < MSG; ++m) {
-        const int sidx = wave + 4 * (grp * MSG + m);
-        srow[m] = -1;
-        if (sidx < nstrip) {
-          const int r0 = sidx * 16 + (sidx * 16 >= j0 ? kGJ : 0);
-          srow[m] = r0;
+        const int sidx = wu + 4 * (grp * MSG + m);
+        srow[m] = sidx < nstrip ? sidx * 16 + (sidx * 16 >= j0 ? kGJ : 0) : -1;
 #pragma unroll
-          for (int q = 0; q < kGJ / 4; ++q) aI[m][q] = -W[(r0 + ar) + (j0 + 4 * q + g) * np];
+        for (int tt = 0; tt < 4; ++tt) Gt[m][tt] = zero4();
+        if (srow[m] < 0) continue;
+        const int r0 = srow[m];
+        // G^T tile tt = (Dinv^T)[16 tt.., :] W[I, J]^T : A = Dinv^T rows
+        // 16 tt + ar(i) (= Dinv columns), B = W[r0 + ar(j), j0 + k]
+#pragma unroll
+        for (int q = 0; q < kGJ / 4; ++q) {
+          const double bv = W[(r0 + ar) + (j0 + 4 * q + g) * np];
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt)
+            Gt[m][tt] = mfma16(Dl[(4 * q + g) * LDD + 16 * tt + ar], bv, Gt[m][tt]);
         }
+        // new W[I, J] = -G: lane (g, i) holds row r0 + ar(i), columns 16 tt + 4 g + v
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) W[(r0 + ar) + (j0 + 16 * tt + 4 * g + v) * np] = -Gt[m][tt][v];
       }
 
-      // 2+3. per 64-column chunk C != J: new = Dinv W[J, C] (to LDS and W),
-      //      then W[I, C] -= W[I, J] new for this wave's strips
 #pragma unroll 1
       for (int C = 0; C < nJ; ++C) {
         if (C == J) continue;
@@ -216,7 +236,8 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
         for (int u = 0; u < 16; ++u)
           Cl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (c0 + cc0 + 4 * u) * np];
         __syncthreads();
-        if (grp == 0) {
+        if (grp == NG - 1) {
+          // W[J, C] <- Dinv W_old[J, C]: this wave's 32 x 32 part
           v4d acc[2][2];
 #pragma unroll
           for (int a = 0; a < 2; ++a)
@@ -235,18 +256,13 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
 #pragma unroll
               for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
           }
-          __syncthreads();  // every wave has read the old chunk
 #pragma unroll
           for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-              const int rr = wr + 16 * a + 4 * g, cc = wc + 16 * b + i16;
-              *reinterpret_cast<v4d *>(W + (j0 + rr) + (c0 + cc) * np) = acc[a][b];
-#pragma unroll
-              for (int v = 0; v < 4; ++v) Cl[(rr + v) * LDD + cc] = acc[a][b][v];
-            }
-          __syncthreads();  // the new chunk is in LDS
+            for (int b = 0; b < 2; ++b)
+              *reinterpret_cast<v4d *>(W + (j0 + wr + 16 * a + 4 * g) + (c0 + wc + 16 * b + i16) * np) = acc[a][b];
         }
+        // W[I, C] -= G W_old[J, C] for this wave's strips
 #pragma unroll
         for (int m = 0; m < MSG; ++m) {
           if (srow[m] < 0) continue;
@@ -256,32 +272,17 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
           for (int b = 0; b < 4; ++b)
             cacc[b] = *reinterpret_cast<const v4d *>(W + (r0 + 4 * g) + (c0 + 16 * b + i16) * np);
 #pragma unroll
-          for (int q = 0; q < kGJ / 4; ++q)
+          for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-              cacc[b] = mfma16(aI[m][q], Cl[(4 * q + g) * LDD + 16 * b + i16], cacc[b]);
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+              for (int b = 0; b < 4; ++b)
+                cacc[b] = mfma16(-Gt[m][tt][v], Cl[(16 * tt + 4 * g + v) * LDD + 16 * b + i16], cacc[b]);
 #pragma unroll
           for (int b = 0; b < 4; ++b)
             *reinterpret_cast<v4d *>(W + (r0 + 4 * g) + (c0 + 16 * b + i16) * np) = cacc[b];
         }
         __syncthreads();  // before the next chunk overwrites Cl
-      }
-
-      // 4. W[I, J] <- -W[I, J] Dinv from the register-held rows
-#pragma unroll
-      for (int m = 0; m < MSG; ++m) {
-        if (srow[m] < 0) continue;
-        const int r0 = srow[m];
-        v4d acc[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[b] = zero4();
-#pragma unroll
-        for (int q = 0; q < kGJ / 4; ++q)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[b] = mfma16(aI[m][q], Dl[(4 * q + g) * LDD + 16 * b + i16], acc[b]);
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          *reinterpret_cast<v4d *>(W + (r0 + 4 * g) + (j0 + 16 * b + i16) * np) = acc[b];
       }
     }
     // 5. W[J, J] <- Dinv
