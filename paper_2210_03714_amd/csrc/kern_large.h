@@ -27,7 +27,7 @@ namespace pfm {
 
 constexpr int kLB = 64;     // Gauss-Jordan block width
 constexpr int kLRows = 128; // rows per update workgroup (4 waves x 32)
-constexpr int kLKC = 1024;  // K chunk of the action-step GEMM
+constexpr int kLKC = 256;   // K chunk of the action-step GEMM (npad > 1024)
 
 // per-shift side buffers: colbuf[2] (npad x 64 column-major each), dinv (64 x 64)
 __host__ __device__ inline int64_t ln_stride(int np) { return 2 * (int64_t)np * kLB + kLB * kLB; }
@@ -403,6 +403,121 @@ ln_vreduce_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ili
         const int rr = r < D.hn ? r : r - D.hn;
         F[2 * ((int64_t)rr * D.ldf + c) + (r < D.hn ? 0 : 1)] = v;
       }
+    }
+  }
+}
+
+// All N steps of the action for one (instance, function, 16-column slab)
+// in one workgroup, for npad <= NPMAX <= 512: U (npad x 16) lives in LDS;
+// each wave computes its 16-row tiles of M U (M = R, or the phi1
+// approximant P on the phi1 chain's first step, scaled by 1/N) into
+// registers, then after a barrier writes them back into U; the phi1 chain
+// keeps u_1 in the instance's workspace (each thread rereads only what it
+// wrote) and adds it every later step.  Only barriers inside
+// the workgroup; M is read from memory every step (L2 / MALL).  The result
+// goes to the caller's output (row-major n x p; complex interleaved).
+// Grid: xcd over list entries x (chains x slabs).
+template <int NPMAX>
+__global__ void __launch_bounds__(256, 1)
+ln_steps_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nl, int nslab,
+                const PlanRec *__restrict__ plan, double *__restrict__ wsd, int want_exp,
+                int want_phi) {
+  constexpr int RT = NPMAX / 64;  // 16-row tiles per wave
+  __shared__ double Us[NPMAX * 16];
+  const int nchain = want_exp + want_phi;
+  int slot, sub;
+  xcd_map(blockIdx.x, nchain * nslab, slot, sub);
+  if (slot >= nl) return;
+  const int ch = sub / nslab, slab = sub % nslab;
+  const bool phi = ch == 1 || !want_exp;
+  const int ii = ilist[slot];
+  const InstDesc D = inst[ii];
+  const int np = D.npad, nr = D.n, hn = D.hn, emb = D.emb, p = D.p;
+  const int c0 = slab * 16;
+  if (np > NPMAX || c0 >= p) return;  // uniform over the workgroup
+  const int N = plan[ii].s;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int i16 = lane & 15, g = lane >> 4;
+  const int ar = arow(i16);
+  const double *Rm = wsd + D.r_off;
+  const double *Pm = Rm + 2 * (int64_t)np * np;
+  const int pp = ln_pp(p);
+  double *U1 = wsd + D.v_off + ch * ln_vchain(np, p) + 2 * (int64_t)np * pp;  // row-major np x pp
+
+  for (int e = t; e < np * 16; e += 256) {  // U = V[:, slab] (real: rows < n; emb: [Re; Im])
+    const int r = e >> 4, c = c0 + (e & 15);
+    double v = 0.0;
+    if (c < p && r < nr) {
+      if (!emb) {
+        v = D.V[(int64_t)r * D.ldv + c];
+      } else {
+        const int rr = r < hn ? r : r - hn;
+        v = D.cin ? D.V[2 * ((int64_t)rr * D.ldv + c) + (r < hn ? 0 : 1)] : (r < hn ? D.V[(int64_t)rr * D.ldv + c] : 0.0);
+      }
+    }
+    Us[e] = v;
+  }
+  __syncthreads();
+
+  constexpr int RTP = RT < 4 ? RT : 4;  // tiles per pass (register budget)
+  constexpr int NPASS = RT / RTP;
+#pragma unroll 1
+  for (int j = 1; j <= N; ++j) {
+    const double *M = (phi && j == 1) ? Pm : Rm;
+    double *Un = wsd + D.v_off + ch * ln_vchain(np, p) + (int64_t)(j & 1) * np * pp;  // new U (row-major)
+#pragma unroll 1
+    for (int pass = 0; pass < NPASS; ++pass) {
+      v4d acc[RTP];
+#pragma unroll
+      for (int rt = 0; rt < RTP; ++rt) acc[rt] = zero4();
+#pragma unroll 2
+      for (int k0 = 0; k0 < nr; k0 += 4) {
+        const int kc = k0 + g;
+        const double b = kc < nr ? Us[kc * 16 + i16] : 0.0;
+#pragma unroll
+        for (int rt = 0; rt < RTP; ++rt) {
+          const int r = (wave + 4 * (pass * RTP + rt)) * 16 + ar;
+          double a = 0.0;
+          if (r < nr && kc < nr) {
+            if (!emb || kc < hn) a = M[r + (int64_t)kc * np];
+            else a = r < hn ? -M[(r + hn) + (int64_t)(kc - hn) * np] : M[(r - hn) + (int64_t)(kc - hn) * np];
+          }
+          acc[rt] = mfma16(a, b, acc[rt]);
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < RTP; ++rt) {
+        const int r = (wave + 4 * (pass * RTP + rt)) * 16 + 4 * g;
+        if (r >= np) continue;
+        if (phi) {
+          double *u = U1 + (int64_t)r * pp + c0 + i16;
+          if (j == 1) {
+            acc[rt] = acc[rt] * (1.0 / (double)N);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) u[(int64_t)v * pp] = acc[rt][v];
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[rt][v] += u[(int64_t)v * pp];
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Un[(int64_t)(r + v) * pp + c0 + i16] = acc[rt][v];
+      }
+    }
+    __syncthreads();  // every wave has read U and written its rows of the new U
+    for (int e = t; e < np * 16; e += 256) Us[e] = Un[(int64_t)(e >> 4) * pp + c0 + (e & 15)];
+    __syncthreads();  // the new U is in LDS
+  }
+  double *F = phi ? D.Fp : D.Fe;
+  for (int e = t; e < nr * 16; e += 256) {
+    const int r = e >> 4, c = c0 + (e & 15);
+    if (c >= p) continue;
+    const double v = Us[e];
+    if (!emb) {
+      F[(int64_t)r * D.ldf + c] = v;
+    } else {
+      const int rr = r < hn ? r : r - hn;
+      F[2 * ((int64_t)rr * D.ldf + c) + (r < hn ? 0 : 1)] = v;
     }
   }
 }

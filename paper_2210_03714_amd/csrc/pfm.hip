@@ -681,6 +681,21 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   for (int c = 0; c < 4; ++c) ln_cls_off[c + 1] += ln_cls_off[c];
   const int ln_off_l = (int)lists.size();
   lists.insert(lists.end(), ln_list.begin(), ln_list.end());
+  // action steps: npad <= 256 / 512 run all steps in one workgroup per
+  // (instance, function, column slab); larger ones step by step over many
+  // workgroups (one workgroup would hold a CU for too long)
+  std::vector<int> act_list[4];
+  int act_off[4] = {0, 0, 0, 0};
+  if (action) {
+    for (int i : ln_list) {
+      const int np_i = desc[i].npad;
+      act_list[np_i <= 256 ? 0 : np_i <= 512 ? 1 : 3].push_back(i);
+    }
+    for (int c = 0; c < 4; ++c) {
+      act_off[c] = (int)lists.size();
+      lists.insert(lists.end(), act_list[c].begin(), act_list[c].end());
+    }
+  }
   const int skip_off_l = (int)lists.size();
   lists.insert(lists.end(), skip_list.begin(), skip_list.end());
   bool any_fast = false;
@@ -886,26 +901,51 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
         hipLaunchKernelGGL(square_level_f64_kernel<1>, dim3(e.second), dim3(256), 0, stream, d_desc,
                            dt + e.first, e.second, 1, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);
       const int nchain = T.want_exp + T.want_phi;
-      hipLaunchKernelGGL(ln_vprep_kernel, dim3(ln_npm / 64, nln), dim3(256), 0, stream, d_desc, dl, nchain, wsd);
+      for (int c = 0; c < 3; ++c) {  // one launch runs all N steps
+        const int nl = (int)act_list[c].size();
+        if (!nl) continue;
+        int maxp = 1;
+        for (int i : act_list[c]) maxp = std::max(maxp, desc[i].p);
+        const int nslab = (maxp + 15) / 16;
+        const int *dla = d_list + act_off[c];
+        const dim3 gs(xcd_grid(nl, nchain * nslab));
+        if (c == 0)
+          hipLaunchKernelGGL(ln_steps_kernel<256>, gs, dim3(256), 0, stream, d_desc, dla, nl, nslab, d_plan, wsd,
+                             T.want_exp, T.want_phi);
+        if (c == 1)
+          hipLaunchKernelGGL(ln_steps_kernel<512>, gs, dim3(256), 0, stream, d_desc, dla, nl, nslab, d_plan, wsd,
+                             T.want_exp, T.want_phi);
+        ctx->cur_launches[1]++;
+      }
+      const int nbig = (int)act_list[3].size();
+      const int *dlb = d_list + act_off[3];
+      int big_npm = 0, big_nmax = 0;
+      for (int i : act_list[3]) {
+        big_npm = std::max(big_npm, desc[i].npad);
+        big_nmax = std::max(big_nmax, h_plan[i].s);
+      }
+      if (nbig)
+        hipLaunchKernelGGL(ln_vprep_kernel, dim3(big_npm / 64, nbig), dim3(256), 0, stream, d_desc, dlb, nchain,
+                           wsd);
       int ppmask = 0, ksmax = 1;
-      for (int i : ln_list) {
+      for (int i : act_list[3]) {
         ppmask |= 1 << (ln_pp(desc[i].p) / 16 - 1);
         ksmax = std::max(ksmax, ln_ks(desc[i].n));
       }
-      const int nsub = (ln_npm / 64) * ksmax;
-      const dim3 gv(xcd_grid(nln, nsub));
-      for (int j = 1; j <= ln_nmax; ++j) {
+      const int nsub = (big_npm / 64) * ksmax;
+      const dim3 gv(xcd_grid(nbig, nsub));
+      for (int j = 1; nbig && j <= big_nmax; ++j) {
         for (int ch = 0; ch < nchain; ++ch) {
           const int phi = (ch == 1 || !T.want_exp) ? 1 : 0;
           const int use_p = phi && j == 1;
           const int inb = (j - 1) & 1, outb = j & 1;
 #define PFM_GEMV(PPV)                                                                              \
   if (ppmask & (1 << (PPV / 16 - 1)))                                                            \
-    hipLaunchKernelGGL(ln_gemv_kernel<PPV>, gv, dim3(256), 0, stream, d_desc, dl, nln, nsub, d_plan, \
+    hipLaunchKernelGGL(ln_gemv_kernel<PPV>, gv, dim3(256), 0, stream, d_desc, dlb, nbig, nsub, d_plan, \
                        wsd, j, ch, use_p, inb);
           PFM_GEMV(16) PFM_GEMV(32) PFM_GEMV(48) PFM_GEMV(64)
 #undef PFM_GEMV
-          hipLaunchKernelGGL(ln_vreduce_kernel, dim3(ln_npm / 64, nln), dim3(256), 0, stream, d_desc, dl,
+          hipLaunchKernelGGL(ln_vreduce_kernel, dim3(big_npm / 64, nbig), dim3(256), 0, stream, d_desc, dlb,
                              d_plan, wsd, j, ch, outb, 1.0, phi);
           ctx->cur_launches[1] += 2;
         }
