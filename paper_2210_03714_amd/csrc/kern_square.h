@@ -2,8 +2,11 @@
 // doubling step Phi <- (R + I) Phi / 2, which uses R before it is squared
 // (phi1(2B) = (e^B + I) phi1(B) / 2).
 //
-// Every instance has its own s.  Level j (j = 1..max s) is one launch over
-// the 64 x 64 output tiles of the instances with s >= j; the host builds the
+// Every instance has its own s.  Level j (j = 1..max s) is one launch per
+// tile size over the output tiles of the instances with s >= j (128 x 128
+// tiles for npad >= 256, 64 x 64 below: each wave owns a (TILE/2)^2 block of
+// 16 x 16 MFMA tiles, so the larger tile does 16 MFMAs per 8 LDS reads and
+// 64 MFMAs between barriers); the host builds the
 // task list from the plan it read back, ordering it so that all tiles of one
 // instance land on one XCD (workgroup b runs on XCD b mod 8) and share its L2.
 // Buffers ping-pong: level j reads buffer (j-1) mod 2 and writes j mod 2.
@@ -35,13 +38,17 @@ struct SqTask {
 // MODE 2: B T for the large instances: T from buffer 1 (3), B from the
 //         row-major A as in MODE 1, output in the factor buffer slot 0 (1),
 //         all npad columns.
-template <int MODE>
-__global__ void __launch_bounds__(256)
+template <int MODE, int TILE>
+__global__ void __launch_bounds__(256, 2)
 square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restrict__ tasks,
                         int ntasks, int level, double *__restrict__ wsd,
                         const PlanRec *__restrict__ plan, double a0e, double a0p,
                         double a1e = 0.0, double a1p = 0.0) {
-  constexpr int LDA = 80, LDB = 80;  // == 16 mod 32 doubles: conflict-free fragment reads
+  static_assert(TILE == 64 || TILE == 128, "tile");
+  constexpr int LDA = TILE + 16, LDB = TILE + 16;  // == 16 mod 32 doubles: conflict-free fragment reads
+  constexpr int NP = TILE / 64;   // staging passes per operand
+  constexpr int WT = TILE / 2;    // per-wave output block
+  constexpr int NT = WT / 16;     // MFMA tiles per wave and dimension
   __shared__ double As[16 * LDA];
   __shared__ double Bs[16 * LDB];
   const int q = blockIdx.x;
@@ -52,8 +59,8 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
   const int np = D.npad, nr = D.n, ncol = D.ncol, hn = D.hn, emb = D.emb;
   const int which = tk.tile >> 20;
   const int lt = tk.tile & ((1 << 20) - 1);
-  const int tl = (np + kSqTile - 1) / kSqTile;
-  const int m0 = (lt % tl) * kSqTile, n0 = (lt / tl) * kSqTile;
+  const int tl = (np + TILE - 1) / TILE;
+  const int m0 = (lt % tl) * TILE, n0 = (lt / tl) * TILE;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int i16 = lane & 15, g = lane >> 4;
   const int ar = arow(i16);
@@ -87,72 +94,79 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
     return act ? a / (double)sdiv : ldexp(a, -sdiv);
   };
 
-  // per-thread staging: A tile 64x16 (4 consecutive rows of one k column),
-  // B tile 16x64 (4 consecutive k of one column)
+  // per-thread staging, in NP passes of 64 rows (A) / columns (B): A tile
+  // TILE x 16 (4 consecutive rows of one k column), B tile 16 x TILE (4
+  // consecutive k of one column)
   const int ak = t >> 4, ar0 = (t & 15) * 4;
   const int bc = t >> 2, bk0 = (t & 3) * 4;
-  double ra[4], rbv[4];
+  double ra[NP][4], rbv[NP][4];
   // MODE 1 reads B row-major: 4 consecutive columns of one row per thread;
   // MODE 2 reads its A operand (B) row-major: 4 consecutive k of one row
   const int bk1 = t >> 4, bc1 = (t & 15) * 4;
   const int ar2 = t >> 2, ak2 = (t & 3) * 4;
   auto load = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = m0 + ar0 + u, kc = k0 + ak;
-      double a = 0.0;
-      if (MODE == 2) {
-        a = bval(m0 + ar2, k0 + ak2 + u);
-      } else if (MODE == 1) {
-        a = (r < np) ? Asrc[r + (int64_t)kc * np] : 0.0;
-      } else if (r < nr && kc < nr) {
-        if (!emb || kc < hn)
-          a = Asrc[r + (int64_t)kc * np];
-        else
-          a = r < hn ? -Asrc[(r + hn) + (int64_t)(kc - hn) * np] : Asrc[(r - hn) + (int64_t)(kc - hn) * np];
-      }
-      if (MODE == 0 && which && r == kc) a += 1.0;  // (R + I) for the phi1 doubling
-      ra[u] = a;
-      if (MODE == 0) {
-        const int c = n0 + bc;
-        rbv[u] = (c < ncol) ? Bsrc[(k0 + bk0 + u) + (int64_t)c * np] : 0.0;
-      } else if (MODE == 2) {
-        const int c = n0 + bc;
-        rbv[u] = Bsrc[(k0 + bk0 + u) + (int64_t)c * np];
-      } else {
-        rbv[u] = bval(k0 + bk1, n0 + bc1 + u);
+    for (int ps = 0; ps < NP; ++ps) {
+      const int mo = m0 + 64 * ps, no = n0 + 64 * ps;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = mo + ar0 + u, kc = k0 + ak;
+        double a = 0.0;
+        if (MODE == 2) {
+          a = bval(mo + ar2, k0 + ak2 + u);
+        } else if (MODE == 1) {
+          a = (r < np) ? Asrc[r + (int64_t)kc * np] : 0.0;
+        } else if (r < nr && kc < nr) {
+          if (!emb || kc < hn)
+            a = Asrc[r + (int64_t)kc * np];
+          else
+            a = r < hn ? -Asrc[(r + hn) + (int64_t)(kc - hn) * np] : Asrc[(r - hn) + (int64_t)(kc - hn) * np];
+        }
+        if (MODE == 0 && which && r == kc) a += 1.0;  // (R + I) for the phi1 doubling
+        ra[ps][u] = a;
+        if (MODE == 0) {
+          const int c = no + bc;
+          rbv[ps][u] = (c < ncol) ? Bsrc[(k0 + bk0 + u) + (int64_t)c * np] : 0.0;
+        } else if (MODE == 2) {
+          const int c = no + bc;
+          rbv[ps][u] = (c < np) ? Bsrc[(k0 + bk0 + u) + (int64_t)c * np] : 0.0;
+        } else {
+          rbv[ps][u] = bval(k0 + bk1, no + bc1 + u);
+        }
       }
     }
   };
 
-  v4d acc[2][2];
+  v4d acc[NT][NT];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = zero4();
+    for (int b = 0; b < NT; ++b) acc[a][b] = zero4();
 
   load(0);
   for (int k0 = 0; k0 < np; k0 += 16) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (MODE == 2) As[ar2 + (ak2 + u) * LDA] = ra[u];
-      else As[ar0 + u + ak * LDA] = ra[u];
-      if (MODE != 1) Bs[(bk0 + u) * LDB + bc] = rbv[u];
-      else Bs[bk1 * LDB + bc1 + u] = rbv[u];
-    }
+    for (int ps = 0; ps < NP; ++ps)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (MODE == 2) As[64 * ps + ar2 + (ak2 + u) * LDA] = ra[ps][u];
+        else As[64 * ps + ar0 + u + ak * LDA] = ra[ps][u];
+        if (MODE != 1) Bs[(bk0 + u) * LDB + 64 * ps + bc] = rbv[ps][u];
+        else Bs[bk1 * LDB + 64 * ps + bc1 + u] = rbv[ps][u];
+      }
     __syncthreads();
     if (k0 + 16 < np) load(k0 + 16);
 #pragma unroll
     for (int qq = 0; qq < 4; ++qq) {
-      double av[2], bv[2];
+      double av[NT], bv[NT];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[(32 * wm + 16 * a + ar) + (4 * qq + g) * LDA];
+      for (int a = 0; a < NT; ++a) av[a] = As[(WT * wm + 16 * a + ar) + (4 * qq + g) * LDA];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[(4 * qq + g) * LDB + 32 * wn + 16 * b + i16];
+      for (int b = 0; b < NT; ++b) bv[b] = Bs[(4 * qq + g) * LDB + WT * wn + 16 * b + i16];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < NT; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < NT; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
     }
     __syncthreads();
   }
@@ -161,11 +175,11 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
   const double lin = q1 ? (which ? a1p : a1e) : 0.0;
   const int oc = MODE == 2 ? np : ncol;  // computed columns
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int c = n0 + 32 * wn + 16 * b + i16;
-      const int r = m0 + 32 * wm + 16 * a + 4 * g;
+    for (int b = 0; b < NT; ++b) {
+      const int c = n0 + WT * wn + 16 * b + i16;
+      const int r = m0 + WT * wm + 16 * a + 4 * g;
       if (c < oc && r < np) {
         v4d o = acc[a][b] * scl;
         if (MODE == 1) {

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdarg>
 #include <map>
 #include <cmath>
@@ -702,17 +703,20 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   for (int i = 0; i < batch; ++i) any_fast |= is_fast[i] != 0;
 
   // GEMM task lists: level 0 = R = a0 I + S B for the Gauss-Jordan instances,
-  // levels 1..smax = squarings.  All tiles of one instance go to one XCD.
+  // levels 1..smax = squarings, and the B T products of the multi-workgroup
+  // route; per level one list per tile size (128 for npad >= 256, else 64).
+  // All tiles of one instance go to one XCD.
   std::vector<SqTask> all;
-  std::vector<std::pair<int64_t, int>> lv;  // (offset, count) per level
-  const int jtop = action ? 0 : smax;  // the action has no squarings
-  for (int j = 0; j <= jtop; ++j) {
+  using LevelLists = std::array<std::pair<int64_t, int>, 2>;  // (offset, count) per tile size
+  auto tile_of = [&](int i) { return desc[i].npad >= 256 ? 1 : 0; };
+  auto build = [&](const std::vector<int> &ids, int tc, bool all_cols) {
     std::vector<std::vector<SqTask>> qx(8);
     int x = 0;
-    for (int i = 0; i < batch; ++i) {
-      if (skip[i] || (j == 0 ? !is_fast[i] : svec[i] < j)) continue;
-      const int tlm = (desc[i].npad + kSqTile - 1) / kSqTile;
-      const int tln = (desc[i].ncol + kSqTile - 1) / kSqTile;
+    const int TL = tc ? 128 : 64;
+    for (int i : ids) {
+      if (tile_of(i) != tc) continue;
+      const int tlm = (desc[i].npad + TL - 1) / TL;
+      const int tln = ((all_cols ? desc[i].npad : desc[i].ncol) + TL - 1) / TL;
       for (int w = 0; w < 1 + T.want_phi; ++w)
         for (int tt = 0; tt < tlm * tln; ++tt) qx[x].push_back(SqTask{i, tt + (w << 20)});
       x = (x + 1) & 7;
@@ -722,26 +726,18 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     const int64_t off = (int64_t)all.size();
     for (size_t qq = 0; qq < mx; ++qq)
       for (int xx = 0; xx < 8; ++xx) all.push_back(qq < qx[xx].size() ? qx[xx][qq] : SqTask{-1, 0});
-    lv.emplace_back(off, (int)(mx * 8));
+    return std::make_pair(off, (int)(mx * 8));
+  };
+  std::vector<LevelLists> lv;
+  const int jtop = action ? 0 : smax;  // the action has no squarings
+  for (int j = 0; j <= jtop; ++j) {
+    std::vector<int> ids;
+    for (int i = 0; i < batch; ++i)
+      if (!skip[i] && (j == 0 ? is_fast[i] != 0 : svec[i] >= j)) ids.push_back(i);
+    lv.push_back(LevelLists{build(ids, 0, false), build(ids, 1, false)});
   }
   // B T products (all npad columns) of the large instances, before level 0
-  std::pair<int64_t, int> lvbt(0, 0);
-  {
-    std::vector<std::vector<SqTask>> qx(8);
-    int x = 0;
-    for (int i : ln_list) {
-      const int tl = desc[i].npad / kSqTile;
-      for (int w = 0; w < 1 + T.want_phi; ++w)
-        for (int tt = 0; tt < tl * tl; ++tt) qx[x].push_back(SqTask{i, tt + (w << 20)});
-      x = (x + 1) & 7;
-    }
-    size_t mx = 0;
-    for (auto &q : qx) mx = std::max(mx, q.size());
-    lvbt.first = (int64_t)all.size();
-    for (size_t qq = 0; qq < mx; ++qq)
-      for (int xx = 0; xx < 8; ++xx) all.push_back(qq < qx[xx].size() ? qx[xx][qq] : SqTask{-1, 0});
-    lvbt.second = (int)(mx * 8);
-  }
+  const LevelLists lvbt{build(ln_list, 0, true), build(ln_list, 1, true)};
   // alpha1 = sum_k w_k of the binary64 weights, summed in extended precision
   double a1e = 0.0, a1p = 0.0;
   {
@@ -783,6 +779,18 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   // Everything from here on depends only on what the host has decided (the
   // descriptors, plans, lists and task lists); a call that repeats all of it
   // replays a captured graph of this sequence.
+  // one launch per tile size with tasks
+#define PFM_SQ(MODE, LL, LEVEL)                                                                     \
+  do {                                                                                              \
+    if ((LL)[0].second)                                                                             \
+      hipLaunchKernelGGL((square_level_f64_kernel<MODE, 64>), dim3((LL)[0].second), dim3(256), 0, stream, \
+                         d_desc, dt + (LL)[0].first, (LL)[0].second, LEVEL, wsd, d_plan, T.a0e, T.a0p, a1e,  \
+                         a1p);                                                                      \
+    if ((LL)[1].second)                                                                             \
+      hipLaunchKernelGGL((square_level_f64_kernel<MODE, 128>), dim3((LL)[1].second), dim3(256), 0,  \
+                         stream, d_desc, dt + (LL)[1].first, (LL)[1].second, LEVEL, wsd, d_plan, T.a0e,     \
+                         T.a0p, a1e, a1p);                                                          \
+  } while (0)
   auto enqueue = [&]() -> int {
   if (!skip_list.empty())
     hipLaunchKernelGGL(mark_status_kernel, dim3(((int)skip_list.size() + 255) / 256), dim3(256), 0, stream,
@@ -893,13 +901,8 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
       const int chunks = (int)(((int64_t)ln_npm * ln_npm / 4 + 255) / 256);
       const int *dl = d_list + ln_off_l;
       hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nln), dim3(256), 0, stream, d_desc, dl, T, wsd, d_plan);
-      if (lvbt.second)  // level argument 1: B = A / N
-        hipLaunchKernelGGL(square_level_f64_kernel<2>, dim3(lvbt.second), dim3(256), 0, stream, d_desc,
-                           dt + lvbt.first, lvbt.second, 1, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);
-      const auto &e = lv[0];
-      if (e.second)
-        hipLaunchKernelGGL(square_level_f64_kernel<1>, dim3(e.second), dim3(256), 0, stream, d_desc,
-                           dt + e.first, e.second, 1, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);
+      PFM_SQ(2, lvbt, 1);  // level argument 1: B = A / N
+      PFM_SQ(1, lv[0], 1);
       const int nchain = T.want_exp + T.want_phi;
       for (int c = 0; c < 3; ++c) {  // one launch runs all N steps
         const int nl = (int)act_list[c].size();
@@ -1008,13 +1011,8 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     if (nln)
       hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nln), dim3(256), 0, stream, d_desc,
                          d_list + ln_off_l, T, wsd, d_plan);
-    if (lvbt.second)
-      hipLaunchKernelGGL(square_level_f64_kernel<2>, dim3(lvbt.second), dim3(256), 0, stream, d_desc,
-                         dt + lvbt.first, lvbt.second, 0, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);
-    const auto &e = lv[0];
-    if (e.second)
-      hipLaunchKernelGGL(square_level_f64_kernel<1>, dim3(e.second), dim3(256), 0, stream, d_desc,
-                         dt + e.first, e.second, 0, wsd, d_plan, T.a0e, T.a0p, a1e, a1p);
+    PFM_SQ(2, lvbt, 0);
+    PFM_SQ(1, lv[0], 0);
     ctx->cur_launches[1] += 2;
   }
   for (int c = 0; c < 3 && !mixed; ++c) {
@@ -1040,10 +1038,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   prof_mark(ctx, 2, stream);
   // 4. squaring levels, one launch per level
   for (int j = 1; j <= smax; ++j) {
-    const auto &e = lv[j];
-    if (!e.second) continue;
-    hipLaunchKernelGGL(square_level_f64_kernel<0>, dim3(e.second), dim3(256), 0, stream, d_desc,
-                       dt + e.first, e.second, j, wsd, d_plan, 0.0, 0.0);
+    PFM_SQ(0, lv[j], j);
     ctx->cur_launches[2]++;
   }
   prof_mark(ctx, 3, stream);
