@@ -22,44 +22,32 @@
 // Each wave keeps its 16-row strips of W[I,J] in registers (MFMA A operand)
 // for the whole step; each 64-column chunk of the transformed row block is
 // staged once in LDS and is the B operand of the update, so the inner loops
-// read only registers and LDS.
+// read only registers and LDS.  M itself is never stored: the first step
+// reads its elements from A as it goes (the update is bound by memory
+// traffic, and this saves one write and one read of the whole matrix).
 #pragma once
+#include <type_traits>
+
 #include "kern_common.h"
 
 namespace pfm {
 
 constexpr int kGJ = 64;
 
-// Loads M = I - c B (B = A 2^-s, or A / N) column-major into W: the same
-// transposed load as the LU kernel, for a real non-embedded instance.
-__device__ __forceinline__ void load_shifted(const InstDesc &D, double c, int s_or_n, int action,
-                                             double *__restrict__ W, double *tile) {
-  const int n = D.n, np = D.npad, t = threadIdx.x;
-  const double cs = ldexp(c, -s_or_n);
-  const double Nd = (double)s_or_n;
-  for (int tr = 0; tr < np; tr += 32) {
-    for (int tc = 0; tc < np; tc += 32) {
-      const int rl = t >> 3, cl = (t & 7) * 4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = tr + rl, cc = tc + cl + u;
-        tile[rl * 33 + cl + u] = (r < n && cc < n) ? D.A[(int64_t)r * D.lda + cc] : 0.0;
-      }
-      __syncthreads();
-      const int cc = tc + rl;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = tr + cl + u;
-        if (r < np && cc < np) {
-          const double a = tile[(cl + u) * 33 + rl];
-          const double cb = action ? c * (a / Nd) : cs * a;
-          W[r + (int64_t)cc * np] = (r == cc ? 1.0 : 0.0) - cb;
-        }
-      }
-      __syncthreads();
-    }
+// Element (r, c) of M = I - c_k B (B = A 2^-s, or A / N for the action) of
+// a real non-embedded instance, from row-major A; identity in the padding.
+template <bool ACT>
+struct ShiftedA {
+  const double *A;
+  int64_t lda;
+  int n;
+  double ck, cs, Nd;
+  __device__ __forceinline__ double operator()(int r, int c) const {
+    const double a = (r < n && c < n) ? A[(int64_t)r * lda + c] : 0.0;
+    const double cb = ACT ? ck * (a / Nd) : cs * a;
+    return (r == c ? 1.0 : 0.0) - cb;
   }
-}
+};
 
 // 64 x 64 Gauss-Jordan inverse without interchanges of the block held
 // row-major in LDS (leading dimension LDD), in place.  Each of the 256
@@ -140,10 +128,11 @@ __device__ __forceinline__ void gj64_regs(double *Dl, double *bcc, double *bcr, 
     for (int b = 0; b < 4; ++b) Dl[(pr0 + a) * LDD + pc0 + b] = x[a][b];
 }
 
-template <int NPMAX>
+// ACT: B = A / N (the action's steps) instead of A 2^-s.
+template <int NPMAX, bool ACT>
 __global__ void __launch_bounds__(256, 2)
 gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nlist,
-              PlanRec *__restrict__ plan, Terms T, double *__restrict__ wsd, int action, int route_val) {
+              PlanRec *__restrict__ plan, Terms T, double *__restrict__ wsd, int route_val) {
   constexpr int LDD = kGJ + 1;
   __shared__ double Dl[kGJ * LDD];      // D, then D^{-1} (row-major, padded)
   __shared__ double Cl[kGJ * LDD];      // staging for the row-block product
@@ -163,20 +152,26 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   const int nJ = np / kGJ;
   if (route_val >= 0 && k == 0 && t == 0) plan[ii].route = route_val;
 
-  load_shifted(D, T.c_re[k], plan[ii].s, action, W, Cl);
+  const ShiftedA<ACT> M0{D.A, D.lda, D.n, T.c_re[k], ldexp(T.c_re[k], -plan[ii].s), (double)plan[ii].s};
 
   // this thread's 4 x 4 patch of a 64 x 64 block, and its place in
   // coalesced block copies (one row per lane, columns (t >> 6) + 4 u)
   const int pr0 = (t >> 4) * 4, pc0 = (t & 15) * 4;
   const int cr = t & 63, cc0 = t >> 6;
 
-#pragma unroll 1
-  for (int J = 0; J < nJ; ++J) {
+  // one block step; the first reads M from A (FIRST), the others from W
+  auto step = [&](const int J, auto first_tag) {
+    constexpr bool FIRST = decltype(first_tag)::value;
     const int j0 = J * kGJ;
     // 1. Dinv in LDS by Gauss-Jordan without interchanges
+    if constexpr (FIRST) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
-      Dl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (j0 + cc0 + 4 * u) * np];
+      for (int u = 0; u < 16; ++u) Dl[(cc0 + 4 * u) * LDD + cr] = M0(cc0 + 4 * u, cr);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        Dl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (j0 + cc0 + 4 * u) * np];
+    }
     __syncthreads();
     gj64_regs<LDD>(Dl, bcc, bcr, pr0, pc0);
     __syncthreads();
@@ -216,7 +211,7 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
         // 16 tt + ar(i) (= Dinv columns), B = W[r0 + ar(j), j0 + k]
 #pragma unroll
         for (int q = 0; q < kGJ / 4; ++q) {
-          const double bv = W[(r0 + ar) + (j0 + 4 * q + g) * np];
+          const double bv = FIRST ? M0(r0 + ar, 4 * q + g) : W[(r0 + ar) + (j0 + 4 * q + g) * np];
 #pragma unroll
           for (int tt = 0; tt < 4; ++tt)
             Gt[m][tt] = mfma16(Dl[(4 * q + g) * LDD + 16 * tt + ar], bv, Gt[m][tt]);
@@ -232,9 +227,14 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
       for (int C = 0; C < nJ; ++C) {
         if (C == J) continue;
         const int c0 = C * kGJ;
+        if constexpr (FIRST) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-          Cl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (c0 + cc0 + 4 * u) * np];
+          for (int u = 0; u < 16; ++u) Cl[(cc0 + 4 * u) * LDD + cr] = M0(cc0 + 4 * u, c0 + cr);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            Cl[cr * LDD + cc0 + 4 * u] = W[(j0 + cr) + (c0 + cc0 + 4 * u) * np];
+        }
         __syncthreads();
         if (grp == NG - 1) {
           // W[J, C] <- Dinv W_old[J, C]: this wave's 32 x 32 part
@@ -268,9 +268,16 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
           if (srow[m] < 0) continue;
           const int r0 = srow[m];
           v4d cacc[4];
+          if constexpr (FIRST) {
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
-            cacc[b] = *reinterpret_cast<const v4d *>(W + (r0 + 4 * g) + (c0 + 16 * b + i16) * np);
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) cacc[b][v] = M0(r0 + 4 * g + v, c0 + 16 * b + i16);
+          } else {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              cacc[b] = *reinterpret_cast<const v4d *>(W + (r0 + 4 * g) + (c0 + 16 * b + i16) * np);
+          }
 #pragma unroll
           for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
@@ -290,7 +297,10 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
     for (int u = 0; u < 16; ++u)
       W[(j0 + cr) + (j0 + cc0 + 4 * u) * np] = Dl[cr * LDD + cc0 + 4 * u];
     __syncthreads();
-  }
+  };
+  step(0, std::true_type{});
+#pragma unroll 1
+  for (int J = 1; J < nJ; ++J) step(J, std::false_type{});
 }
 
 // S_e = sum_k we_k X_k, S_p = sum_k wp_k X_k (binary64, fixed order k = 0..),

@@ -807,9 +807,9 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     if (!nl) continue;
     const int *dl = d_list + fast_off[c];
     const dim3 gg(xcd_grid(nl, nterms));
-    if (c == 0) hipLaunchKernelGGL(gj_inv_kernel<128>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0, 1);
-    if (c == 1) hipLaunchKernelGGL(gj_inv_kernel<256>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0, 1);
-    if (c == 2) hipLaunchKernelGGL(gj_inv_kernel<512>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 0, 1);
+    if (c == 0) hipLaunchKernelGGL((gj_inv_kernel<128, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 1);
+    if (c == 1) hipLaunchKernelGGL((gj_inv_kernel<256, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 1);
+    if (c == 2) hipLaunchKernelGGL((gj_inv_kernel<512, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 1);
     ctx->cur_launches[0]++;
   }
   for (int c = 0; c < 3; ++c) {
@@ -839,10 +839,17 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     if (!nl) continue;
     const int *dl = d_list + ln_off_l + ln_cls_off[c];
     const dim3 gg(xcd_grid(nl, nterms));
-    const int am = action ? 1 : 0;
-    if (c == 0) hipLaunchKernelGGL(gj_inv_kernel<128>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, am, -1);
-    if (c == 1) hipLaunchKernelGGL(gj_inv_kernel<256>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, am, -1);
-    if (c == 2) hipLaunchKernelGGL(gj_inv_kernel<512>, gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, am, -1);
+#define PFM_GJ_LN(NPM)                                                                             \
+  do {                                                                                             \
+    if (action)                                                                                    \
+      hipLaunchKernelGGL((gj_inv_kernel<NPM, true>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, -1); \
+    else                                                                                           \
+      hipLaunchKernelGGL((gj_inv_kernel<NPM, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, -1); \
+  } while (0)
+    if (c == 0) PFM_GJ_LN(128);
+    if (c == 1) PFM_GJ_LN(256);
+    if (c == 2) PFM_GJ_LN(512);
+#undef PFM_GJ_LN
     ctx->cur_launches[0]++;
   }
   if (ln_cls_off[4] > ln_cls_off[3]) {
