@@ -13,8 +13,10 @@ coefficients  exact rational shift/weight sets (Vandermonde system of §2)
 theta         forward error bound and the admissible-norm table θ (§3)
 method        the algorithm itself: norm, plan, shifted LU solves, round-off
               form combination, squaring / N-step recurrence (§1, §2, §4.3)
+banded        the N-step action for a tridiagonal A with tridiagonal LU
+              solves (§2.1, §5)
 
 Every function cites the passage of the paper it follows.
 """
 
-from . import coefficients, theta, method  # noqa: F401
+from . import coefficients, theta, method, banded  # noqa: F401

@@ -1,0 +1,118 @@
+"""The action f(A)V for a tridiagonal A, step by step, in plain FP64 (oracle side).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+A is given by its three diagonals: dl (A[i+1, i], length d - 1), dd (A[i, i],
+length d) and du (A[i, i+1], length d - 1).  The algorithm is the N-step
+recurrence of ``method.action`` (§1, §2, §4.3), written for this storage as
+the paper does for tridiagonal matrices (§2.1, §5): I - c_k B is again
+tridiagonal, so each shifted system is solved by a tridiagonal LU (LAPACK
+gttrf once per shift, gttrs per solve; §5.1 reuses the factors across
+steps), and B v costs one tridiagonal product.
+
+  1. eta = ||A||_1, the largest column sum |du[j-1]| + |dd[j]| + |dl[j]|;
+     θ = θ(f, m, tol); N = max(1, ceil(eta / θ)); B = A / N entry by entry.
+  2. For each shift c_k: the LU of M_k = I - c_k B (subdiagonal -c_k dl/N,
+     diagonal 1 - c_k dd/N, superdiagonal -c_k du/N).
+  3. r(B) y = a0 y + sum_k w_k M_k^{-1} (B y)   (round-off form, §4.3)
+     exp:  v_0 = V, v_j = r(B) v_{j-1}, j = 1..N
+     phi1: u_1 = rho(B) V / N, u_{j+1} = r(B) u_j + u_1 (rho the phi1
+           approximant), and u_N = phi1(A) V.
+
+The only library primitives are LAPACK gttrf / gttrs.
+"""
+
+import numpy as np
+import scipy.linalg.lapack as lapack
+
+from . import method
+
+
+def tri_dense(dl, dd, du):
+    """The dense d x d matrix with the given diagonals."""
+    return np.diag(dd) + np.diag(dl, -1) + np.diag(du, 1)
+
+
+def tri_norm1(dl, dd, du):
+    """||A||_1: the largest column sum of |a_ij| over the three diagonals."""
+    s = np.abs(np.asarray(dd, dtype=np.float64)).copy()
+    s[1:] += np.abs(du)
+    s[:-1] += np.abs(dl)
+    return float(s.max())
+
+
+def tri_matvec(dl, dd, du, X):
+    """A X for tridiagonal A (the 5d-flop product of §2.1), X of shape d x p."""
+    Y = dd[:, None] * X
+    Y[1:] += dl[:, None] * X[:-1]
+    Y[:-1] += du[:, None] * X[1:]
+    return Y
+
+
+def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
+    """f(A) V for a real tridiagonal A and real V (d x p) by the N-step
+    recurrence in the module docstring.  Returns a dict with the results and
+    the plan (N, θ, eta)."""
+    dl = np.asarray(dl, dtype=np.float64)
+    dd = np.asarray(dd, dtype=np.float64)
+    du = np.asarray(du, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    if V.ndim == 1:
+        V = V[:, None]
+    theta = method.theta_for(funcs, m, tol)
+    eta = tri_norm1(dl, dd, du)
+    N = method.plan_steps(eta, theta) if force_plan is None else int(force_plan)
+    bl, bd, bu = dl / N, dd / N, du / N
+    a0, terms = method.build_terms(funcs, m, False)
+    facs = []
+    for c, _, pair in terms:
+        if pair or complex(c).imag != 0.0:
+            raise NotImplementedError("tridiagonal oracle: real shifts only")
+        c = float(complex(c).real)
+        if len(bd) == 1:  # 1 x 1: gttrf needs d >= 2 in scipy's wrapper
+            facs.append(1.0 - c * bd[0])
+            continue
+        f = lapack.dgttrf(-c * bl, 1.0 - c * bd, -c * bu)
+        if f[-1] != 0:
+            raise FloatingPointError("singular shifted tridiagonal matrix")
+        facs.append(f[:5])
+
+    def apply_r(fname, X):
+        Y = tri_matvec(bl, bd, bu, X)
+        out = a0[fname] * X
+        for (c, ws, _), fac in zip(terms, facs):
+            w = float(complex(ws.get(fname, 0.0)).real)
+            if w == 0.0:
+                continue
+            if isinstance(fac, float):
+                Z = Y / fac
+            else:
+                Z, info = lapack.dgttrs(*fac, Y)
+                assert info == 0
+            out = out + w * Z
+        return out
+
+    res = {"plan": N, "theta": theta, "eta": eta}
+    if "exp" in funcs:
+        v = V
+        for _ in range(N):
+            v = apply_r("exp", v)
+        res["exp"] = v
+    if "phi1" in funcs:
+        u1 = apply_r("phi1", V) / N
+        u = u1
+        for _ in range(N - 1):
+            u = apply_r("exp", u) + u1
+        res["phi1"] = u
+    return res
+
+
+def laplacian_1d_eig(d):
+    """Eigen-decomposition of trid{-1, 2, -1} of size d (Dirichlet): the
+    eigenvalues 2 - 2 cos(j pi / (d + 1)) and the orthonormal sine vectors
+    sqrt(2 / (d + 1)) sin(i j pi / (d + 1)), i, j = 1..d (a textbook closed
+    form; the paper's tridiagonal test matrix of §5)."""
+    j = np.arange(1, d + 1)
+    lam = 2.0 - 2.0 * np.cos(j * np.pi / (d + 1))
+    U = np.sqrt(2.0 / (d + 1)) * np.sin(np.outer(j, j) * np.pi / (d + 1))
+    return lam, U
