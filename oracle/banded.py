@@ -19,10 +19,12 @@ steps), and B v costs one tridiagonal product.
      phi1: u_1 = rho(B) V / N, u_{j+1} = r(B) u_j + u_1 (rho the phi1
            approximant), and u_N = phi1(A) V.
 
-The only library primitives are LAPACK gttrf / gttrs.
+The only library primitives are LAPACK gttrf / gttrs (getrf / getrs for
+d <= 2, which scipy's gttrf wrapper does not accept).
 """
 
 import numpy as np
+import scipy.linalg as sla
 import scipy.linalg.lapack as lapack
 
 from . import method
@@ -69,8 +71,8 @@ def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
         if pair or complex(c).imag != 0.0:
             raise NotImplementedError("tridiagonal oracle: real shifts only")
         c = float(complex(c).real)
-        if len(bd) == 1:  # 1 x 1: gttrf needs d >= 2 in scipy's wrapper
-            facs.append(1.0 - c * bd[0])
+        if len(bd) <= 2:  # scipy's gttrf wrapper needs d >= 3: dense LAPACK LU
+            facs.append(sla.lu_factor(tri_dense(-c * bl, 1.0 - c * bd, -c * bu)))
             continue
         f = lapack.dgttrf(-c * bl, 1.0 - c * bd, -c * bu)
         if f[-1] != 0:
@@ -84,8 +86,8 @@ def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
             w = float(complex(ws.get(fname, 0.0)).real)
             if w == 0.0:
                 continue
-            if isinstance(fac, float):
-                Z = Y / fac
+            if len(fac) == 2:
+                Z = sla.lu_solve(fac, Y)
             else:
                 Z, info = lapack.dgttrs(*fac, Y)
                 assert info == 0

@@ -44,13 +44,14 @@ def test_norm_and_product_against_dense():
     assert np.abs(bd.tri_matvec(dl, dd, du, X) - A @ X).max() <= 4 * U64 * np.abs(A).sum(1).max() * np.abs(X).max()
 
 
+@pytest.mark.parametrize("d", [2, 3, 48])
 @pytest.mark.parametrize("funcs", [("exp",), ("phi1",), ("exp", "phi1")])
 @pytest.mark.parametrize("m", [4, 5, 8])
-def test_tridiagonal_equals_dense_oracle(funcs, m):
+def test_tridiagonal_equals_dense_oracle(funcs, m, d):
     """Same plan as the dense oracle, and the same result up to the solvers'
     rounding: each step's difference is at most a few units of rounding times
     sum |w_k| (the round-off form's amplification, §4.3), and N steps add up."""
-    d, p = 48, 3
+    p = 3
     dl, dd, du = _random_tri(d, wl.SEED_BASE + 401 + m)
     V = np.random.default_rng(m).standard_normal((d, p))
     got = bd.tri_action(dl, dd, du, V, funcs, m, 1e-12)
