@@ -111,7 +111,8 @@ typedef struct {
   int32_t route;     /* 1: shifted inverses by Gauss-Jordan without interchanges
                         (every |c_k| ||B||_1 <= 1/2); 2: the same for a large
                         instance (n > 512, complex n > 256), spread over many
-                        workgroups; 0: pivoting LU route */
+                        workgroups; 0: pivoting LU route; 3: tridiagonal
+                        action (pfm_tri_action) */
   double norm1;      /* ||A||_1 */
   double theta;      /* admissible ||B||_1 for the requested tolerance (§3) */
   double resid;      /* mixed path: largest relative refinement residual */
@@ -172,6 +173,54 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec,
 int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int prec, int dtype,
                           int batch, const pfm_problem *probs, pfm_info *info, int force_plan,
                           pfm_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Tridiagonal A (§2.1, §5): the action f(A)V for real A given by its three
+ * diagonals, by the N-step recurrence of the action path (N = max(1,
+ * ceil(||A||_1 / θ)), B = A / N) with r(B) y = a0 y + sum_k w_k (I - c_k B)^{-1}
+ * B y (round-off form, §4.3).  I - c_k B is tridiagonal: its LU is formed
+ * once per shift and reused by all N steps and all columns (§5.1); each
+ * solve is one forward and one backward sweep.
+ *
+ * Problem (all pointers device memory, owned by the caller):
+ *   d       dimension, 1 <= d <= PFM_TRI_MAX_D
+ *   p       columns of V, 1 <= p <= PFM_TRI_MAX_P
+ *   dl      subdiagonal, dl[i] = A[i+1][i], d - 1 entries (may be NULL if d = 1)
+ *   dd      diagonal, dd[i] = A[i][i], d entries
+ *   du      superdiagonal, du[i] = A[i][i+1], d - 1 entries (NULL if d = 1)
+ *   V       d x p row-major, leading dimension ldv >= p; never written
+ *   F_exp, F_phi1   d x p row-major outputs, leading dimension ldf >= p; must
+ *           not overlap the inputs; NULL when f excludes them
+ * ------------------------------------------------------------------------ */
+#define PFM_TRI_MAX_D (1 << 24)
+#define PFM_TRI_MAX_P (1 << 20)
+
+typedef struct {
+  int32_t d;
+  int32_t p;
+  int64_t ldv;
+  int64_t ldf;
+  const double *dl;
+  const double *dd;
+  const double *du;
+  const double *V;
+  double *F_exp;
+  double *F_phi1;
+} pfm_tri_problem;
+
+/* Evaluate a batch of tridiagonal actions (binary64).
+ *   f, tol, info, force_plan, stream   as for pfm_eval_batched (force_plan:
+ *              N >= 1 for every instance; a forced N that leaves some
+ *              |c_k| ||B||_1 >= 1 may meet a zero pivot, reported as
+ *              PFM_SINGULAR_SHIFT, since the sweeps do not interchange rows)
+ *   m          4, 5 or 8 (the real shift sets; PFM_ERR_UNSUPPORTED for m = 1)
+ * pfm_info.route is 3.  With pfm_profile on, phase 0 times the
+ * factorisations and phase 1 the N steps.  The call reads the step counts back once (one
+ * stream synchronisation) and returns PFM_ERR_UNSUPPORTED if some N exceeds
+ * 2^20; everything else is enqueued on `stream`.  Workspace: about
+ * (3 + 2 m) d + n_f (3 + m / 16) d p doubles per instance (n_f functions). */
+int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_tri_problem *probs,
+                   pfm_info *info, int force_plan, pfm_stream_t stream);
 
 /* Block until `stream` is idle and report device-side failures of previous
  * calls on this context (PFM_ERR_DEVICE if a bounded device wait timed out). */

@@ -43,6 +43,13 @@ class Problem(ctypes.Structure):
                 ("F_exp", ctypes.c_void_p), ("F_phi1", ctypes.c_void_p)]
 
 
+class TriProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("ldv", ctypes.c_int64), ("ldf", ctypes.c_int64),
+                ("dl", ctypes.c_void_p), ("dd", ctypes.c_void_p), ("du", ctypes.c_void_p),
+                ("V", ctypes.c_void_p), ("F_exp", ctypes.c_void_p), ("F_phi1", ctypes.c_void_p)]
+
+
 INFO_DTYPE = np.dtype([("status", "<i4"), ("plan", "<i4"), ("order", "<i4"), ("ir_iters", "<i4"),
                        ("bad_shift", "<i4"), ("route", "<i4"), ("norm1", "<f8"),
                        ("theta", "<f8"), ("resid", "<f8")])
@@ -92,6 +99,7 @@ def lib():
         L.pfm_srv_release.argtypes = [vp, ctypes.c_uint64]
         L.pfm_srv_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p, dp]
         L.pfm_profile_read.argtypes = [vp, dp, ip, ip]
+        L.pfm_tri_action.argtypes = [vp, i32, i32, dbl, i32, ctypes.POINTER(TriProblem), vp, i32, vp]
         _lib = L
     return _lib
 
@@ -249,6 +257,14 @@ class Context:
                                       force_plan, _stream_ptr(stream))
 
 
+    def tri_action(self, probs, f, m, tol, info=None, force_plan=-1, stream=None):
+        """Raw call of pfm_tri_action: ``probs`` is a list of TriProblem.
+        Returns the C return code."""
+        arr = (TriProblem * len(probs))(*probs)
+        iptr = ctypes.c_void_p(info.data_ptr()) if info is not None else ctypes.c_void_p()
+        return lib().pfm_tri_action(self._h, f, m, tol, len(probs), arr, iptr, force_plan, _stream_ptr(stream))
+
+
 def _stream_ptr(stream):
     import torch
     if stream is None:
@@ -358,6 +374,48 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx
     info = _info_buffer(info_out, len(mats), mats[0].device)
     rc = ctx.eval_batched(probs, fm, m, tol, {"fp64": FP64, "mixed": MIXED}[prec],
                           C128 if cplx else R64, info, force_plan, stream)
+    if rc:
+        raise PfmError(rc, ctx.last_error())
+    return out, _Info(info)
+
+
+def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=-1, ctx=None, stream=None,
+               out=None, info_out=None):
+    """f(A) V for tridiagonal A (float64): ``dl``, ``dd``, ``du`` are lists of
+    CUDA tensors (sub-, main and superdiagonal of each instance, lengths
+    d - 1, d, d - 1) and ``V`` a list of (d, p) CUDA tensors with unit
+    column stride.  Returns (results, info) like ``action``."""
+    import torch
+    dls, dds, dus, vecs = list(dl), list(dd), list(du), list(V)
+    if not (len(dls) == len(dds) == len(dus) == len(vecs)):
+        raise ValueError("one set of diagonals per V")
+    for t in dls + dds + dus + vecs:
+        _require_gpu(t)
+        if t.dtype != torch.float64:
+            raise ValueError("the tridiagonal path is float64")
+    for a, b, c, v in zip(dls, dds, dus, vecs):
+        dlen = b.numel()
+        if a.numel() != dlen - 1 or c.numel() != dlen - 1 or not (a.is_contiguous() and b.is_contiguous()
+                                                                 and c.is_contiguous()):
+            raise ValueError("diagonals must be contiguous with lengths d - 1, d, d - 1")
+        if v.dim() != 2 or v.shape[0] != dlen or v.stride(1) != 1:
+            raise ValueError("each V must be (d, p) with unit column stride")
+    fm = _fmask(funcs)
+    if out is None:
+        out = {f: [torch.empty_like(v) for v in vecs] for f in funcs}
+    probs = []
+    for i, (a, b, c, v) in enumerate(zip(dls, dds, dus, vecs)):
+        fe = out["exp"][i] if "exp" in funcs else None
+        fp = out["phi1"][i] if "phi1" in funcs else None
+        ldf = (fe if fe is not None else fp).stride(0)
+        probs.append(TriProblem(b.numel(), v.shape[1], v.stride(0), ldf,
+                                a.data_ptr() if a.numel() else None, b.data_ptr(),
+                                c.data_ptr() if c.numel() else None, v.data_ptr(),
+                                fe.data_ptr() if fe is not None else None,
+                                fp.data_ptr() if fp is not None else None))
+    ctx = ctx or default_context(vecs[0].device.index or 0)
+    info = _info_buffer(info_out, len(vecs), vecs[0].device)
+    rc = ctx.tri_action(probs, fm, m, tol, info, force_plan, stream)
     if rc:
         raise PfmError(rc, ctx.last_error())
     return out, _Info(info)

@@ -15,6 +15,8 @@ Matrix families
 * -tau * trid{-1, 2, -1}: the tridiagonal matrix of the sparse experiment of
   §5 with the sign flipped so that e^A is dissipative, stored dense.
 * A_ij = 1 / (1 + (i - j)^2): the symmetric dense test matrix of §5.
+* Tridiagonal (the sparse case of §2.1 and §5), stored as three diagonals:
+  N(0,1) diagonals rescaled to a prescribed ||A||_1, and -tau trid{-1, 2, -1}.
 
 All generators take an explicit seed and use numpy's PCG64 default_rng.
 """
@@ -183,3 +185,30 @@ def serving_stream(rate, duration, seed, pool):
                      "p": int(rng.integers(1, 33)),
                      "tol": (1e-8, 1e-12)[rng.integers(2)]})
     return reqs
+
+
+def _tri_rescale(dl, dd, du, target):
+    col = np.abs(dd).copy()
+    col[1:] += np.abs(du)
+    col[:-1] += np.abs(dl)
+    f = target / col.max()
+    return dl * f, dd * f, du * f
+
+
+def tri_gaussian_batch(batch, d, norm_lo, norm_hi, seed):
+    """``batch`` tridiagonal d x d matrices with N(0,1) diagonals, each
+    rescaled to ||A||_1 ~ U[norm_lo, norm_hi].  Returns a list of
+    (dl, dd, du) float64 arrays (lengths d - 1, d, d - 1)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(batch):
+        dl = rng.standard_normal(d - 1)
+        dd = rng.standard_normal(d)
+        du = rng.standard_normal(d - 1)
+        out.append(_tri_rescale(dl, dd, du, rng.uniform(norm_lo, norm_hi)))
+    return out
+
+
+def tri_neg_laplacian(d, tau=1.0):
+    """Diagonals of -tau trid{-1, 2, -1} (the test matrix of §5, dissipative sign)."""
+    return np.full(d - 1, tau), np.full(d, -2.0 * tau), np.full(d - 1, tau)

@@ -1,0 +1,151 @@
+"""GPU parity of the tridiagonal action path (pfm_tri_action) against the
+tridiagonal oracle (oracle/banded.py), through the C ABI.
+
+Bar: relative Frobenius error per instance and function <= 1e-12, with the
+oracle's own plan equal to the GPU's (N = ceil(eta / θ); the GPU's N is
+handed to the oracle only when eta / θ sits within 1e-12 of an integer), the
+same ||A||_1 bit for bit, and route 3.  Sizes span one and many 16-row
+checkpoint chunks with ragged tails, and one and several 64-column waves
+with ragged last waves."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import banded as bd
+from oracle import method as me
+from paper_2210_03714_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+BAR = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    from paper_2210_03714_amd import pfm
+    pfm.lib()
+    return torch, torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _to(torch, dev, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def _run(torch, dev, tris, vecs, funcs, m, tol, force_plan=-1):
+    from paper_2210_03714_amd import pfm
+    dl = [_to(torch, dev, t[0]) for t in tris]
+    dd = [_to(torch, dev, t[1]) for t in tris]
+    du = [_to(torch, dev, t[2]) for t in tris]
+    V = [_to(torch, dev, v) for v in vecs]
+    res, info = pfm.tri_action(dl, dd, du, V, funcs, m=m, tol=tol, force_plan=force_plan)
+    torch.cuda.synchronize()
+    return res, info
+
+
+def _check(res, info, tris, vecs, funcs, m, tol, cols=None):
+    worst = 0.0
+    for i, ((dl, dd, du), V) in enumerate(zip(tris, vecs)):
+        Vc = V if cols is None else V[:, cols]
+        own = bd.tri_action(dl, dd, du, Vc, funcs, m, tol)
+        q = own["eta"] / own["theta"]
+        N = int(info[i]["plan"])
+        if abs(q - round(q)) < 1e-12 * q:
+            own = bd.tri_action(dl, dd, du, Vc, funcs, m, tol, force_plan=N)
+        else:
+            assert N == own["plan"], (i, N, own["plan"])
+        assert info[i]["norm1"] == own["eta"], (i, info[i]["norm1"], own["eta"])
+        assert info[i]["route"] == 3 and info[i]["status"] == 0 and info[i]["bad_shift"] == -1
+        for f in funcs:
+            got = res[f][i].cpu().numpy()
+            if cols is not None:
+                got = got[:, cols]
+            err = me.rel_fro(got, own[f])
+            worst = max(worst, err)
+            assert err <= BAR, (i, f, V.shape, N, err)
+    return worst
+
+
+@pytest.mark.parametrize("m", [4, 5, 8])
+@pytest.mark.parametrize("funcs", [("exp",), ("phi1",), ("exp", "phi1")])
+def test_uneven_batch(torch_dev, m, funcs):
+    """Several instances of different d and p in one call."""
+    torch, dev = torch_dev
+    shapes = [(1, 1), (2, 3), (15, 2), (16, 1), (17, 5), (33, 64), (100, 65), (257, 7)]
+    tris = []
+    vecs = []
+    for j, (d, p) in enumerate(shapes):
+        tris += wl.tri_gaussian_batch(1, d, 0.5, 8.0, wl.SEED_BASE + 500 + 10 * m + j)
+        vecs.append(wl.vectors(d, p, wl.SEED_BASE + 550 + 10 * m + j))
+    _say("case tri uneven m=%d funcs=%s" % (m, "+".join(funcs)))
+    res, info = _run(torch, dev, tris, vecs, funcs, m, 1e-12)
+    w = _check(res, info, tris, vecs, funcs, m, 1e-12)
+    _say("  worst %.2e" % w)
+
+
+@pytest.mark.parametrize("tol", [1e-8, 1e-12])
+def test_laplacian_and_many_columns(torch_dev, tol):
+    """-tau trid{-1, 2, -1} (the test matrix of §5) at d = 1000 with 130
+    columns (three waves, the last ragged), exp and phi1."""
+    torch, dev = torch_dev
+    tris = [wl.tri_neg_laplacian(1000, 1.0), wl.tri_neg_laplacian(1000, 0.25)]
+    vecs = [wl.vectors(1000, 130, wl.SEED_BASE + 600), wl.vectors(1000, 3, wl.SEED_BASE + 601)]
+    _say("case tri laplacian d=1000 tol=%g" % tol)
+    res, info = _run(torch, dev, tris, vecs, ("exp", "phi1"), 8, tol)
+    w = _check(res, info, tris, vecs, ("exp", "phi1"), 8, tol)
+    _say("  worst %.2e N=%d" % (w, int(info[0]["plan"])))
+
+
+def test_force_plan(torch_dev):
+    torch, dev = torch_dev
+    tris = wl.tri_gaussian_batch(2, 40, 1.0, 2.0, wl.SEED_BASE + 610)
+    vecs = [wl.vectors(40, 4, wl.SEED_BASE + 611), wl.vectors(40, 4, wl.SEED_BASE + 612)]
+    _say("case tri force_plan")
+    res, info = _run(torch, dev, tris, vecs, ("exp", "phi1"), 8, 1e-12, force_plan=37)
+    for i, ((dl, dd, du), V) in enumerate(zip(tris, vecs)):
+        assert info[i]["plan"] == 37
+        own = bd.tri_action(dl, dd, du, V, ("exp", "phi1"), 8, 1e-12, force_plan=37)
+        for f in ("exp", "phi1"):
+            assert me.rel_fro(res[f][i].cpu().numpy(), own[f]) <= BAR
+
+
+def test_headline_shape_sampled(torch_dev):
+    """The benchmark's workload shape (d = 1024, p = 64, ||A||_1 in [0.5, 8]);
+    sampled columns of sampled instances against the oracle (columns are
+    independent, so the oracle runs on those columns alone)."""
+    torch, dev = torch_dev
+    batch, d, p = 64, 1024, 64
+    tris = wl.tri_gaussian_batch(batch, d, 0.5, 8.0, wl.SEED_BASE + 620)
+    vecs = [wl.vectors(d, p, wl.SEED_BASE + 621 + i) for i in range(batch)]
+    _say("case tri headline shape batch=%d d=%d p=%d" % (batch, d, p))
+    res, info = _run(torch, dev, tris, vecs, ("exp",), 8, 1e-12)
+    pick = [0, 17, 63]
+    cols = [0, 31, 63]
+    w = _check({"exp": [res["exp"][i] for i in pick]}, info[pick], [tris[i] for i in pick],
+               [vecs[i] for i in pick], ("exp",), 8, 1e-12, cols=cols)
+    _say("  worst %.2e" % w)
+
+
+def test_nonfinite_and_errors(torch_dev):
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    dl, dd, du = wl.tri_gaussian_batch(1, 20, 1.0, 2.0, wl.SEED_BASE + 630)[0]
+    dd = dd.copy()
+    dd[7] = np.nan
+    V = wl.vectors(20, 2, wl.SEED_BASE + 631)
+    _say("case tri nonfinite")
+    res, info = _run(torch, dev, [(dl, dd, du)], [V], ("exp",), 8, 1e-12)
+    assert info[0]["status"] & pfm.NONFINITE
+    assert np.isnan(info[0]["norm1"])
+    with pytest.raises(pfm.PfmError) as e:
+        _run(torch, dev, [(dl, np.abs(dd), du)], [V], ("exp",), 1, 1e-12)
+    assert e.value.code == pfm.ERR_UNSUPPORTED
+    with pytest.raises(ValueError):
+        _run(torch, dev, [(dl[:-1], dd, du)], [V], ("exp",), 8, 1e-12)
