@@ -65,6 +65,8 @@ def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
     eta = tri_norm1(dl, dd, du)
     N = method.plan_steps(eta, theta) if force_plan is None else int(force_plan)
     bl, bd, bu = dl / N, dd / N, du / N
+    if m in method.co.HYBRID_SETS:
+        raise NotImplementedError("tridiagonal oracle: partial-fraction sets only")
     a0, terms = method.build_terms(funcs, m, False)
     facs = []
     for c, _, pair in terms:

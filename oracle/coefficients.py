@@ -115,6 +115,50 @@ def moments(b, c, K):
 
 
 # --------------------------------------------------------------------------
+# Hybrid 10th-order sets (§4.3): r(x) = d0 + d1 x + d2 x^2 + sum_i b_i/(1 - c_i x)
+# --------------------------------------------------------------------------
+
+
+def shifts_R10(variant):
+    """The ten shifts of the two 10th-order examples of §4.3:
+    'R10':  c_i = 1/(6 + i), i = 1..10;
+    'R10*': c_{2i-1} = -1/(6 + 2i), c_{2i} = 1/(6 + 2i), i = 1..5."""
+    if variant == "R10":
+        return [Fr(1, 6 + i) for i in range(1, 11)]
+    if variant == "R10*":
+        out = []
+        for i in range(1, 6):
+            out += [Fr(-1, 6 + 2 * i), Fr(1, 6 + 2 * i)]
+        return out
+    raise ValueError(variant)
+
+
+HYBRID_FREE = {"R10": (Fr(-50000), Fr(350000)), "R10*": (Fr(2000), Fr(-3500))}
+
+
+def hybrid_set(variant, func="exp"):
+    """Exact (c, b, d) of a §4.3 hybrid set: with b_9, b_10 fixed, b_1..b_8
+    solve sum_{i=1}^{10} b_i c_i^k = a_k for k = 3..10, and
+    d_k = a_k - sum_i b_i c_i^k for k = 0, 1, 2 (so that d_0 + d_1 x + d_2 x^2
+    carries the low orders).  Plain Gaussian elimination on the 8 x 8 system
+    in exact arithmetic."""
+    c = shifts_R10(variant)
+    b9, b10 = HYBRID_FREE[variant]
+    a = taylor_coeffs(func, 11)
+    M = [[c[i] ** k for i in range(8)] + [a[k] - b9 * c[8] ** k - b10 * c[9] ** k] for k in range(3, 11)]
+    for col in range(8):
+        piv = next(r for r in range(col, 8) if M[r][col] != 0)
+        M[col], M[piv] = M[piv], M[col]
+        for r in range(8):
+            if r != col and M[r][col] != 0:
+                f = M[r][col] / M[col][col]
+                M[r] = [x - f * y for x, y in zip(M[r], M[col])]
+    b = [M[i][8] / M[i][i] for i in range(8)] + [b9, b10]
+    d = [a[k] - sum(bi * ci ** k for bi, ci in zip(b, c)) for k in range(3)]
+    return c, b, d
+
+
+# --------------------------------------------------------------------------
 # Complex-conjugate Padé sets (§2, eqs. 5 and 6)
 # --------------------------------------------------------------------------
 
@@ -157,6 +201,9 @@ def pade22_phi1():
 # m counts the shifted solves ("processors"); a zero shift costs nothing
 # (§2: taking c_1 = 0 leaves b_1 as a free constant term).
 REAL_SETS = {4: shifts_R4, 5: shifts_R5, 8: shifts_R8}
+# m = 10: the hybrid set of §4.3 with the smaller coefficients (R10*), for
+# the exponential (the paper gives no phi1 weights for it)
+HYBRID_SETS = {10: "R10*"}
 
 
 def real_set(func, m):
@@ -187,10 +234,25 @@ def roundoff_terms(func, m):
         w = sp.expand(b * c)
         a0 = sp.simplify(d + 2 * sp.re(b))
         return float(a0), [(complex(sp.N(c, 40)), complex(sp.N(w, 40)), True)]
+    if m in HYBRID_SETS:
+        if func != "exp":
+            raise NotImplementedError("the hybrid 10th-order set is given for the exponential only")
+        c, b, d = hybrid_set(HYBRID_SETS[m], func)
+        a0 = d[0] + sum(b, Fr(0))
+        return float(a0), [(float(ci), float(bi * ci), False) for ci, bi in zip(c, b)]
     c, b = real_set(func, m)
     a0 = sum(b, Fr(0))
     terms = [(float(ci), float(bi * ci), False) for ci, bi in zip(c, b) if ci != 0]
     return float(a0), terms
+
+
+def poly_terms(func, m):
+    """(d_1, d_2) of the polynomial part d_1 x + d_2 x^2 of a hybrid set (§4.3),
+    each rounded once; (0, 0) for the pure partial-fraction sets."""
+    if m not in HYBRID_SETS:
+        return 0.0, 0.0
+    _, _, d = hybrid_set(HYBRID_SETS[m], func)
+    return float(d[1]), float(d[2])
 
 
 def order_of(m):
@@ -198,4 +260,6 @@ def order_of(m):
     P = number of shifts including the zero one; 4 for the Padé pair."""
     if m == 1:
         return 4
+    if m in HYBRID_SETS:
+        return 10  # §4.3: ten shifts and a quadratic, order 10
     return len(REAL_SETS[m]()) - 1

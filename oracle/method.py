@@ -11,6 +11,8 @@ Full matrix, f in {exp, phi1} (§1, §2, §4.3):
      independent "processors" of §2.
   4. Round-off form of §4.3: R = a0 I + sum_k w_k Z_k with w_k = b_k c_k; for
      a complex-conjugate pair on real A the pair contributes 2 Re(w_k Z_k).
+     The hybrid set of §4.3 (m = 10) adds its polynomial part d1 B + d2 B^2
+     (its constant d0 is part of a0 = d0 + sum_k b_k).
   5. Undo the scaling (§1): s times { Phi <- (R + I) Phi / 2 ; R <- R R }.
      The phi1 step is the doubling identity of §1 written for B:
      phi1(2B) = (e^B + I) phi1(B) / 2 (the form printed in §1 lacks the
@@ -129,6 +131,10 @@ def expm_full(A, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
     I = np.eye(n)
     out_dtype = np.complex128 if cplx else np.float64
     acc = {f: a0[f] * I.astype(out_dtype) for f in a0}
+    for f in acc:
+        d1, d2 = co.poly_terms(f, m)
+        if d1 or d2:
+            acc[f] = acc[f] + d1 * B + d2 * (B @ B)
     for c, ws, pair in terms:
         M = I - c * B
         lu = sla.lu_factor(M)
@@ -168,6 +174,9 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
     def apply_r(f, X):
         Y = B @ X
         out = a0[f] * X.astype(np.complex128 if cplx else np.float64)
+        d1, d2 = co.poly_terms(f, m)
+        if d1 or d2:
+            out = out + d1 * Y + d2 * (B @ Y)
         for (c, ws, pair), lu in zip(terms, lus):
             w = ws.get(f, 0.0)
             if w == 0.0:

@@ -103,11 +103,25 @@ def theta_set(func, m, tol, K=400):
         pr = co.pade22_exp() if func == "exp" else co.pade22_phi1()
         cf = bound_coeffs_pair(func, pr, K)
         cmax = abs(complex(pr["c"].evalf(30)))
+    elif m in co.HYBRID_SETS:
+        c, b, d = co.hybrid_set(co.HYBRID_SETS[m], func)
+        cf = bound_coeffs_hybrid(func, c, b, d, K)
+        cmax = float(max(abs(x) for x in c))
     else:
         c, b = co.real_set(func, m)
         cf = bound_coeffs_real(func, c, b, K)
         cmax = float(max(abs(x) for x in c))
     return theta(cf, tol, 0.9 / cmax)
+
+
+def bound_coeffs_hybrid(func, c, b, d, K=400):
+    """|a_k - alpha_k| for a hybrid set (§4.3): alpha_k = sum_i b_i c_i^k plus
+    d_k for k <= 2, exact."""
+    a = co.taylor_coeffs(func, K)
+    al = co.moments(b, c, K)
+    for k in range(3):
+        al[k] += d[k]
+    return [abs(x - y) for x, y in zip(a, al)]
 
 
 def theta_taylor(func, degree, tol, K=400):

@@ -5,6 +5,7 @@ Vandermonde system (§2, eq. 4) as the identical rational; the complex Padé
 pairs must reproduce the Padé rational functions of §2 (eqs. 5, 6).
 """
 
+import math
 from fractions import Fraction as Fr
 
 import pytest
@@ -116,3 +117,29 @@ def test_roundoff_form_equals_plain_form(m, func):
             xq = Fr(x)
             rhs = float(sum(bi / (1 - ci * xq) for ci, bi in zip(cs, bs)))
         assert abs(lhs.real - rhs) <= 2e-13 * max(1, abs(rhs))
+
+
+def test_hybrid_sets_are_the_papers(golden):
+    """§4.3: both 10th-order hybrid sets, solved from the order conditions
+    with b_9, b_10 fixed, equal the printed b_1..b_8 and d_0..d_2 exactly."""
+    for e in golden["hybrid"]:
+        c, b, d = co.hybrid_set(e["set"])
+        assert c == [Fr(x) for x in e["shifts"]], e["cite"]
+        assert b[:8] == [Fr(x) for x in e["b"]], e["cite"]
+        assert b[8:] == [Fr(x) for x in e["b_free"]], e["cite"]
+        assert d == [Fr(x) for x in e["d"]], e["cite"]
+        assert d[0] + sum(b) == 1  # a0 = 1: the round-off form's constant
+
+
+def test_hybrid_set_order_conditions():
+    """r(x) = d0 + d1 x + d2 x^2 + sum b_i/(1 - c_i x) matches exp to order 10
+    and misses at order 11 (independent of the solver: the moments are summed
+    directly)."""
+    for v in ("R10", "R10*"):
+        c, b, d = co.hybrid_set(v)
+        for k in range(12):
+            alpha = sum(bi * ci ** k for bi, ci in zip(b, c)) + (d[k] if k < 3 else 0)
+            if k <= 10:
+                assert alpha == Fr(1, math.factorial(k)), (v, k)
+            else:
+                assert alpha != Fr(1, math.factorial(k)), (v, k)

@@ -341,3 +341,25 @@ def test_r_scalar_is_the_rational():
         mag = sum(abs(w * float(xq) / (1 - c * float(xq))) for c, w, _ in terms)
         u = 2.0 ** -53
         assert abs(got - float(exact)) <= (len(terms) + 4) * u * (mag + abs(a0))
+
+
+def test_hybrid_diagonal_reduction(golden):
+    """m = 10 (R10*, §4.3) on a diagonal matrix: the oracle's round-off form
+    with the polynomial part equals the printed plain form
+    d0 + d1 x + d2 x^2 + sum b_i / (1 - c_i x), raised to 2^s, at 40 digits."""
+    e = [e for e in golden["hybrid"] if e["set"] == "R10*"][0]
+    q = lambda x: mpmath.mpf(Fr(x).numerator) / Fr(x).denominator
+    c = [q(x) for x in e["shifts"]]
+    b = [q(x) for x in e["b"]] + [q(x) for x in e["b_free"]]
+    d = [q(x) for x in e["d"]]
+    r = lambda z: d[0] + d[1] * z + d[2] * z ** 2 + sum(bi / (1 - ci * z) for ci, bi in zip(c, b))
+    lam = np.array([-8.0, -3.25, -0.5, 0.0, 0.125, 1.75, 4.0, 7.9])
+    res = me.expm_full(np.diag(lam), ("exp",), 10, 1e-12)
+    s = res["plan"]
+    assert s == max(0, math.ceil(math.log2(8.0 / res["theta"])))
+    sw = sum(abs(float(bi * ci)) for bi, ci in zip(b, c))  # the round-off form's amplification
+    for i, l in enumerate(lam):
+        want = float(r(mpmath.mpf(l) * mpmath.mpf(2) ** -s) ** (2 ** s))
+        got = res["exp"][i, i]
+        # each scaled evaluation rounds to ~sum|w| |x| eps; 2^s squarings amplify it
+        assert abs(got - want) <= 8 * sw * 2.0 ** -53 * 2 ** s * abs(want) + 1e-300, (l, got, want)

@@ -74,3 +74,12 @@ def test_bound_holds_on_matrices():
         r = sum(float(bi) * np.linalg.inv(I - float(ci) * B) for ci, bi in zip(c, b))
         err = np.abs(r - sla.expm(B)).sum(0).max()
         assert err <= tol
+
+
+def test_table2_r10_threshold(golden):
+    """§5.1, Table 2: θ_10 = 1.734 for the r_10^(11) scheme at u <= 2^-24."""
+    e = [e for e in golden["theta_single"] if e["kind"] == "hybrid"][0]
+    c, b, d = co.hybrid_set(e["set"])
+    cf = th.bound_coeffs_hybrid("exp", c, b, d, 400)
+    v = th.theta(cf, 2.0 ** -24, 0.9 / float(max(abs(x) for x in c)))
+    assert round(v, 3) == e["theta"], e["cite"]
