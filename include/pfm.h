@@ -137,11 +137,20 @@ const char *pfm_last_error(const pfm_ctx *ctx);
  * or eq. (6) (phi1) written in this form, one conjugate pair (the conjugate
  * term is implied, *is_pair = 1).  m = 4: the set of §4.1 with alpha = 5;
  * m = 5: the set of §5.1; m = 8: the set of §4.2 with alpha = 5.  phi1 weights
- * solve eq. (4) with a_k = 1/(k+1)! on the same shifts.  Arrays must hold 8
- * entries.  Returns PFM_ERR_UNSUPPORTED for an unknown (f, m). */
+ * solve eq. (4) with a_k = 1/(k+1)! on the same shifts.  m = 10 (exp only):
+ * the hybrid 10th-order set of §4.3 with the smaller coefficients
+ * (c = -+1/8, -+1/10, ..., -+1/16; b_9 = 2000, b_10 = -3500), whose
+ * polynomial part pfm_poly returns (a0 = d0 + sum_k b_k).  Arrays must hold
+ * 16 entries.  Returns PFM_ERR_UNSUPPORTED for an unknown (f, m). */
 int pfm_coeffs(int f, int m, int *n_terms, double *c_re, double *c_im,
                double *w_re, double *w_im, double *a0, int *order,
                int *is_pair);
+
+/* Host only.  The polynomial part d1 x + d2 x^2 of the approximant of (f, m)
+ * (§4.3, hybrid sets): r(x) = a0 + d1 x + d2 x^2 + sum_k w_k x / (1 - c_k x).
+ * Both are 0 for the partial-fraction sets.  PFM_ERR_UNSUPPORTED for an
+ * unknown (f, m). */
+int pfm_poly(int f, int m, double *d1, double *d2);
 
 /* Host only.  θ(f, m, tol): the largest x with sum_k |a_k - alpha_k| x^k <=
  * tol (forward bound of §3; absolute, any consistent norm).  For
@@ -150,7 +159,10 @@ int pfm_theta(int f, int m, double tol, double *theta);
 
 /* Evaluate a batch of problems.
  *   f          PFM_EXP, PFM_PHI1 or both
- *   m          number of shifted solves: 1, 4, 5 or 8
+ *   m          number of shifted solves: 1, 4, 5 or 8; or 10, the hybrid set
+ *              of §4.3, for PFM_EXP of real full matrices in binary64 on the
+ *              Gauss-Jordan routes (every |c_k| ||B||_1 <= 1/2, which planned
+ *              steps meet; PFM_ERR_UNSUPPORTED otherwise)
  *   tol        target of the forward bound per scaled step, in (0, 1)
  *   prec       PFM_FP64 or PFM_MIXED
  *   dtype      PFM_R64 or PFM_C128 (for A, V and outputs)

@@ -8,7 +8,10 @@ constants each rounded once from an exact value:
 * the round-off-form weights w_k = b_k c_k (§4.3) and the constant a0,
 * the order of the approximation,
 * the forward-bound series coefficients d_k = |a_k - alpha_k| (§3), from
-  which the library finds θ(tol) at run time by bisection.
+  which the library finds θ(tol) at run time by bisection,
+* for the hybrid 10th-order set of §4.3 (m = 10, the exponential), the
+  polynomial part d_1 x + d_2 x^2 of r(x) = d_0 + d_1 x + d_2 x^2 +
+  sum b_i / (1 - c_i x); its d_0 is in a0 = d_0 + sum b_i.
 
 Weights come from the transposed Vandermonde system of §2 (eq. 4), solved here
 through the Lagrange basis: the coefficient of x^k in the Lagrange polynomial
@@ -89,6 +92,32 @@ def real_entry(func, m):
     return {"a0": a[0], "order": len(c) - 1, "terms": terms, "pair": 0, "d": d}
 
 
+def hybrid_entry():
+    """§4.3, the set with c_{2i-1} = -1/(6+2i), c_{2i} = 1/(6+2i) and b_9 = 2000,
+    b_10 = -3500: b_1..b_8 from sum_i b_i c_i^k = 1/k!, k = 3..10, through
+    the Lagrange basis of the first eight shifts (x^3 times it gives the
+    rows k = 3..10), then d_k = 1/k! - sum_i b_i c_i^k, k = 0..2."""
+    c = []
+    for i in range(1, 6):
+        c += [Q(-1, 6 + 2 * i), Q(1, 6 + 2 * i)]
+    b9, b10 = Q(2000), Q(-3500)
+    a = series("exp", KBOUND)
+    # sum_{i<8} (b_i c_i^3) c_i^j = a_{j+3} - b9 c9^{j+3} - b10 c10^{j+3}, j = 0..7
+    rhs = [a[j + 3] - b9 * c[8] ** (j + 3) - b10 * c[9] ** (j + 3) for j in range(8)]
+    e = lagrange_weights(c[:8], rhs)
+    b = [ei / ci ** 3 for ei, ci in zip(e, c[:8])] + [b9, b10]
+    dpoly = [a[k] - sum(bi * ci ** k for bi, ci in zip(b, c)) for k in range(3)]
+    a0 = dpoly[0] + sum(b)
+    assert a0 == 1
+    d = []
+    for k in range(KBOUND):
+        alpha = sum(bi * ci ** k for bi, ci in zip(b, c)) + (dpoly[k] if k < 3 else Q(0))
+        d.append(abs(a[k] - alpha))
+    assert all(x == 0 for x in d[:11])
+    terms = [(ci, Q(0), bi * ci, Q(0)) for ci, bi in zip(c, b)]
+    return {"a0": a0, "order": 10, "terms": terms, "pair": 0, "d": d, "poly": (dpoly[1], dpoly[2])}
+
+
 # -- complex pairs in Decimal ------------------------------------------------
 
 
@@ -147,19 +176,23 @@ def emit(path):
         for fi, func in enumerate(("exp", "phi1")):
             e = pair_entry(func) if m == 1 else real_entry(func, m)
             entries.append((m, fi, e))
+    entries.append((10, 0, hybrid_entry()))  # the exponential only
     lines = ["/* Generated by gen_tables.py -- do not edit. */",
              "#define PFM_KBOUND %d" % KBOUND,
              "struct PfmSetEntry { int m; int func; int pair; int order; int nterms; double a0;",
-             "  double c_re[8]; double c_im[8]; double w_re[8]; double w_im[8]; double d[PFM_KBOUND]; };",
+             "  double c_re[16]; double c_im[16]; double w_re[16]; double w_im[16]; double poly[2];",
+             "  double d[PFM_KBOUND]; };",
              "static const PfmSetEntry kPfmSets[] = {"]
     for m, fi, e in entries:
         t = e["terms"]
-        pad = lambda xs: ", ".join(x.hex() for x in (list(xs) + [0.0] * (8 - len(xs))))
+        pad = lambda xs: ", ".join(x.hex() for x in (list(xs) + [0.0] * (16 - len(xs))))
         lines.append("  { %d, %d, %d, %d, %d, %s," % (m, fi, e["pair"], e["order"], len(t), f64(e["a0"]).hex()))
         lines.append("    { %s }," % pad([f64(x[0]) for x in t]))
         lines.append("    { %s }," % pad([f64(x[1]) for x in t]))
         lines.append("    { %s }," % pad([f64(x[2]) for x in t]))
         lines.append("    { %s }," % pad([f64(x[3]) for x in t]))
+        poly = e.get("poly", (Q(0), Q(0)))
+        lines.append("    { %s, %s }," % (f64(poly[0]).hex(), f64(poly[1]).hex()))
         lines.append("    { %s } }," % ", ".join(f64(x).hex() for x in e["d"]))
     lines.append("};")
     lines.append("static const int kPfmNumSets = %d;" % len(entries))

@@ -306,7 +306,9 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
 // S_e = sum_k we_k X_k, S_p = sum_k wp_k X_k (binary64, fixed order k = 0..),
 // into the level-1 squaring buffers (free at this point).  Large instances
 // (route 2) take the weights w_k c_k instead: T = sum_k w_k c_k X_k for the
-// form R = a0 I + alpha1 B + B T B (see square_level_f64_kernel).  Grid:
+// form R = a0 I + alpha1 B + B T B (see square_level_f64_kernel).  The
+// hybrid set of §4.3 adds d1 B + d2 B^2 to R: here S_e + d1 I + d2 B (so that
+// the product gives it), or T + d2 I on route 2 (its d1 joins alpha1).  Grid:
 // x = chunk of 4 * 256 elements, y = instance.
 __global__ void __launch_bounds__(256)
 combine_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, Terms T,
@@ -327,6 +329,20 @@ combine_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ il
     for (int v = 0; v < 4; ++v) {
       se[v] = fma(we, x[v], se[v]);
       sp[v] = fma(wp, x[v], sp[v]);
+    }
+  }
+  if (T.d1e != 0.0 || T.d2e != 0.0) {
+    const int s = plan[ii].s, np = D.npad;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t e = e0 + v;
+      const int r = (int)(e % np), c = (int)(e / np);
+      if (q1) {
+        if (r == c) se[v] += T.d2e;
+      } else {
+        const double b = (r < D.n && c < D.n) ? ldexp(D.A[(int64_t)r * D.lda + c], -s) : 0.0;
+        se[v] += (r == c ? T.d1e : 0.0) + T.d2e * b;
+      }
     }
   }
   double *base = wsd + D.r_off;

@@ -227,7 +227,7 @@ int pfm_profile_read(pfm_ctx *ctx, double *ms, int *launches, int *calls) {
 size_t pfm_workspace_bytes(int f, int m, int prec, int dtype, int batch, const pfm_problem *probs) {
   if (f < 1 || f > 3 || batch < 1 || !probs) return 0;
   const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
-  if (!ee || !ep) return 0;
+  if (!ee || (!ep && (f & PFM_PHI1))) return 0;
   const bool cplx = dtype == PFM_C128, pairs = ee->pair != 0, mixed = prec == PFM_MIXED;
   const bool emb = cplx || pairs;
   const bool phi = (f & PFM_PHI1) != 0;
@@ -316,6 +316,15 @@ int pfm_coeffs(int f, int m, int *n_terms, double *c_re, double *c_im, double *w
   return PFM_OK;
 }
 
+int pfm_poly(int f, int m, double *d1, double *d2) {
+  if (f != PFM_EXP && f != PFM_PHI1) return PFM_ERR_INVALID;
+  const PfmSetEntry *e = find_set(m, f == PFM_EXP ? 0 : 1);
+  if (!e) return PFM_ERR_UNSUPPORTED;
+  if (d1) *d1 = e->poly[0];
+  if (d2) *d2 = e->poly[1];
+  return PFM_OK;
+}
+
 int pfm_theta(int f, int m, double tol, double *theta) {
   if (!theta || !(tol > 0.0 && tol < 1.0)) return PFM_ERR_INVALID;
   if (f < 1 || f > 3) return PFM_ERR_INVALID;
@@ -323,7 +332,7 @@ int pfm_theta(int f, int m, double tol, double *theta) {
   // recurrence apply e^B), so its θ is the smaller of the two.
   const PfmSetEntry *ee = find_set(m, 0);
   const PfmSetEntry *ep = find_set(m, 1);
-  if (!ee || !ep) return PFM_ERR_UNSUPPORTED;
+  if (!ee || (!ep && (f & PFM_PHI1))) return PFM_ERR_UNSUPPORTED;
   double th = theta_of(ee, tol);
   if (f & PFM_PHI1) th = std::min(th, theta_of(ep, tol));
   *theta = th;
@@ -532,7 +541,16 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     if (action && (!P.V || P.ldv < P.p)) return set_err(ctx, PFM_ERR_INVALID, "problem %d: bad V", i);
   }
   const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
-  if (!ee || !ep) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
+  const bool hybrid = ee && (ee->poly[0] != 0.0 || ee->poly[1] != 0.0);
+  if (!ee || (!ep && !hybrid)) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
+  if (hybrid) {
+    // the hybrid set of §4.3: the exponential of real matrices in binary64,
+    // on the Gauss-Jordan routes (checked after the plan)
+    if (f != PFM_EXP || prec != PFM_FP64 || dtype != PFM_R64 || action)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED,
+                     "m = %d (the hybrid set) is provided for exp(A) of real matrices in binary64", m);
+    ep = ee;  // no phi1 weights; never read (want_phi = 0)
+  }
   const bool cplx = dtype == PFM_C128;
   const bool pairs = ee->pair != 0;
   const bool mixed = prec == PFM_MIXED;
@@ -578,6 +596,8 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   T.want_phi = (f & PFM_PHI1) ? 1 : 0;
   T.a0e = ee->a0;
   T.a0p = ep->a0;
+  T.d1e = ee->poly[0];
+  T.d2e = ee->poly[1];
   if (!pairs) {
     // one real shift set shared by both functions (§2)
     T.nterms = ee->nterms;
@@ -616,7 +636,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
                                                 auto it = ctx->tuned.find(batch_key(action, emb, mixed, batch, probs));
                                                 return it == ctx->tuned.end() ? -1 : it->second;
                                               }();
-    if (pidx >= 0 && ctx->gj) {  // an explicit PFM_ROUTE_LU stays authoritative
+    if (pidx >= 0 && ctx->gj && !hybrid) {  // an explicit PFM_ROUTE_LU stays authoritative
       pol_gj = kPolicies[pidx].gj;
       pol_ln = kPolicies[pidx].ln_min;
     }
@@ -795,6 +815,13 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
       (fast ? fast_list : slow_list)[c].push_back(i);
       is_fast[i] = fast;
     }
+  if (hybrid)
+    for (int c = 0; c < 3; ++c)
+      if (!slow_list[c].empty())
+        return set_err(ctx, PFM_ERR_UNSUPPORTED,
+                       "m = %d needs |c_k| ||B||_1 <= 1/2 for every instance (the Gauss-Jordan route); "
+                       "instance %d is on the pivoting LU route (forced plan, PFM_ROUTE_LU or non-finite input)",
+                       m, slow_list[c][0]);
   int fast_off[3], slow_off[3];
   std::vector<int> lists;
   for (int c = 0; c < 3; ++c) {
@@ -882,7 +909,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   {
     long double se = 0.0L, sp = 0.0L;
     for (int k = 0; k < nterms; ++k) { se += (long double)T.we_re[k]; sp += (long double)T.wp_re[k]; }
-    a1e = (double)se;
+    a1e = (double)se + T.d1e;  // the hybrid set's d1 B joins alpha1 B
     a1p = (double)sp;
   }
   const size_t tb = all.size() * sizeof(SqTask);

@@ -68,6 +68,7 @@ struct Terms {
   int32_t pair_real;
   int32_t want_exp, want_phi;
   double a0e, a0p;
+  double d1e, d2e;  // polynomial part d1 B + d2 B^2 of the hybrid set (exp), else 0
   double c_re[kMaxTerms], c_im[kMaxTerms];
   double we_re[kMaxTerms], we_im[kMaxTerms];
   double wp_re[kMaxTerms], wp_im[kMaxTerms];

@@ -73,6 +73,7 @@ def lib():
         L.pfm_last_error.restype = ctypes.c_char_p
         L.pfm_coeffs.argtypes = [i32, i32, ip, dp, dp, dp, dp, dp, ip, ip]
         L.pfm_theta.argtypes = [i32, i32, dbl, dp]
+        L.pfm_poly.argtypes = [i32, i32, dp, dp]
         L.pfm_eval_batched.argtypes = [vp, i32, i32, dbl, i32, i32, i32, ctypes.POINTER(Problem),
                                        vp, i32, vp]
         L.pfm_check.argtypes = [vp, vp]
@@ -112,7 +113,7 @@ def coeffs(f, m):
     """(c, w, a0, order, is_pair) of the library's set for f (EXP or PHI1)."""
     L = lib()
     n = ctypes.c_int()
-    arrs = [(ctypes.c_double * 8)() for _ in range(4)]
+    arrs = [(ctypes.c_double * 16)() for _ in range(4)]
     a0 = ctypes.c_double()
     order = ctypes.c_int()
     pair = ctypes.c_int()
@@ -124,6 +125,15 @@ def coeffs(f, m):
     c = np.array(arrs[0][:k]) + 1j * np.array(arrs[1][:k])
     w = np.array(arrs[2][:k]) + 1j * np.array(arrs[3][:k])
     return c, w, a0.value, order.value, bool(pair.value)
+
+
+def poly(f, m):
+    """(d1, d2) of the polynomial part of the library's set for f (0 unless hybrid)."""
+    d1, d2 = ctypes.c_double(), ctypes.c_double()
+    rc = lib().pfm_poly(f, m, ctypes.byref(d1), ctypes.byref(d2))
+    if rc:
+        raise ValueError("pfm_poly(%d, %d) -> %d" % (f, m, rc))
+    return d1.value, d2.value
 
 
 def theta(f, m, tol):

@@ -98,3 +98,25 @@ def test_workspace_bytes_host(L):
     assert ws(600, prec="mixed") == 0          # large instances: FP64 only
     assert ws(64, p=4, prec="mixed") == 0      # mixed: full matrix only
     assert ws(600, p=65) == 0                   # large action: p <= 64
+
+
+def test_hybrid_set_bitwise_equal_oracle(L):
+    """m = 10 (the hybrid set of §4.3): shifts, weights, a0 and the polynomial
+    part equal the oracle's, which come from an independent exact solve; phi1
+    has no m = 10 set."""
+    c, w, a0, order, pair = pfm.coeffs(pfm.EXP, 10)
+    a0o, terms = co.roundoff_terms("exp", 10)
+    assert not pair and order == co.order_of(10) == 10
+    assert a0 == a0o == 1.0
+    assert list(c.real) == [t[0] for t in terms]
+    assert list(w.real) == [t[1] for t in terms]
+    assert pfm.poly(pfm.EXP, 10) == co.poly_terms("exp", 10)
+    assert pfm.poly(pfm.EXP, 8) == (0.0, 0.0)
+    with pytest.raises(ValueError):
+        pfm.coeffs(pfm.PHI1, 10)
+    out = ctypes.c_double()
+    assert L.pfm_theta(pfm.PHI1, 10, 1e-12, ctypes.byref(out)) == pfm.ERR_UNSUPPORTED
+    for tol in (2.0 ** -24, 1e-8, 1e-12):
+        lib_t = pfm.theta(pfm.EXP, 10, tol)
+        orc_t = th.theta_set("exp", 10, tol)
+        assert abs(lib_t - orc_t) <= 1e-13 * orc_t, (tol, lib_t, orc_t)
