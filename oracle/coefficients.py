@@ -201,6 +201,10 @@ def pade22_phi1():
 # m counts the shifted solves ("processors"); a zero shift costs nothing
 # (§2: taking c_1 = 0 leaves b_1 as a free constant term).
 REAL_SETS = {4: shifts_R4, 5: shifts_R5, 8: shifts_R8}
+# log(1 - x) (§2, worked example): the five shifts c_i = 1/(i + 1), with the
+# weights of eq. (4) for a_k = -1/k (a_0 = 0); it has no scaling identity,
+# so it is evaluated at s = 0 only
+LOG1M_SETS = {5: shifts_frac4}
 # m = 10: the hybrid set of §4.3 with the smaller coefficients (R10*), for
 # the exponential (the paper gives no phi1 weights for it)
 HYBRID_SETS = {10: "R10*"}
@@ -211,7 +215,7 @@ def real_set(func, m):
     sets; phi1 re-solves eq. (4) with a_k = 1/(k+1)! on the *same* shifts,
     which §2 allows ("different functions ... just by looking for a new set
     of coefficients b_i")."""
-    c = REAL_SETS[m]()
+    c = LOG1M_SETS[m]() if func == "log1m" else REAL_SETS[m]()
     a = taylor_coeffs(func, len(c))
     return c, solve_weights(c, a)
 
@@ -263,3 +267,8 @@ def order_of(m):
     if m in HYBRID_SETS:
         return 10  # §4.3: ten shifts and a quadratic, order 10
     return len(REAL_SETS[m]()) - 1
+
+
+def order_of_log1m(m):
+    """Order of the log(1 - x) set: P shifts, none zero, match a_0..a_{P-1}."""
+    return len(LOG1M_SETS[m]()) - 1

@@ -54,7 +54,7 @@ def theta_for(funcs, m, tol):
     request containing phi1 takes min(θ_exp, θ_phi1)."""
     key = (tuple(sorted(funcs)), m, float(tol))
     if key not in _THETA_CACHE:
-        need = {"exp"} | set(funcs)
+        need = set(funcs) if "log1m" in funcs else {"exp"} | set(funcs)
         _THETA_CACHE[key] = min(th.theta_set(f, m, tol) for f in need)
     return _THETA_CACHE[key]
 
@@ -84,6 +84,12 @@ def build_terms(funcs, m, complex_A):
     Padé poles and so need a pair each.  For complex A a conjugate pair cannot
     be folded into 2 Re(.), so it is expanded into its two conjugate terms.
     """
+    if "log1m" in funcs:
+        # log(1 - x) alone, on its own shift set (§2)
+        if tuple(funcs) != ("log1m",):
+            raise ValueError("log1m is evaluated on its own")
+        a0l, tl = co.roundoff_terms("log1m", m)
+        return {"log1m": a0l}, [(c, {"log1m": w}, pair) for c, w, pair in tl]
     need = ["exp"] + (["phi1"] if "phi1" in funcs else [])
     a0 = {}
     terms = []
@@ -125,7 +131,10 @@ def expm_full(A, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
     cplx = np.iscomplexobj(A)
     theta = theta_for(funcs, m, tol)
     eta = norm1(A)
-    s = plan_scaling(eta, theta) if force_plan is None else int(force_plan)
+    if "log1m" in funcs:
+        s = 0  # no scaling identity: r(A) itself (the bound holds for eta <= θ)
+    else:
+        s = plan_scaling(eta, theta) if force_plan is None else int(force_plan)
     B = np.ldexp(A.real, -s) + (1j * np.ldexp(A.imag, -s) if cplx else 0.0)
     a0, terms = build_terms(funcs, m, cplx)
     I = np.eye(n)
@@ -141,6 +150,8 @@ def expm_full(A, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
         Z = sla.lu_solve(lu, B.astype(M.dtype))
         for f, w in ws.items():
             _accumulate(acc[f], Z, w, pair and not cplx)
+    if "log1m" in funcs:
+        return {"plan": 0, "theta": theta, "eta": eta, "log1m": acc["log1m"]}
     R = acc["exp"]
     Phi = acc.get("phi1")
     for _ in range(s):

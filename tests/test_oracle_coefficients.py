@@ -143,3 +143,14 @@ def test_hybrid_set_order_conditions():
                 assert alpha == Fr(1, math.factorial(k)), (v, k)
             else:
                 assert alpha != Fr(1, math.factorial(k)), (v, k)
+
+
+def test_log1m_registry_is_the_papers(golden):
+    """The log(1 - x) set (m = 5) is the §2 worked example: shifts 1/2..1/6 and
+    the printed weights."""
+    e = [e for e in golden["weights"] if e["func"] == "log1m"][0]
+    c, b = co.real_set("log1m", 5)
+    assert c == [Fr(x) for x in e["shifts"]]
+    assert b == [Fr(x) for x in e["b"]]
+    a0, terms = co.roundoff_terms("log1m", 5)
+    assert a0 == 0.0 and len(terms) == 5

@@ -363,3 +363,26 @@ def test_hybrid_diagonal_reduction(golden):
         got = res["exp"][i, i]
         # each scaled evaluation rounds to ~sum|w| |x| eps; 2^s squarings amplify it
         assert abs(got - want) <= 8 * sw * 2.0 ** -53 * 2 ** s * abs(want) + 1e-300, (l, got, want)
+
+
+def test_log1m_diagonal_and_logm(golden):
+    """log(1 - x) (§2 worked example) has no scaling identity: s = 0.  On a
+    diagonal matrix the round-off form equals the printed plain form
+    sum b_i / (1 - c_i x) at 40 digits; on a dense matrix with ||A||_1 = θ/2
+    the result meets logm(I - A) within the absolute bound of §3."""
+    e = [e for e in golden["weights"] if e["func"] == "log1m"][0]
+    q = lambda x: mpmath.mpf(Fr(x).numerator) / Fr(x).denominator
+    c = [q(x) for x in e["shifts"]]
+    b = [q(x) for x in e["b"]]
+    th_ = me.theta_for(("log1m",), 5, 1e-12)
+    lam = np.array([-1.0, -0.5, 0.0, 0.25, 0.9]) * th_
+    res = me.expm_full(np.diag(lam), ("log1m",), 5, 1e-12)
+    assert res["plan"] == 0
+    for i, l in enumerate(lam):
+        want = float(sum(bi / (1 - ci * mpmath.mpf(l)) for ci, bi in zip(c, b)))
+        # round-off form: sum |w_k| |x| / (1 - c_k x) eps, about 100 |x| eps here
+        assert abs(res["log1m"][i, i] - want) <= 1e3 * 2.0 ** -53 * max(abs(l), 1e-300)
+    A = wl.gaussian(24, th_ / 2, 11)
+    got = me.expm_full(A, ("log1m",), 5, 1e-12)["log1m"]
+    exact = sla.logm(np.eye(24) - A).real
+    assert np.abs(got - exact).sum(axis=0).max() <= 1e-12 + 1e-14
