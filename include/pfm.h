@@ -51,6 +51,11 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
 /* functions (bit mask: EXP|PHI1 computes both from one set of solves, §2) */
 #define PFM_EXP 1
 #define PFM_PHI1 2
+/* log(1 - A) (§2 worked example): on its own (f == PFM_LOG1M), m = 5 (the
+ * shifts 1/2..1/6), real binary64 full matrices.  It has no scaling
+ * identity, so r(A) is evaluated directly (s = 0); the bound of §3 holds for
+ * ||A||_1 <= θ (PFM_OUT_OF_RANGE otherwise).  The result goes to F_exp. */
+#define PFM_LOG1M 4
 
 /* element types */
 #define PFM_R64 0  /* real binary64 */
@@ -84,6 +89,8 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
                                 I - c_k B is not diagonally dominant enough for
                                 the large-instance route (|c_k| ||B||_1 <= 1/2;
                                 the planner's B always is, a forced plan may not) */
+#define PFM_OUT_OF_RANGE 16  /* PFM_LOG1M: ||A||_1 > θ, so the tolerance is not
+                                guaranteed (the result is still computed) */
 
 /* One problem instance.  p == 0: full matrix, F_exp / F_phi1 are n x n with
  * leading dimension ldf.  p >= 1: action on the n x p block V (leading

@@ -38,6 +38,8 @@ def series(func, K):
         return [Q(1, factorial(k)) for k in range(K)]
     if func == "phi1":
         return [Q(1, factorial(k + 1)) for k in range(K)]
+    if func == "log1m":  # log(1 - x) = -sum_{k >= 1} x^k / k
+        return [Q(0)] + [Q(-1, k) for k in range(1, K)]
     raise ValueError(func)
 
 
@@ -80,7 +82,8 @@ def shifts(m):
 
 
 def real_entry(func, m):
-    c = shifts(m)
+    # log(1 - x): the five shifts 1/2..1/6 of the §2 example
+    c = [Q(1, i + 1) for i in range(1, 6)] if func == "log1m" else shifts(m)
     a = series(func, KBOUND)
     b = lagrange_weights(c, a[:len(c)])
     assert sum(b) == a[0]
@@ -177,6 +180,7 @@ def emit(path):
             e = pair_entry(func) if m == 1 else real_entry(func, m)
             entries.append((m, fi, e))
     entries.append((10, 0, hybrid_entry()))  # the exponential only
+    entries.append((5, 2, real_entry("log1m", 5)))  # log(1 - x), evaluated at s = 0
     lines = ["/* Generated by gen_tables.py -- do not edit. */",
              "#define PFM_KBOUND %d" % KBOUND,
              "struct PfmSetEntry { int m; int func; int pair; int order; int nterms; double a0;",

@@ -70,7 +70,7 @@ norm_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan) {
 
 __global__ void __launch_bounds__(256)
 plan_finish_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan, int batch, int action,
-                   int force_plan) {
+                   int force_plan, int unscaled) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= batch) return;
   const double theta = inst[i].theta;
@@ -93,6 +93,10 @@ plan_finish_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan
     int s = 0;
     while (ldexp(eta, -s) > theta && s < 1023) ++s;
     plan_v = s;
+  }
+  if (unscaled) {  // a function without a scaling identity: s = 0
+    plan_v = 0;
+    if (!bad && eta > theta) P.status |= 16;  // PFM_OUT_OF_RANGE
   }
   P.s = plan_v;
   plan[i] = P;

@@ -101,6 +101,9 @@ int set_err(pfm_ctx *ctx, int code, const char *fmt, ...) {
       return set_err(ctx, PFM_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
   } while (0)
 
+// table index of a single function bit (PFM_EXP 0, PFM_PHI1 1, PFM_LOG1M 2)
+inline int func_index(int f) { return f == PFM_EXP ? 0 : (f == PFM_PHI1 ? 1 : 2); }
+
 const PfmSetEntry *find_set(int m, int func) {
   for (int i = 0; i < kPfmNumSets; ++i)
     if (kPfmSets[i].m == m && kPfmSets[i].func == func) return &kPfmSets[i];
@@ -300,8 +303,8 @@ const char *pfm_last_error(const pfm_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 int pfm_coeffs(int f, int m, int *n_terms, double *c_re, double *c_im, double *w_re, double *w_im,
                double *a0, int *order, int *is_pair) {
-  if (f != PFM_EXP && f != PFM_PHI1) return PFM_ERR_INVALID;
-  const PfmSetEntry *e = find_set(m, f == PFM_EXP ? 0 : 1);
+  if (f != PFM_EXP && f != PFM_PHI1 && f != PFM_LOG1M) return PFM_ERR_INVALID;
+  const PfmSetEntry *e = find_set(m, func_index(f));
   if (!e) return PFM_ERR_UNSUPPORTED;
   if (n_terms) *n_terms = e->nterms;
   for (int k = 0; k < e->nterms; ++k) {
@@ -317,8 +320,8 @@ int pfm_coeffs(int f, int m, int *n_terms, double *c_re, double *c_im, double *w
 }
 
 int pfm_poly(int f, int m, double *d1, double *d2) {
-  if (f != PFM_EXP && f != PFM_PHI1) return PFM_ERR_INVALID;
-  const PfmSetEntry *e = find_set(m, f == PFM_EXP ? 0 : 1);
+  if (f != PFM_EXP && f != PFM_PHI1 && f != PFM_LOG1M) return PFM_ERR_INVALID;
+  const PfmSetEntry *e = find_set(m, func_index(f));
   if (!e) return PFM_ERR_UNSUPPORTED;
   if (d1) *d1 = e->poly[0];
   if (d2) *d2 = e->poly[1];
@@ -327,6 +330,12 @@ int pfm_poly(int f, int m, double *d1, double *d2) {
 
 int pfm_theta(int f, int m, double tol, double *theta) {
   if (!theta || !(tol > 0.0 && tol < 1.0)) return PFM_ERR_INVALID;
+  if (f == PFM_LOG1M) {  // on its own set, without the exponential
+    const PfmSetEntry *el = find_set(m, 2);
+    if (!el) return PFM_ERR_UNSUPPORTED;
+    *theta = theta_of(el, tol);
+    return PFM_OK;
+  }
   if (f < 1 || f > 3) return PFM_ERR_INVALID;
   // phi1 always carries the exponential approximant too (its doubling and its
   // recurrence apply e^B), so its θ is the smaller of the two.
@@ -514,7 +523,8 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
                           int batch, const pfm_problem *probs, pfm_info *info, int force_plan,
                           pfm_stream_t stream_) {
   if (!ctx) return PFM_ERR_INVALID;
-  if (f < 1 || f > 3) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
+  const bool log1m = f == PFM_LOG1M;
+  if ((f < 1 || f > 3) && !log1m) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
   if (tols) {  // per-instance tolerances: the scalar is their minimum
     if (batch < 1) return set_err(ctx, PFM_ERR_INVALID, "empty batch");
     tol = tols[0];
@@ -536,11 +546,18 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     if (P.lda < P.n) return set_err(ctx, PFM_ERR_INVALID, "problem %d: lda < n", i);
     const int64_t ocols = action ? P.p : P.n;
     if (P.ldf < ocols) return set_err(ctx, PFM_ERR_INVALID, "problem %d: ldf too small", i);
-    if ((f & PFM_EXP) && !P.F_exp) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_exp null", i);
+    if (((f & PFM_EXP) || log1m) && !P.F_exp) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_exp null", i);
     if ((f & PFM_PHI1) && !P.F_phi1) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_phi1 null", i);
     if (action && (!P.V || P.ldv < P.p)) return set_err(ctx, PFM_ERR_INVALID, "problem %d: bad V", i);
   }
-  const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
+  const PfmSetEntry *ee = find_set(m, log1m ? 2 : 0), *ep = find_set(m, 1);
+  if (log1m) {
+    // log(1 - A): its own set, evaluated at s = 0 (no scaling identity)
+    if (!ee) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no log(1 - x) set for m = %d", m);
+    if (prec != PFM_FP64 || dtype != PFM_R64 || action)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED, "log(1 - A) is provided for real full matrices in binary64");
+    ep = ee;  // the phi1 slot is never read (want_phi = 0)
+  }
   const bool hybrid = ee && (ee->poly[0] != 0.0 || ee->poly[1] != 0.0);
   if (!ee || (!ep && !hybrid)) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
   if (hybrid) {
@@ -592,7 +609,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
 
   Terms T;
   memset(&T, 0, sizeof T);
-  T.want_exp = (f & PFM_EXP) ? 1 : 0;
+  T.want_exp = ((f & PFM_EXP) || log1m) ? 1 : 0;  // log(1 - A) runs in the exp slot
   T.want_phi = (f & PFM_PHI1) ? 1 : 0;
   T.a0e = ee->a0;
   T.a0p = ep->a0;
@@ -757,7 +774,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     hipLaunchKernelGGL(plan_init_kernel, dim3(nb), dim3(256), 0, stream, d_plan, batch);
     hipLaunchKernelGGL(norm_kernel, dim3((maxc + 63) / 64, batch), dim3(256), 0, stream, d_desc, d_plan);
     hipLaunchKernelGGL(plan_finish_kernel, dim3(nb), dim3(256), 0, stream, d_desc, d_plan, batch,
-                       action ? 1 : 0, force_plan);
+                       action ? 1 : 0, force_plan, log1m ? 1 : 0);
   }
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipMemcpyAsync(h_plan, d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libpfm.so")
 
 EXP = 1
 PHI1 = 2
+LOG1M = 4  # log(1 - A), on its own (its result goes to F_exp)
 R64 = 0
 C128 = 1
 FP64 = 0
@@ -34,6 +35,7 @@ SINGULAR_SHIFT = 1
 NONFINITE = 2
 IR_STALL = 4
 NOT_COMPUTED = 8
+OUT_OF_RANGE = 16
 
 
 class Problem(ctypes.Structure):
@@ -285,7 +287,7 @@ def _stream_ptr(stream):
 def _fmask(funcs):
     m = 0
     for f in funcs:
-        m |= {"exp": EXP, "phi1": PHI1}[f]
+        m |= {"exp": EXP, "phi1": PHI1, "log1m": LOG1M}[f]
     return m
 
 
@@ -330,7 +332,8 @@ def expm(A, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None
             for f in funcs}
     probs = []
     for i, a in enumerate(mats):
-        fe = outs["exp"][i] if "exp" in funcs else None
+        # log(1 - A) is written to the F_exp slot
+        fe = outs["exp"][i] if "exp" in funcs else (outs["log1m"][i] if "log1m" in funcs else None)
         fp = outs["phi1"][i] if "phi1" in funcs else None
         ldf = (fe if fe is not None else fp).stride(0)
         probs.append(Problem(a.shape[0], 0, a.stride(0), 0, ldf, a.data_ptr(), None,
@@ -374,7 +377,7 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx
         out = {f: [torch.empty_like(v) for v in vecs] for f in funcs}
     probs = []
     for i, (a, v) in enumerate(zip(mats, vecs)):
-        fe = out["exp"][i] if "exp" in funcs else None
+        fe = out["exp"][i] if "exp" in funcs else (out["log1m"][i] if "log1m" in funcs else None)
         fp = out["phi1"][i] if "phi1" in funcs else None
         ldf = (fe if fe is not None else fp).stride(0)
         probs.append(Problem(a.shape[0], v.shape[1], a.stride(0), v.stride(0), ldf, a.data_ptr(),

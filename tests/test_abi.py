@@ -120,3 +120,18 @@ def test_hybrid_set_bitwise_equal_oracle(L):
         lib_t = pfm.theta(pfm.EXP, 10, tol)
         orc_t = th.theta_set("exp", 10, tol)
         assert abs(lib_t - orc_t) <= 1e-13 * orc_t, (tol, lib_t, orc_t)
+
+
+def test_log1m_set_bitwise_equal_oracle(L):
+    """log(1 - x) (m = 5, the §2 example's shifts): the library's table equals
+    the oracle's exact solve; θ likewise; mixing it with exp is rejected."""
+    c, w, a0, order, pair = pfm.coeffs(pfm.LOG1M, 5)
+    a0o, terms = co.roundoff_terms("log1m", 5)
+    assert a0 == a0o == 0.0 and order == co.order_of_log1m(5) == 4 and not pair
+    assert list(c.real) == [t[0] for t in terms]
+    assert list(w.real) == [t[1] for t in terms]
+    for tol in (1e-8, 1e-12):
+        assert abs(pfm.theta(pfm.LOG1M, 5, tol) - th.theta_set("log1m", 5, tol)) <= 1e-13 * th.theta_set("log1m", 5, tol)
+    out = ctypes.c_double()
+    assert L.pfm_theta(pfm.LOG1M, 8, 1e-12, ctypes.byref(out)) == pfm.ERR_UNSUPPORTED
+    assert L.pfm_eval_batched(None, pfm.LOG1M | pfm.EXP, 5, 1e-12, 0, 0, 1, None, None, -1, None) == pfm.ERR_INVALID
