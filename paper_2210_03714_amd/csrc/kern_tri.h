@@ -41,8 +41,8 @@ struct TriDesc {
   int64_t f_off;  // factors: [k][l, ui][d]
   int64_t v_off;  // vectors: [slot][3][d][p]
   int64_t c_off;  // checkpoints: [slot][chunk][k][p]
-  int32_t wave0;  // first wave of this instance in the step launch
-  int32_t nwaves;
+  int32_t wave0;   // first wave of this instance in the step launch
+  int32_t nwaves;  // its waves: functions x ceil(p / 64)
 };
 
 struct TriTerms {
@@ -147,12 +147,12 @@ tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
 // All N steps of one column (lane) of one function slot; one wave per
 // workgroup, 64 consecutive columns of one instance.  The instance's B and
 // factor rows are staged through LDS in blocks of kTriRB rows (a coalesced
-// load by the whole wave, double-buffered through registers so the next
-// block's load overlaps the current block's sweeps); the sweeps read them as
-// broadcasts.  The column's own values are read 16 rows ahead.  fac is the
-// read-only view of B and the factors; vws holds the vectors and checkpoints
-// (disjoint parts of the same workspace).  Lanes past p take part in the
-// block loads and barriers and store nothing.
+// load by the whole wave into the buffer not being read, at each block
+// boundary); the sweeps read them as broadcasts.  The column's own values
+// are read two chunks ahead in the forward pass and one chunk ahead in the
+// backward pass.  fac is the read-only view of B and the factors; vws holds
+// the vectors and checkpoints (disjoint parts of the same workspace).  Lanes
+// past p repeat column p - 1 and so store what that lane stores.
 constexpr int kTriRB = 64;                // rows per staged block (one per lane)
 
 // Vector loads and stores through global (not flat) instructions: flat
