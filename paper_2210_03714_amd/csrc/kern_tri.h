@@ -12,8 +12,10 @@
 // one instance, so every factor read is the same address in all lanes):
 //   B:        sub[r] = B[r][r-1] (sub[0] = 0), dia[r], sup[r] = B[r][r+1]
 //             (sup[d-1] = 0)
-//   factors:  per shift k, l[r] = M[r][r-1] / u[r-1] (l[0] = 0) and
-//             ui[r] = 1 / u[r], M = I - c_k B = L U
+//   factors:  per shift k, l[r] = M[r][r-1] / u[r-1] (l[0] = 0),
+//             ui[r] = 1 / u[r] and em[r] = M[r][r+1] / u[r] (em[d-1] = 0),
+//             M = I - c_k B = L U; the backward sweep is then
+//             x_r = ui[r] z_r - em[r] x_{r+1}
 //   vectors:  per function slot, two ping-pong buffers and u_1 (phi1), each
 //             d x p row-major (lanes read consecutive addresses)
 //   checkpoints: the forward sweep's value at the end of every kTriL-row
@@ -24,6 +26,8 @@
 // chunk's forward values from its checkpoint in registers, and runs the
 // backward sweep, accumulating a0 x + sum_k w_k x_k on the way.
 #pragma once
+#include <type_traits>
+
 #include "kern_common.h"
 
 namespace pfm {
@@ -38,7 +42,7 @@ struct TriDesc {
   int32_t d, p;
   double theta;
   int64_t b_off;  // sub, dia, sup: 3 d
-  int64_t f_off;  // factors: [k][l, ui][d]
+  int64_t f_off;  // factors: [k][l, ui, em][d]
   int64_t v_off;  // vectors: [slot][3][d][p]
   int64_t c_off;  // checkpoints: [slot][chunk][k][p]
   int32_t wave0;   // first wave of this instance in the step launch
@@ -116,7 +120,7 @@ tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
   const double Nd = (double)plan[ii].s;
   const double c = T.c[k];
   double *sub = wsd + D.b_off, *dia = sub + d, *sup = dia + d;
-  double *l = wsd + D.f_off + (int64_t)k * 2 * d, *ui = l + d;
+  double *l = wsd + D.f_off + (int64_t)k * 3 * d, *ui = l + d, *em = ui + d;
   if (k == 0) {
     for (int r = 0; r < d; ++r) {
       sub[r] = r > 0 ? D.dl[r - 1] / Nd : 0.0;
@@ -126,18 +130,22 @@ tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
   }
   bool bad = false;
   double u = 1.0 - c * (D.dd[0] / Nd);
+  double uinv = 1.0 / u;
   bad |= !(u != 0.0 && isfinite(u));
   l[0] = 0.0;
-  ui[0] = 1.0 / u;
+  ui[0] = uinv;
   for (int r = 1; r < d; ++r) {
     const double mlo = -c * (D.dl[r - 1] / Nd);  // M[r][r-1]
     const double mup = -c * (D.du[r - 1] / Nd);  // M[r-1][r]
     const double lr = mlo / u;
+    em[r - 1] = mup * uinv;
     u = (1.0 - c * (D.dd[r] / Nd)) - lr * mup;
+    uinv = 1.0 / u;
     bad |= !(u != 0.0 && isfinite(u));
     l[r] = lr;
-    ui[r] = 1.0 / u;
+    ui[r] = uinv;
   }
+  em[d - 1] = 0.0;
   if (bad) {
     atomicOr(&plan[ii].status, 1);
     atomicMin(&plan[ii].bad_shift, k);
@@ -146,14 +154,22 @@ tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
 
 // All N steps of one column (lane) of one function slot; one wave per
 // workgroup, 64 consecutive columns of one instance.  The instance's B and
-// factor rows are staged through LDS in blocks of kTriRB rows (a coalesced
-// load by the whole wave into the buffer not being read, at each block
-// boundary); the sweeps read them as broadcasts.  The column's own values
-// are read two chunks ahead in the forward pass and one chunk ahead in the
-// backward pass.  fac is the read-only view of B and the factors; vws holds
+// factor rows are staged through LDS in blocks of kTriRB rows (each lane
+// loads one row into registers at the start of a block, and writes it into
+// the buffer not being read at the block's end); the sweeps read them as
+// broadcasts.  The column's own values are read ahead through rings of
+// register slots: a ring of kTriFR chunks of x in the forward pass and of
+// kTriBR chunk operand sets in the backward pass.  Every chunk of a block is
+// unrolled, so a chunk's slot is fixed at compile time and a slot is
+// refilled as soon as it has been read: no register move has to wait for a
+// load in flight.  fac is the read-only view of B and the factors; vws holds
 // the vectors and checkpoints (disjoint parts of the same workspace).  Lanes
 // past p repeat column p - 1 and so store what that lane stores.
-constexpr int kTriRB = 64;                // rows per staged block (one per lane)
+constexpr int kTriRB = 64;               // rows per staged block (one per lane)
+constexpr int kTriCB = kTriRB / kTriL;   // chunks per block
+constexpr int kTriFR = 4;                // forward pass: chunks of x in flight
+constexpr int kTriBR = 2;                // backward pass: chunk operand sets in flight
+static_assert(kTriCB % kTriFR == 0 && kTriCB % kTriBR == 0, "ring sizes divide the chunks of a block");
 
 // Vector loads and stores through global (not flat) instructions: flat
 // accesses also count against the LDS counter, so every wait for an LDS read
@@ -164,17 +180,22 @@ __device__ __forceinline__ double gld(const double *a) {
 __device__ __forceinline__ void gst(double *a, double v) {
   *(__attribute__((address_space(1))) double *)a = v;
 }
-constexpr int kTriF = 3 + 2 * kTriTerms;  // sub, dia, sup, l_k, u_k
+constexpr int kTriF = 3 + 3 * kTriTerms;  // sub, dia, sup, l_k, ui_k, em_k
 
 // NT: the number of shifts (4, 5 or 8), so that the sweeps of all shifts
-// unroll without branches and their chains interleave.  Rows past d (the
-// tail of the last chunk) are swept too, on the clamped last row's factors,
-// and never stored.
-template <int NT>
+// unroll without branches and their chains interleave.  PHI: some slot of
+// the launch is phi1, whose steps after the first add u_1 (without it, no
+// u_1 row is read).  The backward sweeps run in two halves of the shifts
+// (all of them for NT = 4), so that only half of the recomputed forward
+// values are held at a time; the sum a0 x + sum_k w_k x_k keeps the order
+// k = 0, 1, ...  Chunks that start past d are skipped; the tail rows of the
+// last chunk are swept on zero factors and never stored.
+template <int NT, bool PHI>
 __global__ void __launch_bounds__(64)
 tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
                  const double *__restrict__ fac, double *__restrict__ vws) {
   __shared__ double fb[2][kTriF][kTriRB];
+  constexpr int NA = NT > 4 ? (NT + 1) / 2 : NT;  // shifts of the first half
   const int lane = threadIdx.x;
   const int gw = blockIdx.x;
   int lo = 0, hi = batch - 1;  // the instance whose waves contain gw
@@ -186,7 +207,6 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
   const int ii = __builtin_amdgcn_readfirstlane(lo);
   const TriDesc D = desc[ii];
   const int d = D.d, p = D.p;
-  constexpr int nt = NT;
   const int cpw = (p + 63) / 64;
   const int wl = gw - D.wave0;
   const int slot = wl / cpw;
@@ -203,20 +223,27 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
   const int64_t dp = (int64_t)d * p;
   double *vb = vws + D.v_off + (int64_t)slot * 3 * dp;
   double *u1 = vb + 2 * dp;
-  double *ck = vws + D.c_off + (int64_t)slot * nch * nt * p;
+  double *ck = vws + D.c_off + (int64_t)slot * nch * NT * p;
 
   double nf[kTriF];
+  // rows past d are staged as zeros (read from sub[0]): there y = 0, z = 0
+  // and x = 0, so the last real row sees x_d = 0 with no test in the sweeps
   auto fetch = [&](int blk) {
-    const int r = blk * kTriRB + lane < d ? blk * kTriRB + lane : d - 1;
-    nf[0] = sub[r];
-    nf[1] = dia[r];
-    nf[2] = sup[r];
+    const int r = blk * kTriRB + lane;
+    const bool in = r < d;
+    nf[0] = gld(in ? sub + r : sub);
+    nf[1] = gld(in ? dia + r : sub);
+    nf[2] = gld(in ? sup + r : sub);
 #pragma unroll
     for (int k = 0; k < kTriTerms; ++k) {
-      const bool on = k < nt;
-      const int64_t o = (int64_t)(on ? k : 0) * 2 * d + r;
-      nf[3 + k] = on ? lf[o] : 0.0;
-      nf[3 + kTriTerms + k] = on ? lf[o + d] : 0.0;
+      const double *a = lf + (int64_t)k * 3 * d + r;
+      if (k < NT) {
+        nf[3 + k] = gld(in ? a : sub);
+        nf[3 + kTriTerms + k] = gld(in ? a + d : sub);
+        nf[3 + 2 * kTriTerms + k] = gld(in ? a + 2 * d : sub);
+      } else {
+        nf[3 + k] = nf[3 + kTriTerms + k] = nf[3 + 2 * kTriTerms + k] = 0.0;
+      }
     }
   };
   auto put = [&](int buf) {
@@ -233,8 +260,10 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
     const int64_t lds = j == 0 ? D.ldv : p;
     double *dst = j == N - 1 ? (fn ? D.Fp : D.Fe) + c : vb + (int64_t)(j & 1) * dp + c;
     const int64_t ldd = j == N - 1 ? D.ldf : p;
+    // phi1's first step is u_1 = rho(B) V / N: the 1/N is folded into its
+    // weights
     const bool first_phi = fn == 1 && j == 0;
-    const double a0 = first_phi ? T.a0p : T.a0e;
+    const double a0 = first_phi ? T.a0p / (double)N : T.a0e;
     // rows outside [0, d) read sub[0], which is 0: the address is chosen,
     // not the value, so no load sits behind a branch
     auto xload = [&](int r) {
@@ -244,135 +273,162 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
 
     // pass 1 (block 0 is staged in buffer 0): forward sweeps
     // z_r = y_r - l_r z_{r-1} of every shift, y = B x; keep z at the end of
-    // each chunk that has a successor.  x is read two chunks ahead.
+    // each chunk.  Chunk g's rows sit in ring slot g mod kTriFR; the slot is
+    // refilled with the rows kTriFR chunks further down once it is read.
     {
-      double z[kTriTerms];
+      double z[NT];
 #pragma unroll
-      for (int k = 0; k < kTriTerms; ++k) z[k] = 0.0;
-      double xm = 0.0, xg[kTriL], xn[kTriL], xnn[kTriL];
+      for (int k = 0; k < NT; ++k) z[k] = 0.0;
+      double xm = 0.0, xr[kTriFR][kTriL];
 #pragma unroll
-      for (int jj = 0; jj < kTriL; ++jj) {
-        xg[jj] = xload(jj);
-        xn[jj] = xload(kTriL + jj);
-      }
+      for (int i = 0; i < kTriFR; ++i)
+#pragma unroll
+        for (int jj = 0; jj < kTriL; ++jj) xr[i][jj] = xload(i * kTriL + jj);
 #pragma unroll 1
       for (int b = 0; b < nb; ++b) {
         const int buf = b & 1;
-#pragma unroll 1
-        for (int g = 0; g < kTriRB / kTriL; ++g) {
+        fetch(b + 1 < nb ? b + 1 : b);  // staged at the end of this block
+#pragma unroll
+        for (int g = 0; g < kTriCB; ++g) {
           const int rg = b * kTriRB + g * kTriL;
-          if (rg >= d) break;
+          const int sl = g % kTriFR, sn = (g + 1) % kTriFR;
+          if (rg < d) {
 #pragma unroll
-          for (int jj = 0; jj < kTriL; ++jj) xnn[jj] = xload(rg + 2 * kTriL + jj);
+            for (int jj = 0; jj < kTriL; ++jj) {
+              const int lr = g * kTriL + jj;
+              const double x0 = xr[sl][jj];
+              const double xp = jj + 1 < kTriL ? xr[sl][jj + 1] : xr[sn][0];
+              const double y = fma(fb[buf][2][lr], xp, fma(fb[buf][0][lr], xm, fb[buf][1][lr] * x0));
 #pragma unroll
-          for (int jj = 0; jj < kTriL; ++jj) {
-            const int lr = g * kTriL + jj;
-            const double x0 = xg[jj];
-            const double xp = jj + 1 < kTriL ? xg[jj + 1] : xn[0];
-            const double y = fma(fb[buf][2][lr], xp, fma(fb[buf][0][lr], xm, fb[buf][1][lr] * x0));
-#pragma unroll
-            for (int k = 0; k < NT; ++k) z[k] = fma(-fb[buf][3 + k][lr], z[k], y);
-            xm = x0;
-          }
-          {  // the last chunk's slot is written and never read
-            double *cq = ck + (int64_t)(rg / kTriL) * nt * p + c;
+              for (int k = 0; k < NT; ++k) z[k] = fma(-fb[buf][3 + k][lr], z[k], y);
+              xm = x0;
+            }
+            // (the last chunk's slot is written and never read)
+            double *cq = ck + (int64_t)(rg / kTriL) * NT * p + c;
 #pragma unroll
             for (int k = 0; k < NT; ++k) gst(cq + (int64_t)k * p, z[k]);
           }
 #pragma unroll
-          for (int jj = 0; jj < kTriL; ++jj) {
-            xg[jj] = xn[jj];
-            xn[jj] = xnn[jj];
-          }
+          for (int jj = 0; jj < kTriL; ++jj) xr[sl][jj] = xload(rg + kTriFR * kTriL + jj);
         }
         if (b + 1 < nb) {
-          fetch(b + 1);
           put(buf ^ 1);
           __syncthreads();
         }
       }
     }
 
-    // pass 2 (block nb - 1 is staged): chunks from the last.  Per chunk, the
-    // forward values of every shift from the chunk's checkpoints, then the
-    // backward sweeps x_r = (z_r - s_r x_{r+1}) / u_r with
-    // s_r = M[r][r+1] = -c_k sup[r], all shifts row by row (independent
-    // chains side by side), and out_r = a0 x_r + sum_k w_k x_{k,r}.  The next
-    // chunk's rows and checkpoints are read during the backward sweeps.
-    double xc[NT], zc[NT];
-    double xs[kTriL + 2];  // rows r0 - 1 .. r0 + kTriL of the current chunk
-    double us[kTriL];      // u_1 on the chunk's rows (phi1 after its first step)
-    const bool add_u1 = fn == 1 && j > 0;
-    auto chunk_loads = [&](int q) {
+    // pass 2 (block nb - 1 is staged): chunks from the last.  Per chunk q
+    // (ring slot q mod kTriBR): y = B x on its rows, then for each half of
+    // the shifts the forward values from the chunk's checkpoints and the
+    // backward sweeps x_r = ui_r z_r - em_r x_{r+1}, the shifts of the half
+    // row by row
+    // (independent chains side by side), and out_r = a0 x_r + sum_k w_k x_{k,r}.
+    // Once the slot is read, it is refilled with chunk q - kTriBR.
+    {
+      const bool add_u1 = PHI && fn == 1 && j > 0;
+      double xs[kTriBR][kTriL + 1];            // rows r0 - 1 .. r0 + kTriL - 1
+      double us[kTriBR][PHI ? kTriL : 1];      // u_1 on the chunk's rows
+      double zc[kTriBR][NT];                   // checkpoints: z at row r0 - 1
+      auto chunk_loads = [&](int q, int sl) {
 #pragma unroll
-      for (int jj = 0; jj < kTriL + 2; ++jj) xs[jj] = xload(q * kTriL - 1 + jj);
+        for (int jj = 0; jj <= kTriL; ++jj) xs[sl][jj] = xload(q * kTriL - 1 + jj);
+        if constexpr (PHI) {
 #pragma unroll
-      for (int jj = 0; jj < kTriL; ++jj) {
-        const int r = q * kTriL + jj;
-        const double *a = (add_u1 && r < d) ? u1 + (int64_t)r * p + c : sub;
-        us[jj] = gld(a);
-      }
+          for (int jj = 0; jj < kTriL; ++jj) {
+            const int r = q * kTriL + jj;
+            const double *a = (add_u1 && r >= 0 && r < d) ? u1 + (int64_t)r * p + c : sub;
+            us[sl][jj] = gld(a);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+          const double *a = (q > 0 && q < nch) ? ck + ((int64_t)(q - 1) * NT + k) * p + c : sub;
+          zc[sl][k] = gld(a);
+        }
+      };
+      double xc[NT], wk[NT];
 #pragma unroll
       for (int k = 0; k < NT; ++k) {
-        const double *a = q > 0 ? ck + ((int64_t)(q - 1) * NT + k) * p + c : sub;
-        zc[k] = gld(a);
+        xc[k] = 0.0;
+        wk[k] = first_phi ? T.wp[k] / (double)N : T.we[k];
       }
-    };
-    double wk[NT], sk[NT];
+      const int qtop = nb * kTriCB - 1;  // the last block's last chunk
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      xc[k] = 0.0;
-      wk[k] = first_phi ? T.wp[k] : T.we[k];
-      sk[k] = -T.c[k];
-    }
-    chunk_loads(nch - 1);
-    const double rN = (double)N;
+      for (int i = 0; i < kTriBR; ++i) chunk_loads(qtop - i, (kTriCB - 1 - i) % kTriBR);
+      double xt = 0.0;  // x on row r0 + kTriL (0 past the last row)
 #pragma unroll 1
-    for (int b = nb - 1; b >= 0; --b) {
-      const int buf = b & 1;
-#pragma unroll 1
-      for (int g = kTriRB / kTriL - 1; g >= 0; --g) {
-        const int r0 = b * kTriRB + g * kTriL;
-        if (r0 >= d) continue;
-        const int q = r0 / kTriL;
-        const int len = d - r0 < kTriL ? d - r0 : kTriL;
-        double zz[NT][kTriL], ax[kTriL];
+      for (int b = nb - 1; b >= 0; --b) {
+        const int buf = b & 1;
+        fetch(b > 0 ? b - 1 : 0);  // staged at the end of this block
 #pragma unroll
-        for (int jj = 0; jj < kTriL; ++jj) {
-          const int lr = g * kTriL + jj;
-          const double y = fma(fb[buf][2][lr], xs[jj + 2], fma(fb[buf][0][lr], xs[jj], fb[buf][1][lr] * xs[jj + 1]));
+        for (int g = kTriCB - 1; g >= 0; --g) {
+          const int sl = g % kTriBR;
+          const int q = b * kTriCB + g;
+          const int r0 = q * kTriL;
+          const bool live = r0 < d;
+          const int len = d - r0 < kTriL ? d - r0 : kTriL;
+          double y[kTriL], o[kTriL];
+          // one half of the shifts, [K0, K1): forward values from the
+          // checkpoints, then (when SWEEP) the backward sweeps into o
+          auto recompute = [&](auto k0c, auto k1c, double (*zz)[kTriL]) {
+            constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
 #pragma unroll
-          for (int k = 0; k < NT; ++k) {
-            zc[k] = fma(-fb[buf][3 + k][lr], zc[k], y);
-            zz[k][jj] = zc[k];
+            for (int jj = 0; jj < kTriL; ++jj) {
+              const int lr = g * kTriL + jj;
+#pragma unroll
+              for (int k = K0; k < K1; ++k) {
+                zc[sl][k] = fma(-fb[buf][3 + k][lr], zc[sl][k], y[jj]);
+                zz[k - K0][jj] = zc[sl][k];
+              }
+            }
+          };
+          auto sweep = [&](auto k0c, auto k1c, double (*zz)[kTriL]) {
+            constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+#pragma unroll
+            for (int jj = kTriL - 1; jj >= 0; --jj) {
+              const int lr = g * kTriL + jj;
+#pragma unroll
+              for (int k = K0; k < K1; ++k) {
+                xc[k] = fma(-fb[buf][3 + 2 * kTriTerms + k][lr], xc[k], fb[buf][3 + kTriTerms + k][lr] * zz[k - K0][jj]);
+                o[jj] = fma(wk[k], xc[k], o[jj]);
+              }
+            }
+          };
+          double za[NA][kTriL];
+          double zb[NT - NA > 0 ? NT - NA : 1][kTriL];
+          if (live) {
+#pragma unroll
+            for (int jj = 0; jj < kTriL; ++jj) {
+              const int lr = g * kTriL + jj;
+              const double xh = jj + 1 < kTriL ? xs[sl][jj + 2] : xt;
+              y[jj] = fma(fb[buf][2][lr], xh, fma(fb[buf][0][lr], xs[sl][jj], fb[buf][1][lr] * xs[sl][jj + 1]));
+              double ax = a0 * xs[sl][jj + 1];
+              if constexpr (PHI) ax += us[sl][jj];  // u_1 (phi1 after its first step; else 0)
+              o[jj] = ax;
+            }
+            xt = xs[sl][1];
+            recompute(std::integral_constant<int, 0>(), std::integral_constant<int, NA>(), za);
+            sweep(std::integral_constant<int, 0>(), std::integral_constant<int, NA>(), za);
+            if constexpr (NT > NA)
+              recompute(std::integral_constant<int, NA>(), std::integral_constant<int, NT>(), zb);
           }
-          ax[jj] = a0 * xs[jj + 1] + us[jj];  // + u_1 (phi1 after its first step; else 0)
-        }
-        chunk_loads(q > 0 ? q - 1 : 0);  // (for q = 0: harmless reads, unused)
+          chunk_loads(q - kTriBR, sl);  // (chunks below 0 read harmless addresses, unused)
+          if (live) {
+            if constexpr (NT > NA) sweep(std::integral_constant<int, NA>(), std::integral_constant<int, NT>(), zb);
 #pragma unroll
-        for (int jj = kTriL - 1; jj >= 0; --jj) {
-          const int lr = g * kTriL + jj;
-          const double sp = fb[buf][2][lr];
-          double o = ax[jj];
-#pragma unroll
-          for (int k = 0; k < NT; ++k) {
-            // rows past d (tail of the last chunk) leave the carry alone, so
-            // the last real row sees x_d = 0
-            const double nx = (zz[k][jj] - sk[k] * sp * xc[k]) * fb[buf][3 + kTriTerms + k][lr];
-            xc[k] = jj < len ? nx : xc[k];
-            o = fma(wk[k], xc[k], o);
+            for (int jj = kTriL - 1; jj >= 0; --jj) {
+              // rows past d store to row r0, which row jj = 0 rewrites last
+              const int64_t r = jj < len ? r0 + jj : r0;
+              gst(dst + r * ldd, o[jj]);
+              if (first_phi && N > 1) gst(u1 + r * p + c, o[jj]);
+            }
           }
-          // rows past d store to row r0, which row jj = 0 rewrites last
-          const int64_t r = jj < len ? r0 + jj : r0;
-          o = first_phi ? o / rN : o;
-          gst(dst + r * ldd, o);
-          if (first_phi && N > 1) gst(u1 + r * p + c, o);
         }
-      }
-      if (b > 0) {
-        fetch(b - 1);
-        put((b - 1) & 1);
-        __syncthreads();
+        if (b > 0) {
+          put((b - 1) & 1);
+          __syncthreads();
+        }
       }
     }
     // block 0 is staged in buffer 0 again for the next step's pass 1

@@ -407,7 +407,7 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
     D.theta = theta;
     const int64_t d = P.d, p = P.p, nch = (d + kTriL - 1) / kTriL;
     D.b_off = dofs; dofs += align_up(3 * d, 64);
-    D.f_off = dofs; dofs += align_up(2 * d * T.nterms, 64);
+    D.f_off = dofs; dofs += align_up(3 * d * T.nterms, 64);
     D.wave0 = (int32_t)waves;
     D.nwaves = T.nf * (int32_t)((p + 63) / 64);
     waves += D.nwaves;
@@ -467,12 +467,20 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
                      wsd);
   ctx->cur_launches[0]++;
   prof_mark(ctx, 1, stream);
-#define PFM_TRI_STEPS(NT)                                                                                   \
-  hipLaunchKernelGGL((tri_steps_kernel<NT>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, batch, d_plan, T, \
-                     (const double *)wsd, wsd)
-  if (T.nterms == 4) PFM_TRI_STEPS(4);
-  else if (T.nterms == 5) PFM_TRI_STEPS(5);
-  else PFM_TRI_STEPS(8);
+#define PFM_TRI_STEPS(NT, PHI)                                                                                  \
+  hipLaunchKernelGGL((tri_steps_kernel<NT, PHI>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, batch, d_plan, \
+                     T, (const double *)wsd, wsd)
+  const bool tri_phi = T.fn[0] == 1 || (T.nf > 1 && T.fn[1] == 1);
+  if (T.nterms == 4) {
+    if (tri_phi) PFM_TRI_STEPS(4, true);
+    else PFM_TRI_STEPS(4, false);
+  } else if (T.nterms == 5) {
+    if (tri_phi) PFM_TRI_STEPS(5, true);
+    else PFM_TRI_STEPS(5, false);
+  } else {
+    if (tri_phi) PFM_TRI_STEPS(8, true);
+    else PFM_TRI_STEPS(8, false);
+  }
 #undef PFM_TRI_STEPS
   ctx->cur_launches[1]++;
   prof_mark(ctx, 2, stream);
