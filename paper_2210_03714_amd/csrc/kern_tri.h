@@ -171,16 +171,25 @@ constexpr int kTriFR = 4;                // forward pass: chunks of x in flight
 constexpr int kTriBR = 2;                // backward pass: chunk operand sets in flight
 static_assert(kTriCB % kTriFR == 0 && kTriCB % kTriBR == 0, "ring sizes divide the chunks of a block");
 
-// Vector loads and stores through global (not flat) instructions: flat
+// Vector loads through global (not flat) instructions: flat
 // accesses also count against the LDS counter, so every wait for an LDS read
 // would wait for the in-flight prefetches as well.
 __device__ __forceinline__ double gld(const double *a) {
   return *(const __attribute__((address_space(1))) double *)a;
 }
-__device__ __forceinline__ void gst(double *a, double v) {
-  *(__attribute__((address_space(1))) double *)a = v;
+// The same for this lane's element of a row whose address is wave-uniform:
+// the row address (scalar registers; it includes the wave's first column)
+// plus the lane's byte offset (a vector register, below 512) is the saddr
+// form of the global instructions, so the only address arithmetic left is
+// scalar, one add per row.  A row outside the vector reads kTriZeroRow.
+__device__ __forceinline__ double gldr(const void *row, uint32_t off) {
+  return *(const __attribute__((address_space(1))) double *)((const char *)row + off);
+}
+__device__ __forceinline__ void gstr(void *row, uint32_t off, double v) {
+  *(__attribute__((address_space(1))) double *)((char *)row + off) = v;
 }
 constexpr int kTriF = 3 + 3 * kTriTerms;  // sub, dia, sup, l_k, ui_k, em_k
+__device__ double kTriZeroRow[64];        // zero-initialised, never written
 
 // NT: the number of shifts (4, 5 or 8), so that the sweeps of all shifts
 // unroll without branches and their chains interleave.  PHI: some slot of
@@ -210,10 +219,10 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
   const int cpw = (p + 63) / 64;
   const int wl = gw - D.wave0;
   const int slot = wl / cpw;
-  const int c0 = (wl - slot * cpw) * 64 + lane;
+  const int cb = (wl - slot * cpw) * 64;  // the wave's first column
   // lanes past p repeat column p - 1 exactly (same inputs, same arithmetic),
   // so their stores write the values that lane writes: no store needs a mask
-  const int c = c0 < p ? c0 : p - 1;
+  const int c = cb + lane < p ? cb + lane : p - 1;
   const int fn = slot == 0 ? T.fn[0] : T.fn[1];
   const int N = plan[ii].s;
   const int nch = (d + kTriL - 1) / kTriL;
@@ -223,7 +232,11 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
   const int64_t dp = (int64_t)d * p;
   double *vb = vws + D.v_off + (int64_t)slot * 3 * dp;
   double *u1 = vb + 2 * dp;
-  double *ck = vws + D.c_off + (int64_t)slot * nch * NT * p;
+  char *ckb = (char *)(vws + D.c_off + (int64_t)slot * nch * NT * p + cb);
+  char *u1b = (char *)(u1 + cb);
+  const char *zrow = (const char *)kTriZeroRow;
+  const uint32_t cofs = 8u * (uint32_t)(c - cb);  // this lane's byte offset from column cb
+  const int64_t p8 = 8 * (int64_t)p;
 
   double nf[kTriF];
   // rows past d are staged as zeros (read from sub[0]): there y = 0, z = 0
@@ -256,20 +269,26 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
 
 #pragma unroll 1
   for (int j = 0; j < N; ++j) {
-    const double *src = j == 0 ? D.V + c : vb + (int64_t)((j - 1) & 1) * dp + c;
-    const int64_t lds = j == 0 ? D.ldv : p;
-    double *dst = j == N - 1 ? (fn ? D.Fp : D.Fe) + c : vb + (int64_t)(j & 1) * dp + c;
-    const int64_t ldd = j == N - 1 ? D.ldf : p;
+    const char *srcb = (const char *)((j == 0 ? D.V : vb + (int64_t)((j - 1) & 1) * dp) + cb);
+    const int64_t lds8 = 8 * (j == 0 ? D.ldv : (int64_t)p);
+    char *dstb = (char *)((j == N - 1 ? (fn ? D.Fp : D.Fe) : vb + (int64_t)(j & 1) * dp) + cb);
+    const int64_t ldd8 = 8 * (j == N - 1 ? D.ldf : (int64_t)p);
     // phi1's first step is u_1 = rho(B) V / N: the 1/N is folded into its
     // weights
     const bool first_phi = fn == 1 && j == 0;
     const double a0 = first_phi ? T.a0p / (double)N : T.a0e;
-    // rows outside [0, d) read sub[0], which is 0: the address is chosen,
-    // not the value, so no load sits behind a branch
-    auto xload = [&](int r) {
-      const double *a = (r >= 0 && r < d) ? src + (int64_t)r * lds : sub;
-      return gld(a);
+    // cnt consecutive rows of x from row r (rows outside [0, d) read the
+    // zero row: the address is chosen, not the value, so no load sits behind
+    // a branch)
+    auto xrows = [&](int r, double *out, auto cntc) {
+      const char *rp = srcb + (int64_t)r * lds8;
+#pragma unroll
+      for (int jj = 0; jj < decltype(cntc)::value; ++jj, rp += lds8) {
+        const bool ok = r + jj >= 0 && r + jj < d;
+        out[jj] = gldr(ok ? rp : zrow, cofs);
+      }
     };
+    using Lc = std::integral_constant<int, kTriL>;
 
     // pass 1 (block 0 is staged in buffer 0): forward sweeps
     // z_r = y_r - l_r z_{r-1} of every shift, y = B x; keep z at the end of
@@ -281,9 +300,7 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
       for (int k = 0; k < NT; ++k) z[k] = 0.0;
       double xm = 0.0, xr[kTriFR][kTriL];
 #pragma unroll
-      for (int i = 0; i < kTriFR; ++i)
-#pragma unroll
-        for (int jj = 0; jj < kTriL; ++jj) xr[i][jj] = xload(i * kTriL + jj);
+      for (int i = 0; i < kTriFR; ++i) xrows(i * kTriL, xr[i], Lc());
 #pragma unroll 1
       for (int b = 0; b < nb; ++b) {
         const int buf = b & 1;
@@ -304,12 +321,11 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
               xm = x0;
             }
             // (the last chunk's slot is written and never read)
-            double *cq = ck + (int64_t)(rg / kTriL) * NT * p + c;
+            char *cq = ckb + (int64_t)(rg / kTriL) * NT * p8;
 #pragma unroll
-            for (int k = 0; k < NT; ++k) gst(cq + (int64_t)k * p, z[k]);
+            for (int k = 0; k < NT; ++k, cq += p8) gstr(cq, cofs, z[k]);
           }
-#pragma unroll
-          for (int jj = 0; jj < kTriL; ++jj) xr[sl][jj] = xload(rg + kTriFR * kTriL + jj);
+          xrows(rg + kTriFR * kTriL, xr[sl], Lc());
         }
         if (b + 1 < nb) {
           put(buf ^ 1);
@@ -331,21 +347,20 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
       double us[kTriBR][PHI ? kTriL : 1];      // u_1 on the chunk's rows
       double zc[kTriBR][NT];                   // checkpoints: z at row r0 - 1
       auto chunk_loads = [&](int q, int sl) {
-#pragma unroll
-        for (int jj = 0; jj <= kTriL; ++jj) xs[sl][jj] = xload(q * kTriL - 1 + jj);
+        xrows(q * kTriL - 1, xs[sl], std::integral_constant<int, kTriL + 1>());
         if constexpr (PHI) {
+          const char *up = u1b + (int64_t)q * kTriL * p8;
 #pragma unroll
-          for (int jj = 0; jj < kTriL; ++jj) {
+          for (int jj = 0; jj < kTriL; ++jj, up += p8) {
             const int r = q * kTriL + jj;
-            const double *a = (add_u1 && r >= 0 && r < d) ? u1 + (int64_t)r * p + c : sub;
-            us[sl][jj] = gld(a);
+            const bool ok = add_u1 && r >= 0 && r < d;
+            us[sl][jj] = gldr(ok ? up : zrow, cofs);
           }
         }
+        const bool okc = q > 0 && q < nch;
+        const char *cp = ckb + (int64_t)(q - 1) * NT * p8;
 #pragma unroll
-        for (int k = 0; k < NT; ++k) {
-          const double *a = (q > 0 && q < nch) ? ck + ((int64_t)(q - 1) * NT + k) * p + c : sub;
-          zc[sl][k] = gld(a);
-        }
+        for (int k = 0; k < NT; ++k, cp += p8) zc[sl][k] = gldr(okc ? cp : zrow, cofs);
       };
       double xc[NT], wk[NT];
 #pragma unroll
@@ -420,8 +435,8 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
             for (int jj = kTriL - 1; jj >= 0; --jj) {
               // rows past d store to row r0, which row jj = 0 rewrites last
               const int64_t r = jj < len ? r0 + jj : r0;
-              gst(dst + r * ldd, o[jj]);
-              if (first_phi && N > 1) gst(u1 + r * p + c, o[jj]);
+              gstr(dstb + r * ldd8, cofs, o[jj]);
+              if (first_phi && N > 1) gstr(u1b + r * p8, cofs, o[jj]);
             }
           }
         }
