@@ -420,6 +420,15 @@ def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=-1, ctx
     for i, (a, b, c, v) in enumerate(zip(dls, dds, dus, vecs)):
         fe = out["exp"][i] if "exp" in funcs else None
         fp = out["phi1"][i] if "phi1" in funcs else None
+        # the library writes every function's result with one row stride
+        for o in (fe, fp):
+            if o is None:
+                continue
+            _require_gpu(o)
+            if o.dtype != torch.float64 or o.shape != v.shape or o.stride(1) != 1:
+                raise ValueError("each output must be a float64 (d, p) tensor with unit column stride")
+        if fe is not None and fp is not None and fe.stride(0) != fp.stride(0):
+            raise ValueError("the exp and phi1 outputs of an instance must share their row stride")
         ldf = (fe if fe is not None else fp).stride(0)
         probs.append(TriProblem(b.numel(), v.shape[1], v.stride(0), ldf,
                                 a.data_ptr() if a.numel() else None, b.data_ptr(),

@@ -133,6 +133,40 @@ def test_headline_shape_sampled(torch_dev):
     _say("  worst %.2e" % w)
 
 
+def test_strided_vectors(torch_dev):
+    """V and the results as column slices of wider matrices (row strides 80
+    and 72 for p = 64 columns), d = 130 (three blocks, a ragged last chunk):
+    the library reads and writes only the slices."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    d, p = 130, 64
+    tris = wl.tri_gaussian_batch(2, d, 0.5, 8.0, wl.SEED_BASE + 640)
+    vecs = [wl.vectors(d, p, wl.SEED_BASE + 641 + i) for i in range(2)]
+    wideV = [torch.zeros((d, 80), dtype=torch.float64, device=dev) for _ in vecs]
+    for w, v in zip(wideV, vecs):
+        w[:, 5:5 + p] = torch.from_numpy(v).to(dev)
+    sentinel = 12345.0
+    wide = {f: [torch.full((d, 72), sentinel, dtype=torch.float64, device=dev) for _ in vecs]
+            for f in ("exp", "phi1")}
+    out = {f: [w[:, 3:3 + p] for w in wide[f]] for f in ("exp", "phi1")}
+    dl = [torch.from_numpy(t[0]).to(dev) for t in tris]
+    dd = [torch.from_numpy(t[1]).to(dev) for t in tris]
+    du = [torch.from_numpy(t[2]).to(dev) for t in tris]
+    _say("case tri strided V and outputs d=%d p=%d" % (d, p))
+    res, info = pfm.tri_action(dl, dd, du, [w[:, 5:5 + p] for w in wideV], ("exp", "phi1"), m=8,
+                               tol=1e-12, out=out)
+    torch.cuda.synchronize()
+    for f in ("exp", "phi1"):
+        for w in wide[f]:
+            wc = w.cpu().numpy()
+            assert np.all(wc[:, :3] == sentinel) and np.all(wc[:, 3 + p:] == sentinel)
+    w = _check(res, info, tris, vecs, ("exp", "phi1"), 8, 1e-12)
+    _say("  worst %.2e" % w)
+    bad = {"exp": out["exp"], "phi1": [torch.empty((d, p), dtype=torch.float64, device=dev) for _ in vecs]}
+    with pytest.raises(ValueError):
+        pfm.tri_action(dl, dd, du, [w[:, 5:5 + p] for w in wideV], ("exp", "phi1"), m=8, out=bad)
+
+
 def test_nonfinite_and_errors(torch_dev):
     torch, dev = torch_dev
     from paper_2210_03714_amd import pfm
