@@ -155,9 +155,9 @@ def tri_leg(batch, d, p, reps, cpu_seconds):
            "config": {"workload": "batch %d x tridiagonal d=%d, N(0,1) diagonals rescaled to ||A||_1~U[0.5,8], "
                                   "p=%d columns N(0,1), exp(A)V, m=8 (R8), tol 1e-12, FP64" % (batch, d, p),
                       "batch": batch, "d": d, "p": p},
-           "roofline": {"bound": "hbm", "kernel": "tri_steps_kernel<8>", "achieved": round(achieved / 1e9, 1),
+           "roofline": {"bound": "hbm", "kernel": "tri_steps_kernel<8,false>", "achieved": round(achieved / 1e9, 1),
                         "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
-                        "traffic": traffic_from_profile("tri_steps_kernel<8>")}}
+                        "traffic": traffic_from_profile("tri_steps_kernel<8,false>")}}
     if cpu_seconds > 0:
         from oracle import banded as bd
         k, t0 = 0, time.perf_counter()

@@ -319,6 +319,8 @@ def expm(A, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None
         _require_gpu(a)
         if a.dim() != 2 or a.shape[0] != a.shape[1] or a.stride(1) != 1:
             raise ValueError("each A must be square with unit column stride")
+        if a.dtype != mats[0].dtype or a.dtype not in (torch.float64, torch.complex128):
+            raise ValueError("every A must be float64, or every A complex128")
     cplx = mats[0].is_complex()
     fm = _fmask(funcs)
     if out is None:
@@ -335,6 +337,7 @@ def expm(A, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None
         # log(1 - A) is written to the F_exp slot
         fe = outs["exp"][i] if "exp" in funcs else (outs["log1m"][i] if "log1m" in funcs else None)
         fp = outs["phi1"][i] if "phi1" in funcs else None
+        _check_outputs(fe, fp, a.shape, a.dtype)
         ldf = (fe if fe is not None else fp).stride(0)
         probs.append(Problem(a.shape[0], 0, a.stride(0), 0, ldf, a.data_ptr(), None,
                              fe.data_ptr() if fe is not None else None,
@@ -346,6 +349,21 @@ def expm(A, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None
     if rc:
         raise PfmError(rc, ctx.last_error())
     return out, _Info(info)
+
+
+def _check_outputs(fe, fp, shape, dtype):
+    """The result tensors of one instance: on the GPU, of the instance's shape
+    and element type, unit column stride, and one row stride for both
+    functions (the library writes both with the same leading dimension)."""
+    for o in (fe, fp):
+        if o is None:
+            continue
+        _require_gpu(o)
+        if o.dtype != dtype or tuple(o.shape) != tuple(shape) or o.stride(1) != 1:
+            raise ValueError("each output must be a %s tensor of shape %s with unit column stride"
+                             % (dtype, tuple(shape)))
+    if fe is not None and fp is not None and fe.stride(0) != fp.stride(0):
+        raise ValueError("the outputs of one instance must share their row stride")
 
 
 def _info_buffer(info_out, count, device):
@@ -365,9 +383,17 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx
     import torch
     mats = list(A) if isinstance(A, (list, tuple)) else [A[i] for i in range(A.shape[0])]
     vecs = list(V) if isinstance(V, (list, tuple)) else [V[i] for i in range(V.shape[0])]
+    if len(mats) != len(vecs):
+        raise ValueError("one V per A")
     for a, v in zip(mats, vecs):
         _require_gpu(a)
         _require_gpu(v)
+        if a.dim() != 2 or a.shape[0] != a.shape[1] or a.stride(1) != 1:
+            raise ValueError("each A must be square with unit column stride")
+        if v.dim() != 2 or v.shape[0] != a.shape[0] or v.stride(1) != 1:
+            raise ValueError("each V must be (n, p) with unit column stride")
+        if a.dtype not in (torch.float64, torch.complex128) or v.dtype not in (torch.float64, torch.complex128):
+            raise ValueError("A and V must be float64 or complex128")
     cplx = mats[0].is_complex() or vecs[0].is_complex()
     if cplx:  # one element type per call: complex A and V (interleaved)
         mats = [a if a.is_complex() else a.to(torch.complex128) for a in mats]
@@ -379,6 +405,7 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx
     for i, (a, v) in enumerate(zip(mats, vecs)):
         fe = out["exp"][i] if "exp" in funcs else (out["log1m"][i] if "log1m" in funcs else None)
         fp = out["phi1"][i] if "phi1" in funcs else None
+        _check_outputs(fe, fp, v.shape, v.dtype)
         ldf = (fe if fe is not None else fp).stride(0)
         probs.append(Problem(a.shape[0], v.shape[1], a.stride(0), v.stride(0), ldf, a.data_ptr(),
                              v.data_ptr(), fe.data_ptr() if fe is not None else None,
@@ -420,15 +447,7 @@ def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=-1, ctx
     for i, (a, b, c, v) in enumerate(zip(dls, dds, dus, vecs)):
         fe = out["exp"][i] if "exp" in funcs else None
         fp = out["phi1"][i] if "phi1" in funcs else None
-        # the library writes every function's result with one row stride
-        for o in (fe, fp):
-            if o is None:
-                continue
-            _require_gpu(o)
-            if o.dtype != torch.float64 or o.shape != v.shape or o.stride(1) != 1:
-                raise ValueError("each output must be a float64 (d, p) tensor with unit column stride")
-        if fe is not None and fp is not None and fe.stride(0) != fp.stride(0):
-            raise ValueError("the exp and phi1 outputs of an instance must share their row stride")
+        _check_outputs(fe, fp, v.shape, torch.float64)
         ldf = (fe if fe is not None else fp).stride(0)
         probs.append(TriProblem(b.numel(), v.shape[1], v.stride(0), ldf,
                                 a.data_ptr() if a.numel() else None, b.data_ptr(),

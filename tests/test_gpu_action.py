@@ -100,3 +100,36 @@ def test_action_pivoting_forced_N(torch_dev):
     torch.cuda.synchronize()
     ref = me.action(A, V, ("exp",), 8, 1e-12, force_plan=1)
     assert me.rel_fro(res["exp"][0].cpu().numpy(), ref["exp"]) <= 1e-11
+
+
+def test_binding_rejects_mismatched_tensors(torch_dev):
+    """Shapes, element types and strides the library cannot address safely
+    are refused by the binding before anything is enqueued."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    A = torch.from_numpy(wl.gaussian(32, 4.0, wl.SEED_BASE + 660)).to(dev)
+    V = torch.from_numpy(wl.vectors(32, 3, wl.SEED_BASE + 661)).to(dev)
+    _say("case binding validation")
+    bad_outs = [
+        {"exp": [torch.empty((32, 31), dtype=torch.float64, device=dev)]},      # wrong shape
+        {"exp": [torch.empty((32, 32), dtype=torch.complex128, device=dev)]},   # wrong type
+        {"exp": [torch.empty((32, 64), dtype=torch.float64, device=dev)[:, ::2]]},  # column stride 2
+        {"exp": [torch.empty((32, 40), dtype=torch.float64, device=dev)[:, :32]],   # row strides differ
+         "phi1": [torch.empty((32, 32), dtype=torch.float64, device=dev)]},
+    ]
+    for out in bad_outs:
+        with pytest.raises(ValueError):
+            pfm.expm([A], tuple(out), m=8, out=out)
+    with pytest.raises(ValueError):  # one element type per call
+        pfm.expm([A, A.to(torch.complex128)], ("exp",), m=8)
+    with pytest.raises(ValueError):  # V rows != n
+        pfm.action([A], [V[:31]], ("exp",), m=8)
+    with pytest.raises(ValueError):  # non-square A
+        pfm.action([A[:, :31]], [V], ("exp",), m=8)
+    with pytest.raises(ValueError):  # complex A: the results are complex
+        pfm.action([A.to(torch.complex128)], [V], ("exp",), m=8,
+                   out={"exp": [torch.empty_like(V)]})
+    # the same call with matching tensors runs
+    res, info = pfm.action([A], [V], ("exp",), m=8, out={"exp": [torch.empty_like(V)]})
+    torch.cuda.synchronize()
+    assert info[0]["status"] == 0
