@@ -379,7 +379,7 @@ def main():
         ctx.check()
         inf10 = np.frombuffer(info10.cpu().numpy().tobytes(), dtype=pfm.INFO_DTYPE)
         rel = ((out - r8).flatten(1).norm(dim=1) / r8.flatten(1).norm(dim=1)).max().item()
-        res["hybrid_r10star"] = {
+        res["hybrid_r10"] = {
             "value": round(batch / (ms10 / 1e3), 2), "unit": "evals/s", "ms_per_step": round(ms10, 4),
             "m": 10, "mean_s": round(float(inf10["plan"].mean()), 4), "mean_s_r8": round(float(svals.mean()), 4),
             "phases_ms_per_step": {p: round(v[0] / max(1, calls10), 4) for p, v in ph10.items()},

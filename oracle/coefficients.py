@@ -120,12 +120,14 @@ def moments(b, c, K):
 
 
 def shifts_R10(variant):
-    """The ten shifts of the two 10th-order examples of §4.3:
-    'R10':  c_i = 1/(6 + i), i = 1..10;
-    'R10*': c_{2i-1} = -1/(6 + 2i), c_{2i} = 1/(6 + 2i), i = 1..5."""
-    if variant == "R10":
-        return [Fr(1, 6 + i) for i in range(1, 11)]
+    """The ten shifts of the two 10th-order examples of §4.3, named as in the
+    list of methods of the numerical examples (§5):
+    'R10*': c_i = 1/(6 + i), i = 1..10 (eqs. Frac10ciNO, Frac10biNO);
+    'R10':  c_{2i-1} = -1/(6 + 2i), c_{2i} = 1/(6 + 2i), i = 1..5
+            (eqs. Frac10ci, Frac10bi)."""
     if variant == "R10*":
+        return [Fr(1, 6 + i) for i in range(1, 11)]
+    if variant == "R10":
         out = []
         for i in range(1, 6):
             out += [Fr(-1, 6 + 2 * i), Fr(1, 6 + 2 * i)]
@@ -133,7 +135,7 @@ def shifts_R10(variant):
     raise ValueError(variant)
 
 
-HYBRID_FREE = {"R10": (Fr(-50000), Fr(350000)), "R10*": (Fr(2000), Fr(-3500))}
+HYBRID_FREE = {"R10*": (Fr(-50000), Fr(350000)), "R10": (Fr(2000), Fr(-3500))}
 
 
 def hybrid_set(variant, func="exp"):
@@ -205,9 +207,9 @@ REAL_SETS = {4: shifts_R4, 5: shifts_R5, 8: shifts_R8}
 # weights of eq. (4) for a_k = -1/k (a_0 = 0); it has no scaling identity,
 # so it is evaluated at s = 0 only
 LOG1M_SETS = {5: shifts_frac4}
-# m = 10: the hybrid set of §4.3 with the smaller coefficients (R10*), for
+# m = 10: the hybrid set of §4.3 with the smaller coefficients (R10), for
 # the exponential (the paper gives no phi1 weights for it)
-HYBRID_SETS = {10: "R10*"}
+HYBRID_SETS = {10: "R10"}
 
 
 def real_set(func, m):

@@ -344,10 +344,10 @@ def test_r_scalar_is_the_rational():
 
 
 def test_hybrid_diagonal_reduction(golden):
-    """m = 10 (R10*, §4.3) on a diagonal matrix: the oracle's round-off form
+    """m = 10 (R10, §4.3) on a diagonal matrix: the oracle's round-off form
     with the polynomial part equals the printed plain form
     d0 + d1 x + d2 x^2 + sum b_i / (1 - c_i x), raised to 2^s, at 40 digits."""
-    e = [e for e in golden["hybrid"] if e["set"] == "R10*"][0]
+    e = [e for e in golden["hybrid"] if e["set"] == "R10"][0]
     q = lambda x: mpmath.mpf(Fr(x).numerator) / Fr(x).denominator
     c = [q(x) for x in e["shifts"]]
     b = [q(x) for x in e["b"]] + [q(x) for x in e["b_free"]]
