@@ -14,7 +14,10 @@ steps), and B v costs one tridiagonal product.
      θ = θ(f, m, tol); N = max(1, ceil(eta / θ)); B = A / N entry by entry.
   2. For each shift c_k: the LU of M_k = I - c_k B (subdiagonal -c_k dl/N,
      diagonal 1 - c_k dd/N, superdiagonal -c_k du/N).
-  3. r(B) y = a0 y + sum_k w_k M_k^{-1} (B y)   (round-off form, §4.3)
+  3. r(B) y = a0 y + sum_k w_k M_k^{-1} (B y)   (round-off form, §4.3);
+     the hybrid set of §4.3 (m = 10, exp) adds d1 B y + d2 B (B y), the
+     scheme the numerical examples (§5) apply to a tridiagonal A as R10':
+     one product and the tridiagonal solves per step
      exp:  v_0 = V, v_j = r(B) v_{j-1}, j = 1..N
      phi1: u_1 = rho(B) V / N, u_{j+1} = r(B) u_j + u_1 (rho the phi1
            approximant), and u_N = phi1(A) V.
@@ -65,8 +68,6 @@ def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
     eta = tri_norm1(dl, dd, du)
     N = method.plan_steps(eta, theta) if force_plan is None else int(force_plan)
     bl, bd, bu = dl / N, dd / N, du / N
-    if m in method.co.HYBRID_SETS:
-        raise NotImplementedError("tridiagonal oracle: partial-fraction sets only")
     a0, terms = method.build_terms(funcs, m, False)
     facs = []
     for c, _, pair in terms:
@@ -84,6 +85,9 @@ def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
     def apply_r(fname, X):
         Y = tri_matvec(bl, bd, bu, X)
         out = a0[fname] * X
+        d1, d2 = method.co.poly_terms(fname, m)
+        if d1 or d2:  # the hybrid sets: d1 B + d2 B^2
+            out = out + d1 * Y + d2 * tri_matvec(bl, bd, bu, Y)
         for (c, ws, _), fac in zip(terms, facs):
             w = float(complex(ws.get(fname, 0.0)).real)
             if w == 0.0:

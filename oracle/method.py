@@ -213,10 +213,14 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
 
 def r_scalar(func, m, x):
     """The approximant of ``func`` on the m-solve set at scalars x (array),
-    in the round-off form of §4.3: a0 + sum_k w_k x / (1 - c_k x)."""
+    in the round-off form of §4.3: a0 + sum_k w_k x / (1 - c_k x), plus
+    d1 x + d2 x^2 for the hybrid sets of §4.3."""
     x = np.asarray(x, dtype=np.complex128)
     a0, terms = co.roundoff_terms(func, m)
     out = np.full(x.shape, a0, dtype=np.complex128)
+    d1, d2 = co.poly_terms(func, m)
+    if d1 or d2:
+        out += d1 * x + d2 * x * x
     for c, w, pair in terms:
         t = w * x / (1 - c * x)
         out += t + np.conj(w) * x / (1 - np.conj(c) * x) if pair else t
@@ -229,11 +233,14 @@ def _r_mp(func, m, xs, N, geo):
     method uses; returned as complex128."""
     import mpmath
     a0e, te = co.roundoff_terms("exp", m)
-    a0p, tp = co.roundoff_terms("phi1", m)
+    pe = co.poly_terms("exp", m)
+    if geo:
+        a0p, tp = co.roundoff_terms("phi1", m)
+        pp = co.poly_terms("phi1", m)
     out = np.empty(len(xs), dtype=np.complex128)
     with mpmath.workdps(40):
-        def rat(a0, terms, x):
-            v = mpmath.mpc(a0)
+        def rat(a0, terms, poly, x):
+            v = mpmath.mpc(a0) + mpmath.mpf(poly[0]) * x + mpmath.mpf(poly[1]) * x * x
             for c, w, pair in terms:
                 v += mpmath.mpc(w) * x / (1 - mpmath.mpc(c) * x)
                 if pair:
@@ -241,12 +248,12 @@ def _r_mp(func, m, xs, N, geo):
             return v
         for i, x in enumerate(xs):
             xm = mpmath.mpc(complex(x))
-            r = rat(a0e, te, xm)
+            r = rat(a0e, te, pe, xm)
             if not geo:
                 v = r ** N
             else:
                 s = mpmath.mpf(N) if r == 1 else (1 - r ** N) / (1 - r)
-                v = rat(a0p, tp, xm) / N * s
+                v = rat(a0p, tp, pp, xm) / N * s
             out[i] = complex(v)
     return out
 

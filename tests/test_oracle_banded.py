@@ -62,6 +62,42 @@ def test_tridiagonal_equals_dense_oracle(funcs, m, d):
         assert me.rel_fro(got[f], ref[f]) <= bound, (f, me.rel_fro(got[f], ref[f]), bound)
 
 
+@pytest.mark.parametrize("d", [2, 3, 48])
+def test_tridiagonal_hybrid_equals_dense_oracle(d):
+    """The hybrid set of §4.3 (m = 10, exp; R10' of §5 on a tridiagonal A):
+    same plan and result as the dense oracle, whose polynomial part is a
+    dense product, to the rounding bound above with the polynomial
+    coefficients added to the amplification."""
+    p = 3
+    dl, dd, du = _random_tri(d, wl.SEED_BASE + 411)
+    V = np.random.default_rng(10).standard_normal((d, p))
+    got = bd.tri_action(dl, dd, du, V, ("exp",), 10, 1e-12)
+    ref = me.action(bd.tri_dense(dl, dd, du), V, ("exp",), 10, 1e-12)
+    assert got["plan"] == ref["plan"]
+    d1, d2 = co.poly_terms("exp", 10)
+    bound = 16 * d * got["plan"] * (1 + _sum_abs_w(("exp",), 10) + abs(d1) + abs(d2)) * U64
+    assert me.rel_fro(got["exp"], ref["exp"]) <= bound, (me.rel_fro(got["exp"], ref["exp"]), bound)
+
+
+def test_laplacian_hybrid_closed_form():
+    """R10' on A = -trid{-1, 2, -1}, d = 64: per eigenvalue the N steps
+    multiply by r(x)^N, and the result is exp(A) V within the N-step bound."""
+    d, p = 64, 2
+    dl = np.full(d - 1, 1.0)
+    dd = np.full(d, -2.0)
+    du = np.full(d - 1, 1.0)
+    lam, U = bd.laplacian_1d_eig(d)
+    mu = -lam
+    V = np.random.default_rng(8).standard_normal((d, p))
+    got = bd.tri_action(dl, dd, du, V, ("exp",), 10, 1e-12)
+    N = got["plan"]
+    meth = me.action_normal(mu, U, V, ("exp",), 10, N, exact_scalars=True)
+    d1, d2 = co.poly_terms("exp", 10)
+    assert me.rel_fro(got["exp"], meth["exp"]) <= 64 * N * U64 * (1 + _sum_abs_w(("exp",), 10) + abs(d1) + abs(d2))
+    ex = U @ (np.exp(mu)[:, None] * (U.T @ V))
+    assert me.rel_fro(got["exp"], ex) <= N * 1e-12 * 10
+
+
 @pytest.mark.parametrize("tau", [1.0, 8.0])
 def test_laplacian_closed_form(tau):
     """A = -tau trid{-1, 2, -1} (the test matrix of §5) is symmetric, with the

@@ -327,6 +327,28 @@ def test_action_normal_matches_step_by_step(kind):
     assert me.rel_fro(got["exp"], ex) <= ref["plan"] * 1e-12 * 10
 
 
+def test_r_scalar_hybrid_is_the_rational():
+    """For the hybrid set (m = 10, §4.3) r_scalar equals
+    d0 + d1 x + d2 x^2 + sum b_i / (1 - c_i x) summed exactly at rational
+    points, and so meets exp to the order-11 truncation at small x."""
+    from fractions import Fraction as Fr
+    c, b, d = co.hybrid_set(co.HYBRID_SETS[10])
+    a0, terms = co.roundoff_terms("exp", 10)
+    d1, d2 = co.poly_terms("exp", 10)
+    u = 2.0 ** -53
+    for xq in (Fr(1, 7), Fr(-3, 10), Fr(1, 20)):
+        exact = d[0] + d[1] * xq + d[2] * xq * xq + sum((bi / (1 - ci * xq) for ci, bi in zip(c, b)), Fr(0))
+        got = me.r_scalar("exp", 10, np.array([float(xq)]))[0]
+        x = float(xq)
+        mag = abs(a0) + abs(d1 * x) + abs(d2 * x * x) + sum(abs(w * x / (1 - cc * x)) for cc, w, _ in terms)
+        assert abs(got - float(exact)) <= (len(terms) + 6) * u * mag, (xq, got, float(exact))
+    # at x = 0.05 the truncation (order 11) is far below the rounding of the
+    # round-off form, which the cancellation in sum |w_k| ~ 1e4 dominates
+    x = 0.05
+    mag = abs(a0) + abs(d1 * x) + abs(d2 * x * x) + sum(abs(w * x / (1 - cc * x)) for cc, w, _ in terms)
+    assert abs(me.r_scalar("exp", 10, np.array([x]))[0] - np.exp(x)) <= (len(terms) + 6) * u * mag + x ** 11
+
+
 def test_r_scalar_is_the_rational():
     """r_scalar in the round-off form equals sum b_k / (1 - c_k x) summed
     exactly at rational points (the partial-fraction form of eq. 2)."""
