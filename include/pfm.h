@@ -73,7 +73,7 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
 
 /* return codes */
 #define PFM_OK 0
-#define PFM_ERR_INVALID (-1)     /* null pointer, n < 1, ld < n, p < 0, tol not in (0,1), ... */
+#define PFM_ERR_INVALID (-1)     /* null pointer, n < 1, ld < n, p < 0, tol not in (0,1), an array not 8-byte aligned, ... */
 #define PFM_ERR_UNSUPPORTED (-2) /* (f, m, dtype, prec) combination not provided */
 #define PFM_ERR_BUDGET (-3)      /* workspace would exceed the context's HBM budget */
 #define PFM_ERR_HIP (-4)         /* HIP runtime error */
@@ -95,7 +95,9 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
 /* One problem instance.  p == 0: full matrix, F_exp / F_phi1 are n x n with
  * leading dimension ldf.  p >= 1: action on the n x p block V (leading
  * dimension ldv), F_exp / F_phi1 are n x p with leading dimension ldf.
- * Outputs not requested by the function mask may be NULL. */
+ * Outputs not requested by the function mask may be NULL.  Every array is
+ * device memory at an address that is a multiple of 8 (PFM_ERR_INVALID
+ * otherwise). */
 typedef struct {
   int32_t n;
   int32_t p;
@@ -210,6 +212,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
  *   V       d x p row-major, leading dimension ldv >= p; never written
  *   F_exp, F_phi1   d x p row-major outputs, leading dimension ldf >= p; must
  *           not overlap the inputs; NULL when f excludes them
+ * Every array's address is a multiple of 8 (PFM_ERR_INVALID otherwise).
  * ------------------------------------------------------------------------ */
 #define PFM_TRI_MAX_D (1 << 24)
 #define PFM_TRI_MAX_P (1 << 20)
@@ -232,7 +235,9 @@ typedef struct {
  *              N >= 1 for every instance; a forced N that leaves some
  *              |c_k| ||B||_1 >= 1 may meet a zero pivot, reported as
  *              PFM_SINGULAR_SHIFT, since the sweeps do not interchange rows)
- *   m          4, 5 or 8 (the real shift sets; PFM_ERR_UNSUPPORTED for m = 1)
+ *   m          4, 5 or 8 (the real shift sets; PFM_ERR_UNSUPPORTED for m = 1),
+ *              or 10: the hybrid set of §4.3 in the round-off form (R10' of
+ *              §5), exp only (PFM_ERR_UNSUPPORTED with PFM_PHI1)
  * pfm_info.route is 3.  With pfm_profile on, phase 0 times the
  * factorisations and phase 1 the N steps.  The call reads the step counts back once (one
  * stream synchronisation) and returns PFM_ERR_UNSUPPORTED if some N exceeds

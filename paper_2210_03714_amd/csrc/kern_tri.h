@@ -33,7 +33,7 @@
 namespace pfm {
 
 constexpr int kTriL = 8;         // rows per checkpoint chunk
-constexpr int kTriTerms = 8;     // most shifts in a real set
+constexpr int kTriTerms = 10;    // most shifts in a real set (the hybrid set of §4.3)
 
 struct TriDesc {
   const double *dl, *dd, *du, *V;
@@ -54,6 +54,7 @@ struct TriTerms {
   int32_t fn[2];  // function of each slot: 0 exp, 1 phi1
   double a0e, a0p;
   double c[kTriTerms], we[kTriTerms], wp[kTriTerms];
+  double d1, d2;  // the hybrid set's polynomial part d1 x + d2 x^2 (else 0)
 };
 
 // ||A||_1 (largest column sum |du[j-1]| + |dd[j]| + |dl[j]|, summed in that
@@ -188,22 +189,26 @@ __device__ __forceinline__ double gldr(const void *row, uint32_t off) {
 __device__ __forceinline__ void gstr(void *row, uint32_t off, double v) {
   *(__attribute__((address_space(1))) double *)((char *)row + off) = v;
 }
-constexpr int kTriF = 3 + 3 * kTriTerms;  // sub, dia, sup, l_k, ui_k, em_k
 __device__ double kTriZeroRow[64];        // zero-initialised, never written
 
-// NT: the number of shifts (4, 5 or 8), so that the sweeps of all shifts
-// unroll without branches and their chains interleave.  PHI: some slot of
-// the launch is phi1, whose steps after the first add u_1 (without it, no
-// u_1 row is read).  The backward sweeps run in two halves of the shifts
+// NT: the number of shifts (4, 5, 8, or 10 for the hybrid set), so that the
+// sweeps of all shifts unroll without branches and their chains interleave.
+// PHI: some slot of the launch is phi1, whose steps after the first add u_1
+// (without it, no u_1 row is read).  HYB: the hybrid set of §4.3 (exp only;
+// R10' of §5 on a tridiagonal A): the forward pass also forms
+// P = d1 B y + d2 B (B y) for y = x, one row behind, into the slot's u_1
+// buffer, and the backward pass adds it where phi1 adds u_1.  The backward sweeps run in two halves of the shifts
 // (all of them for NT = 4), so that only half of the recomputed forward
 // values are held at a time; the sum a0 x + sum_k w_k x_k keeps the order
 // k = 0, 1, ...  Chunks that start past d are skipped; the tail rows of the
 // last chunk are swept on zero factors and never stored.
-template <int NT, bool PHI>
+template <int NT, bool PHI, bool HYB>
 __global__ void __launch_bounds__(64)
 tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
                  const double *__restrict__ fac, double *__restrict__ vws) {
-  __shared__ double fb[2][kTriF][kTriRB];
+  constexpr int KF = 3 + 3 * NT;  // staged fields: sub, dia, sup, then l_k, ui_k, em_k
+  constexpr bool ADD = PHI || HYB;  // the backward pass adds a stored row (u_1 or P)
+  __shared__ double fb[2][KF][kTriRB];
   constexpr int NA = NT > 4 ? (NT + 1) / 2 : NT;  // shifts of the first half
   const int lane = threadIdx.x;
   const int gw = blockIdx.x;
@@ -238,7 +243,7 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
   const uint32_t cofs = 8u * (uint32_t)(c - cb);  // this lane's byte offset from column cb
   const int64_t p8 = 8 * (int64_t)p;
 
-  double nf[kTriF];
+  double nf[KF];
   // rows past d are staged as zeros (read from sub[0]): there y = 0, z = 0
   // and x = 0, so the last real row sees x_d = 0 with no test in the sweeps
   auto fetch = [&](int blk) {
@@ -248,20 +253,16 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
     nf[1] = gld(in ? dia + r : sub);
     nf[2] = gld(in ? sup + r : sub);
 #pragma unroll
-    for (int k = 0; k < kTriTerms; ++k) {
+    for (int k = 0; k < NT; ++k) {
       const double *a = lf + (int64_t)k * 3 * d + r;
-      if (k < NT) {
-        nf[3 + k] = gld(in ? a : sub);
-        nf[3 + kTriTerms + k] = gld(in ? a + d : sub);
-        nf[3 + 2 * kTriTerms + k] = gld(in ? a + 2 * d : sub);
-      } else {
-        nf[3 + k] = nf[3 + kTriTerms + k] = nf[3 + 2 * kTriTerms + k] = 0.0;
-      }
+      nf[3 + k] = gld(in ? a : sub);
+      nf[3 + NT + k] = gld(in ? a + d : sub);
+      nf[3 + 2 * NT + k] = gld(in ? a + 2 * d : sub);
     }
   };
   auto put = [&](int buf) {
 #pragma unroll
-    for (int f = 0; f < kTriF; ++f) fb[buf][f][lane] = nf[f];
+    for (int f = 0; f < KF; ++f) fb[buf][f][lane] = nf[f];
   };
   fetch(0);
   put(0);
@@ -301,6 +302,8 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
       double xm = 0.0, xr[kTriFR][kTriL];
 #pragma unroll
       for (int i = 0; i < kTriFR; ++i) xrows(i * kTriL, xr[i], Lc());
+      // HYB: y and B's row of the two rows before the current one
+      double ym1 = 0.0, ym2 = 0.0, bs1 = 0.0, bd1 = 0.0, bu1 = 0.0;
 #pragma unroll 1
       for (int b = 0; b < nb; ++b) {
         const int buf = b & 1;
@@ -319,6 +322,19 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
 #pragma unroll
               for (int k = 0; k < NT; ++k) z[k] = fma(-fb[buf][3 + k][lr], z[k], y);
               xm = x0;
+              if constexpr (HYB) {
+                // P on the row before: d1 y + d2 (B y), whose last term needs
+                // this row's y (rows past d have y = 0)
+                const int r = rg + jj;
+                const double by = fma(bu1, y, fma(bs1, ym2, bd1 * ym1));
+                const double pv = fma(T.d2, by, T.d1 * ym1);
+                if (r >= 1 && r - 1 < d) gstr(u1b + (int64_t)(r - 1) * p8, cofs, pv);
+                ym2 = ym1;
+                ym1 = y;
+                bs1 = fb[buf][0][lr];
+                bd1 = fb[buf][1][lr];
+                bu1 = fb[buf][2][lr];
+              }
             }
             // (the last chunk's slot is written and never read)
             char *cq = ckb + (int64_t)(rg / kTriL) * NT * p8;
@@ -332,6 +348,14 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
           __syncthreads();
         }
       }
+      if constexpr (HYB) {
+        // d a multiple of kTriL: no row past d was swept, and P on the last
+        // row (whose B y has no row below) is still due
+        if (d % kTriL == 0) {
+          const double by = fma(bs1, ym2, bd1 * ym1);
+          gstr(u1b + (int64_t)(d - 1) * p8, cofs, fma(T.d2, by, T.d1 * ym1));
+        }
+      }
     }
 
     // pass 2 (block nb - 1 is staged): chunks from the last.  Per chunk q
@@ -342,13 +366,13 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
     // (independent chains side by side), and out_r = a0 x_r + sum_k w_k x_{k,r}.
     // Once the slot is read, it is refilled with chunk q - kTriBR.
     {
-      const bool add_u1 = PHI && fn == 1 && j > 0;
+      const bool add_u1 = (PHI && fn == 1 && j > 0) || HYB;
       double xs[kTriBR][kTriL + 1];            // rows r0 - 1 .. r0 + kTriL - 1
-      double us[kTriBR][PHI ? kTriL : 1];      // u_1 on the chunk's rows
+      double us[kTriBR][ADD ? kTriL : 1];      // u_1 (or P) on the chunk's rows
       double zc[kTriBR][NT];                   // checkpoints: z at row r0 - 1
       auto chunk_loads = [&](int q, int sl) {
         xrows(q * kTriL - 1, xs[sl], std::integral_constant<int, kTriL + 1>());
-        if constexpr (PHI) {
+        if constexpr (ADD) {
           const char *up = u1b + (int64_t)q * kTriL * p8;
 #pragma unroll
           for (int jj = 0; jj < kTriL; ++jj, up += p8) {
@@ -405,7 +429,7 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
               const int lr = g * kTriL + jj;
 #pragma unroll
               for (int k = K0; k < K1; ++k) {
-                xc[k] = fma(-fb[buf][3 + 2 * kTriTerms + k][lr], xc[k], fb[buf][3 + kTriTerms + k][lr] * zz[k - K0][jj]);
+                xc[k] = fma(-fb[buf][3 + 2 * NT + k][lr], xc[k], fb[buf][3 + NT + k][lr] * zz[k - K0][jj]);
                 o[jj] = fma(wk[k], xc[k], o[jj]);
               }
             }
@@ -419,7 +443,7 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
               const double xh = jj + 1 < kTriL ? xs[sl][jj + 2] : xt;
               y[jj] = fma(fb[buf][2][lr], xh, fma(fb[buf][0][lr], xs[sl][jj], fb[buf][1][lr] * xs[sl][jj + 1]));
               double ax = a0 * xs[sl][jj + 1];
-              if constexpr (PHI) ax += us[sl][jj];  // u_1 (phi1 after its first step; else 0)
+              if constexpr (ADD) ax += us[sl][jj];  // u_1 (phi1 after its first step) or P; else 0
               o[jj] = ax;
             }
             xt = xs[sl][1];

@@ -132,6 +132,9 @@ double theta_of(const PfmSetEntry *e, double tol) {
 }
 
 inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+// user arrays are read and written one binary64 element (or half of a
+// complex one) at a time: their addresses must be multiples of 8
+inline bool misaligned(const void *p) { return ((uintptr_t)p & 7) != 0; }
 
 // Pinned staging area of at least `bytes`; waits until the previous upload
 // that read it has executed.
@@ -363,11 +366,19 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
     if (P.ldv < P.p || P.ldf < P.p) return set_err(ctx, PFM_ERR_INVALID, "problem %d: ldv or ldf < p", i);
     if ((f & PFM_EXP) && !P.F_exp) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_exp null", i);
     if ((f & PFM_PHI1) && !P.F_phi1) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_phi1 null", i);
+    if (misaligned(P.dl) || misaligned(P.dd) || misaligned(P.du) || misaligned(P.V) || misaligned(P.F_exp) ||
+        misaligned(P.F_phi1))
+      return set_err(ctx, PFM_ERR_INVALID, "problem %d: an array is not 8-byte aligned", i);
   }
   const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
-  if (!ee || !ep) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
-  if (ee->pair || (ee->nterms != 4 && ee->nterms != 5 && ee->nterms != 8))
-    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the tridiagonal path takes the real shift sets (m = 4, 5, 8)");
+  if (!ee || (!ep && (f & PFM_PHI1))) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
+  // the hybrid set of §4.3 (m = 10, real shifts, d1 x + d2 x^2): the
+  // exponential only, as the paper gives it
+  const bool hybrid = ee->poly[0] != 0.0 || ee->poly[1] != 0.0;
+  if (ee->pair || !(ee->nterms == 4 || ee->nterms == 5 || ee->nterms == 8 || (hybrid && ee->nterms == 10)))
+    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the tridiagonal path takes the real shift sets (m = 4, 5, 8, 10)");
+  if (hybrid && f != PFM_EXP)
+    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the hybrid set is provided for the exponential only");
   double theta;
   int rc = pfm_theta(f, m, tol, &theta);
   if (rc) return set_err(ctx, rc, "theta failed");
@@ -380,12 +391,14 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
   if (f & PFM_EXP) T.fn[T.nf++] = 0;
   if (f & PFM_PHI1) T.fn[T.nf++] = 1;
   T.a0e = ee->a0;
-  T.a0p = ep->a0;
+  T.a0p = ep ? ep->a0 : 0.0;
   for (int k = 0; k < T.nterms; ++k) {
     T.c[k] = ee->c_re[k];
     T.we[k] = ee->w_re[k];
-    T.wp[k] = ep->w_re[k];
+    T.wp[k] = ep ? ep->w_re[k] : 0.0;
   }
+  T.d1 = ee->poly[0];
+  T.d2 = ee->poly[1];
   // workspace: B and the factors, then the vectors and checkpoints
   std::vector<TriDesc> desc(batch);
   int64_t dofs = 0;
@@ -467,19 +480,21 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
                      wsd);
   ctx->cur_launches[0]++;
   prof_mark(ctx, 1, stream);
-#define PFM_TRI_STEPS(NT, PHI)                                                                                  \
-  hipLaunchKernelGGL((tri_steps_kernel<NT, PHI>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, batch, d_plan, \
-                     T, (const double *)wsd, wsd)
+#define PFM_TRI_STEPS(NT, PHI, HYB)                                                                            \
+  hipLaunchKernelGGL((tri_steps_kernel<NT, PHI, HYB>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, batch, \
+                     d_plan, T, (const double *)wsd, wsd)
   const bool tri_phi = T.fn[0] == 1 || (T.nf > 1 && T.fn[1] == 1);
-  if (T.nterms == 4) {
-    if (tri_phi) PFM_TRI_STEPS(4, true);
-    else PFM_TRI_STEPS(4, false);
+  if (hybrid) {
+    PFM_TRI_STEPS(10, false, true);
+  } else if (T.nterms == 4) {
+    if (tri_phi) PFM_TRI_STEPS(4, true, false);
+    else PFM_TRI_STEPS(4, false, false);
   } else if (T.nterms == 5) {
-    if (tri_phi) PFM_TRI_STEPS(5, true);
-    else PFM_TRI_STEPS(5, false);
+    if (tri_phi) PFM_TRI_STEPS(5, true, false);
+    else PFM_TRI_STEPS(5, false, false);
   } else {
-    if (tri_phi) PFM_TRI_STEPS(8, true);
-    else PFM_TRI_STEPS(8, false);
+    if (tri_phi) PFM_TRI_STEPS(8, true, false);
+    else PFM_TRI_STEPS(8, false, false);
   }
 #undef PFM_TRI_STEPS
   ctx->cur_launches[1]++;
@@ -557,6 +572,8 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     if (((f & PFM_EXP) || log1m) && !P.F_exp) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_exp null", i);
     if ((f & PFM_PHI1) && !P.F_phi1) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_phi1 null", i);
     if (action && (!P.V || P.ldv < P.p)) return set_err(ctx, PFM_ERR_INVALID, "problem %d: bad V", i);
+    if (misaligned(P.A) || misaligned(P.V) || misaligned(P.F_exp) || misaligned(P.F_phi1))
+      return set_err(ctx, PFM_ERR_INVALID, "problem %d: an array is not 8-byte aligned", i);
   }
   const PfmSetEntry *ee = find_set(m, log1m ? 2 : 0), *ep = find_set(m, 1);
   if (log1m) {

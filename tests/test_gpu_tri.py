@@ -8,12 +8,14 @@ same ||A||_1 bit for bit, and route 3.  Sizes span one and many 16-row
 checkpoint chunks with ragged tails, and one and several 64-column waves
 with ragged last waves."""
 
+import ctypes
 import sys
 
 import numpy as np
 import pytest
 
 from oracle import banded as bd
+from oracle import coefficients as co
 from oracle import method as me
 from paper_2210_03714_amd import workloads as wl
 
@@ -183,3 +185,82 @@ def test_nonfinite_and_errors(torch_dev):
     assert e.value.code == pfm.ERR_UNSUPPORTED
     with pytest.raises(ValueError):
         _run(torch, dev, [(dl[:-1], dd, du)], [V], ("exp",), 8, 1e-12)
+
+
+def test_misaligned_pointers_rejected(torch_dev):
+    """An array whose address is not a multiple of 8 is refused on the host
+    (PFM_ERR_INVALID) before anything is enqueued; the pointers are never
+    dereferenced."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    d, p = 16, 4
+    dl, dd, du = [torch.from_numpy(x).to(dev) for x in wl.tri_gaussian_batch(1, d, 1.0, 2.0, wl.SEED_BASE + 650)[0]]
+    V = torch.from_numpy(wl.vectors(d, p, wl.SEED_BASE + 651)).to(dev)
+    F = torch.empty_like(V)
+    ctx = pfm.Context(0)
+    info = torch.empty(pfm.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    L = pfm.lib()
+    _say("case tri misaligned pointers")
+    for field in ("dl", "dd", "du", "V", "F"):
+        ptr = {"dl": dl.data_ptr(), "dd": dd.data_ptr(), "du": du.data_ptr(), "V": V.data_ptr(), "F": F.data_ptr()}
+        ptr[field] += 4
+        probs = (pfm.TriProblem * 1)()
+        probs[0] = pfm.TriProblem(d, p, p, p, ptr["dl"], ptr["dd"], ptr["du"], ptr["V"], ptr["F"], None)
+        rc = L.pfm_tri_action(ctx.handle, pfm.EXP, 8, 1e-12, 1, probs, ctypes.c_void_p(info.data_ptr()), -1, None)
+        assert rc == pfm.ERR_INVALID, field
+    A = torch.from_numpy(wl.gaussian(8, 2.0, wl.SEED_BASE + 652)).to(dev)
+    FA = torch.empty_like(A)
+    for field in ("A", "F"):
+        pa, pf = A.data_ptr() + (4 if field == "A" else 0), FA.data_ptr() + (4 if field == "F" else 0)
+        probs = (pfm.Problem * 1)()
+        probs[0] = pfm.Problem(8, 0, 8, 0, 8, pa, None, pf, None)
+        rc = L.pfm_eval_batched(ctx.handle, pfm.EXP, 8, 1e-12, pfm.FP64, pfm.R64, 1, probs,
+                                ctypes.c_void_p(info.data_ptr()), -1, None)
+        assert rc == pfm.ERR_INVALID, field
+    ctx.close()
+
+
+def _hybrid_bar(N):
+    """Derived from the arithmetic: per step each side's rounding is a few
+    units (16 here) times 1 + sum_k |w_k| + |d1| + |d2| (about 1e4 for this
+    set: the cancellation the paper notes), over N steps, on both sides."""
+    _, terms = co.roundoff_terms("exp", 10)
+    d1, d2 = co.poly_terms("exp", 10)
+    amp = 1 + sum(abs(w) for _, w, _ in terms) + abs(d1) + abs(d2)
+    return 2 * 16 * N * amp * 2.0 ** -53
+
+
+def test_hybrid_r10_prime(torch_dev):
+    """R10' of §5: the hybrid set of §4.3 (m = 10, exp) in the round-off form
+    on tridiagonal A, P = d1 B y + d2 B^2 y formed in the forward pass.
+    Uneven shapes (d a multiple of 8 or not, ragged column groups) and the
+    paper's trid{-1, 2, -1} at d = 1000, against the tridiagonal oracle."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    shapes = [(1, 1), (3, 2), (16, 5), (17, 64), (100, 65)]
+    tris = [wl.tri_gaussian_batch(1, d, 0.5, 8.0, wl.SEED_BASE + 700 + j)[0] for j, (d, p) in enumerate(shapes)]
+    vecs = [wl.vectors(d, p, wl.SEED_BASE + 720 + j) for j, (d, p) in enumerate(shapes)]
+    tris.append(wl.tri_neg_laplacian(1000, 1.0))
+    vecs.append(wl.vectors(1000, 3, wl.SEED_BASE + 730))
+    _say("case tri hybrid m=10")
+    res, info = _run(torch, dev, tris, vecs, ("exp",), 10, 1e-12)
+    worst = 0.0
+    for i, ((dl, dd, du), V) in enumerate(zip(tris, vecs)):
+        N = int(info[i]["plan"])
+        own = bd.tri_action(dl, dd, du, V, ("exp",), 10, 1e-12)
+        q = own["eta"] / own["theta"]
+        if abs(q - round(q)) < 1e-12 * q:
+            own = bd.tri_action(dl, dd, du, V, ("exp",), 10, 1e-12, force_plan=N)
+        else:
+            assert N == own["plan"], (i, N, own["plan"])
+        assert info[i]["route"] == 3 and info[i]["status"] == 0 and info[i]["order"] == 10
+        err = me.rel_fro(res["exp"][i].cpu().numpy(), own["exp"])
+        bar = _hybrid_bar(N)
+        worst = max(worst, err / bar)
+        assert err <= bar, (i, V.shape, N, err, bar)
+    _say("  worst err / bar %.2e" % worst)
+    dl, dd, du = [_to(torch, dev, x) for x in tris[0]]
+    V = _to(torch, dev, vecs[0])
+    with pytest.raises(pfm.PfmError) as e:
+        pfm.tri_action([dl], [dd], [du], [V], ("phi1",), m=10)
+    assert e.value.code == pfm.ERR_UNSUPPORTED
