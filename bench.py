@@ -94,7 +94,7 @@ def cpu_baseline(A, seconds):
                       "numpy/scipy LAPACK with %d BLAS threads, %.1f s" % (k, threads, dt)}
 
 
-def tri_leg(batch, d, p, reps, cpu_seconds):
+def tri_leg(batch, d, p, reps, cpu_seconds, hybrid=True):
     """Tridiagonal action leg (§2.1, §5): ``batch`` real tridiagonal d x d
     matrices with N(0,1) diagonals rescaled to ||A||_1 ~ U[0.5, 8], each acting
     on p synthetic N(0,1) columns; exp, m = 8, tol 1e-12, FP64.  The step
@@ -124,8 +124,8 @@ def tri_leg(batch, d, p, reps, cpu_seconds):
     L = pfm.lib()
     sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
-    def call():
-        rc = L.pfm_tri_action(ctx.handle, pfm.EXP, 8, 1e-12, batch, probs, ctypes.c_void_p(info.data_ptr()), -1,
+    def call(m=8):
+        rc = L.pfm_tri_action(ctx.handle, pfm.EXP, m, 1e-12, batch, probs, ctypes.c_void_p(info.data_ptr()), -1,
                               sptr)
         if rc:
             raise pfm.PfmError(rc, ctx.last_error())
@@ -155,9 +155,30 @@ def tri_leg(batch, d, p, reps, cpu_seconds):
            "config": {"workload": "batch %d x tridiagonal d=%d, N(0,1) diagonals rescaled to ||A||_1~U[0.5,8], "
                                   "p=%d columns N(0,1), exp(A)V, m=8 (R8), tol 1e-12, FP64" % (batch, d, p),
                       "batch": batch, "d": d, "p": p},
-           "roofline": {"bound": "hbm", "kernel": "tri_steps_kernel<8,false>", "achieved": round(achieved / 1e9, 1),
+           "roofline": {"bound": "hbm", "kernel": "tri_steps_kernel<8,false,false>", "achieved": round(achieved / 1e9, 1),
                         "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
-                        "traffic": traffic_from_profile("tri_steps_kernel<8,false>")}}
+                        "traffic": traffic_from_profile("tri_steps_kernel<8,false,false>")}}
+    if hybrid:
+        # R10' of §5: the hybrid set of §4.3 (m = 10) on the same batch
+        F8 = F.clone()
+        call(10)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call(10)
+        torch.cuda.synchronize()
+        wall10 = (time.perf_counter() - t0) / reps
+        ph10, calls10 = ctx.profile_read()
+        ctx.profile(False)
+        ctx.check()
+        inf10 = np.frombuffer(info.cpu().numpy().tobytes(), dtype=pfm.INFO_DTYPE)
+        rel = ((F - F8).flatten(1).norm(dim=1) / F8.flatten(1).norm(dim=1)).max().item()
+        res["hybrid_r10_prime"] = {
+            "value": round(batch * p / wall10, 1), "unit": "columns/s", "ms_per_call": round(wall10 * 1e3, 3),
+            "steps_kernel_ms": round(ph10["solve_combine"][0] / max(1, calls10), 3), "m": 10,
+            "mean_N": round(float(inf10["plan"].astype(np.int64).mean()), 3), "max_rel_diff_vs_r8": rel,
+            "config": "the same batch with the hybrid set of §4.3 (m = 10) in the round-off form, exp, tol 1e-12"}
     if cpu_seconds > 0:
         from oracle import banded as bd
         k, t0 = 0, time.perf_counter()
@@ -387,7 +408,7 @@ def main():
             "config": "the headline batch with the hybrid set of §4.3 (m = 10), tol 1e-12, FP64"}
     if not args.no_tri:
         res["tridiagonal"] = tri_leg(args.tri_batch, args.tri_d, args.tri_p, 3,
-                                     0.0 if args.no_cpu_baseline else 10.0)
+                                     0.0 if args.no_cpu_baseline else 10.0, hybrid=not args.no_hybrid)
     if args.no_mixed:
         if args.serve_seconds > 0:
             res["serving"] = serving_leg(args.serve_rate, args.serve_seconds)
