@@ -212,3 +212,22 @@ def tri_gaussian_batch(batch, d, norm_lo, norm_hi, seed):
 def tri_neg_laplacian(d, tau=1.0):
     """Diagonals of -tau trid{-1, 2, -1} (the test matrix of §5, dissipative sign)."""
     return np.full(d - 1, tau), np.full(d, -2.0 * tau), np.full(d - 1, tau)
+
+
+def band_gaussian_batch(batch, d, b, norm_lo, norm_hi, seed):
+    """``batch`` banded d x d matrices (half-bandwidth b) with N(0,1)
+    diagonals, each rescaled to ||A||_1 ~ U[norm_lo, norm_hi].  Returns a
+    list of float64 arrays of shape (2b + 1, d), bands[b + o, i] = A[i, i + o];
+    entries outside A are zero."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(batch):
+        bands = rng.standard_normal((2 * b + 1, d))
+        col = np.zeros(d)
+        for o in range(-b, b + 1):
+            lo, hi = max(0, -o), min(d, d - o)
+            bands[b + o, :lo] = 0.0
+            bands[b + o, hi:] = 0.0
+            col[lo + o:hi + o] += np.abs(bands[b + o, lo:hi])
+        out.append(bands * (rng.uniform(norm_lo, norm_hi) / col.max()))
+    return out
