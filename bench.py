@@ -200,6 +200,86 @@ def tri_leg(batch, d, p, reps, cpu_seconds, hybrid=True):
     return res
 
 
+def band_leg(batch, d, p, b, reps, cpu_seconds):
+    """The banded action (b = 2: pentadiagonal): ``batch`` instances of
+    dimension d with N(0,1) diagonals rescaled to ||A||_1 ~ U[0.5, 8], each on
+    p synthetic N(0,1) columns; exp, m = 8, tol 1e-12, FP64.  The step kernel's
+    time comes from the library's HIP events on the call's stream (pfm_profile
+    phase 1).  Algorithmic traffic per column-step is one read and one write
+    of the vector (16 d bytes)."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_2210_03714_amd import pfm
+    from paper_2210_03714_amd import workloads as wl
+    dev = torch.device("cuda:0")
+    bands = wl.band_gaussian_batch(batch, d, b, 0.5, 8.0, wl.SEED_BASE + 30)
+    BT = torch.from_numpy(np.stack(bands)).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(wl.SEED_BASE + 31)
+    V = torch.randn((batch, d, p), dtype=torch.float64, device=dev, generator=gen)
+    F = torch.empty_like(V)
+    probs = (pfm.BandProblem * batch)()
+    for i in range(batch):
+        probs[i] = pfm.BandProblem(d, p, p, p, BT[i].data_ptr(), V[i].data_ptr(), F[i].data_ptr(), None)
+    info = torch.empty(batch * pfm.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    ctx = pfm.Context(0)
+    L = pfm.lib()
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call():
+        rc = L.pfm_band_action(ctx.handle, pfm.EXP, 8, 1e-12, b, batch, probs, ctypes.c_void_p(info.data_ptr()),
+                               -1, sptr)
+        if rc:
+            raise pfm.PfmError(rc, ctx.last_error())
+
+    call()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    phases, calls = ctx.profile_read()
+    ctx.profile(False)
+    ctx.check()
+    inf = np.frombuffer(info.cpu().numpy().tobytes(), dtype=pfm.INFO_DTYPE)
+    Ns = inf["plan"].astype(np.int64)
+    colsteps = float(Ns.sum()) * p
+    steps_ms = phases["solve_combine"][0] / max(1, calls)
+    achieved = colsteps * 16.0 * d / (steps_ms * 1e-3)
+    kname = "band_steps_kernel<%d>" % b
+    res = {"metric": "banded exp(A)v columns/s", "value": round(batch * p / wall, 1), "unit": "columns/s",
+           "ms_per_call": round(wall * 1e3, 3), "steps_kernel_ms": round(steps_ms, 3),
+           "factor_kernel_ms": round(phases["lu"][0] / max(1, calls), 3),
+           "column_steps_per_s": round(colsteps / (steps_ms * 1e-3), 1), "mean_N": round(float(Ns.mean()), 3),
+           "max_N": int(Ns.max()),
+           "config": {"workload": "batch %d x banded d=%d, half-bandwidth b=%d, N(0,1) diagonals rescaled to "
+                                  "||A||_1~U[0.5,8], p=%d columns N(0,1), exp(A)V, m=8 (R8), tol 1e-12, FP64"
+                                  % (batch, d, b, p), "batch": batch, "d": d, "p": p, "b": b},
+           "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved / 1e9, 1),
+                        "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
+                        "traffic": traffic_from_profile(kname)}}
+    if cpu_seconds > 0:
+        from oracle import banded as bd
+        k, t0 = 0, time.perf_counter()
+        Vh = V[:64].cpu().numpy()
+        while k < 64 and (time.perf_counter() - t0) < cpu_seconds:
+            bd.band_action(bands[k], b, Vh[k], ("exp",), 8, 1e-12)
+            k += 1
+        dt = time.perf_counter() - t0
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([x.get("num_threads", 1) for x in threadpool_info() if x.get("user_api") == "blas"] or [1])
+        except Exception:
+            threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        res["cpu_baseline"] = {"value": round(k * p / dt, 1), "unit": "columns/s", "kind": "oracle",
+                               "cores": threads, "sample": "%d consecutive instances (all %d columns each), "
+                               "scipy LAPACK gbtrf/gbtrs, %d BLAS threads, %.1f s" % (k, p, threads, dt)}
+    return res
+
+
 def serving_leg(rate, seconds):
     """The serving stream: open-loop Poisson arrivals at ``rate`` per second
     for ``seconds``; each request draws n log-uniform in [16, 1024] (from a
@@ -245,6 +325,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--no-tri", action="store_true", help="skip the tridiagonal action leg")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid 10th-order leg")
+    ap.add_argument("--no-band", action="store_true", help="skip the banded (pentadiagonal) action leg")
+    ap.add_argument("--band-batch", type=int, default=1024)
+    ap.add_argument("--band-only", action="store_true", help="run only the banded leg (profiling)")
     ap.add_argument("--tri-batch", type=int, default=4096)
     ap.add_argument("--tri-d", type=int, default=1024)
     ap.add_argument("--tri-p", type=int, default=64)
@@ -268,6 +351,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes_read": src.numel() * 8, "calib_copy_bytes_written": dst.numel() * 8}))
+        return
+
+    if args.band_only:
+        print(json.dumps(band_leg(args.band_batch, args.tri_d, args.tri_p, 2, 3, 0.0)))
         return
 
     from paper_2210_03714_amd import pfm
@@ -409,6 +496,9 @@ def main():
     if not args.no_tri:
         res["tridiagonal"] = tri_leg(args.tri_batch, args.tri_d, args.tri_p, 3,
                                      0.0 if args.no_cpu_baseline else 10.0, hybrid=not args.no_hybrid)
+    if not args.no_band:
+        res["banded"] = band_leg(args.band_batch, args.tri_d, args.tri_p, 2, 3,
+                                 0.0 if args.no_cpu_baseline else 10.0)
     if args.no_mixed:
         if args.serve_seconds > 0:
             res["serving"] = serving_leg(args.serve_rate, args.serve_seconds)

@@ -121,7 +121,8 @@ typedef struct {
                         (every |c_k| ||B||_1 <= 1/2); 2: the same for a large
                         instance (n > 512, complex n > 256), spread over many
                         workgroups; 0: pivoting LU route; 3: tridiagonal
-                        action (pfm_tri_action) */
+                        action (pfm_tri_action); 4: banded action
+                        (pfm_band_action) */
   double norm1;      /* ||A||_1 */
   double theta;      /* admissible ||B||_1 for the requested tolerance (§3) */
   double resid;      /* mixed path: largest relative refinement residual */
@@ -245,6 +246,51 @@ typedef struct {
  * (3 + 2 m) d + n_f (3 + m / 16) d p doubles per instance (n_f functions). */
 int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_tri_problem *probs,
                    pfm_info *info, int force_plan, pfm_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Banded A (§2.1 and §5 name the pentadiagonal case beside the tridiagonal
+ * one): the action f(A)V for real A with half-bandwidth b (b = 2:
+ * pentadiagonal), by the same N-step recurrence and round-off form as
+ * pfm_tri_action.  I - c_k B keeps the band of A: its LU (no interchanges)
+ * is formed once per shift and reused by all N steps and all columns (§5.1);
+ * each solve is one banded forward and one backward sweep.
+ *
+ * Problem (all pointers device memory, owned by the caller):
+ *   d       dimension, 1 <= d <= PFM_TRI_MAX_D
+ *   p       columns of V, 1 <= p <= PFM_TRI_MAX_P
+ *   bands   (2b + 1) x d row-major: bands[(b + o) d + i] = A[i][i + o] for
+ *           o = -b..b; the entries with i + o outside [0, d) are not part of
+ *           A and are never read; never written
+ *   V       d x p row-major, leading dimension ldv >= p; never written
+ *   F_exp, F_phi1   d x p row-major outputs, leading dimension ldf >= p; must
+ *           not overlap the inputs; NULL when f excludes them
+ * Every array's address is a multiple of 8 (PFM_ERR_INVALID otherwise).
+ * ------------------------------------------------------------------------ */
+#define PFM_BAND_MAX_B 4
+
+typedef struct {
+  int32_t d;
+  int32_t p;
+  int64_t ldv;
+  int64_t ldf;
+  const double *bands;
+  const double *V;
+  double *F_exp;
+  double *F_phi1;
+} pfm_band_problem;
+
+/* Evaluate a batch of banded actions (binary64), all with half-bandwidth b.
+ *   b          1 <= b <= PFM_BAND_MAX_B (PFM_ERR_INVALID otherwise)
+ *   f, m, tol, info, force_plan, stream   as for pfm_tri_action (m = 4, 5,
+ *              8, or 10: the hybrid set of §4.3, exp only)
+ * pfm_info.route is 4.  ||A||_1 adds column j's entries from the top row
+ * down.  With pfm_profile on, phase 0 times the factorisations and phase 1
+ * the N steps.  The call reads the step counts back once (one stream
+ * synchronisation) and returns PFM_ERR_UNSUPPORTED if some N exceeds 2^20;
+ * everything else is enqueued on `stream`.  Workspace: about
+ * (m + 1) (2b + 1) d + n_f (3 + m) d p doubles per instance (n_f functions). */
+int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, const pfm_band_problem *probs,
+                    pfm_info *info, int force_plan, pfm_stream_t stream);
 
 /* Block until `stream` is idle and report device-side failures of previous
  * calls on this context (PFM_ERR_DEVICE if a bounded device wait timed out). */

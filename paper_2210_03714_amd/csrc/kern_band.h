@@ -1,0 +1,309 @@
+// Banded A (half-bandwidth b, 1 <= b <= kBandMaxB): the action f(A)V by the
+// N-step recurrence with the round-off form of §4.3.  §2.1 and §5 name the
+// pentadiagonal case (b = 2) beside the tridiagonal one: I - c_k B keeps the
+// band of A, so each shifted system costs one banded forward and backward
+// sweep, and the LU of every shifted matrix is formed once and reused by all
+// N steps and all columns (§5.1).  With ||B||_1 <= θ every I - c_k B is
+// strictly column diagonally dominant, so elimination without interchanges
+// is the partial-pivoting LU.
+//
+// Layout (one lane per column of V, a wave per 64 consecutive columns of one
+// instance, so every read of B or of a factor is the same address in all
+// lanes):
+//   A:        bands[(b + o) d + i] = A[i][i + o], o = -b..b (caller's; the
+//             entries with i + o outside [0, d) are never read)
+//   B:        the same layout, A / N, zero outside A
+//   factors:  per shift k, rows l_1..l_b, ui, em_1..em_b of d each:
+//             l_i[r] = L[r][r - i], ui[r] = 1 / U[r][r],
+//             em_j[r] = U[r][r + j] / U[r][r] (zero outside the matrix), so
+//             the backward sweep is x_r = ui[r] z_r - sum_j em_j[r] x_{r+j}
+//   vectors:  per function slot, two ping-pong buffers and one for u_1 (φ1)
+//             or the hybrid set's polynomial part, d x p row-major
+//   forward values: per slot and shift, z_k d x p row-major
+// A step reads the input twice (forward pass: y = B x and the forward
+// sweeps of all shifts, storing z_k; backward pass: the backward sweeps of
+// all shifts and out = a0 x + sum_k w_k x_k) and writes the output once.
+#pragma once
+
+#include "kern_common.h"
+#include "kern_tri.h"
+
+namespace pfm {
+
+constexpr int kBandMaxB = 4;
+
+struct BandDesc {
+  const double *bands, *V;
+  double *Fe, *Fp;
+  int64_t ldv, ldf;
+  int32_t d, p, b, pad_;
+  double theta;
+  int64_t b_off;  // B: (2b + 1) d
+  int64_t f_off;  // factors: [k][2b + 1][d]
+  int64_t v_off;  // vectors: [slot][3][d][p]
+  int64_t z_off;  // forward values: [slot][k][d][p]
+  int32_t wave0;   // first wave of this instance in the step launch
+  int32_t nwaves;  // its waves: functions x ceil(p / 64)
+};
+
+// ||A||_1 (column j adds |A[i][j]| for rows i = j - b .. j + b in increasing
+// order) and N = max(1, ceil(eta / θ)); one workgroup per instance.
+__global__ void __launch_bounds__(256)
+band_plan_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan, int force_plan) {
+  __shared__ double red[4];
+  __shared__ int bad[4];
+  const int ii = blockIdx.x, t = threadIdx.x;
+  const BandDesc D = desc[ii];
+  const int d = D.d, b = D.b;
+  double mx = 0.0;
+  int nan = 0;
+  for (int j = t; j < d; j += 256) {
+    double s = 0.0;
+    for (int o = b; o >= -b; --o) {
+      const int i = j - o;
+      if (i >= 0 && i < d) s += fabs(D.bands[(int64_t)(b + o) * d + i]);
+    }
+    if (isnan(s)) nan = 1;
+    else mx = fmax(mx, s);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off));
+    nan |= __shfl_xor(nan, off);
+  }
+  if ((t & 63) == 0) {
+    red[t >> 6] = mx;
+    bad[t >> 6] = nan;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  nan = bad[0] | bad[1] | bad[2] | bad[3];
+  PlanRec P;
+  P.s = 1;
+  P.status = 0;
+  P.bad_shift = 0x7fffffff;
+  P.ir_iters = 0;
+  P.route = 4;
+  P.pad_ = 0;
+  P.eta = nan ? __builtin_nan("") : mx;
+  P.resid = 0.0;
+  const bool nonfinite = !isfinite(P.eta);
+  if (nonfinite) P.status = 2;
+  if (force_plan >= 0) {
+    P.s = force_plan < 1 ? 1 : force_plan;
+  } else if (!nonfinite) {
+    const double q = ceil(P.eta / D.theta);
+    P.s = q < 1.0 ? 1 : (q > 1e9 ? 1000000000 : (int)q);
+  }
+  plan[ii] = P;
+}
+
+// B = A / N and the LU of M = I - c_k B for every (instance, shift): one
+// thread each, elimination down the band without interchanges.  The factor
+// rows first hold M (l_i[r] = M[r][r - i], ui[r] = M[r][r],
+// em_j[r] = M[r][r + j]); step q subtracts l M[q][.] from the b rows below
+// it and then normalises row q.  A zero or non-finite pivot sets
+// PFM_SINGULAR_SHIFT with the smallest such shift.
+__global__ void __launch_bounds__(64)
+band_factor_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan, int batch, TriTerms T,
+                   double *__restrict__ wsd) {
+  const int gid = blockIdx.x * 64 + threadIdx.x;
+  const int ii = gid / T.nterms, k = gid - ii * T.nterms;
+  if (ii >= batch) return;
+  const BandDesc D = desc[ii];
+  const int d = D.d, b = D.b;
+  const double Nd = (double)plan[ii].s;
+  const double c = T.c[k];
+  const double *A = D.bands;
+  double *Bw = wsd + D.b_off;
+  double *F = wsd + D.f_off + (int64_t)k * (2 * b + 1) * d;
+  double *ui = F + (int64_t)b * d;
+  auto lrow = [&](int i) { return F + (int64_t)(i - 1) * d; };   // l_i, i = 1..b
+  auto erow = [&](int j) { return F + (int64_t)(b + j) * d; };   // em_j, j = 1..b
+  if (k == 0) {
+    for (int o = -b; o <= b; ++o)
+      for (int r = 0; r < d; ++r)
+        Bw[(int64_t)(b + o) * d + r] = (r + o >= 0 && r + o < d) ? A[(int64_t)(b + o) * d + r] / Nd : 0.0;
+  }
+  for (int r = 0; r < d; ++r) {
+    for (int i = 1; i <= b; ++i) lrow(i)[r] = r - i >= 0 ? -c * (A[(int64_t)(b - i) * d + r] / Nd) : 0.0;
+    ui[r] = 1.0 - c * (A[(int64_t)b * d + r] / Nd);
+    for (int j = 1; j <= b; ++j) erow(j)[r] = r + j < d ? -c * (A[(int64_t)(b + j) * d + r] / Nd) : 0.0;
+  }
+  bool bad = false;
+  for (int q = 0; q < d; ++q) {
+    const double piv = ui[q];
+    bad |= !(piv != 0.0 && isfinite(piv));
+    for (int i = 1; i <= b && q + i < d; ++i) {
+      const int r = q + i;
+      const double lv = lrow(i)[r] / piv;  // M[r][q] / U[q][q]
+      lrow(i)[r] = lv;
+      for (int j = 1; j <= b && q + j < d; ++j) {
+        const double u = erow(j)[q];  // U[q][q + j], not yet normalised
+        const int off = j - i;        // column q + j relative to row r
+        if (off == 0) ui[r] -= lv * u;
+        else if (off > 0) erow(off)[r] -= lv * u;
+        else lrow(-off)[r] -= lv * u;
+      }
+    }
+    const double inv = 1.0 / piv;
+    ui[q] = inv;
+    for (int j = 1; j <= b; ++j) erow(j)[q] *= inv;
+  }
+  if (bad) {
+    atomicOr(&plan[ii].status, 1);
+    atomicMin(&plan[ii].bad_shift, k);
+  }
+}
+
+// All N steps of one column (lane) of one function slot; 64 consecutive
+// columns of one instance per wave.  BW is the half-bandwidth b.  The
+// forward pass keeps windows of x (2 BW + 1 rows, y_r = sum_o B[r][r+o]
+// x_{r+o} needs x_{r+BW}) and, for the hybrid set, of y (P_s =
+// d1 y_s + d2 (B y)_s needs y_{s+BW}); the sweeps keep the last BW values of
+// every shift.  Shift loops run to kTriTerms with a test against the call's
+// count, so the windows stay in registers.  Lanes past p leave at once:
+// every value a lane reads was written by itself (the kernel has no
+// barrier).
+template <int BW>
+__global__ void __launch_bounds__(64)
+band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
+                  const double *__restrict__ fac, double *__restrict__ vws) {
+  const int lane = threadIdx.x;
+  const int gw = blockIdx.x;
+  int lo = 0, hi = batch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].wave0 <= gw) lo = mid;
+    else hi = mid - 1;
+  }
+  const BandDesc D = desc[lo];
+  const int d = D.d, p = D.p;
+  const int ncw = (p + 63) / 64;
+  const int w = gw - D.wave0;
+  const int slot = w / ncw;
+  const int c = (w - slot * ncw) * 64 + lane;
+  if (c >= p) return;
+  const int fn = T.fn[slot];
+  const int nt = T.nterms;
+  const int N = plan[lo].s;
+  const bool hyb = T.d1 != 0.0 || T.d2 != 0.0;
+  const int64_t dp = (int64_t)d * p;
+  const double *Bw = fac + D.b_off;
+  const double *F0 = fac + D.f_off;
+  const int64_t fst = (int64_t)(2 * BW + 1) * d;  // factor rows of one shift
+  double *buf0 = vws + D.v_off + (int64_t)slot * 3 * dp, *buf1 = buf0 + dp, *ub = buf1 + dp;
+  double *zb = vws + D.z_off + (int64_t)slot * nt * dp;
+  double *out_final = fn ? D.Fp : D.Fe;
+
+  for (int j = 0; j < N; ++j) {
+    const double *src = j == 0 ? D.V : ((j - 1) & 1 ? buf1 : buf0);
+    const int64_t lds = j == 0 ? D.ldv : p;
+    double *dst = j == N - 1 ? out_final : (j & 1 ? buf1 : buf0);
+    const int64_t ldd = j == N - 1 ? D.ldf : p;
+    const bool first_phi = fn == 1 && j == 0;
+    const bool add = (fn == 1 && j > 0) || hyb;
+    const bool keep_u1 = first_phi && N > 1;
+    // φ1's first step is rho(B) V / N: the 1/N goes into its weights
+    const double a0 = first_phi ? T.a0p / N : T.a0e;
+
+    // forward pass
+    {
+      double xw[2 * BW + 1], yw[2 * BW + 1], zw[kTriTerms][BW];
+#pragma unroll
+      for (int q = 0; q <= 2 * BW; ++q) xw[q] = yw[q] = 0.0;
+#pragma unroll
+      for (int k = 0; k < kTriTerms; ++k)
+#pragma unroll
+        for (int i = 0; i < BW; ++i) zw[k][i] = 0.0;
+      const int tend = d + (hyb ? 2 * BW : BW);
+      for (int t = 0; t < tend; ++t) {
+#pragma unroll
+        for (int q = 0; q < 2 * BW; ++q) xw[q] = xw[q + 1];
+        xw[2 * BW] = t < d ? src[(int64_t)t * lds + c] : 0.0;
+        const int r = t - BW;
+        double y = 0.0;
+        if (r >= 0 && r < d) {
+#pragma unroll
+          for (int o = -BW; o <= BW; ++o) y = fma(Bw[(int64_t)(BW + o) * d + r], xw[BW + o], y);
+#pragma unroll
+          for (int k = 0; k < kTriTerms; ++k) {
+            if (k < nt) {
+              const double *Fk = F0 + k * fst;
+              double z = y;
+#pragma unroll
+              for (int i = 1; i <= BW; ++i) z = fma(-Fk[(int64_t)(i - 1) * d + r], zw[k][BW - i], z);
+#pragma unroll
+              for (int i = 0; i + 1 < BW; ++i) zw[k][i] = zw[k][i + 1];
+              zw[k][BW - 1] = z;
+              zb[k * dp + (int64_t)r * p + c] = z;
+            }
+          }
+        }
+        if (hyb) {
+#pragma unroll
+          for (int q = 0; q < 2 * BW; ++q) yw[q] = yw[q + 1];
+          yw[2 * BW] = y;
+          const int s = t - 2 * BW;
+          if (s >= 0 && s < d) {
+            double by = 0.0;
+#pragma unroll
+            for (int o = -BW; o <= BW; ++o) by = fma(Bw[(int64_t)(BW + o) * d + s], yw[BW + o], by);
+            ub[(int64_t)s * p + c] = fma(T.d2, by, T.d1 * yw[BW]);
+          }
+        }
+      }
+    }
+
+    // backward pass
+    {
+      double xk[kTriTerms][BW];  // xk[k][i] = x_{k, r + 1 + i}
+#pragma unroll
+      for (int k = 0; k < kTriTerms; ++k)
+#pragma unroll
+        for (int i = 0; i < BW; ++i) xk[k][i] = 0.0;
+      for (int r = d - 1; r >= 0; --r) {
+        double o = a0 * src[(int64_t)r * lds + c];
+        if (add) o += ub[(int64_t)r * p + c];
+#pragma unroll
+        for (int k = 0; k < kTriTerms; ++k) {
+          if (k < nt) {
+            const double *Fk = F0 + k * fst;
+            double x = Fk[(int64_t)BW * d + r] * zb[k * dp + (int64_t)r * p + c];
+#pragma unroll
+            for (int jj = 1; jj <= BW; ++jj) x = fma(-Fk[(int64_t)(BW + jj) * d + r], xk[k][jj - 1], x);
+#pragma unroll
+            for (int i = BW - 1; i > 0; --i) xk[k][i] = xk[k][i - 1];
+            xk[k][0] = x;
+            const double wk = first_phi ? T.wp[k] / N : T.we[k];
+            o = fma(wk, x, o);
+          }
+        }
+        dst[(int64_t)r * ldd + c] = o;
+        if (keep_u1) ub[(int64_t)r * p + c] = o;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+band_info_kernel(const BandDesc *__restrict__ desc, const PlanRec *__restrict__ plan, InfoRec *__restrict__ info,
+                 int batch, int order) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const PlanRec P = plan[i];
+  InfoRec r;
+  r.status = P.status;
+  r.plan = P.s;
+  r.order = order;
+  r.ir_iters = 0;
+  r.bad_shift = P.bad_shift == 0x7fffffff ? -1 : P.bad_shift;
+  r.route = P.route;
+  r.norm1 = P.eta;
+  r.theta = desc[i].theta;
+  r.resid = 0.0;
+  info[i] = r;
+}
+
+}  // namespace pfm

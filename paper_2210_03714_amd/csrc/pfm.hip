@@ -31,6 +31,7 @@
 #include "kern_gj.h"
 #include "kern_large.h"
 #include "kern_tri.h"
+#include "kern_band.h"
 
 using namespace pfm;
 
@@ -502,6 +503,149 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
   prof_mark(ctx, 3, stream);
   if (info)
     hipLaunchKernelGGL(tri_info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_desc, d_plan,
+                       (InfoRec *)info, batch, ee->order);
+  prof_mark(ctx, 4, stream);
+  if (ctx->prof) ctx->prof_pending = true;
+  HIP_TRY(ctx, hipGetLastError());
+  return PFM_OK;
+}
+
+int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, const pfm_band_problem *probs,
+                    pfm_info *info, int force_plan, pfm_stream_t stream_) {
+  if (!ctx) return PFM_ERR_INVALID;
+  if (f < 1 || f > 3) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
+  if (!(tol > 0.0 && tol < 1.0)) return set_err(ctx, PFM_ERR_INVALID, "tol must lie in (0,1)");
+  if (b < 1 || b > PFM_BAND_MAX_B) return set_err(ctx, PFM_ERR_INVALID, "half-bandwidth b = %d not in [1, %d]", b,
+                                                  PFM_BAND_MAX_B);
+  if (batch < 1 || !probs) return set_err(ctx, PFM_ERR_INVALID, "empty batch");
+  for (int i = 0; i < batch; ++i) {
+    const pfm_band_problem &P = probs[i];
+    if (P.d < 1 || P.d > PFM_TRI_MAX_D || P.p < 1 || P.p > PFM_TRI_MAX_P)
+      return set_err(ctx, PFM_ERR_INVALID, "problem %d: bad d or p", i);
+    if (!P.bands || !P.V) return set_err(ctx, PFM_ERR_INVALID, "problem %d: null bands or V", i);
+    if (P.ldv < P.p || P.ldf < P.p) return set_err(ctx, PFM_ERR_INVALID, "problem %d: ldv or ldf < p", i);
+    if ((f & PFM_EXP) && !P.F_exp) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_exp null", i);
+    if ((f & PFM_PHI1) && !P.F_phi1) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_phi1 null", i);
+    if (misaligned(P.bands) || misaligned(P.V) || misaligned(P.F_exp) || misaligned(P.F_phi1))
+      return set_err(ctx, PFM_ERR_INVALID, "problem %d: an array is not 8-byte aligned", i);
+  }
+  const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
+  if (!ee || (!ep && (f & PFM_PHI1))) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
+  const bool hybrid = ee->poly[0] != 0.0 || ee->poly[1] != 0.0;
+  if (ee->pair || !(ee->nterms == 4 || ee->nterms == 5 || ee->nterms == 8 || (hybrid && ee->nterms == 10)))
+    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the banded path takes the real shift sets (m = 4, 5, 8, 10)");
+  if (hybrid && f != PFM_EXP)
+    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the hybrid set is provided for the exponential only");
+  double theta;
+  int rc = pfm_theta(f, m, tol, &theta);
+  if (rc) return set_err(ctx, rc, "theta failed");
+  hipStream_t stream = (hipStream_t)stream_;
+
+  TriTerms T;
+  memset(&T, 0, sizeof T);
+  T.nterms = ee->nterms;
+  T.nf = 0;
+  if (f & PFM_EXP) T.fn[T.nf++] = 0;
+  if (f & PFM_PHI1) T.fn[T.nf++] = 1;
+  T.a0e = ee->a0;
+  T.a0p = ep ? ep->a0 : 0.0;
+  for (int k = 0; k < T.nterms; ++k) {
+    T.c[k] = ee->c_re[k];
+    T.we[k] = ee->w_re[k];
+    T.wp[k] = ep ? ep->w_re[k] : 0.0;
+  }
+  T.d1 = ee->poly[0];
+  T.d2 = ee->poly[1];
+  std::vector<BandDesc> desc(batch);
+  int64_t dofs = 0;
+  int64_t waves = 0;
+  for (int i = 0; i < batch; ++i) {
+    const pfm_band_problem &P = probs[i];
+    BandDesc &D = desc[i];
+    memset(&D, 0, sizeof D);
+    D.bands = P.bands;
+    D.V = P.V;
+    D.Fe = P.F_exp;
+    D.Fp = P.F_phi1;
+    D.ldv = P.ldv;
+    D.ldf = P.ldf;
+    D.d = P.d;
+    D.p = P.p;
+    D.b = b;
+    D.theta = theta;
+    const int64_t d = P.d, p = P.p;
+    D.b_off = dofs; dofs += align_up((2 * b + 1) * d, 64);
+    D.f_off = dofs; dofs += align_up((int64_t)T.nterms * (2 * b + 1) * d, 64);
+    D.v_off = dofs; dofs += align_up((int64_t)T.nf * 3 * d * p, 64);
+    D.z_off = dofs; dofs += align_up((int64_t)T.nf * T.nterms * d * p, 64);
+    D.wave0 = (int32_t)waves;
+    D.nwaves = T.nf * (int32_t)((p + 63) / 64);
+    waves += D.nwaves;
+    if (waves > (int64_t)1 << 30) return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
+  }
+  const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
+  const int64_t desc_bytes = align_up((int64_t)batch * sizeof(BandDesc), 256);
+  const int64_t need = dofs * 8 + plan_bytes + desc_bytes + 4096;
+  if (ctx->budget && (size_t)need > ctx->budget)
+    return set_err(ctx, PFM_ERR_BUDGET, "workspace %lld bytes exceeds budget %zu", (long long)need, ctx->budget);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((size_t)need > ctx->ws_bytes) {
+    if (ctx->ws) {
+      HIP_TRY(ctx, hipStreamSynchronize(stream));
+      HIP_TRY(ctx, hipFree(ctx->ws));
+      ctx->ws = nullptr;
+      ctx->ws_bytes = 0;
+    }
+    HIP_TRY(ctx, hipMalloc(&ctx->ws, (size_t)need));
+    ctx->ws_bytes = (size_t)need;
+  }
+  char *base = (char *)ctx->ws;
+  double *wsd = (double *)base;
+  PlanRec *d_plan = (PlanRec *)(base + dofs * 8);
+  BandDesc *d_desc = (BandDesc *)(base + dofs * 8 + plan_bytes);
+
+  char *pin = nullptr;
+  int rcs = staging(ctx, desc_bytes + plan_bytes, &pin);
+  if (rcs) return rcs;
+  memcpy(pin, desc.data(), batch * sizeof(BandDesc));
+  PlanRec *h_plan = (PlanRec *)(pin + desc_bytes);
+  HIP_TRY(ctx, hipMemcpyAsync(d_desc, pin, batch * sizeof(BandDesc), hipMemcpyHostToDevice, stream));
+  hipLaunchKernelGGL(band_plan_kernel, dim3(batch), dim3(256), 0, stream, d_desc, d_plan, force_plan);
+  HIP_TRY(ctx, hipGetLastError());
+  // the step count bounds the run time: read the plans back once
+  HIP_TRY(ctx, hipMemcpyAsync(h_plan, d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  for (int i = 0; i < batch; ++i)
+    if (h_plan[i].s > kNCap)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED, "problem %d: N = %d steps exceeds %d (||A||_1 too large for tol)",
+                     i, h_plan[i].s, kNCap);
+  {
+    int rcp = prof_harvest(ctx);
+    if (rcp) return rcp;
+  }
+  // phase timing (pfm_profile): 0 the factorisations, 1 the N steps
+  for (int ph = 0; ph < kNumPhases; ++ph) ctx->cur_launches[ph] = 0;
+  prof_mark(ctx, 0, stream);
+  const int nfac = batch * T.nterms;
+  hipLaunchKernelGGL(band_factor_kernel, dim3((nfac + 63) / 64), dim3(64), 0, stream, d_desc, d_plan, batch, T,
+                     wsd);
+  ctx->cur_launches[0]++;
+  prof_mark(ctx, 1, stream);
+#define PFM_BAND_STEPS(BW)                                                                                       \
+  hipLaunchKernelGGL((band_steps_kernel<BW>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, batch, d_plan, T, \
+                     (const double *)wsd, wsd)
+  switch (b) {
+    case 1: PFM_BAND_STEPS(1); break;
+    case 2: PFM_BAND_STEPS(2); break;
+    case 3: PFM_BAND_STEPS(3); break;
+    default: PFM_BAND_STEPS(4); break;
+  }
+#undef PFM_BAND_STEPS
+  ctx->cur_launches[1]++;
+  prof_mark(ctx, 2, stream);
+  prof_mark(ctx, 3, stream);
+  if (info)
+    hipLaunchKernelGGL(band_info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_desc, d_plan,
                        (InfoRec *)info, batch, ee->order);
   prof_mark(ctx, 4, stream);
   if (ctx->prof) ctx->prof_pending = true;

@@ -52,6 +52,13 @@ class TriProblem(ctypes.Structure):
                 ("V", ctypes.c_void_p), ("F_exp", ctypes.c_void_p), ("F_phi1", ctypes.c_void_p)]
 
 
+class BandProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("ldv", ctypes.c_int64), ("ldf", ctypes.c_int64),
+                ("bands", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("F_exp", ctypes.c_void_p), ("F_phi1", ctypes.c_void_p)]
+
+
 INFO_DTYPE = np.dtype([("status", "<i4"), ("plan", "<i4"), ("order", "<i4"), ("ir_iters", "<i4"),
                        ("bad_shift", "<i4"), ("route", "<i4"), ("norm1", "<f8"),
                        ("theta", "<f8"), ("resid", "<f8")])
@@ -103,6 +110,7 @@ def lib():
         L.pfm_srv_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p, dp]
         L.pfm_profile_read.argtypes = [vp, dp, ip, ip]
         L.pfm_tri_action.argtypes = [vp, i32, i32, dbl, i32, ctypes.POINTER(TriProblem), vp, i32, vp]
+        L.pfm_band_action.argtypes = [vp, i32, i32, dbl, i32, i32, ctypes.POINTER(BandProblem), vp, i32, vp]
         _lib = L
     return _lib
 
@@ -275,6 +283,14 @@ class Context:
         arr = (TriProblem * len(probs))(*probs)
         iptr = ctypes.c_void_p(info.data_ptr()) if info is not None else ctypes.c_void_p()
         return lib().pfm_tri_action(self._h, f, m, tol, len(probs), arr, iptr, force_plan, _stream_ptr(stream))
+
+    def band_action(self, probs, f, m, tol, b, info=None, force_plan=-1, stream=None):
+        """Raw call of pfm_band_action: ``probs`` is a list of BandProblem.
+        Returns the C return code."""
+        arr = (BandProblem * len(probs))(*probs)
+        iptr = ctypes.c_void_p(info.data_ptr()) if info is not None else ctypes.c_void_p()
+        return lib().pfm_band_action(self._h, f, m, tol, b, len(probs), arr, iptr, force_plan,
+                                     _stream_ptr(stream))
 
 
 def _stream_ptr(stream):
@@ -457,6 +473,46 @@ def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=-1, ctx
     ctx = ctx or default_context(vecs[0].device.index or 0)
     info = _info_buffer(info_out, len(vecs), vecs[0].device)
     rc = ctx.tri_action(probs, fm, m, tol, info, force_plan, stream)
+    if rc:
+        raise PfmError(rc, ctx.last_error())
+    return out, _Info(info)
+
+
+def band_action(bands, V, b, funcs=("exp",), m=8, tol=1e-12, force_plan=-1, ctx=None, stream=None,
+                out=None, info_out=None):
+    """f(A) V for banded A (float64, half-bandwidth b; b = 2 is pentadiagonal):
+    ``bands`` is a list of contiguous (2b + 1, d) CUDA tensors with
+    bands[b + o, i] = A[i, i + o] (entries outside A are never read) and ``V``
+    a list of (d, p) CUDA tensors with unit column stride.  Returns
+    (results, info) like ``action``."""
+    import torch
+    bl, vecs = list(bands), list(V)
+    if len(bl) != len(vecs):
+        raise ValueError("one set of bands per V")
+    for t in bl + vecs:
+        _require_gpu(t)
+        if t.dtype != torch.float64:
+            raise ValueError("the banded path is float64")
+    for a, v in zip(bl, vecs):
+        if a.dim() != 2 or a.shape[0] != 2 * b + 1 or not a.is_contiguous():
+            raise ValueError("bands must be contiguous (2b + 1, d)")
+        if v.dim() != 2 or v.shape[0] != a.shape[1] or v.stride(1) != 1:
+            raise ValueError("each V must be (d, p) with unit column stride")
+    fm = _fmask(funcs)
+    if out is None:
+        out = {f: [torch.empty_like(v) for v in vecs] for f in funcs}
+    probs = []
+    for i, (a, v) in enumerate(zip(bl, vecs)):
+        fe = out["exp"][i] if "exp" in funcs else None
+        fp = out["phi1"][i] if "phi1" in funcs else None
+        _check_outputs(fe, fp, v.shape, torch.float64)
+        ldf = (fe if fe is not None else fp).stride(0)
+        probs.append(BandProblem(v.shape[0], v.shape[1], v.stride(0), ldf, a.data_ptr(), v.data_ptr(),
+                                 fe.data_ptr() if fe is not None else None,
+                                 fp.data_ptr() if fp is not None else None))
+    ctx = ctx or default_context(vecs[0].device.index or 0)
+    info = _info_buffer(info_out, len(vecs), vecs[0].device)
+    rc = ctx.band_action(probs, fm, m, tol, b, info, force_plan, stream)
     if rc:
         raise PfmError(rc, ctx.last_error())
     return out, _Info(info)

@@ -80,6 +80,7 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.pfm_theta(1, 8, 1.5, ctypes.byref(out)) == pfm.ERR_INVALID
     assert L.pfm_theta(1, 3, 1e-12, ctypes.byref(out)) == pfm.ERR_UNSUPPORTED
     assert L.pfm_eval_batched(None, 1, 8, 1e-12, 0, 0, 1, None, None, -1, None) == pfm.ERR_INVALID
+    assert L.pfm_band_action(None, 1, 8, 1e-12, 2, 1, None, None, -1, None) == pfm.ERR_INVALID
     n = ctypes.c_int()
     assert L.pfm_coeffs(3, 8, ctypes.byref(n), None, None, None, None, None, None, None) == pfm.ERR_INVALID
     assert L.pfm_coeffs(1, 7, ctypes.byref(n), None, None, None, None, None, None, None) == pfm.ERR_UNSUPPORTED
