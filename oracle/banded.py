@@ -153,7 +153,8 @@ def _band_clean(bands, b):
     B = np.array(bands, dtype=np.float64, copy=True)
     d = B.shape[1]
     for o in range(-b, b + 1):
-        lo, hi = max(0, -o), min(d, d - o)
+        lo = min(d, max(0, -o))
+        hi = max(lo, min(d, d - o))
         B[b + o, :lo] = 0.0
         B[b + o, hi:] = 0.0
     return B
@@ -183,7 +184,8 @@ def band_matvec(bands, b, X):
     d = B.shape[1]
     Y = np.zeros_like(X, dtype=np.float64)
     for o in range(-b, b + 1):
-        lo, hi = max(0, -o), min(d, d - o)
+        lo = min(d, max(0, -o))
+        hi = max(lo, min(d, d - o))
         Y[lo:hi] += B[b + o, lo:hi, None] * X[lo + o:hi + o]
     return Y
 

@@ -225,7 +225,8 @@ def band_gaussian_batch(batch, d, b, norm_lo, norm_hi, seed):
         bands = rng.standard_normal((2 * b + 1, d))
         col = np.zeros(d)
         for o in range(-b, b + 1):
-            lo, hi = max(0, -o), min(d, d - o)
+            lo = min(d, max(0, -o))
+            hi = max(lo, min(d, d - o))
             bands[b + o, :lo] = 0.0
             bands[b + o, hi:] = 0.0
             col[lo + o:hi + o] += np.abs(bands[b + o, lo:hi])

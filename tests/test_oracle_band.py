@@ -35,8 +35,9 @@ def _outside_nan(bands, b):
     B = np.array(bands, copy=True)
     d = B.shape[1]
     for o in range(-b, b + 1):
-        B[b + o, :max(0, -o)] = np.nan
-        B[b + o, min(d, d - o):] = np.nan
+        lo = min(d, max(0, -o))
+        B[b + o, :lo] = np.nan
+        B[b + o, max(lo, min(d, d - o)):] = np.nan
     return B
 
 
@@ -51,7 +52,7 @@ def test_norm_and_product_against_dense(b):
     assert np.abs(bd.band_matvec(bands, b, X) - A @ X).max() <= 8 * U64 * np.abs(A).sum(1).max() * np.abs(X).max()
 
 
-@pytest.mark.parametrize("b,d", [(1, 5), (2, 2), (2, 3), (2, 40), (3, 7), (4, 33)])
+@pytest.mark.parametrize("b,d", [(1, 5), (2, 2), (2, 3), (2, 40), (3, 2), (3, 7), (4, 1), (4, 3), (4, 33)])
 @pytest.mark.parametrize("funcs", [("exp",), ("phi1",), ("exp", "phi1")])
 @pytest.mark.parametrize("m", [4, 8])
 def test_banded_equals_dense_oracle(funcs, m, b, d):
