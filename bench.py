@@ -326,7 +326,7 @@ def main():
     ap.add_argument("--no-tri", action="store_true", help="skip the tridiagonal action leg")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid 10th-order leg")
     ap.add_argument("--no-band", action="store_true", help="skip the banded (pentadiagonal) action leg")
-    ap.add_argument("--band-batch", type=int, default=1024)
+    ap.add_argument("--band-batch", type=int, default=4096)
     ap.add_argument("--band-only", action="store_true", help="run only the banded leg (profiling)")
     ap.add_argument("--tri-batch", type=int, default=4096)
     ap.add_argument("--tri-d", type=int, default=1024)

@@ -31,6 +31,7 @@
 namespace pfm {
 
 constexpr int kBandMaxB = 4;
+constexpr int kBandCH = 8;  // rows whose loads are issued together
 
 struct BandDesc {
   const double *bands, *V;
@@ -208,9 +209,9 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
     // φ1's first step is rho(B) V / N: the 1/N goes into its weights
     const double a0 = first_phi ? T.a0p / N : T.a0e;
 
-    // forward pass
+    // forward pass: x read one chunk of kBandCH rows ahead
     {
-      double xw[2 * BW + 1], yw[2 * BW + 1], zw[kTriTerms][BW];
+      double xw[2 * BW + 1], yw[2 * BW + 1], zw[kTriTerms][BW], xn[kBandCH];
 #pragma unroll
       for (int q = 0; q <= 2 * BW; ++q) xw[q] = yw[q] = 0.0;
 #pragma unroll
@@ -218,70 +219,103 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
 #pragma unroll
         for (int i = 0; i < BW; ++i) zw[k][i] = 0.0;
       const int tend = d + (hyb ? 2 * BW : BW);
-      for (int t = 0; t < tend; ++t) {
+      auto load_x = [&](int t0) {
 #pragma unroll
-        for (int q = 0; q < 2 * BW; ++q) xw[q] = xw[q + 1];
-        xw[2 * BW] = t < d ? src[(int64_t)t * lds + c] : 0.0;
-        const int r = t - BW;
-        double y = 0.0;
-        if (r >= 0 && r < d) {
+        for (int u = 0; u < kBandCH; ++u) xn[u] = t0 + u < d ? src[(int64_t)(t0 + u) * lds + c] : 0.0;
+      };
+      load_x(0);
+      for (int t0 = 0; t0 < tend; t0 += kBandCH) {
+        double xc[kBandCH];
 #pragma unroll
-          for (int o = -BW; o <= BW; ++o) y = fma(Bw[(int64_t)(BW + o) * d + r], xw[BW + o], y);
+        for (int u = 0; u < kBandCH; ++u) xc[u] = xn[u];
+        if (t0 + kBandCH < tend) load_x(t0 + kBandCH);  // rows past d load as zeros
 #pragma unroll
-          for (int k = 0; k < kTriTerms; ++k) {
-            if (k < nt) {
-              const double *Fk = F0 + k * fst;
-              double z = y;
+        for (int u = 0; u < kBandCH; ++u) {
+          const int t = t0 + u;
+          if (t < tend) {
 #pragma unroll
-              for (int i = 1; i <= BW; ++i) z = fma(-Fk[(int64_t)(i - 1) * d + r], zw[k][BW - i], z);
+            for (int q = 0; q < 2 * BW; ++q) xw[q] = xw[q + 1];
+            xw[2 * BW] = xc[u];
+            const int r = t - BW;
+            double y = 0.0;
+            if (r >= 0 && r < d) {
 #pragma unroll
-              for (int i = 0; i + 1 < BW; ++i) zw[k][i] = zw[k][i + 1];
-              zw[k][BW - 1] = z;
-              zb[k * dp + (int64_t)r * p + c] = z;
+              for (int o = -BW; o <= BW; ++o) y = fma(Bw[(int64_t)(BW + o) * d + r], xw[BW + o], y);
+#pragma unroll
+              for (int k = 0; k < kTriTerms; ++k) {
+                if (k < nt) {
+                  const double *Fk = F0 + k * fst;
+                  double z = y;
+#pragma unroll
+                  for (int i = 1; i <= BW; ++i) z = fma(-Fk[(int64_t)(i - 1) * d + r], zw[k][BW - i], z);
+#pragma unroll
+                  for (int i = 0; i + 1 < BW; ++i) zw[k][i] = zw[k][i + 1];
+                  zw[k][BW - 1] = z;
+                  zb[k * dp + (int64_t)r * p + c] = z;
+                }
+              }
             }
-          }
-        }
-        if (hyb) {
+            if (hyb) {
 #pragma unroll
-          for (int q = 0; q < 2 * BW; ++q) yw[q] = yw[q + 1];
-          yw[2 * BW] = y;
-          const int s = t - 2 * BW;
-          if (s >= 0 && s < d) {
-            double by = 0.0;
+              for (int q = 0; q < 2 * BW; ++q) yw[q] = yw[q + 1];
+              yw[2 * BW] = y;
+              const int s = t - 2 * BW;
+              if (s >= 0 && s < d) {
+                double by = 0.0;
 #pragma unroll
-            for (int o = -BW; o <= BW; ++o) by = fma(Bw[(int64_t)(BW + o) * d + s], yw[BW + o], by);
-            ub[(int64_t)s * p + c] = fma(T.d2, by, T.d1 * yw[BW]);
+                for (int o = -BW; o <= BW; ++o) by = fma(Bw[(int64_t)(BW + o) * d + s], yw[BW + o], by);
+                ub[(int64_t)s * p + c] = fma(T.d2, by, T.d1 * yw[BW]);
+              }
+            }
           }
         }
       }
     }
 
-    // backward pass
+    // backward pass: the operands of kBandCH rows loaded together, then
+    // the rows swept from the last
     {
       double xk[kTriTerms][BW];  // xk[k][i] = x_{k, r + 1 + i}
 #pragma unroll
       for (int k = 0; k < kTriTerms; ++k)
 #pragma unroll
         for (int i = 0; i < BW; ++i) xk[k][i] = 0.0;
-      for (int r = d - 1; r >= 0; --r) {
-        double o = a0 * src[(int64_t)r * lds + c];
-        if (add) o += ub[(int64_t)r * p + c];
+      for (int r0 = d - 1; r0 >= 0; r0 -= kBandCH) {
+        double xs[kBandCH], us[kBandCH], zs[kTriTerms][kBandCH];
 #pragma unroll
-        for (int k = 0; k < kTriTerms; ++k) {
-          if (k < nt) {
-            const double *Fk = F0 + k * fst;
-            double x = Fk[(int64_t)BW * d + r] * zb[k * dp + (int64_t)r * p + c];
+        for (int u = 0; u < kBandCH; ++u) {
+          const int r = r0 - u;
+          if (r >= 0) {
+            xs[u] = src[(int64_t)r * lds + c];
+            us[u] = add ? ub[(int64_t)r * p + c] : 0.0;
 #pragma unroll
-            for (int jj = 1; jj <= BW; ++jj) x = fma(-Fk[(int64_t)(BW + jj) * d + r], xk[k][jj - 1], x);
-#pragma unroll
-            for (int i = BW - 1; i > 0; --i) xk[k][i] = xk[k][i - 1];
-            xk[k][0] = x;
-            const double wk = first_phi ? T.wp[k] / N : T.we[k];
-            o = fma(wk, x, o);
+            for (int k = 0; k < kTriTerms; ++k)
+              if (k < nt) zs[k][u] = zb[k * dp + (int64_t)r * p + c];
           }
         }
-        dst[(int64_t)r * ldd + c] = o;
-        if (keep_u1) ub[(int64_t)r * p + c] = o;
+#pragma unroll
+        for (int u = 0; u < kBandCH; ++u) {
+          const int r = r0 - u;
+          if (r >= 0) {
+            double o = fma(a0, xs[u], us[u]);
+#pragma unroll
+            for (int k = 0; k < kTriTerms; ++k) {
+              if (k < nt) {
+                const double *Fk = F0 + k * fst;
+                double x = Fk[(int64_t)BW * d + r] * zs[k][u];
+#pragma unroll
+                for (int jj = 1; jj <= BW; ++jj) x = fma(-Fk[(int64_t)(BW + jj) * d + r], xk[k][jj - 1], x);
+#pragma unroll
+                for (int i = BW - 1; i > 0; --i) xk[k][i] = xk[k][i - 1];
+                xk[k][0] = x;
+                const double wk = first_phi ? T.wp[k] / N : T.we[k];
+                o = fma(wk, x, o);
+              }
+            }
+            dst[(int64_t)r * ldd + c] = o;
+            if (keep_u1) ub[(int64_t)r * p + c] = o;
+          }
+        }
       }
     }
   }
