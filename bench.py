@@ -249,7 +249,7 @@ def band_leg(batch, d, p, b, reps, cpu_seconds):
     colsteps = float(Ns.sum()) * p
     steps_ms = phases["solve_combine"][0] / max(1, calls)
     achieved = colsteps * 16.0 * d / (steps_ms * 1e-3)
-    kname = "band_steps_kernel<%d>" % b
+    kname = "band_steps_kernel<%d,8>" % b
     res = {"metric": "banded exp(A)v columns/s", "value": round(batch * p / wall, 1), "unit": "columns/s",
            "ms_per_call": round(wall * 1e3, 3), "steps_kernel_ms": round(steps_ms, 3),
            "factor_kernel_ms": round(phases["lu"][0] / max(1, calls), 3),

@@ -288,7 +288,8 @@ typedef struct {
  * the N steps.  The call reads the step counts back once (one stream
  * synchronisation) and returns PFM_ERR_UNSUPPORTED if some N exceeds 2^20;
  * everything else is enqueued on `stream`.  Workspace: about
- * (m + 1) (2b + 1) d + n_f (3 + m) d p doubles per instance (n_f functions). */
+ * (m + 1) (2b + 1) d + n_f (3 + m b / L) d p doubles per instance (n_f
+ * functions; L = 8 rows per checkpoint for b <= 2, else 4). */
 int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, const pfm_band_problem *probs,
                     pfm_info *info, int force_plan, pfm_stream_t stream);
 

@@ -12,17 +12,26 @@
 // lanes):
 //   A:        bands[(b + o) d + i] = A[i][i + o], o = -b..b (caller's; the
 //             entries with i + o outside [0, d) are never read)
-//   B:        the same layout, A / N, zero outside A
-//   factors:  per shift k, rows l_1..l_b, ui, em_1..em_b of d each:
-//             l_i[r] = L[r][r - i], ui[r] = 1 / U[r][r],
-//             em_j[r] = U[r][r + j] / U[r][r] (zero outside the matrix), so
-//             the backward sweep is x_r = ui[r] z_r - sum_j em_j[r] x_{r+j}
+//   B:        row-major, B[r][r + o] at r (2b + 1) + b + o (A / N, zero
+//             outside A)
+//   factors:  row-major over the shifts, [r][k][2b + 1]: l_1..l_b, ui, em_1..em_b
+//             with l_i = L[r][r - i], ui = 1 / U[r][r],
+//             em_j = U[r][r + j] / U[r][r] (zero outside the matrix), so the
+//             backward sweep is x_r = ui z_r - sum_j em_j x_{r+j}.  One row's
+//             values of all shifts are contiguous: the sweeps read them with
+//             a few wide uniform loads
 //   vectors:  per function slot, two ping-pong buffers and one for u_1 (φ1)
 //             or the hybrid set's polynomial part, d x p row-major
-//   forward values: per slot and shift, z_k d x p row-major
-// A step reads the input twice (forward pass: y = B x and the forward
-// sweeps of all shifts, storing z_k; backward pass: the backward sweeps of
-// all shifts and out = a0 x + sum_k w_k x_k) and writes the output once.
+//   checkpoints: per slot, the last b forward values of every shift at the
+//             end of each chunk of kBandL(b) rows, [chunk][k][b][p]
+// A step makes two passes over the column.  The forward pass forms y = B x
+// and runs the forward sweeps of all shifts, keeping only the checkpoints.
+// The backward pass walks the chunks from the last: it recomputes the
+// chunk's forward values from its checkpoint in registers (reading x again,
+// with b rows on either side), then runs the backward sweeps of all shifts
+// and forms out = a0 x + sum_k w_k x_k.  Per column-step the vector moves
+// about (3 + 2b/L + 2 m b / L) d x 8 bytes instead of (3 + 2m) d x 8 when
+// every forward value is stored.
 #pragma once
 
 #include "kern_common.h"
@@ -31,7 +40,11 @@
 namespace pfm {
 
 constexpr int kBandMaxB = 4;
-constexpr int kBandCH = 8;  // rows whose loads are issued together
+constexpr int kBandCH = 8;  // forward pass: x rows read ahead
+// rows per checkpoint chunk: the backward pass holds the chunk's forward
+// values of every shift in registers (4 rows keep the kernel within the
+// registers of two waves per SIMD)
+__host__ __device__ constexpr int kBandL(int b) { return 4; }
 
 struct BandDesc {
   const double *bands, *V;
@@ -39,10 +52,10 @@ struct BandDesc {
   int64_t ldv, ldf;
   int32_t d, p, b, pad_;
   double theta;
-  int64_t b_off;  // B: (2b + 1) d
-  int64_t f_off;  // factors: [k][2b + 1][d]
+  int64_t b_off;  // B: [d][2b + 1]
+  int64_t f_off;  // factors: [d][k][2b + 1]
   int64_t v_off;  // vectors: [slot][3][d][p]
-  int64_t z_off;  // forward values: [slot][k][d][p]
+  int64_t z_off;  // checkpoints: [slot][chunk][k][b][p]
   int32_t wave0;   // first wave of this instance in the step launch
   int32_t nwaves;  // its waves: functions x ceil(p / 64)
 };
@@ -118,39 +131,39 @@ band_factor_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan
   const double c = T.c[k];
   const double *A = D.bands;
   double *Bw = wsd + D.b_off;
-  double *F = wsd + D.f_off + (int64_t)k * (2 * b + 1) * d;
-  double *ui = F + (int64_t)b * d;
-  auto lrow = [&](int i) { return F + (int64_t)(i - 1) * d; };   // l_i, i = 1..b
-  auto erow = [&](int j) { return F + (int64_t)(b + j) * d; };   // em_j, j = 1..b
+  const int nt = T.nterms, w = 2 * b + 1;
+  double *Fb = wsd + D.f_off;
+  // row r's value j (0..2b) of this shift
+  auto at = [&](int r, int j) -> double & { return Fb[((int64_t)r * nt + k) * w + j]; };
   if (k == 0) {
     for (int o = -b; o <= b; ++o)
       for (int r = 0; r < d; ++r)
-        Bw[(int64_t)(b + o) * d + r] = (r + o >= 0 && r + o < d) ? A[(int64_t)(b + o) * d + r] / Nd : 0.0;
+        Bw[(int64_t)r * w + b + o] = (r + o >= 0 && r + o < d) ? A[(int64_t)(b + o) * d + r] / Nd : 0.0;
   }
   for (int r = 0; r < d; ++r) {
-    for (int i = 1; i <= b; ++i) lrow(i)[r] = r - i >= 0 ? -c * (A[(int64_t)(b - i) * d + r] / Nd) : 0.0;
-    ui[r] = 1.0 - c * (A[(int64_t)b * d + r] / Nd);
-    for (int j = 1; j <= b; ++j) erow(j)[r] = r + j < d ? -c * (A[(int64_t)(b + j) * d + r] / Nd) : 0.0;
+    for (int i = 1; i <= b; ++i) at(r, i - 1) = r - i >= 0 ? -c * (A[(int64_t)(b - i) * d + r] / Nd) : 0.0;
+    at(r, b) = 1.0 - c * (A[(int64_t)b * d + r] / Nd);
+    for (int j = 1; j <= b; ++j) at(r, b + j) = r + j < d ? -c * (A[(int64_t)(b + j) * d + r] / Nd) : 0.0;
   }
   bool bad = false;
   for (int q = 0; q < d; ++q) {
-    const double piv = ui[q];
+    const double piv = at(q, b);
     bad |= !(piv != 0.0 && isfinite(piv));
     for (int i = 1; i <= b && q + i < d; ++i) {
       const int r = q + i;
-      const double lv = lrow(i)[r] / piv;  // M[r][q] / U[q][q]
-      lrow(i)[r] = lv;
+      const double lv = at(r, i - 1) / piv;  // M[r][q] / U[q][q]
+      at(r, i - 1) = lv;
       for (int j = 1; j <= b && q + j < d; ++j) {
-        const double u = erow(j)[q];  // U[q][q + j], not yet normalised
-        const int off = j - i;        // column q + j relative to row r
-        if (off == 0) ui[r] -= lv * u;
-        else if (off > 0) erow(off)[r] -= lv * u;
-        else lrow(-off)[r] -= lv * u;
+        const double u = at(q, b + j);  // U[q][q + j], not yet normalised
+        const int off = j - i;          // column q + j relative to row r
+        if (off == 0) at(r, b) -= lv * u;
+        else if (off > 0) at(r, b + off) -= lv * u;
+        else at(r, -off - 1) -= lv * u;
       }
     }
     const double inv = 1.0 / piv;
-    ui[q] = inv;
-    for (int j = 1; j <= b; ++j) erow(j)[q] *= inv;
+    at(q, b) = inv;
+    for (int j = 1; j <= b; ++j) at(q, b + j) *= inv;
   }
   if (bad) {
     atomicOr(&plan[ii].status, 1);
@@ -163,11 +176,11 @@ band_factor_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan
 // forward pass keeps windows of x (2 BW + 1 rows, y_r = sum_o B[r][r+o]
 // x_{r+o} needs x_{r+BW}) and, for the hybrid set, of y (P_s =
 // d1 y_s + d2 (B y)_s needs y_{s+BW}); the sweeps keep the last BW values of
-// every shift.  Shift loops run to kTriTerms with a test against the call's
-// count, so the windows stay in registers.  Lanes past p leave at once:
+// every shift.  NT is the number of shifts (4, 5, 8 or 10), so the
+// windows are sized to the set and stay in registers.  Lanes past p leave at once:
 // every value a lane reads was written by itself (the kernel has no
 // barrier).
-template <int BW>
+template <int BW, int NT>
 __global__ void __launch_bounds__(64)
 band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
                   const double *__restrict__ fac, double *__restrict__ vws) {
@@ -187,15 +200,18 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
   const int c = (w - slot * ncw) * 64 + lane;
   if (c >= p) return;
   const int fn = T.fn[slot];
-  const int nt = T.nterms;
+  constexpr int nt = NT;
   const int N = plan[lo].s;
   const bool hyb = T.d1 != 0.0 || T.d2 != 0.0;
   const int64_t dp = (int64_t)d * p;
   const double *Bw = fac + D.b_off;
   const double *F0 = fac + D.f_off;
-  const int64_t fst = (int64_t)(2 * BW + 1) * d;  // factor rows of one shift
+  constexpr int W = 2 * BW + 1;                     // values per row and shift
   double *buf0 = vws + D.v_off + (int64_t)slot * 3 * dp, *buf1 = buf0 + dp, *ub = buf1 + dp;
-  double *zb = vws + D.z_off + (int64_t)slot * nt * dp;
+  constexpr int LC = kBandL(BW);
+  const int nch = (d + LC - 1) / LC;
+  const int64_t ckst = (int64_t)nt * BW * p;  // one chunk's checkpoints
+  double *ckb = vws + D.z_off + (int64_t)slot * nch * ckst;
   double *out_final = fn ? D.Fp : D.Fe;
 
   for (int j = 0; j < N; ++j) {
@@ -211,11 +227,11 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
 
     // forward pass: x read one chunk of kBandCH rows ahead
     {
-      double xw[2 * BW + 1], yw[2 * BW + 1], zw[kTriTerms][BW], xn[kBandCH];
+      double xw[2 * BW + 1], yw[2 * BW + 1], zw[NT][BW], xn[kBandCH];
 #pragma unroll
       for (int q = 0; q <= 2 * BW; ++q) xw[q] = yw[q] = 0.0;
 #pragma unroll
-      for (int k = 0; k < kTriTerms; ++k)
+      for (int k = 0; k < NT; ++k)
 #pragma unroll
         for (int i = 0; i < BW; ++i) zw[k][i] = 0.0;
       const int tend = d + (hyb ? 2 * BW : BW);
@@ -240,19 +256,27 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
             double y = 0.0;
             if (r >= 0 && r < d) {
 #pragma unroll
-              for (int o = -BW; o <= BW; ++o) y = fma(Bw[(int64_t)(BW + o) * d + r], xw[BW + o], y);
+              for (int o = -BW; o <= BW; ++o) y = fma(Bw[(int64_t)r * W + BW + o], xw[BW + o], y);
 #pragma unroll
-              for (int k = 0; k < kTriTerms; ++k) {
+              for (int k = 0; k < NT; ++k) {
                 if (k < nt) {
-                  const double *Fk = F0 + k * fst;
+                  const double *Fk = F0 + ((int64_t)r * nt + k) * W;
                   double z = y;
 #pragma unroll
-                  for (int i = 1; i <= BW; ++i) z = fma(-Fk[(int64_t)(i - 1) * d + r], zw[k][BW - i], z);
+                  for (int i = 1; i <= BW; ++i) z = fma(-Fk[i - 1], zw[k][BW - i], z);
 #pragma unroll
                   for (int i = 0; i + 1 < BW; ++i) zw[k][i] = zw[k][i + 1];
                   zw[k][BW - 1] = z;
-                  zb[k * dp + (int64_t)r * p + c] = z;
                 }
+              }
+              // checkpoint for the chunk that starts at row r + 1
+              if ((r + 1) % LC == 0 && r + 1 < d) {
+                double *cq = ckb + (int64_t)((r + 1) / LC) * ckst + c;
+#pragma unroll
+                for (int k = 0; k < NT; ++k)
+                  if (k < nt)
+#pragma unroll
+                    for (int i = 0; i < BW; ++i) cq[(int64_t)(k * BW + i) * p] = zw[k][i];
               }
             }
             if (hyb) {
@@ -263,7 +287,7 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
               if (s >= 0 && s < d) {
                 double by = 0.0;
 #pragma unroll
-                for (int o = -BW; o <= BW; ++o) by = fma(Bw[(int64_t)(BW + o) * d + s], yw[BW + o], by);
+                for (int o = -BW; o <= BW; ++o) by = fma(Bw[(int64_t)s * W + BW + o], yw[BW + o], by);
                 ub[(int64_t)s * p + c] = fma(T.d2, by, T.d1 * yw[BW]);
               }
             }
@@ -272,39 +296,69 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
       }
     }
 
-    // backward pass: the operands of kBandCH rows loaded together, then
-    // the rows swept from the last
+    // backward pass, chunk by chunk from the last
     {
-      double xk[kTriTerms][BW];  // xk[k][i] = x_{k, r + 1 + i}
+      double xk[NT][BW];  // xk[k][i] = x_{k, r + 1 + i}
 #pragma unroll
-      for (int k = 0; k < kTriTerms; ++k)
+      for (int k = 0; k < NT; ++k)
 #pragma unroll
         for (int i = 0; i < BW; ++i) xk[k][i] = 0.0;
-      for (int r0 = d - 1; r0 >= 0; r0 -= kBandCH) {
-        double xs[kBandCH], us[kBandCH], zs[kTriTerms][kBandCH];
+      for (int q = nch - 1; q >= 0; --q) {
+        const int r0 = q * LC;
+        // x_{r0 - BW} .. x_{r0 + LC - 1 + BW} (zero outside the vector), u_1
+        // or P, and the checkpoint z_{k, r0 - BW} .. z_{k, r0 - 1}
+        double xh[LC + 2 * BW], us[LC], zc[NT][LC], zk[NT][BW];
 #pragma unroll
-        for (int u = 0; u < kBandCH; ++u) {
-          const int r = r0 - u;
-          if (r >= 0) {
-            xs[u] = src[(int64_t)r * lds + c];
-            us[u] = add ? ub[(int64_t)r * p + c] : 0.0;
-#pragma unroll
-            for (int k = 0; k < kTriTerms; ++k)
-              if (k < nt) zs[k][u] = zb[k * dp + (int64_t)r * p + c];
-          }
+        for (int i = 0; i < LC + 2 * BW; ++i) {
+          const int r = r0 - BW + i;
+          xh[i] = (r >= 0 && r < d) ? src[(int64_t)r * lds + c] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kBandCH; ++u) {
-          const int r = r0 - u;
-          if (r >= 0) {
-            double o = fma(a0, xs[u], us[u]);
+        for (int u = 0; u < LC; ++u) us[u] = (add && r0 + u < d) ? ub[(int64_t)(r0 + u) * p + c] : 0.0;
+        {
+          const double *cq = ckb + (int64_t)q * ckst + c;
 #pragma unroll
-            for (int k = 0; k < kTriTerms; ++k) {
+          for (int k = 0; k < NT; ++k)
+            if (k < nt)
+#pragma unroll
+              for (int i = 0; i < BW; ++i) zk[k][i] = q > 0 ? cq[(int64_t)(k * BW + i) * p] : 0.0;
+        }
+        // the chunk's forward values, in registers
+#pragma unroll
+        for (int u = 0; u < LC; ++u) {
+          const int r = r0 + u;
+          if (r < d) {
+            double y = 0.0;
+#pragma unroll
+            for (int o = -BW; o <= BW; ++o) y = fma(Bw[(int64_t)r * W + BW + o], xh[BW + u + o], y);
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
               if (k < nt) {
-                const double *Fk = F0 + k * fst;
-                double x = Fk[(int64_t)BW * d + r] * zs[k][u];
+                const double *Fk = F0 + ((int64_t)r * nt + k) * W;
+                double z = y;
 #pragma unroll
-                for (int jj = 1; jj <= BW; ++jj) x = fma(-Fk[(int64_t)(BW + jj) * d + r], xk[k][jj - 1], x);
+                for (int i = 1; i <= BW; ++i) {
+                  const double zp = u - i >= 0 ? zc[k][u - i >= 0 ? u - i : 0] : zk[k][BW + u - i >= 0 ? BW + u - i : 0];
+                  z = fma(-Fk[i - 1], zp, z);
+                }
+                zc[k][u] = z;
+              }
+            }
+          }
+        }
+        // the backward sweeps and the combination
+#pragma unroll
+        for (int u = LC - 1; u >= 0; --u) {
+          const int r = r0 + u;
+          if (r < d) {
+            double o = fma(a0, xh[BW + u], us[u]);
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+              if (k < nt) {
+                const double *Fk = F0 + ((int64_t)r * nt + k) * W;
+                double x = Fk[BW] * zc[k][u];
+#pragma unroll
+                for (int jj = 1; jj <= BW; ++jj) x = fma(-Fk[BW + jj], xk[k][jj - 1], x);
 #pragma unroll
                 for (int i = BW - 1; i > 0; --i) xk[k][i] = xk[k][i - 1];
                 xk[k][0] = x;

@@ -577,7 +577,7 @@ int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, co
     D.b_off = dofs; dofs += align_up((2 * b + 1) * d, 64);
     D.f_off = dofs; dofs += align_up((int64_t)T.nterms * (2 * b + 1) * d, 64);
     D.v_off = dofs; dofs += align_up((int64_t)T.nf * 3 * d * p, 64);
-    D.z_off = dofs; dofs += align_up((int64_t)T.nf * T.nterms * d * p, 64);
+    D.z_off = dofs; dofs += align_up((int64_t)T.nf * ((d + kBandL(b) - 1) / kBandL(b)) * T.nterms * b * p, 64);
     D.wave0 = (int32_t)waves;
     D.nwaves = T.nf * (int32_t)((p + 63) / 64);
     waves += D.nwaves;
@@ -631,15 +631,23 @@ int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, co
                      wsd);
   ctx->cur_launches[0]++;
   prof_mark(ctx, 1, stream);
-#define PFM_BAND_STEPS(BW)                                                                                       \
-  hipLaunchKernelGGL((band_steps_kernel<BW>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, batch, d_plan, T, \
-                     (const double *)wsd, wsd)
-  switch (b) {
-    case 1: PFM_BAND_STEPS(1); break;
-    case 2: PFM_BAND_STEPS(2); break;
-    case 3: PFM_BAND_STEPS(3); break;
-    default: PFM_BAND_STEPS(4); break;
+#define PFM_BAND_STEPS(BW, NT)                                                                                 \
+  hipLaunchKernelGGL((band_steps_kernel<BW, NT>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, batch, d_plan, \
+                     T, (const double *)wsd, wsd)
+#define PFM_BAND_NT(BW)                                   \
+  switch (T.nterms) {                                     \
+    case 4: PFM_BAND_STEPS(BW, 4); break;                 \
+    case 5: PFM_BAND_STEPS(BW, 5); break;                 \
+    case 8: PFM_BAND_STEPS(BW, 8); break;                 \
+    default: PFM_BAND_STEPS(BW, 10); break;               \
   }
+  switch (b) {
+    case 1: PFM_BAND_NT(1); break;
+    case 2: PFM_BAND_NT(2); break;
+    case 3: PFM_BAND_NT(3); break;
+    default: PFM_BAND_NT(4); break;
+  }
+#undef PFM_BAND_NT
 #undef PFM_BAND_STEPS
   ctx->cur_launches[1]++;
   prof_mark(ctx, 2, stream);
