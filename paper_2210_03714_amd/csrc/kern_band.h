@@ -197,8 +197,10 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
   const int ncw = (p + 63) / 64;
   const int w = gw - D.wave0;
   const int slot = w / ncw;
-  const int c = (w - slot * ncw) * 64 + lane;
-  if (c >= p) return;
+  // lanes past p follow column p - 1 and store nothing (every lane takes
+  // part in staging the factor rows)
+  const bool active = (w - slot * ncw) * 64 + lane < p;
+  const int c = active ? (w - slot * ncw) * 64 + lane : p - 1;
   const int fn = T.fn[slot];
   constexpr int nt = NT;
   const int N = plan[lo].s;
@@ -213,6 +215,33 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
   const int64_t ckst = (int64_t)nt * BW * p;  // one chunk's checkpoints
   double *ckb = vws + D.z_off + (int64_t)slot * nch * ckst;
   double *out_final = fn ? D.Fp : D.Fe;
+  // factor rows staged through LDS: row u of a block holds B's row, then the
+  // W values of every shift (R doubles); blocks of SB rows, two buffers
+  constexpr int R = (NT + 1) * W;
+  constexpr int SF = kBandCH, SBK = LC;               // rows per block: forward, backward
+  constexpr int PL = (SF * R + 63) / 64;              // values per lane per forward block
+  __shared__ double st[2][SF * R];
+  double sv[PL];
+  // this lane's share of the block of n rows from row r0 (rows past d as 0)
+  auto stage_load = [&](int r0, int n) {
+#pragma unroll
+    for (int i = 0; i < PL; ++i) {
+      const int e = lane + 64 * i;
+      const int u = e / R, q = e - u * R;
+      const int r = r0 + u;
+      double v = 0.0;
+      if (e < n * R && r >= 0 && r < d)
+        v = q < W ? gld(Bw + (int64_t)r * W + q) : gld(F0 + (int64_t)r * NT * W + (q - W));
+      sv[i] = v;
+    }
+  };
+  auto stage_put = [&](int buf, int n) {
+#pragma unroll
+    for (int i = 0; i < PL; ++i) {
+      const int e = lane + 64 * i;
+      if (e < n * R) st[buf][e] = sv[i];
+    }
+  };
 
   for (int j = 0; j < N; ++j) {
     const double *src = j == 0 ? D.V : ((j - 1) & 1 ? buf1 : buf0);
@@ -224,74 +253,102 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
     const bool keep_u1 = first_phi && N > 1;
     // φ1's first step is rho(B) V / N: the 1/N goes into its weights
     const double a0 = first_phi ? T.a0p / N : T.a0e;
+    double wts[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) wts[k] = first_phi ? T.wp[k] / N : T.we[k];
 
-    // forward pass: x read one chunk of kBandCH rows ahead
+    // forward pass over blocks of SF rows: x read one block ahead, the
+    // block's factor rows from LDS (staged while the previous block ran)
     {
-      double xw[2 * BW + 1], yw[2 * BW + 1], zw[NT][BW], xn[kBandCH];
+      double xw[2 * BW + 1], yw[2 * BW + 1], zw[NT][BW], xn[SF];
 #pragma unroll
       for (int q = 0; q <= 2 * BW; ++q) xw[q] = yw[q] = 0.0;
 #pragma unroll
       for (int k = 0; k < NT; ++k)
 #pragma unroll
         for (int i = 0; i < BW; ++i) zw[k][i] = 0.0;
-      const int tend = d + (hyb ? 2 * BW : BW);
-      auto load_x = [&](int t0) {
+      // rows r < rend are visited: y and z for r < d, the hybrid set's P
+      // one window behind (rows past d have y = 0)
+      const int rend = d + (hyb ? BW : 0);
+      const int nbl = (rend + SF - 1) / SF;
+      // x_0 .. x_{BW-1} enter the window first; block i then pushes
+      // x_{r0 + BW} .. x_{r0 + SF - 1 + BW}
 #pragma unroll
-        for (int u = 0; u < kBandCH; ++u) xn[u] = t0 + u < d ? src[(int64_t)(t0 + u) * lds + c] : 0.0;
+      for (int t = 0; t < BW; ++t) {
+#pragma unroll
+        for (int q = 0; q < 2 * BW; ++q) xw[q] = xw[q + 1];
+        xw[2 * BW] = t < d ? gld(src + (int64_t)t * lds + c) : 0.0;
+      }
+      auto load_x = [&](int r0) {
+#pragma unroll
+        for (int u = 0; u < SF; ++u) {
+          const int t = r0 + BW + u;
+          xn[u] = t < d ? gld(src + (int64_t)t * lds + c) : 0.0;
+        }
       };
       load_x(0);
-      for (int t0 = 0; t0 < tend; t0 += kBandCH) {
-        double xc[kBandCH];
+      stage_load(0, SF);
+      __syncthreads();  // the previous step's last chunk has read its buffer
+      stage_put(0, SF);
+      __syncthreads();
+      for (int bi = 0; bi < nbl; ++bi) {
+        const int r0 = bi * SF;
+        const double *sb = st[bi & 1];
+        double xc[SF];
 #pragma unroll
-        for (int u = 0; u < kBandCH; ++u) xc[u] = xn[u];
-        if (t0 + kBandCH < tend) load_x(t0 + kBandCH);  // rows past d load as zeros
+        for (int u = 0; u < SF; ++u) xc[u] = xn[u];
+        if (bi + 1 < nbl) {
+          load_x(r0 + SF);
+          stage_load(r0 + SF, SF);
+        }
 #pragma unroll
-        for (int u = 0; u < kBandCH; ++u) {
-          const int t = t0 + u;
-          if (t < tend) {
+        for (int u = 0; u < SF; ++u) {
+          const int r = r0 + u;
+          if (r < rend) {
 #pragma unroll
             for (int q = 0; q < 2 * BW; ++q) xw[q] = xw[q + 1];
             xw[2 * BW] = xc[u];
-            const int r = t - BW;
+            const double *fr = sb + u * R;
             double y = 0.0;
-            if (r >= 0 && r < d) {
+            if (r < d) {
 #pragma unroll
-              for (int o = -BW; o <= BW; ++o) y = fma(Bw[(int64_t)r * W + BW + o], xw[BW + o], y);
+              for (int o = -BW; o <= BW; ++o) y = fma(fr[BW + o], xw[BW + o], y);
 #pragma unroll
               for (int k = 0; k < NT; ++k) {
-                if (k < nt) {
-                  const double *Fk = F0 + ((int64_t)r * nt + k) * W;
-                  double z = y;
+                double z = y;
 #pragma unroll
-                  for (int i = 1; i <= BW; ++i) z = fma(-Fk[i - 1], zw[k][BW - i], z);
+                for (int i = 1; i <= BW; ++i) z = fma(-fr[W + k * W + i - 1], zw[k][BW - i], z);
 #pragma unroll
-                  for (int i = 0; i + 1 < BW; ++i) zw[k][i] = zw[k][i + 1];
-                  zw[k][BW - 1] = z;
-                }
+                for (int i = 0; i + 1 < BW; ++i) zw[k][i] = zw[k][i + 1];
+                zw[k][BW - 1] = z;
               }
               // checkpoint for the chunk that starts at row r + 1
-              if ((r + 1) % LC == 0 && r + 1 < d) {
+              if ((r + 1) % LC == 0 && r + 1 < d && active) {
                 double *cq = ckb + (int64_t)((r + 1) / LC) * ckst + c;
 #pragma unroll
                 for (int k = 0; k < NT; ++k)
-                  if (k < nt)
 #pragma unroll
-                    for (int i = 0; i < BW; ++i) cq[(int64_t)(k * BW + i) * p] = zw[k][i];
+                  for (int i = 0; i < BW; ++i) cq[(int64_t)(k * BW + i) * p] = zw[k][i];
               }
             }
             if (hyb) {
 #pragma unroll
               for (int q = 0; q < 2 * BW; ++q) yw[q] = yw[q + 1];
               yw[2 * BW] = y;
-              const int s = t - 2 * BW;
+              const int s = r - BW;
               if (s >= 0 && s < d) {
                 double by = 0.0;
 #pragma unroll
                 for (int o = -BW; o <= BW; ++o) by = fma(Bw[(int64_t)s * W + BW + o], yw[BW + o], by);
-                ub[(int64_t)s * p + c] = fma(T.d2, by, T.d1 * yw[BW]);
+                if (active) ub[(int64_t)s * p + c] = fma(T.d2, by, T.d1 * yw[BW]);
               }
             }
           }
+        }
+        if (bi + 1 < nbl) {
+          __syncthreads();  // every lane is done with the other buffer
+          stage_put((bi + 1) & 1, SF);
+          __syncthreads();
         }
       }
     }
@@ -303,25 +360,31 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
       for (int k = 0; k < NT; ++k)
 #pragma unroll
         for (int i = 0; i < BW; ++i) xk[k][i] = 0.0;
+      __syncthreads();
+      stage_load((nch - 1) * LC, SBK);
+      stage_put(0, SBK);
+      __syncthreads();
       for (int q = nch - 1; q >= 0; --q) {
         const int r0 = q * LC;
+        const double *sb = st[(nch - 1 - q) & 1];
+        if (q > 0) stage_load(r0 - LC, SBK);
         // x_{r0 - BW} .. x_{r0 + LC - 1 + BW} (zero outside the vector), u_1
         // or P, and the checkpoint z_{k, r0 - BW} .. z_{k, r0 - 1}
         double xh[LC + 2 * BW], us[LC], zc[NT][LC], zk[NT][BW];
 #pragma unroll
         for (int i = 0; i < LC + 2 * BW; ++i) {
           const int r = r0 - BW + i;
-          xh[i] = (r >= 0 && r < d) ? src[(int64_t)r * lds + c] : 0.0;
+          xh[i] = (r >= 0 && r < d) ? gld(src + (int64_t)r * lds + c) : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < LC; ++u) us[u] = (add && r0 + u < d) ? ub[(int64_t)(r0 + u) * p + c] : 0.0;
+        for (int u = 0; u < LC; ++u) us[u] = (add && r0 + u < d) ? gld(ub + (int64_t)(r0 + u) * p + c) : 0.0;
         {
           const double *cq = ckb + (int64_t)q * ckst + c;
 #pragma unroll
           for (int k = 0; k < NT; ++k)
             if (k < nt)
 #pragma unroll
-              for (int i = 0; i < BW; ++i) zk[k][i] = q > 0 ? cq[(int64_t)(k * BW + i) * p] : 0.0;
+              for (int i = 0; i < BW; ++i) zk[k][i] = q > 0 ? gld(cq + (int64_t)(k * BW + i) * p) : 0.0;
         }
         // the chunk's forward values, in registers
 #pragma unroll
@@ -330,11 +393,11 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
           if (r < d) {
             double y = 0.0;
 #pragma unroll
-            for (int o = -BW; o <= BW; ++o) y = fma(Bw[(int64_t)r * W + BW + o], xh[BW + u + o], y);
+            for (int o = -BW; o <= BW; ++o) y = fma(sb[u * R + BW + o], xh[BW + u + o], y);
 #pragma unroll
             for (int k = 0; k < NT; ++k) {
               if (k < nt) {
-                const double *Fk = F0 + ((int64_t)r * nt + k) * W;
+                const double *Fk = sb + u * R + W + k * W;
                 double z = y;
 #pragma unroll
                 for (int i = 1; i <= BW; ++i) {
@@ -355,20 +418,26 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
 #pragma unroll
             for (int k = 0; k < NT; ++k) {
               if (k < nt) {
-                const double *Fk = F0 + ((int64_t)r * nt + k) * W;
+                const double *Fk = sb + u * R + W + k * W;
                 double x = Fk[BW] * zc[k][u];
 #pragma unroll
                 for (int jj = 1; jj <= BW; ++jj) x = fma(-Fk[BW + jj], xk[k][jj - 1], x);
 #pragma unroll
                 for (int i = BW - 1; i > 0; --i) xk[k][i] = xk[k][i - 1];
                 xk[k][0] = x;
-                const double wk = first_phi ? T.wp[k] / N : T.we[k];
-                o = fma(wk, x, o);
+                o = fma(wts[k], x, o);
               }
             }
-            dst[(int64_t)r * ldd + c] = o;
-            if (keep_u1) ub[(int64_t)r * p + c] = o;
+            if (active) {
+              dst[(int64_t)r * ldd + c] = o;
+              if (keep_u1) ub[(int64_t)r * p + c] = o;
+            }
           }
+        }
+        if (q > 0) {
+          __syncthreads();
+          stage_put((nch - q) & 1, SBK);
+          __syncthreads();
         }
       }
     }
