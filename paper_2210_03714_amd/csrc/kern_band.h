@@ -8,8 +8,7 @@
 // is the partial-pivoting LU.
 //
 // Layout (one lane per column of V, a wave per 64 consecutive columns of one
-// instance, so every read of B or of a factor is the same address in all
-// lanes):
+// instance, so every lane needs the same rows of B and of the factors):
 //   A:        bands[(b + o) d + i] = A[i][i + o], o = -b..b (caller's; the
 //             entries with i + o outside [0, d) are never read)
 //   B:        row-major, B[r][r + o] at r (2b + 1) + b + o (A / N, zero
@@ -18,8 +17,8 @@
 //             with l_i = L[r][r - i], ui = 1 / U[r][r],
 //             em_j = U[r][r + j] / U[r][r] (zero outside the matrix), so the
 //             backward sweep is x_r = ui z_r - sum_j em_j x_{r+j}.  One row's
-//             values of all shifts are contiguous: the sweeps read them with
-//             a few wide uniform loads
+//             values of all shifts are contiguous, so a block of rows is one
+//             contiguous range that the wave stages through LDS
 //   vectors:  per function slot, two ping-pong buffers and one for u_1 (φ1)
 //             or the hybrid set's polynomial part, d x p row-major
 //   checkpoints: per slot, the last b forward values of every shift at the
@@ -177,9 +176,13 @@ band_factor_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan
 // x_{r+o} needs x_{r+BW}) and, for the hybrid set, of y (P_s =
 // d1 y_s + d2 (B y)_s needs y_{s+BW}); the sweeps keep the last BW values of
 // every shift.  NT is the number of shifts (4, 5, 8 or 10), so the
-// windows are sized to the set and stay in registers.  Lanes past p leave at once:
-// every value a lane reads was written by itself (the kernel has no
-// barrier).
+// windows are sized to the set and stay in registers.  B and the factor rows
+// of each block (kBandCH rows forward, kBandL rows backward) are loaded by
+// all 64 lanes with vector loads one block ahead, written to the LDS buffer
+// not being read, and read by the sweeps as broadcasts; the workgroup is one
+// wave, so its barriers only order the LDS accesses.  Lanes past p follow
+// column p - 1 and store nothing: apart from the staged rows, every value a
+// lane uses was written by a lane of its own column.
 template <int BW, int NT>
 __global__ void __launch_bounds__(64)
 band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
