@@ -198,3 +198,73 @@ def test_errors(torch_dev):
     ctx.close()
     with pytest.raises(ValueError):
         pfm.band_action([bands], [V], 1)
+
+
+def test_force_plan(torch_dev):
+    """A forced N (more steps than planned) against the oracle at that N."""
+    torch, dev = torch_dev
+    b = 2
+    bands = wl.band_gaussian_batch(2, 40, b, 1.0, 2.0, wl.SEED_BASE + 1010)
+    vecs = [wl.vectors(40, 4, wl.SEED_BASE + 1011), wl.vectors(40, 70, wl.SEED_BASE + 1012)]
+    _say("case band force_plan")
+    res, info = _run(torch, dev, bands, vecs, b, ("exp", "phi1"), 8, 1e-12, force_plan=37)
+    for i in range(2):
+        assert info[i]["plan"] == 37
+        own = bd.band_action(bands[i], b, vecs[i], ("exp", "phi1"), 8, 1e-12, force_plan=37)
+        for f in ("exp", "phi1"):
+            assert me.rel_fro(res[f][i].cpu().numpy(), own[f]) <= BAR
+
+
+def test_strided_vectors(torch_dev):
+    """V and the results as column slices of wider matrices (row strides 80
+    and 72 for p = 64 columns), d = 130 (a ragged last block): the library
+    reads and writes only the slices."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    d, p, b = 130, 64, 3
+    bands = wl.band_gaussian_batch(2, d, b, 0.5, 8.0, wl.SEED_BASE + 1020)
+    vecs = [wl.vectors(d, p, wl.SEED_BASE + 1021 + i) for i in range(2)]
+    wideV = [torch.zeros((d, 80), dtype=torch.float64, device=dev) for _ in vecs]
+    for w, v in zip(wideV, vecs):
+        w[:, 5:5 + p] = torch.from_numpy(v).to(dev)
+    sentinel = 12345.0
+    wide = {f: [torch.full((d, 72), sentinel, dtype=torch.float64, device=dev) for _ in vecs]
+            for f in ("exp", "phi1")}
+    out = {f: [w[:, 3:3 + p] for w in wide[f]] for f in ("exp", "phi1")}
+    Bt = [torch.from_numpy(np.ascontiguousarray(_outside_nan(x, b))).to(dev) for x in bands]
+    _say("case band strided V and outputs d=%d p=%d b=%d" % (d, p, b))
+    res, info = pfm.band_action(Bt, [w[:, 5:5 + p] for w in wideV], b, ("exp", "phi1"), m=8, tol=1e-12, out=out)
+    torch.cuda.synchronize()
+    for f in ("exp", "phi1"):
+        for w in wide[f]:
+            h = w.cpu().numpy()
+            assert (h[:, :3] == sentinel).all() and (h[:, 3 + p:] == sentinel).all()
+    _check(res, info, bands, vecs, b, ("exp", "phi1"), 8, 1e-12)
+
+
+def test_nonfinite_and_singular(torch_dev):
+    """A NaN inside A sets PFM_NONFINITE (and ||A||_1 NaN); an exactly zero
+    pivot sets PFM_SINGULAR_SHIFT with that shift's index: A[0][0] = 8 with N
+    forced to 1 and the shift 1/8 of the m = 10 set, where 1 - c A[0][0] is 0
+    exactly whether or not the product and difference are fused (c is a
+    power of two).  Both calls complete; the status says the results are not
+    valid."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    b, d = 2, 20
+    x = wl.band_gaussian_batch(1, d, b, 1.0, 2.0, wl.SEED_BASE + 1030)[0].copy()
+    x[b, 7] = np.nan
+    V = wl.vectors(d, 2, wl.SEED_BASE + 1031)
+    _say("case band nonfinite")
+    res, info = _run(torch, dev, [x], [V], b, ("exp",), 8, 1e-12)
+    assert info[0]["status"] & pfm.NONFINITE
+    assert np.isnan(info[0]["norm1"])
+    y = np.zeros((2 * b + 1, 6))
+    y[b] = [8.0, 0.5, 0.5, 0.5, 0.5, 0.5]
+    c = list(pfm.coeffs(pfm.EXP, 10)[0])
+    k = [i for i, ci in enumerate(c) if complex(ci) == 0.125]
+    assert len(k) == 1
+    _say("case band singular shift")
+    res, info = _run(torch, dev, [y], [wl.vectors(6, 1, wl.SEED_BASE + 1032)], b, ("exp",), 10, 1e-12, force_plan=1)
+    assert info[0]["status"] & pfm.SINGULAR_SHIFT
+    assert info[0]["bad_shift"] == k[0]
