@@ -200,7 +200,7 @@ def tri_leg(batch, d, p, reps, cpu_seconds, hybrid=True):
     return res
 
 
-def band_leg(batch, d, p, b, reps, cpu_seconds):
+def band_leg(batch, d, p, b, reps, cpu_seconds, hybrid=True):
     """The banded action (b = 2: pentadiagonal): ``batch`` instances of
     dimension d with N(0,1) diagonals rescaled to ||A||_1 ~ U[0.5, 8], each on
     p synthetic N(0,1) columns; exp, m = 8, tol 1e-12, FP64.  The step kernel's
@@ -227,8 +227,8 @@ def band_leg(batch, d, p, b, reps, cpu_seconds):
     L = pfm.lib()
     sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
-    def call():
-        rc = L.pfm_band_action(ctx.handle, pfm.EXP, 8, 1e-12, b, batch, probs, ctypes.c_void_p(info.data_ptr()),
+    def call(m=8):
+        rc = L.pfm_band_action(ctx.handle, pfm.EXP, m, 1e-12, b, batch, probs, ctypes.c_void_p(info.data_ptr()),
                                -1, sptr)
         if rc:
             raise pfm.PfmError(rc, ctx.last_error())
@@ -261,6 +261,27 @@ def band_leg(batch, d, p, b, reps, cpu_seconds):
            "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved / 1e9, 1),
                         "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
                         "traffic": traffic_from_profile(kname)}}
+    if hybrid:
+        # R10' of §5 on the same batch: the hybrid set of §4.3 (m = 10)
+        F8 = F.clone()
+        call(10)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call(10)
+        torch.cuda.synchronize()
+        wall10 = (time.perf_counter() - t0) / reps
+        ph10, calls10 = ctx.profile_read()
+        ctx.profile(False)
+        ctx.check()
+        inf10 = np.frombuffer(info.cpu().numpy().tobytes(), dtype=pfm.INFO_DTYPE)
+        rel = ((F - F8).flatten(1).norm(dim=1) / F8.flatten(1).norm(dim=1)).max().item()
+        res["hybrid_r10_prime"] = {
+            "value": round(batch * p / wall10, 1), "unit": "columns/s", "ms_per_call": round(wall10 * 1e3, 3),
+            "steps_kernel_ms": round(ph10["solve_combine"][0] / max(1, calls10), 3), "m": 10,
+            "mean_N": round(float(inf10["plan"].astype(np.int64).mean()), 3), "max_rel_diff_vs_r8": rel,
+            "config": "the same batch with the hybrid set of §4.3 (m = 10) in the round-off form, exp, tol 1e-12"}
     if cpu_seconds > 0:
         from oracle import banded as bd
         k, t0 = 0, time.perf_counter()
@@ -498,7 +519,7 @@ def main():
                                      0.0 if args.no_cpu_baseline else 10.0, hybrid=not args.no_hybrid)
     if not args.no_band:
         res["banded"] = band_leg(args.band_batch, args.tri_d, args.tri_p, 2, 3,
-                                 0.0 if args.no_cpu_baseline else 10.0)
+                                 0.0 if args.no_cpu_baseline else 10.0, hybrid=not args.no_hybrid)
     if args.no_mixed:
         if args.serve_seconds > 0:
             res["serving"] = serving_leg(args.serve_rate, args.serve_seconds)
