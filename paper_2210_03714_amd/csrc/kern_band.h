@@ -182,9 +182,12 @@ band_factor_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan
 // not being read, and read by the sweeps as broadcasts; the workgroup is one
 // wave, so its barriers only order the LDS accesses.  Lanes past p follow
 // column p - 1 and store nothing: apart from the staged rows, every value a
-// lane uses was written by a lane of its own column.
+// lane uses was written by a lane of its own column.  For b <= 2 the kernel
+// is held to the registers of two waves per SIMD: it spills about 150 bytes
+// per lane (b = 2, m = 8) and still runs 1.4x faster than one wave without
+// spills; wider bands spill far more and keep one wave.
 template <int BW, int NT>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, BW <= 2 ? 2 : 1)
 band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
                   const double *__restrict__ fac, double *__restrict__ vws) {
   const int lane = threadIdx.x;
