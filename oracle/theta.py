@@ -45,11 +45,13 @@ def bound_coeffs_pair(func, pair, K=400):
                        str(pair["b"].as_real_imag()[1].evalf(DPS)))
         d = mpmath.mpf(str(pair["d"].evalf(DPS)))
         a = co.taylor_coeffs(func, K)
-        out = []
-        for k in range(K):
-            alpha = d + 2 * mpmath.re(b) if k == 0 else 2 * mpmath.re(b * c ** k)
-            out.append(abs(_mpf(a[k]) - alpha))
-        return out
+        return [abs(_mpf(a[k]) - pair_moment(d, b, c, k)) for k in range(K)]
+
+
+def pair_moment(d, b, c, k):
+    """Taylor coefficient k of d + b/(1 - c x) + conj(b)/(1 - conj(c) x):
+    the two geometric series add to 2 Re(b c^k); the constant d joins k = 0."""
+    return d + 2 * mpmath.re(b) if k == 0 else 2 * mpmath.re(b * c ** k)
 
 
 def bound_coeffs_taylor(func, degree, K=400):

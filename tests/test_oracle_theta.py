@@ -83,3 +83,59 @@ def test_table2_r10_threshold(golden):
     cf = th.bound_coeffs_hybrid("exp", c, b, d, 400)
     v = th.theta(cf, 2.0 ** -24, 0.9 / float(max(abs(x) for x in c)))
     assert round(v, 3) == e["theta"], e["cite"]
+
+
+# ------------------- the m = 1 Padé pairs: bound coefficients from eqs. 5, 6 --
+
+def _printed_pade(func):
+    """The rational forms printed in §2: r22 (eq. 5) and r~22 (eq. 6)."""
+    import sympy as sp
+    x = sp.symbols("x")
+    if func == "exp":
+        return x, (1 + x / 2 + x ** 2 / 12) / (1 - x / 2 + x ** 2 / 12)
+    return x, (1 + sp.Rational(1, 10) * x + x ** 2 / 60) / (1 - sp.Rational(2, 5) * x + x ** 2 / 20)
+
+
+def check_pair_bound_against_printed_form(func, K=13):
+    """|a_k - alpha_k| of the oracle's pole form equals |a_k - d_k|, where d_k
+    are the Taylor coefficients of the printed quotient of quadratics (§3: the
+    d_k of the Padé bounds are the series coefficients of r22 / r~22), for
+    k < K.  The quotient's series is taken by sympy from the printed
+    numerator and denominator, independently of the partial fractions."""
+    import sympy as sp
+    import mpmath
+    x, r = _printed_pade(func)
+    ser = sp.series(r, x, 0, K).removeO()
+    dk = [sp.Rational(ser.coeff(x, k)) for k in range(K)]
+    ak = co.taylor_coeffs(func, K)
+    want = [abs(Fr(int(a.numerator), int(a.denominator)) - Fr(int(d.p), int(d.q))) for a, d in zip(ak, dk)]
+    got = th.bound_coeffs_pair(func, co.pade22_exp() if func == "exp" else co.pade22_phi1(), K)
+    with mpmath.workdps(50):
+        for k in range(K):
+            w = mpmath.mpf(want[k].numerator) / want[k].denominator
+            assert abs(got[k] - w) <= mpmath.mpf(10) ** -40 * max(1, abs(w)), (func, k, got[k], w)
+    return want
+
+
+@pytest.mark.parametrize("func", ["exp", "phi1"])
+def test_pair_bound_coefficients_match_printed_pade(func):
+    want = check_pair_bound_against_printed_form(func)
+    # both are 4th order (eqs. 5, 6): zero through k = 4, nonzero at k = 5
+    assert all(w == 0 for w in want[:5]) and want[5] != 0
+    if func == "exp":
+        # e^x - r22(x): 1/720 x^5 + 1/720 x^6 + 47/60480 x^7 + 19/60480 x^8 ...
+        assert want[5:9] == [Fr(1, 720), Fr(1, 720), Fr(47, 60480), Fr(19, 60480)]
+
+
+def test_planted_pair_factor_error_is_caught(monkeypatch):
+    """Drop the factor 2 of the conjugate pair's moments in the oracle: the
+    printed-form pin must fail (while theta(R4) > theta(r22) alone would
+    still hold)."""
+    import mpmath
+
+    def broken(d, b, c, k):
+        return d + mpmath.re(b) if k == 0 else mpmath.re(b * c ** k)
+    monkeypatch.setattr(th, "pair_moment", broken)
+    assert th.theta_set("exp", 4, 1e-12) > th.theta_set("exp", 1, 1e-12)
+    with pytest.raises(AssertionError):
+        check_pair_bound_against_printed_form("exp")
