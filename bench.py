@@ -73,28 +73,151 @@ def traffic_from_profile(kernel):
     return k.get("bytes_per_launch")
 
 
-def cpu_baseline(A, seconds):
-    """The oracle, untuned, on consecutive instances of the same batch until
-    ``seconds`` have elapsed."""
-    from oracle import method as me
+def _oracle_eval(kind, item):
+    """One evaluation of the oracle on one instance of a leg's workload."""
+    if kind == "dense":
+        from oracle import method as me
+        me.expm_full(item, ("exp",), 8, 1e-12)
+    elif kind == "dense_exp_phi1":
+        from oracle import method as me
+        me.expm_full(item, ("exp", "phi1"), 8, 1e-12)
+    elif kind == "tri":
+        from oracle import banded as bd
+        bd.tri_action(item[0], item[1], item[2], item[3], ("exp",), 8, 1e-12)
+    elif kind == "band":
+        from oracle import banded as bd
+        bd.band_action(item[0], item[1], item[2], ("exp",), 8, 1e-12)
+    else:
+        raise ValueError(kind)
+
+
+def _oracle_warm():
+    """Import the oracle in a worker process (before any timing)."""
+    import oracle.banded  # noqa: F401
+    import oracle.method  # noqa: F401
+    import threadpoolctl  # noqa: F401
+    time.sleep(0.2)
+    return os.getpid()
+
+
+def _oracle_worker(task):
+    """Throughput-mode worker (a separate process): BLAS pinned to one
+    thread; one untimed warm-up evaluation, then its share of instances."""
+    kind, items = task
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1, user_api="blas"):
+        _oracle_eval(kind, items[0])
+        t0 = time.perf_counter()
+        for it in items[1:]:
+            _oracle_eval(kind, it)
+        return len(items) - 1, time.perf_counter() - t0
+
+
+def cpu_cores():
+    """Host cores this process may use, capped at the 16 a one-GPU share of
+    the box has."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
-    except Exception:
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    me.expm_full(A[0], ("exp",), 8, 1e-12)  # warm the θ cache
-    t0 = time.perf_counter()
-    k = 0
-    while k < A.shape[0] and (time.perf_counter() - t0) < seconds:
-        me.expm_full(A[k], ("exp",), 8, 1e-12)
-        k += 1
-    dt = time.perf_counter() - t0
-    return {"value": k / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": "%d consecutive instances of the n=256 batch (R8 exp, tol 1e-12), one process, "
-                      "numpy/scipy LAPACK with %d BLAS threads, %.1f s" % (k, threads, dt)}
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def tri_leg(batch, d, p, reps, cpu_seconds, hybrid=True):
+class OracleBaseline:
+    """The oracle timed on the host cores in the two modes of the plan for
+    the CPU baseline: throughput (one process per core, BLAS pinned to one
+    thread, the instances split evenly) and latency (one process, BLAS on
+    all cores).  Each mode reports the median of `runs` timed runs of about
+    `run_s` seconds each, after a warm-up."""
+
+    def __init__(self, runs=5, run_s=1.5):
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        self.cores = cpu_cores()
+        self.runs, self.run_s = runs, run_s
+        # workers are started before this process touches the GPU, with
+        # single-threaded BLAS from their first import
+        saved = {k: os.environ.get(k) for k in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS")}
+        for k in saved:
+            os.environ[k] = "1"
+        try:
+            self.pool = ProcessPoolExecutor(max_workers=self.cores, mp_context=mp.get_context("spawn"))
+            # one task per worker, submitted together, starts all of them now
+            futs = [self.pool.submit(_oracle_warm) for _ in range(self.cores)]
+            self.pids = sorted({f.result() for f in futs})
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+
+    def measure(self, kind, items, per_item, unit, what):
+        """Rates in `unit` per second (per_item units per instance)."""
+        import statistics
+        from threadpoolctl import threadpool_limits, threadpool_info
+        P = self.cores
+        nitems = len(items)
+        # latency mode: this process, BLAS on all P cores
+        with threadpool_limits(limits=P, user_api="blas"):
+            blas = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+            _oracle_eval(kind, items[0])
+            t0 = time.perf_counter()
+            _oracle_eval(kind, items[1 % nitems])
+            t1 = max(time.perf_counter() - t0, 1e-6)
+            k_lat = max(1, int(round(self.run_s / t1)))
+            lat = []
+            for r in range(self.runs):
+                sel = [items[(r * k_lat + j) % nitems] for j in range(k_lat)]
+                t0 = time.perf_counter()
+                for it in sel:
+                    _oracle_eval(kind, it)
+                lat.append(k_lat * per_item / (time.perf_counter() - t0))
+        # throughput mode: P processes, one BLAS thread each; one timed
+        # instance per worker first sizes the runs
+        cal = list(self.pool.map(_oracle_worker, [(kind, [items[w % nitems], items[(w + 1) % nitems]])
+                                                  for w in range(P)]))
+        t_one = max(dt for _, dt in cal)
+        k_thr = max(1, int(round(self.run_s / max(t_one, 1e-6))))
+        thr = []
+        for r in range(self.runs):
+            tasks = []
+            for w in range(P):
+                base = (r * P + w) * k_thr
+                tasks.append((kind, [items[(base + j) % nitems] for j in range(k_thr + 1)]))
+            out = list(self.pool.map(_oracle_worker, tasks))
+            done = sum(c for c, _ in out)
+            thr.append(done * per_item / max(dt for _, dt in out))
+        v_thr, v_lat = statistics.median(thr), statistics.median(lat)
+        return {"value": round(v_thr, 2), "unit": unit, "cores": P, "kind": "oracle",
+                "mode": "throughput", "cpu_model": cpu_model(),
+                "sample": "%s; throughput mode: %d processes x 1 BLAS thread, %d instances each per run; "
+                          "median of %d runs" % (what, P, k_thr, self.runs),
+                "latency_mode": {"value": round(v_lat, 2), "unit": unit, "blas_threads": blas,
+                                 "sample": "one process, %d BLAS threads, %d consecutive instances per run; "
+                                           "median of %d runs" % (blas, k_lat, self.runs)},
+                "runs_throughput": [round(x, 2) for x in thr], "runs_latency": [round(x, 2) for x in lat]}
+
+
+def headline_cpu(cpu, A):
+    """The oracle on the headline workload (R8 exp at tol 1e-12, n = 256)."""
+    items = [A[k] for k in range(min(64, A.shape[0]))]
+    return cpu.measure("dense", items, 1.0, "evals/s",
+                       "the first %d instances of the n=256 batch (R8 exp, tol 1e-12), numpy/scipy LAPACK "
+                       "getrf/getrs" % len(items))
+
+
+def tri_leg(batch, d, p, reps, cpu, hybrid=True):
     """Tridiagonal action leg (§2.1, §5): ``batch`` real tridiagonal d x d
     matrices with N(0,1) diagonals rescaled to ||A||_1 ~ U[0.5, 8], each acting
     on p synthetic N(0,1) columns; exp, m = 8, tol 1e-12, FP64.  The step
@@ -179,28 +302,16 @@ def tri_leg(batch, d, p, reps, cpu_seconds, hybrid=True):
             "steps_kernel_ms": round(ph10["solve_combine"][0] / max(1, calls10), 3), "m": 10,
             "mean_N": round(float(inf10["plan"].astype(np.int64).mean()), 3), "max_rel_diff_vs_r8": rel,
             "config": "the same batch with the hybrid set of §4.3 (m = 10) in the round-off form, exp, tol 1e-12"}
-    if cpu_seconds > 0:
-        from oracle import banded as bd
-        k, t0 = 0, time.perf_counter()
+    if cpu is not None:
         Vh = V[:64].cpu().numpy()
-        done_cols = 0
-        while k < 64 and (time.perf_counter() - t0) < cpu_seconds:
-            bd.tri_action(tris[k][0], tris[k][1], tris[k][2], Vh[k], ("exp",), 8, 1e-12)
-            done_cols += p
-            k += 1
-        dt = time.perf_counter() - t0
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([x.get("num_threads", 1) for x in threadpool_info() if x.get("user_api") == "blas"] or [1])
-        except Exception:
-            threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        res["cpu_baseline"] = {"value": round(done_cols / dt, 1), "unit": "columns/s", "kind": "oracle",
-                               "cores": threads, "sample": "%d consecutive instances (all %d columns each), "
-                               "scipy LAPACK gttrf/gttrs, %d BLAS threads, %.1f s" % (k, p, threads, dt)}
+        items = [(tris[k][0], tris[k][1], tris[k][2], Vh[k]) for k in range(64)]
+        res["cpu_baseline"] = cpu.measure("tri", items, p, "columns/s",
+                                          "the first 64 instances of the batch (all %d columns each), "
+                                          "scipy LAPACK gttrf/gttrs" % p)
     return res
 
 
-def band_leg(batch, d, p, b, reps, cpu_seconds, hybrid=True):
+def band_leg(batch, d, p, b, reps, cpu, hybrid=True):
     """The banded action (b = 2: pentadiagonal): ``batch`` instances of
     dimension d with N(0,1) diagonals rescaled to ||A||_1 ~ U[0.5, 8], each on
     p synthetic N(0,1) columns; exp, m = 8, tol 1e-12, FP64.  The step kernel's
@@ -282,22 +393,124 @@ def band_leg(batch, d, p, b, reps, cpu_seconds, hybrid=True):
             "steps_kernel_ms": round(ph10["solve_combine"][0] / max(1, calls10), 3), "m": 10,
             "mean_N": round(float(inf10["plan"].astype(np.int64).mean()), 3), "max_rel_diff_vs_r8": rel,
             "config": "the same batch with the hybrid set of §4.3 (m = 10) in the round-off form, exp, tol 1e-12"}
-    if cpu_seconds > 0:
-        from oracle import banded as bd
-        k, t0 = 0, time.perf_counter()
+    if cpu is not None:
         Vh = V[:64].cpu().numpy()
-        while k < 64 and (time.perf_counter() - t0) < cpu_seconds:
-            bd.band_action(bands[k], b, Vh[k], ("exp",), 8, 1e-12)
-            k += 1
-        dt = time.perf_counter() - t0
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([x.get("num_threads", 1) for x in threadpool_info() if x.get("user_api") == "blas"] or [1])
-        except Exception:
-            threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        res["cpu_baseline"] = {"value": round(k * p / dt, 1), "unit": "columns/s", "kind": "oracle",
-                               "cores": threads, "sample": "%d consecutive instances (all %d columns each), "
-                               "scipy LAPACK gbtrf/gbtrs, %d BLAS threads, %.1f s" % (k, p, threads, dt)}
+        items = [(bands[k], b, Vh[k]) for k in range(64)]
+        res["cpu_baseline"] = cpu.measure("band", items, p, "columns/s",
+                                          "the first 64 instances of the batch (all %d columns each), "
+                                          "scipy LAPACK gbtrf/gbtrs" % p)
+    return res
+
+
+def lu_route_leg(ctx, L, pptr, info, batch, n, m, tol, sptr, steps, warmup):
+    """The headline batch forced onto the pivoting LU route (pfm_set_route):
+    batched LU of every I - c_k B (lu_kernel, MFMA trailing updates), the
+    fused substitution + combination, the squarings.  Per-kernel algorithmic
+    rates from the library's phase events: LU (2/3) n^3 and substitution
+    2 n^3 per shift."""
+    import ctypes
+    import numpy as np
+    from paper_2210_03714_amd import pfm
+    ctx.set_route(pfm.ROUTE_LU)
+    try:
+        def step():
+            rc = L.pfm_eval_batched(ctx.handle, pfm.EXP, m, tol, pfm.FP64, pfm.R64, batch, pptr,
+                                    ctypes.c_void_p(info.data_ptr()), -1, sptr)
+            if rc:
+                raise pfm.PfmError(rc, ctx.last_error())
+        import torch
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        k = max(1, steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / k
+        ph, calls = ctx.profile_read()
+        ctx.profile(False)
+        ctx.check()
+    finally:
+        ctx.set_route(pfm.ROUTE_AUTO)
+    inf = np.frombuffer(info.cpu().numpy().tobytes(), dtype=pfm.INFO_DTYPE)
+    assert np.all(inf["route"] == 0)
+    n3 = float(n) ** 3
+    lu_ms = ph["lu"][0] / max(1, calls)
+    sv_ms = ph["solve_combine"][0] / max(1, calls)
+    lu_tf = batch * m * (2.0 / 3.0) * n3 / (lu_ms * 1e-3) / 1e12
+    sv_tf = batch * m * 2.0 * n3 / (sv_ms * 1e-3) / 1e12
+    return {"value": round(batch / (ms * 1e-3), 2), "unit": "evals/s", "ms_per_step": round(ms, 4),
+            "phases_ms_per_step": {p: round(v[0] / max(1, calls), 4) for p, v in ph.items()},
+            "lu_kernel": {"kernel": "lu_kernel<256,double>", "achieved": round(lu_tf, 3), "unit": "TFLOP/s",
+                          "frac": round(lu_tf * 1e12 / PEAK_FP64, 4)},
+            "solve_kernel": {"kernel": "solve_full_f64_kernel<256,16>", "achieved": round(sv_tf, 3),
+                             "unit": "TFLOP/s", "frac": round(sv_tf * 1e12 / PEAK_FP64, 4)},
+            "config": "the headline batch on the pivoting LU route (every instance), exp, m=8, tol 1e-12, FP64"}
+
+
+def config4_leg(steps):
+    """The uneven mixed-precision batch: 2048 Gaussian instances, n uniform
+    over {64, 96, ..., 512}, ||A||_1 ~ U[0.5, 4], exp and phi1, m = 8.  The
+    mixed path at tol 1e-10 against the binary64 GPU path at 1e-10 (same
+    plan) and at 1e-12."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_2210_03714_amd import pfm
+    from paper_2210_03714_amd import workloads as wl
+    dev = torch.device("cuda:0")
+    mats = wl.gaussian_uneven(2048, list(range(64, 513, 32)), 0.5, 4.0, wl.SEED_BASE + 4)
+    At = [torch.from_numpy(a).to(dev) for a in mats]
+    ns = np.array([a.shape[0] for a in mats], dtype=np.float64)
+    ctx = pfm.Context(0)
+    L = pfm.lib()
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    outs = {}
+    res = {}
+    for name, prec, tol in (("mixed", pfm.MIXED, 1e-10), ("fp64", pfm.FP64, 1e-10), ("fp64_1e-12", pfm.FP64, 1e-12)):
+        fe = [torch.empty_like(a) for a in At]
+        fp = [torch.empty_like(a) for a in At]
+        probs = (pfm.Problem * len(At))()
+        for i, a in enumerate(At):
+            probs[i] = pfm.Problem(a.shape[0], 0, a.stride(0), 0, a.shape[0], a.data_ptr(), None,
+                                   fe[i].data_ptr(), fp[i].data_ptr())
+        info = torch.empty(len(At) * pfm.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+
+        def call():
+            rc = L.pfm_eval_batched(ctx.handle, pfm.EXP | pfm.PHI1, 8, tol, prec, pfm.R64, len(At), probs,
+                                    ctypes.c_void_p(info.data_ptr()), -1, sptr)
+            if rc:
+                raise pfm.PfmError(rc, ctx.last_error())
+        call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ctx.check()
+        inf = np.frombuffer(info.cpu().numpy().tobytes(), dtype=pfm.INFO_DTYPE)
+        outs[name] = (fe, fp)
+        res[name] = {"value": round(len(At) / (ms * 1e-3), 2), "unit": "evals/s (exp and phi1)",
+                     "ms_per_call": round(ms, 3), "mean_s": round(float(inf["plan"].mean()), 4),
+                     "status_nonzero": int((inf["status"] != 0).sum())}
+        if name == "mixed":
+            res[name]["ir_iters_hist"] = np.bincount(inf["ir_iters"]).tolist()
+            res[name]["max_resid"] = float(inf["resid"].max())
+
+    def worst(a, b):
+        w = 0.0
+        for f in range(2):
+            for x, y in zip(outs[a][f], outs[b][f]):
+                w = max(w, float((x - y).norm() / y.norm()))
+        return w
+    res["max_rel_err_mixed_vs_fp64_same_tol"] = worst("mixed", "fp64")
+    res["max_rel_err_mixed_vs_fp64_1e-12"] = worst("mixed", "fp64_1e-12")
+    res["mixed_over_fp64_time"] = round(res["mixed"]["ms_per_call"] / res["fp64"]["ms_per_call"], 3)
+    res["config"] = ("2048 Gaussian instances, n uniform over {64,...,512} (mean n^3 %.3g), ||A||_1~U[0.5,4], "
+                     "exp+phi1, m=8; mixed at tol 1e-10 vs FP64 at 1e-10 and 1e-12" % float((ns ** 3).mean()))
     return res
 
 
@@ -338,7 +551,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-runs", type=int, default=5, help="timed runs per CPU-baseline mode (median)")
+    ap.add_argument("--cpu-run-seconds", type=float, default=1.5, help="length of one CPU-baseline run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
@@ -347,6 +561,8 @@ def main():
     ap.add_argument("--no-tri", action="store_true", help="skip the tridiagonal action leg")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid 10th-order leg")
     ap.add_argument("--no-band", action="store_true", help="skip the banded (pentadiagonal) action leg")
+    ap.add_argument("--no-lu", action="store_true", help="skip the leg forced onto the pivoting LU route")
+    ap.add_argument("--no-config4", action="store_true", help="skip the uneven mixed-precision batch")
     ap.add_argument("--band-batch", type=int, default=4096)
     ap.add_argument("--band-only", action="store_true", help="run only the banded leg (profiling)")
     ap.add_argument("--tri-batch", type=int, default=4096)
@@ -362,6 +578,11 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # the oracle's worker processes start before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and not args.calib_copy and not args.band_only:
+        cpu = OracleBaseline(runs=args.cpu_runs, run_s=args.cpu_run_seconds)
+
     import numpy as np
     import torch
 
@@ -375,7 +596,7 @@ def main():
         return
 
     if args.band_only:
-        print(json.dumps(band_leg(args.band_batch, args.tri_d, args.tri_p, 2, 3, 0.0)))
+        print(json.dumps(band_leg(args.band_batch, args.tri_d, args.tri_p, 2, 3, None)))
         return
 
     from paper_2210_03714_amd import pfm
@@ -514,17 +735,21 @@ def main():
             "phases_ms_per_step": {p: round(v[0] / max(1, calls10), 4) for p, v in ph10.items()},
             "max_rel_diff_vs_r8": rel,
             "config": "the headline batch with the hybrid set of §4.3 (m = 10), tol 1e-12, FP64"}
+    if not args.no_lu:
+        res["lu_route"] = lu_route_leg(ctx, L, pptr, info, batch, n, m, tol, sptr, args.steps, args.warmup)
     if not args.no_tri:
-        res["tridiagonal"] = tri_leg(args.tri_batch, args.tri_d, args.tri_p, 3,
-                                     0.0 if args.no_cpu_baseline else 10.0, hybrid=not args.no_hybrid)
+        res["tridiagonal"] = tri_leg(args.tri_batch, args.tri_d, args.tri_p, 3, cpu, hybrid=not args.no_hybrid)
     if not args.no_band:
-        res["banded"] = band_leg(args.band_batch, args.tri_d, args.tri_p, 2, 3,
-                                 0.0 if args.no_cpu_baseline else 10.0, hybrid=not args.no_hybrid)
+        res["banded"] = band_leg(args.band_batch, args.tri_d, args.tri_p, 2, 3, cpu, hybrid=not args.no_hybrid)
+    if not args.no_config4 and not args.no_mixed:
+        res["config4_mixed"] = config4_leg(2)
     if args.no_mixed:
         if args.serve_seconds > 0:
             res["serving"] = serving_leg(args.serve_rate, args.serve_seconds)
         if not args.no_cpu_baseline:
-            res["cpu_baseline"] = cpu_baseline(A, args.cpu_seconds)
+            res["cpu_baseline"] = headline_cpu(cpu, A)
+        if cpu is not None:
+            cpu.close()
         print(json.dumps(res))
         return
     outm = torch.empty_like(At)
@@ -560,7 +785,9 @@ def main():
     if args.serve_seconds > 0:
         res["serving"] = serving_leg(args.serve_rate, args.serve_seconds)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(A, args.cpu_seconds)
+        res["cpu_baseline"] = headline_cpu(cpu, A)
+    if cpu is not None:
+        cpu.close()
     print(json.dumps(res))
 
 

@@ -83,12 +83,14 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
 #define PFM_SINGULAR_SHIFT 1 /* an exact zero pivot in I - c_k B; bad_shift = k */
 #define PFM_NONFINITE 2      /* ||A||_1 is not finite (NaN or Inf in A) */
 #define PFM_IR_STALL 4       /* mixed path: refinement did not reach the target */
-#define PFM_NOT_COMPUTED 8   /* n > 512 (complex: > 256): the instance was not
-                                computed and its outputs were not written,
-                                because A is not finite or some shifted matrix
-                                I - c_k B is not diagonally dominant enough for
+#define PFM_NOT_COMPUTED 8   /* the instance was not computed and its outputs
+                                were not written: n > 512 (complex: > 256)
+                                with A not finite or some shifted matrix
+                                I - c_k B not diagonally dominant enough for
                                 the large-instance route (|c_k| ||B||_1 <= 1/2;
-                                the planner's B always is, a forced plan may not) */
+                                the planner's B always is, a forced plan may
+                                not); or, on the tridiagonal and banded paths,
+                                more than PFM_MAX_STEPS steps */
 #define PFM_OUT_OF_RANGE 16  /* PFM_LOG1M: ||A||_1 > θ, so the tolerance is not
                                 guaranteed (the result is still computed) */
 
@@ -240,10 +242,13 @@ typedef struct {
  *              or 10: the hybrid set of §4.3 in the round-off form (R10' of
  *              §5), exp only (PFM_ERR_UNSUPPORTED with PFM_PHI1)
  * pfm_info.route is 3.  With pfm_profile on, phase 0 times the
- * factorisations and phase 1 the N steps.  The call reads the step counts back once (one
- * stream synchronisation) and returns PFM_ERR_UNSUPPORTED if some N exceeds
- * 2^20; everything else is enqueued on `stream`.  Workspace: about
- * (3 + 2 m) d + n_f (3 + m / 16) d p doubles per instance (n_f functions). */
+ * factorisations and phase 1 the N steps.  The call only enqueues work on
+ * `stream` (nothing is read back): an instance whose N would exceed
+ * PFM_MAX_STEPS is flagged PFM_NOT_COMPUTED on the device and its outputs
+ * are not written.  Workspace (grown with hipMalloc when a call needs more,
+ * after synchronising `stream`): about (3 + 3 m) d + n_f (3 + m / 8) d p
+ * doubles per instance (n_f functions). */
+#define PFM_MAX_STEPS (1 << 20)
 int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_tri_problem *probs,
                    pfm_info *info, int force_plan, pfm_stream_t stream);
 
@@ -285,11 +290,10 @@ typedef struct {
  *              8, or 10: the hybrid set of §4.3, exp only)
  * pfm_info.route is 4.  ||A||_1 adds column j's entries from the top row
  * down.  With pfm_profile on, phase 0 times the factorisations and phase 1
- * the N steps.  The call reads the step counts back once (one stream
- * synchronisation) and returns PFM_ERR_UNSUPPORTED if some N exceeds 2^20;
- * everything else is enqueued on `stream`.  Workspace: about
- * (m + 1) (2b + 1) d + n_f (3 + m b / L) d p doubles per instance (n_f
- * functions; L = 8 rows per checkpoint for b <= 2, else 4). */
+ * the N steps.  As for pfm_tri_action, the call only enqueues work, and an
+ * instance whose N would exceed PFM_MAX_STEPS is flagged PFM_NOT_COMPUTED.
+ * Workspace: about (m + 1) (2b + 1) d + n_f (3 + m b / 4) d p doubles per
+ * instance (n_f functions; one checkpoint per 4 rows). */
 int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, const pfm_band_problem *probs,
                     pfm_info *info, int force_plan, pfm_stream_t stream);
 

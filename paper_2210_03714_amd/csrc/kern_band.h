@@ -109,6 +109,8 @@ band_plan_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
     const double q = ceil(P.eta / D.theta);
     P.s = q < 1.0 ? 1 : (q > 1e9 ? 1000000000 : (int)q);
   }
+  // more than kNCap steps: PFM_NOT_COMPUTED, the instance is skipped
+  if (P.s > kNCap) P.status |= 8;
   plan[ii] = P;
 }
 
@@ -124,6 +126,7 @@ band_factor_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan
   const int gid = blockIdx.x * 64 + threadIdx.x;
   const int ii = gid / T.nterms, k = gid - ii * T.nterms;
   if (ii >= batch) return;
+  if (plan[ii].status & 8) return;  // PFM_NOT_COMPUTED (too many steps)
   const BandDesc D = desc[ii];
   const int d = D.d, b = D.b;
   const double Nd = (double)plan[ii].s;
@@ -198,6 +201,7 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
     if (desc[mid].wave0 <= gw) lo = mid;
     else hi = mid - 1;
   }
+  if (plan[lo].status & 8) return;  // PFM_NOT_COMPUTED: the whole wave leaves before any barrier
   const BandDesc D = desc[lo];
   const int d = D.d, p = D.p;
   const int ncw = (p + 63) / 64;

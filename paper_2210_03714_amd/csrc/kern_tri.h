@@ -104,6 +104,9 @@ tri_plan_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, in
     const double q = ceil(P.eta / D.theta);
     P.s = q < 1.0 ? 1 : (q > 1e9 ? 1000000000 : (int)q);
   }
+  // more than kNCap steps: PFM_NOT_COMPUTED, the instance is skipped (the
+  // host never reads the plans back, so the cap is applied here)
+  if (P.s > kNCap) P.status |= 8;
   plan[ii] = P;
 }
 
@@ -116,6 +119,7 @@ tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
   const int gid = blockIdx.x * 64 + threadIdx.x;
   const int ii = gid / T.nterms, k = gid - ii * T.nterms;
   if (ii >= batch) return;
+  if (plan[ii].status & 8) return;  // PFM_NOT_COMPUTED (too many steps)
   const TriDesc D = desc[ii];
   const int d = D.d;
   const double Nd = (double)plan[ii].s;
@@ -219,6 +223,7 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
     else hi = mid - 1;
   }
   const int ii = __builtin_amdgcn_readfirstlane(lo);
+  if (plan[ii].status & 8) return;  // PFM_NOT_COMPUTED: the whole wave leaves before any barrier
   const TriDesc D = desc[ii];
   const int d = D.d, p = D.p;
   const int cpw = (p + 63) / 64;

@@ -34,6 +34,7 @@
 #include "kern_band.h"
 
 using namespace pfm;
+static_assert(kNCap == PFM_MAX_STEPS, "the device-side step cap is the documented one");
 
 // phases timed by pfm_profile: LU, solve+combine, squaring, store
 constexpr int kNumPhases = 4;
@@ -352,9 +353,50 @@ int pfm_theta(int f, int m, double tol, double *theta) {
   return PFM_OK;
 }
 
-int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_tri_problem *probs,
-                   pfm_info *info, int force_plan, pfm_stream_t stream_) {
-  if (!ctx) return PFM_ERR_INVALID;
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Tridiagonal and banded actions: host set-up shared by pfm_tri_action and
+// pfm_band_action.  Neither
+// reads anything back from the device: the plan kernels cap N themselves
+// (PFM_NOT_COMPUTED above kNCap), so a call only enqueues work.
+// ---------------------------------------------------------------------------
+
+// Coefficients of a tridiagonal / banded call: a real shift set (m = 4, 5,
+// 8, or 10, the hybrid set of §4.3 for the exponential only), θ(f, m, tol)
+// and the order of the approximation.
+int sparse_terms(pfm_ctx *ctx, const char *what, int f, int m, double tol, TriTerms *T, double *theta,
+                 int *order) {
+  const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
+  if (!ee || (!ep && (f & PFM_PHI1))) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
+  const bool hybrid = ee->poly[0] != 0.0 || ee->poly[1] != 0.0;
+  if (ee->pair || !(ee->nterms == 4 || ee->nterms == 5 || ee->nterms == 8 || (hybrid && ee->nterms == 10)))
+    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the %s path takes the real shift sets (m = 4, 5, 8, 10)", what);
+  if (hybrid && f != PFM_EXP)
+    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the hybrid set is provided for the exponential only");
+  const int rc = pfm_theta(f, m, tol, theta);
+  if (rc) return set_err(ctx, rc, "theta failed");
+  memset(T, 0, sizeof *T);
+  T->nterms = ee->nterms;
+  T->nf = 0;
+  if (f & PFM_EXP) T->fn[T->nf++] = 0;
+  if (f & PFM_PHI1) T->fn[T->nf++] = 1;
+  T->a0e = ee->a0;
+  T->a0p = ep ? ep->a0 : 0.0;
+  for (int k = 0; k < T->nterms; ++k) {
+    T->c[k] = ee->c_re[k];
+    T->we[k] = ee->w_re[k];
+    T->wp[k] = ep ? ep->w_re[k] : 0.0;
+  }
+  T->d1 = ee->poly[0];
+  T->d2 = ee->poly[1];
+  *order = ee->order;
+  return PFM_OK;
+}
+
+int tri_validate(pfm_ctx *ctx, int f, double tol, int batch, const pfm_tri_problem *probs) {
   if (f < 1 || f > 3) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
   if (!(tol > 0.0 && tol < 1.0)) return set_err(ctx, PFM_ERR_INVALID, "tol must lie in (0,1)");
   if (batch < 1 || !probs) return set_err(ctx, PFM_ERR_INVALID, "empty batch");
@@ -371,104 +413,42 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
         misaligned(P.F_phi1))
       return set_err(ctx, PFM_ERR_INVALID, "problem %d: an array is not 8-byte aligned", i);
   }
-  const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
-  if (!ee || (!ep && (f & PFM_PHI1))) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
-  // the hybrid set of §4.3 (m = 10, real shifts, d1 x + d2 x^2): the
-  // exponential only, as the paper gives it
-  const bool hybrid = ee->poly[0] != 0.0 || ee->poly[1] != 0.0;
-  if (ee->pair || !(ee->nterms == 4 || ee->nterms == 5 || ee->nterms == 8 || (hybrid && ee->nterms == 10)))
-    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the tridiagonal path takes the real shift sets (m = 4, 5, 8, 10)");
-  if (hybrid && f != PFM_EXP)
-    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the hybrid set is provided for the exponential only");
-  double theta;
-  int rc = pfm_theta(f, m, tol, &theta);
-  if (rc) return set_err(ctx, rc, "theta failed");
-  hipStream_t stream = (hipStream_t)stream_;
+  return PFM_OK;
+}
 
-  TriTerms T;
-  memset(&T, 0, sizeof T);
-  T.nterms = ee->nterms;
-  T.nf = 0;
-  if (f & PFM_EXP) T.fn[T.nf++] = 0;
-  if (f & PFM_PHI1) T.fn[T.nf++] = 1;
-  T.a0e = ee->a0;
-  T.a0p = ep ? ep->a0 : 0.0;
-  for (int k = 0; k < T.nterms; ++k) {
-    T.c[k] = ee->c_re[k];
-    T.we[k] = ee->w_re[k];
-    T.wp[k] = ep ? ep->w_re[k] : 0.0;
-  }
-  T.d1 = ee->poly[0];
-  T.d2 = ee->poly[1];
-  // workspace: B and the factors, then the vectors and checkpoints
-  std::vector<TriDesc> desc(batch);
-  int64_t dofs = 0;
-  int64_t waves = 0;
-  for (int i = 0; i < batch; ++i) {
-    const pfm_tri_problem &P = probs[i];
-    TriDesc &D = desc[i];
-    memset(&D, 0, sizeof D);
-    D.dl = P.dl;
-    D.dd = P.dd;
-    D.du = P.du;
-    D.V = P.V;
-    D.Fe = P.F_exp;
-    D.Fp = P.F_phi1;
-    D.ldv = P.ldv;
-    D.ldf = P.ldf;
-    D.d = P.d;
-    D.p = P.p;
-    D.theta = theta;
-    const int64_t d = P.d, p = P.p, nch = (d + kTriL - 1) / kTriL;
-    D.b_off = dofs; dofs += align_up(3 * d, 64);
-    D.f_off = dofs; dofs += align_up(3 * d * T.nterms, 64);
-    D.wave0 = (int32_t)waves;
-    D.nwaves = T.nf * (int32_t)((p + 63) / 64);
-    waves += D.nwaves;
-    if (waves > (int64_t)1 << 30) return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
-  }
-  for (int i = 0; i < batch; ++i) {
-    TriDesc &D = desc[i];
-    const int64_t d = D.d, p = D.p, nch = (d + kTriL - 1) / kTriL;
-    D.v_off = dofs; dofs += align_up((int64_t)T.nf * 3 * d * p, 64);
-    D.c_off = dofs; dofs += align_up((int64_t)T.nf * nch * T.nterms * p, 64);
-  }
-  const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
-  const int64_t desc_bytes = align_up((int64_t)batch * sizeof(TriDesc), 256);
-  const int64_t need = dofs * 8 + plan_bytes + desc_bytes + 4096;
-  if (ctx->budget && (size_t)need > ctx->budget)
-    return set_err(ctx, PFM_ERR_BUDGET, "workspace %lld bytes exceeds budget %zu", (long long)need, ctx->budget);
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  if ((size_t)need > ctx->ws_bytes) {
-    if (ctx->ws) {
-      HIP_TRY(ctx, hipStreamSynchronize(stream));
-      HIP_TRY(ctx, hipFree(ctx->ws));
-      ctx->ws = nullptr;
-      ctx->ws_bytes = 0;
-    }
-    HIP_TRY(ctx, hipMalloc(&ctx->ws, (size_t)need));
-    ctx->ws_bytes = (size_t)need;
-  }
-  char *base = (char *)ctx->ws;
-  double *wsd = (double *)base;
-  PlanRec *d_plan = (PlanRec *)(base + dofs * 8);
-  TriDesc *d_desc = (TriDesc *)(base + dofs * 8 + plan_bytes);
+// Descriptor of one tridiagonal instance; its B, factors, vectors and
+// checkpoints take the next doubles of the workspace from *dofs, its waves
+// the next ones of the step launch from *waves.
+void tri_desc(const pfm_tri_problem &P, const TriTerms &T, double theta, int64_t *dofs, int64_t *waves,
+              TriDesc *D) {
+  memset(D, 0, sizeof *D);
+  D->dl = P.dl;
+  D->dd = P.dd;
+  D->du = P.du;
+  D->V = P.V;
+  D->Fe = P.F_exp;
+  D->Fp = P.F_phi1;
+  D->ldv = P.ldv;
+  D->ldf = P.ldf;
+  D->d = P.d;
+  D->p = P.p;
+  D->theta = theta;
+  const int64_t d = P.d, p = P.p, nch = (d + kTriL - 1) / kTriL;
+  D->b_off = *dofs; *dofs += align_up(3 * d, 64);
+  D->f_off = *dofs; *dofs += align_up(3 * d * T.nterms, 64);
+  D->v_off = *dofs; *dofs += align_up((int64_t)T.nf * 3 * d * p, 64);
+  D->c_off = *dofs; *dofs += align_up((int64_t)T.nf * nch * T.nterms * p, 64);
+  D->wave0 = (int32_t)*waves;
+  D->nwaves = T.nf * (int32_t)((p + 63) / 64);
+  *waves += D->nwaves;
+}
 
-  char *pin = nullptr;
-  int rcs = staging(ctx, desc_bytes + plan_bytes, &pin);
-  if (rcs) return rcs;
-  memcpy(pin, desc.data(), batch * sizeof(TriDesc));
-  PlanRec *h_plan = (PlanRec *)(pin + desc_bytes);
-  HIP_TRY(ctx, hipMemcpyAsync(d_desc, pin, batch * sizeof(TriDesc), hipMemcpyHostToDevice, stream));
+// Enqueue a tridiagonal call whose descriptors are (or will be, earlier on
+// the stream) at d_desc: plan, factorisations, the N steps, the info records.
+int tri_launch(pfm_ctx *ctx, const TriTerms &T, int order, int batch, const TriDesc *d_desc, PlanRec *d_plan,
+               double *wsd, int64_t waves, pfm_info *info, int force_plan, hipStream_t stream) {
   hipLaunchKernelGGL(tri_plan_kernel, dim3(batch), dim3(256), 0, stream, d_desc, d_plan, force_plan);
   HIP_TRY(ctx, hipGetLastError());
-  // the step count bounds the run time: read the plans back once
-  HIP_TRY(ctx, hipMemcpyAsync(h_plan, d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(ctx, hipStreamSynchronize(stream));
-  for (int i = 0; i < batch; ++i)
-    if (h_plan[i].s > kNCap)
-      return set_err(ctx, PFM_ERR_UNSUPPORTED, "problem %d: N = %d steps exceeds %d (||A||_1 too large for tol)",
-                     i, h_plan[i].s, kNCap);
   {
     int rcp = prof_harvest(ctx);
     if (rcp) return rcp;
@@ -484,6 +464,7 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
 #define PFM_TRI_STEPS(NT, PHI, HYB)                                                                            \
   hipLaunchKernelGGL((tri_steps_kernel<NT, PHI, HYB>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, batch, \
                      d_plan, T, (const double *)wsd, wsd)
+  const bool hybrid = T.d1 != 0.0 || T.d2 != 0.0;
   const bool tri_phi = T.fn[0] == 1 || (T.nf > 1 && T.fn[1] == 1);
   if (hybrid) {
     PFM_TRI_STEPS(10, false, true);
@@ -503,11 +484,76 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
   prof_mark(ctx, 3, stream);
   if (info)
     hipLaunchKernelGGL(tri_info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_desc, d_plan,
-                       (InfoRec *)info, batch, ee->order);
+                       (InfoRec *)info, batch, order);
   prof_mark(ctx, 4, stream);
   if (ctx->prof) ctx->prof_pending = true;
   HIP_TRY(ctx, hipGetLastError());
   return PFM_OK;
+}
+
+// Grow the context's workspace to at least `need` bytes.
+int ws_reserve(pfm_ctx *ctx, int64_t need, hipStream_t stream) {
+  if (ctx->budget && (size_t)need > ctx->budget)
+    return set_err(ctx, PFM_ERR_BUDGET, "workspace %lld bytes exceeds budget %zu", (long long)need, ctx->budget);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((size_t)need > ctx->ws_bytes) {
+    if (ctx->ws) {
+      HIP_TRY(ctx, hipStreamSynchronize(stream));
+      HIP_TRY(ctx, hipFree(ctx->ws));
+      ctx->ws = nullptr;
+      ctx->ws_bytes = 0;
+    }
+    HIP_TRY(ctx, hipMalloc(&ctx->ws, (size_t)need));
+    ctx->ws_bytes = (size_t)need;
+  }
+  return PFM_OK;
+}
+
+// Copy `bytes` of descriptors to d_dst through the pinned staging area; the
+// staging is reused only after this upload has executed.
+int upload_desc(pfm_ctx *ctx, void *d_dst, const void *src, size_t bytes, hipStream_t stream) {
+  char *pin = nullptr;
+  int rcs = staging(ctx, bytes, &pin);
+  if (rcs) return rcs;
+  memcpy(pin, src, bytes);
+  HIP_TRY(ctx, hipMemcpyAsync(d_dst, pin, bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
+  ctx->pin_pending = true;
+  return PFM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_tri_problem *probs,
+                   pfm_info *info, int force_plan, pfm_stream_t stream_) {
+  if (!ctx) return PFM_ERR_INVALID;
+  int rc = tri_validate(ctx, f, tol, batch, probs);
+  if (rc) return rc;
+  TriTerms T;
+  double theta;
+  int order;
+  rc = sparse_terms(ctx, "tridiagonal", f, m, tol, &T, &theta, &order);
+  if (rc) return rc;
+  hipStream_t stream = (hipStream_t)stream_;
+  std::vector<TriDesc> desc(batch);
+  int64_t dofs = 0, waves = 0;
+  for (int i = 0; i < batch; ++i) {
+    tri_desc(probs[i], T, theta, &dofs, &waves, &desc[i]);
+    if (waves > (int64_t)1 << 30) return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
+  }
+  const int64_t desc_bytes = align_up((int64_t)batch * sizeof(TriDesc), 256);
+  const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
+  rc = ws_reserve(ctx, desc_bytes + plan_bytes + dofs * 8, stream);
+  if (rc) return rc;
+  char *base = (char *)ctx->ws;
+  TriDesc *d_desc = (TriDesc *)base;
+  PlanRec *d_plan = (PlanRec *)(base + desc_bytes);
+  double *wsd = (double *)(base + desc_bytes + plan_bytes);
+  rc = upload_desc(ctx, d_desc, desc.data(), batch * sizeof(TriDesc), stream);
+  if (rc) return rc;
+  return tri_launch(ctx, T, order, batch, d_desc, d_plan, wsd, waves, info, force_plan, stream);
 }
 
 int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, const pfm_band_problem *probs,
@@ -529,33 +575,12 @@ int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, co
     if (misaligned(P.bands) || misaligned(P.V) || misaligned(P.F_exp) || misaligned(P.F_phi1))
       return set_err(ctx, PFM_ERR_INVALID, "problem %d: an array is not 8-byte aligned", i);
   }
-  const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
-  if (!ee || (!ep && (f & PFM_PHI1))) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
-  const bool hybrid = ee->poly[0] != 0.0 || ee->poly[1] != 0.0;
-  if (ee->pair || !(ee->nterms == 4 || ee->nterms == 5 || ee->nterms == 8 || (hybrid && ee->nterms == 10)))
-    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the banded path takes the real shift sets (m = 4, 5, 8, 10)");
-  if (hybrid && f != PFM_EXP)
-    return set_err(ctx, PFM_ERR_UNSUPPORTED, "the hybrid set is provided for the exponential only");
-  double theta;
-  int rc = pfm_theta(f, m, tol, &theta);
-  if (rc) return set_err(ctx, rc, "theta failed");
-  hipStream_t stream = (hipStream_t)stream_;
-
   TriTerms T;
-  memset(&T, 0, sizeof T);
-  T.nterms = ee->nterms;
-  T.nf = 0;
-  if (f & PFM_EXP) T.fn[T.nf++] = 0;
-  if (f & PFM_PHI1) T.fn[T.nf++] = 1;
-  T.a0e = ee->a0;
-  T.a0p = ep ? ep->a0 : 0.0;
-  for (int k = 0; k < T.nterms; ++k) {
-    T.c[k] = ee->c_re[k];
-    T.we[k] = ee->w_re[k];
-    T.wp[k] = ep ? ep->w_re[k] : 0.0;
-  }
-  T.d1 = ee->poly[0];
-  T.d2 = ee->poly[1];
+  double theta;
+  int order;
+  int rc = sparse_terms(ctx, "banded", f, m, tol, &T, &theta, &order);
+  if (rc) return rc;
+  hipStream_t stream = (hipStream_t)stream_;
   std::vector<BandDesc> desc(batch);
   int64_t dofs = 0;
   int64_t waves = 0;
@@ -583,42 +608,18 @@ int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, co
     waves += D.nwaves;
     if (waves > (int64_t)1 << 30) return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
   }
-  const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
   const int64_t desc_bytes = align_up((int64_t)batch * sizeof(BandDesc), 256);
-  const int64_t need = dofs * 8 + plan_bytes + desc_bytes + 4096;
-  if (ctx->budget && (size_t)need > ctx->budget)
-    return set_err(ctx, PFM_ERR_BUDGET, "workspace %lld bytes exceeds budget %zu", (long long)need, ctx->budget);
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  if ((size_t)need > ctx->ws_bytes) {
-    if (ctx->ws) {
-      HIP_TRY(ctx, hipStreamSynchronize(stream));
-      HIP_TRY(ctx, hipFree(ctx->ws));
-      ctx->ws = nullptr;
-      ctx->ws_bytes = 0;
-    }
-    HIP_TRY(ctx, hipMalloc(&ctx->ws, (size_t)need));
-    ctx->ws_bytes = (size_t)need;
-  }
+  const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
+  rc = ws_reserve(ctx, desc_bytes + plan_bytes + dofs * 8, stream);
+  if (rc) return rc;
   char *base = (char *)ctx->ws;
-  double *wsd = (double *)base;
-  PlanRec *d_plan = (PlanRec *)(base + dofs * 8);
-  BandDesc *d_desc = (BandDesc *)(base + dofs * 8 + plan_bytes);
-
-  char *pin = nullptr;
-  int rcs = staging(ctx, desc_bytes + plan_bytes, &pin);
-  if (rcs) return rcs;
-  memcpy(pin, desc.data(), batch * sizeof(BandDesc));
-  PlanRec *h_plan = (PlanRec *)(pin + desc_bytes);
-  HIP_TRY(ctx, hipMemcpyAsync(d_desc, pin, batch * sizeof(BandDesc), hipMemcpyHostToDevice, stream));
+  BandDesc *d_desc = (BandDesc *)base;
+  PlanRec *d_plan = (PlanRec *)(base + desc_bytes);
+  double *wsd = (double *)(base + desc_bytes + plan_bytes);
+  rc = upload_desc(ctx, d_desc, desc.data(), batch * sizeof(BandDesc), stream);
+  if (rc) return rc;
   hipLaunchKernelGGL(band_plan_kernel, dim3(batch), dim3(256), 0, stream, d_desc, d_plan, force_plan);
   HIP_TRY(ctx, hipGetLastError());
-  // the step count bounds the run time: read the plans back once
-  HIP_TRY(ctx, hipMemcpyAsync(h_plan, d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(ctx, hipStreamSynchronize(stream));
-  for (int i = 0; i < batch; ++i)
-    if (h_plan[i].s > kNCap)
-      return set_err(ctx, PFM_ERR_UNSUPPORTED, "problem %d: N = %d steps exceeds %d (||A||_1 too large for tol)",
-                     i, h_plan[i].s, kNCap);
   {
     int rcp = prof_harvest(ctx);
     if (rcp) return rcp;
@@ -654,7 +655,7 @@ int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, co
   prof_mark(ctx, 3, stream);
   if (info)
     hipLaunchKernelGGL(band_info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_desc, d_plan,
-                       (InfoRec *)info, batch, ee->order);
+                       (InfoRec *)info, batch, order);
   prof_mark(ctx, 4, stream);
   if (ctx->prof) ctx->prof_pending = true;
   HIP_TRY(ctx, hipGetLastError());

@@ -31,6 +31,8 @@ ERR_BUDGET = -3
 ERR_HIP = -4
 ERR_DEVICE = -5
 
+MAX_STEPS = 1 << 20                 # PFM_MAX_STEPS: more action steps are PFM_NOT_COMPUTED
+
 SINGULAR_SHIFT = 1
 NONFINITE = 2
 IR_STALL = 4

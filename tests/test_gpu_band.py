@@ -158,7 +158,7 @@ def _hybrid_bar(N):
     return 2 * 16 * N * amp * 2.0 ** -53
 
 
-@pytest.mark.parametrize("b", [2, 3])
+@pytest.mark.parametrize("b", [1, 2, 3, 4])
 def test_hybrid_r10_prime(torch_dev, b):
     """R10' (the hybrid set of §4.3, exp) on banded A: P = d1 B y + d2 B^2 y
     formed in the forward pass, against the banded oracle."""
@@ -168,12 +168,15 @@ def test_hybrid_r10_prime(torch_dev, b):
     vecs = [wl.vectors(d, p, wl.SEED_BASE + 995 + j) for j, (d, p) in enumerate(shapes)]
     _say("case band hybrid m=10 b=%d" % b)
     res, info = _run(torch, dev, bands, vecs, b, ("exp",), 10, 1e-12)
+    worst, worst_rel = 0.0, 0.0
     for i in range(len(shapes)):
         N = int(info[i]["plan"])
         own = _own(bands[i], b, vecs[i], ("exp",), 10, 1e-12, N)
         assert info[i]["route"] == 4 and info[i]["status"] == 0 and info[i]["order"] == 10
         err = me.rel_fro(res["exp"][i].cpu().numpy(), own["exp"])
+        worst, worst_rel = max(worst, err), max(worst_rel, err / _hybrid_bar(N))
         assert err <= _hybrid_bar(N), (i, N, err)
+    _say("  worst rel. error %.3e (%.2e of the bar)" % (worst, worst_rel))
 
 
 def test_errors(torch_dev):
@@ -268,3 +271,19 @@ def test_nonfinite_and_singular(torch_dev):
     res, info = _run(torch, dev, [y], [wl.vectors(6, 1, wl.SEED_BASE + 1032)], b, ("exp",), 10, 1e-12, force_plan=1)
     assert info[0]["status"] & pfm.SINGULAR_SHIFT
     assert info[0]["bad_shift"] == k[0]
+
+
+def test_step_cap_not_computed(torch_dev):
+    """A forced N above PFM_MAX_STEPS: PFM_NOT_COMPUTED from the plan kernel,
+    outputs untouched."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    bands = wl.band_gaussian_batch(1, 30, 2, 1.0, 2.0, wl.SEED_BASE + 690)[0]
+    V = torch.from_numpy(wl.vectors(30, 2, wl.SEED_BASE + 691)).to(dev)
+    out = {"exp": [torch.full_like(V, 7.25)]}
+    _say("case band step cap")
+    res, info = pfm.band_action([torch.from_numpy(bands).to(dev)], [V], 2, ("exp",), m=8, tol=1e-12,
+                                force_plan=pfm.MAX_STEPS + 1, out=out)
+    torch.cuda.synchronize()
+    assert info[0]["status"] & pfm.NOT_COMPUTED and info[0]["plan"] == pfm.MAX_STEPS + 1
+    assert torch.all(res["exp"][0] == 7.25)

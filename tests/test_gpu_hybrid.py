@@ -6,9 +6,9 @@ Bar, derived from the arithmetic: both sides evaluate the same r(B) in
 binary64 in different orders.  Per scaled step the round-off form's result
 carries rounding of about sum_k |w_k| ||(I - c_k B)^{-1} B|| u
 <= sum_k |w_k| θ / (1 - max|c_k| θ) u, times sqrt(n) for the length-n inner
-products (with a factor 8 of slack for the few roundings per element), and the
-s squarings amplify a relative error at most 2^s-fold; the two sides' errors
-add.  With sum |w_k| ~ 9.7e3 (the cancellation the paper warns of for this
+products (rounding errors of independent signs add like a random walk: the
+probabilistic bound of Higham and Mary, 2019), and the s squarings amplify a
+relative error at most 2^s-fold; the two sides' errors add.  With sum |w_k| ~ 9.7e3 (the cancellation the paper warns of for this
 set) this is far above the 1e-12 bar of the partial-fraction sets, which is
 why it is stated here; a wrong term (a dropped d1 B or d2 B^2, a wrong sign)
 misses it by many orders of magnitude."""
@@ -45,7 +45,7 @@ def _bar(n, s, theta):
     _, terms = co.roundoff_terms("exp", 10)
     sw = sum(abs(w) for _, w, _ in terms)
     cmax = max(abs(c) for c, _, _ in terms)
-    return 2 * 2 ** s * 8 * math.sqrt(n) * sw * theta / (1 - cmax * theta) * U
+    return 2 * 2 ** s * math.sqrt(n) * sw * theta / (1 - cmax * theta) * U
 
 
 def _run(torch, dev, mats, tol=1e-12, force_plan=-1, route=None):

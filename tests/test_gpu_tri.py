@@ -244,7 +244,7 @@ def test_hybrid_r10_prime(torch_dev):
     vecs.append(wl.vectors(1000, 3, wl.SEED_BASE + 730))
     _say("case tri hybrid m=10")
     res, info = _run(torch, dev, tris, vecs, ("exp",), 10, 1e-12)
-    worst = 0.0
+    worst, worst_abs = 0.0, 0.0
     for i, ((dl, dd, du), V) in enumerate(zip(tris, vecs)):
         N = int(info[i]["plan"])
         own = bd.tri_action(dl, dd, du, V, ("exp",), 10, 1e-12)
@@ -257,10 +257,32 @@ def test_hybrid_r10_prime(torch_dev):
         err = me.rel_fro(res["exp"][i].cpu().numpy(), own["exp"])
         bar = _hybrid_bar(N)
         worst = max(worst, err / bar)
+        worst_abs = max(worst_abs, err)
         assert err <= bar, (i, V.shape, N, err, bar)
-    _say("  worst err / bar %.2e" % worst)
+    _say("  worst err / bar %.2e, worst rel. error %.3e" % (worst, worst_abs))
     dl, dd, du = [_to(torch, dev, x) for x in tris[0]]
     V = _to(torch, dev, vecs[0])
     with pytest.raises(pfm.PfmError) as e:
         pfm.tri_action([dl], [dd], [du], [V], ("phi1",), m=10)
     assert e.value.code == pfm.ERR_UNSUPPORTED
+
+
+def test_step_cap_not_computed(torch_dev):
+    """A forced N above PFM_MAX_STEPS: the plan kernel flags the instance
+    PFM_NOT_COMPUTED on the device (nothing is read back) and no kernel
+    writes its outputs; the other instance of the call is computed."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    tris = wl.tri_gaussian_batch(2, 24, 1.0, 2.0, wl.SEED_BASE + 660)
+    vecs = [wl.vectors(24, 3, wl.SEED_BASE + 661 + i) for i in range(2)]
+    dl = [_to(torch, dev, t[0]) for t in tris]
+    dd = [_to(torch, dev, t[1]) for t in tris]
+    du = [_to(torch, dev, t[2]) for t in tris]
+    V = [_to(torch, dev, v) for v in vecs]
+    out = {"exp": [torch.full_like(v, 7.25) for v in V]}
+    _say("case tri step cap")
+    res, info = pfm.tri_action(dl, dd, du, V, ("exp",), m=8, tol=1e-12, force_plan=pfm.MAX_STEPS + 1, out=out)
+    torch.cuda.synchronize()
+    for i in range(2):
+        assert info[i]["status"] & pfm.NOT_COMPUTED and info[i]["plan"] == pfm.MAX_STEPS + 1
+        assert torch.all(res["exp"][i] == 7.25)
