@@ -252,6 +252,26 @@ typedef struct {
 int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_tri_problem *probs,
                    pfm_info *info, int force_plan, pfm_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as pfm_tri_action, with the same arguments, results and
+ * per-instance status, but every scratch byte (descriptors, plans, B and the
+ * factors, step vectors, checkpoints) lives in one fixed device array of
+ * PFM_NOALLOC_MAX_BYTES that the library holds on each device from the
+ * first pfm_create on it until the process ends.  The call allocates
+ * nothing (no hipMalloc, hipFree or pinned host memory; the descriptors are
+ * copied from a static host array).  Returns PFM_ERR_BUDGET, with nothing
+ * enqueued, when batch > PFM_NOALLOC_MAX_BATCH or the call needs more than
+ * PFM_NOALLOC_MAX_BYTES (about 8 d (3 + 3 m + n_f (3 + m / 8) p) bytes per
+ * instance plus 256 per instance for its descriptor and plan).  All calls on
+ * one device share that array, and each call overwrites what the previous
+ * one left there: calls that overlap on one device (two streams, or two
+ * threads) race and must be serialised by the caller. */
+#define PFM_NOALLOC_MAX_BYTES (64u << 20)
+#define PFM_NOALLOC_MAX_BATCH 1024
+int pfm_tri_action_noalloc(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_tri_problem *probs,
+                           pfm_info *info, int force_plan, pfm_stream_t stream);
+
 /* ------------------------------------------------------------------------
  * Banded A (§2.1 and §5 name the pentadiagonal case beside the tridiagonal
  * one): the action f(A)V for real A with half-bandwidth b (b = 2:

@@ -11,6 +11,7 @@
 #include <array>
 #include <cstdarg>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -80,6 +81,17 @@ struct pfm_ctx {
   int cur_launches[kNumPhases] = {};
   std::string err;
 };
+
+// ---------------------------------------------------------------------------
+// Allocation-free scratch.  pfm_tri_action_noalloc keeps its descriptors,
+// plans, factors, vectors and checkpoints in this fixed array instead of the
+// context's workspace.  The name is a host-side stand-in, never a device
+// address: host code uses only the address hipGetSymbolAddress returned for
+// the device (g_scratch_dev), looked up once per device by pfm_create with
+// that device current.  Every call on a device shares that device's copy.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)PFM_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace {
 
@@ -194,6 +206,26 @@ inline void prof_mark(pfm_ctx *ctx, int idx, hipStream_t stream) {
   if (ctx->prof) (void)hipEventRecord(ctx->pev[idx], stream);
 }
 
+// The device addresses of `scratch`, one per device (see above).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;             // guards the table and the host descriptor staging below
+char *g_scratch_dev[kMaxDevices] = {};
+// host-side descriptors of the allocation-free call (static, so that no call
+// allocates); hipMemcpyAsync from this pageable memory stages it before it
+// returns, so the next call may overwrite it
+TriDesc g_noalloc_desc[PFM_NOALLOC_MAX_BATCH];
+
+// Resolve the device address of `scratch` for the current device.
+int scratch_resolve(int device) {
+  if (device < 0 || device >= kMaxDevices) return PFM_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return PFM_OK;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PFM_ERR_HIP;
+  g_scratch_dev[device] = (char *)ptr;
+  return PFM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -276,6 +308,9 @@ int pfm_create(pfm_ctx **out, int device, size_t budget) {
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) { delete ctx; return PFM_ERR_HIP; }
   ctx->num_cu = prop.multiProcessorCount;
+  // library set-up for this device: the address of its allocation-free
+  // scratch array (pfm_tri_action_noalloc), with the device current
+  if (scratch_resolve(device) != PFM_OK) { delete ctx; return PFM_ERR_HIP; }
   e = hipMalloc(&ctx->d_err, 64);
   if (e != hipSuccess) { delete ctx; return PFM_ERR_HIP; }
   e = hipMemset(ctx->d_err, 0, 64);
@@ -358,8 +393,8 @@ int pfm_theta(int f, int m, double tol, double *theta) {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Tridiagonal and banded actions: host set-up shared by pfm_tri_action and
-// pfm_band_action.  Neither
+// Tridiagonal and banded actions: host set-up shared by pfm_tri_action,
+// pfm_band_action and the allocation-free pfm_tri_action_noalloc.  Neither
 // reads anything back from the device: the plan kernels cap N themselves
 // (PFM_NOT_COMPUTED above kNCap), so a call only enqueues work.
 // ---------------------------------------------------------------------------
@@ -553,6 +588,43 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
   double *wsd = (double *)(base + desc_bytes + plan_bytes);
   rc = upload_desc(ctx, d_desc, desc.data(), batch * sizeof(TriDesc), stream);
   if (rc) return rc;
+  return tri_launch(ctx, T, order, batch, d_desc, d_plan, wsd, waves, info, force_plan, stream);
+}
+
+int pfm_tri_action_noalloc(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_tri_problem *probs,
+                           pfm_info *info, int force_plan, pfm_stream_t stream_) {
+  if (!ctx) return PFM_ERR_INVALID;
+  int rc = tri_validate(ctx, f, tol, batch, probs);
+  if (rc) return rc;
+  if (batch > PFM_NOALLOC_MAX_BATCH)
+    return set_err(ctx, PFM_ERR_BUDGET, "batch %d exceeds the allocation-free limit of %d instances", batch,
+                   PFM_NOALLOC_MAX_BATCH);
+  TriTerms T;
+  double theta;
+  int order;
+  rc = sparse_terms(ctx, "tridiagonal", f, m, tol, &T, &theta, &order);
+  if (rc) return rc;
+  hipStream_t stream = (hipStream_t)stream_;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  char *base = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_scratch_dev[ctx->device] : nullptr;
+  if (!base) return set_err(ctx, PFM_ERR_HIP, "the scratch array of device %d was not resolved", ctx->device);
+  const int64_t desc_bytes = align_up((int64_t)batch * sizeof(TriDesc), 256);
+  const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
+  int64_t dofs = 0, waves = 0;
+  for (int i = 0; i < batch; ++i) {
+    tri_desc(probs[i], T, theta, &dofs, &waves, &g_noalloc_desc[i]);
+    if (waves > (int64_t)1 << 30) return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
+  }
+  const int64_t need = desc_bytes + plan_bytes + dofs * 8;
+  if ((size_t)need > kScratchBytes)
+    return set_err(ctx, PFM_ERR_BUDGET,
+                   "the call needs %lld bytes of scratch, more than the allocation-free limit of %zu",
+                   (long long)need, kScratchBytes);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  TriDesc *d_desc = (TriDesc *)base;
+  PlanRec *d_plan = (PlanRec *)(base + desc_bytes);
+  double *wsd = (double *)(base + desc_bytes + plan_bytes);
+  HIP_TRY(ctx, hipMemcpyAsync(d_desc, g_noalloc_desc, batch * sizeof(TriDesc), hipMemcpyHostToDevice, stream));
   return tri_launch(ctx, T, order, batch, d_desc, d_plan, wsd, waves, info, force_plan, stream);
 }
 

@@ -32,6 +32,8 @@ ERR_HIP = -4
 ERR_DEVICE = -5
 
 MAX_STEPS = 1 << 20                 # PFM_MAX_STEPS: more action steps are PFM_NOT_COMPUTED
+NOALLOC_MAX_BYTES = 64 << 20        # PFM_NOALLOC_MAX_BYTES
+NOALLOC_MAX_BATCH = 1024            # PFM_NOALLOC_MAX_BATCH
 
 SINGULAR_SHIFT = 1
 NONFINITE = 2
@@ -112,6 +114,7 @@ def lib():
         L.pfm_srv_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p, dp]
         L.pfm_profile_read.argtypes = [vp, dp, ip, ip]
         L.pfm_tri_action.argtypes = [vp, i32, i32, dbl, i32, ctypes.POINTER(TriProblem), vp, i32, vp]
+        L.pfm_tri_action_noalloc.argtypes = [vp, i32, i32, dbl, i32, ctypes.POINTER(TriProblem), vp, i32, vp]
         L.pfm_band_action.argtypes = [vp, i32, i32, dbl, i32, i32, ctypes.POINTER(BandProblem), vp, i32, vp]
         _lib = L
     return _lib
@@ -279,12 +282,13 @@ class Context:
                                       force_plan, _stream_ptr(stream))
 
 
-    def tri_action(self, probs, f, m, tol, info=None, force_plan=-1, stream=None):
-        """Raw call of pfm_tri_action: ``probs`` is a list of TriProblem.
-        Returns the C return code."""
+    def tri_action(self, probs, f, m, tol, info=None, force_plan=-1, stream=None, noalloc=False):
+        """Raw call of pfm_tri_action (``noalloc``: pfm_tri_action_noalloc):
+        ``probs`` is a list of TriProblem.  Returns the C return code."""
         arr = (TriProblem * len(probs))(*probs)
         iptr = ctypes.c_void_p(info.data_ptr()) if info is not None else ctypes.c_void_p()
-        return lib().pfm_tri_action(self._h, f, m, tol, len(probs), arr, iptr, force_plan, _stream_ptr(stream))
+        fn = lib().pfm_tri_action_noalloc if noalloc else lib().pfm_tri_action
+        return fn(self._h, f, m, tol, len(probs), arr, iptr, force_plan, _stream_ptr(stream))
 
     def band_action(self, probs, f, m, tol, b, info=None, force_plan=-1, stream=None):
         """Raw call of pfm_band_action: ``probs`` is a list of BandProblem.
@@ -438,11 +442,14 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx
 
 
 def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=-1, ctx=None, stream=None,
-               out=None, info_out=None):
+               out=None, info_out=None, noalloc=False):
     """f(A) V for tridiagonal A (float64): ``dl``, ``dd``, ``du`` are lists of
     CUDA tensors (sub-, main and superdiagonal of each instance, lengths
     d - 1, d, d - 1) and ``V`` a list of (d, p) CUDA tensors with unit
-    column stride.  Returns (results, info) like ``action``."""
+    column stride.  Returns (results, info) like ``action``.  ``noalloc``
+    calls the allocation-free entry point (the library's fixed scratch
+    array; pass ``out`` and ``info_out`` as well for a call in which nothing
+    is allocated)."""
     import torch
     dls, dds, dus, vecs = list(dl), list(dd), list(du), list(V)
     if not (len(dls) == len(dds) == len(dus) == len(vecs)):
@@ -474,7 +481,7 @@ def tri_action(dl, dd, du, V, funcs=("exp",), m=8, tol=1e-12, force_plan=-1, ctx
                                 fp.data_ptr() if fp is not None else None))
     ctx = ctx or default_context(vecs[0].device.index or 0)
     info = _info_buffer(info_out, len(vecs), vecs[0].device)
-    rc = ctx.tri_action(probs, fm, m, tol, info, force_plan, stream)
+    rc = ctx.tri_action(probs, fm, m, tol, info, force_plan, stream, noalloc=noalloc)
     if rc:
         raise PfmError(rc, ctx.last_error())
     return out, _Info(info)
