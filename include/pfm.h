@@ -17,23 +17,24 @@
  * ---------------------------------------
  * - Return value: PFM_OK (0) on success; a negative PFM_ERR_* code means that
  *   nothing was enqueued and outputs are untouched (text via pfm_last_error).
- *   A positive return k from pfm_eval_batched means the batch ran and k
- *   instances carry a nonzero per-instance status; all other instances are
- *   valid.  Because results are produced asynchronously, the positive count
- *   is only known after the stream synchronises: pfm_eval_batched itself
- *   returns PFM_OK and the caller reads pfm_info.status.
+ *   Per-instance outcomes (a singular shift, non-finite input, an instance
+ *   not computed) are decided on the device, after the call has returned:
+ *   the calls return PFM_OK and the caller reads pfm_info.status once the
+ *   stream has synchronised.
  * - Matrices are row-major with a leading dimension counted in elements
  *   (ld >= n).  Complex data is interleaved (re, im) binary64, the layout of
  *   C99 double _Complex and torch.complex128.
  * - Device pointers are HIP device pointers on the context's device.  The
  *   caller owns every buffer it passes; the library never frees them and never
  *   writes to inputs.  The context owns all workspace.
- * - All device work is enqueued on the caller's stream.  pfm_eval_batched
- *   waits once on that stream, right after the norm/plan kernel, to read the
- *   per-instance plans (it sizes the squaring and step launches and routes
- *   each instance from them); the rest of the call is asynchronous.  One
- *   context must not be used from two streams at the same time (its
- *   workspace is shared between calls).
+ * - All device work is enqueued on the caller's stream and the calls return
+ *   without waiting for it: the norm, the plan (s or N), the route of every
+ *   instance and the number of squarings are decided by kernels, and no
+ *   result is read back (the one exception: an action on an instance above
+ *   512, complex above 256, whose steps are launched one by one, reads its
+ *   step count back).  A call waits on the stream only to grow the
+ *   workspace.  One context must not be used from two streams at the same
+ *   time (its workspace is shared between calls).
  */
 #ifndef PFM_H
 #define PFM_H
@@ -77,7 +78,7 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
 #define PFM_ERR_UNSUPPORTED (-2) /* (f, m, dtype, prec) combination not provided */
 #define PFM_ERR_BUDGET (-3)      /* workspace would exceed the context's HBM budget */
 #define PFM_ERR_HIP (-4)         /* HIP runtime error */
-#define PFM_ERR_DEVICE (-5)      /* a device-side wait timed out (reported by pfm_check) */
+#define PFM_ERR_DEVICE (-5)      /* a bounded device-side wait of the squaring queue gave up (pfm_check) */
 
 /* per-instance status bits (pfm_info.status) */
 #define PFM_SINGULAR_SHIFT 1 /* an exact zero pivot in I - c_k B; bad_shift = k */
@@ -89,8 +90,10 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
                                 I - c_k B not diagonally dominant enough for
                                 the large-instance route (|c_k| ||B||_1 <= 1/2;
                                 the planner's B always is, a forced plan may
-                                not); or, on the tridiagonal and banded paths,
-                                more than PFM_MAX_STEPS steps */
+                                not); the hybrid set (m = 10) on an instance
+                                that is not (only a forced plan or non-finite
+                                input can do that); more than PFM_MAX_SQUARINGS
+                                squarings; or more than PFM_MAX_STEPS steps */
 #define PFM_OUT_OF_RANGE 16  /* PFM_LOG1M: ||A||_1 > θ, so the tolerance is not
                                 guaranteed (the result is still computed) */
 
@@ -169,6 +172,10 @@ int pfm_poly(int f, int m, double *d1, double *d2);
  * f = PFM_EXP|PFM_PHI1 the minimum of the two. */
 int pfm_theta(int f, int m, double tol, double *theta);
 
+/* Largest squaring count s of the full-matrix path (above it the instance is
+ * PFM_NOT_COMPUTED). */
+#define PFM_MAX_SQUARINGS 1000
+
 /* Evaluate a batch of problems.
  *   f          PFM_EXP, PFM_PHI1 or both
  *   m          number of shifted solves: 1, 4, 5 or 8; or 10, the hybrid set
@@ -184,7 +191,14 @@ int pfm_theta(int f, int m, double tol, double *theta);
  *   force_plan -1: planner (s or N from ||A||_1 and θ).  >= 0: use this s
  *              (full matrix) or N >= 1 (action) for every instance (tests).
  *   stream     HIP stream to enqueue on
- * A problem with p == 0 and one with p >= 1 may not be mixed in one call. */
+ * A problem with p == 0 and one with p >= 1 may not be mixed in one call.
+ * The call may be recorded into the caller's own stream capture (a hipGraph)
+ * when it repeats the previous call on the same context exactly (same
+ * arguments, problems and pointers) and that call ran eagerly: then it
+ * allocates nothing, copies nothing from the host and only launches
+ * kernels; otherwise, inside a capture, it returns PFM_ERR_INVALID with
+ * nothing recorded.  A captured call stays valid while no other call on the
+ * context runs (they share the workspace). */
 int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec,
                      int dtype, int batch, const pfm_problem *probs,
                      pfm_info *info, int force_plan, pfm_stream_t stream);
@@ -318,7 +332,9 @@ int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, co
                     pfm_info *info, int force_plan, pfm_stream_t stream);
 
 /* Block until `stream` is idle and report device-side failures of previous
- * calls on this context (PFM_ERR_DEVICE if a bounded device wait timed out). */
+ * calls on this context: PFM_ERR_DEVICE if a bounded wait of the persistent
+ * squaring queue gave up (its results are then not to be trusted); the flag
+ * is cleared. */
 int pfm_check(pfm_ctx *ctx, pfm_stream_t stream);
 
 /* Phase timing.  enable != 0: every later pfm_eval_batched on this context
@@ -342,6 +358,18 @@ int pfm_profile(pfm_ctx *ctx, int enable);
  * on the next pfm_eval_batched call. */
 int pfm_set_route(pfm_ctx *ctx, int route);
 
+/* Squaring schedule of the full-matrix path (§1: s squarings per instance,
+ * s decided on the device).  The first direct_levels levels are one launch
+ * each over every instance's product tiles (a tile of an instance with fewer
+ * squarings returns at once); the levels beyond them, however many, run in
+ * one persistent launch that takes (level, instance, tile) tasks from a
+ * queue built on the device, each task waiting (bounded) until the tiles of
+ * its instance's previous level are done.  Default 8; 0 runs every level
+ * from the queue.  0 <= direct_levels <= PFM_MAX_SQUARINGS (PFM_ERR_INVALID
+ * otherwise); takes effect on the next call, and a tuned schedule
+ * (pfm_tune) no longer overrides it. */
+int pfm_set_schedule(pfm_ctx *ctx, int direct_levels);
+
 /* Totals since the last pfm_profile call: ms[4] milliseconds per phase,
  * launches[4] kernel launches per phase (may be NULL), *calls the number of
  * timed calls (may be NULL).  Waits for the last timed call to finish. */
@@ -361,15 +389,21 @@ int pfm_set_graphs(pfm_ctx *ctx, int enable);
 int pfm_graph_stats(pfm_ctx *ctx, int *captures, int *replays);
 
 /* Autotuner.  Runs the batch (same arguments as pfm_eval_batched, outputs
- * written) under each route policy that can make a difference for it --
- * real full matrices: single-workgroup Gauss-Jordan inverses vs the pivoting
- * LU route; action or complex: the multi-workgroup route for sizes above
- * 128 vs only above 512 -- timing `reps` calls of each with hipEvents on
- * `stream` after one warm-up call, and keeps the fastest for the batch's key
- * (mode, complex, precision, size bucket of the largest instance, batch-size
- * bucket).  Later calls with the same key use it (an explicit
- * PFM_ROUTE_LU still wins).  Synchronises the stream.  *policy and *ms (may
- * be NULL) receive the choice (0..3) and its time per call. */
+ * written) under each policy that can make a difference for it, timing
+ * `reps` calls of each with hipEvents on `stream` after one warm-up call,
+ * and keeps the fastest for the batch's key (mode, complex, precision, size
+ * bucket of the largest instance, batch-size bucket).  A policy is
+ * route + 4 (schedule + 2 tile):
+ *   route    real full matrices: 0 single-workgroup Gauss-Jordan inverses
+ *            where dominant, 1 the pivoting LU route; action or complex: 0
+ *            the multi-workgroup route for sizes above 128, 2 only above 512;
+ *   schedule full matrices: 0 the first 8 squaring levels launched one by
+ *            one, 1 every level from the persistent queue (pfm_set_schedule);
+ *   tile     full matrices: 0 128 x 128 product tiles from npad 256 on, 1
+ *            64 x 64 tiles for every size up to 512.
+ * Later calls with the same key use it (an explicit PFM_ROUTE_LU or
+ * pfm_set_schedule still wins).  Synchronises the stream.  *policy and *ms
+ * (may be NULL) receive the choice (0..15) and its time per call. */
 int pfm_tune(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype, int batch, const pfm_problem *probs,
              int reps, pfm_stream_t stream, int *policy, double *ms);
 

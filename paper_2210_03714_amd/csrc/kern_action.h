@@ -73,6 +73,7 @@ action_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ili
   xcd_map(blockIdx.x, nslab, slot, sl);
   if (slot >= nlist) return;
   const int ii = ilist[slot];
+  if (!on_route(plan[ii], 0)) return;  // not on the pivoting LU route
   const InstDesc D = inst[ii];
   const int n = D.n, np = D.npad, p = D.p;
   if (np > NPMAX || (np & 15) || n > np || n < 1) return;  // sizes the host never sends

@@ -142,6 +142,7 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   xcd_map(blockIdx.x, T.nterms, slot, k);
   if (slot >= nlist) return;
   const int ii = ilist[slot];
+  if (!on_route(plan[ii], route_val)) return;  // the device chose another route (uniform per workgroup)
   const InstDesc D = inst[ii];
   const int np = D.npad;
   if (np > NPMAX || (np % kGJ) || D.n > np || D.n < 1) return;  // never sent
@@ -150,7 +151,6 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   const int ar = arow(i16);
   double *W = wsd + D.fac_off + (int64_t)k * np * np;  // 32-bit offsets below: npad <= 512
   const int nJ = np / kGJ;
-  if (route_val >= 0 && k == 0 && t == 0) plan[ii].route = route_val;
 
   const ShiftedA<ACT> M0{D.A, D.lda, D.n, T.c_re[k], ldexp(T.c_re[k], -plan[ii].s), (double)plan[ii].s};
 
@@ -314,6 +314,7 @@ __global__ void __launch_bounds__(256)
 combine_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, Terms T,
                    double *__restrict__ wsd, const PlanRec *__restrict__ plan) {
   const int ii = ilist[blockIdx.y];
+  if (!on_route(plan[ii], 1) && !on_route(plan[ii], 2)) return;
   const InstDesc D = inst[ii];
   const int64_t nn = (int64_t)D.npad * D.npad;
   const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;

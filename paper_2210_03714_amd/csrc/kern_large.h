@@ -46,6 +46,7 @@ ln_load_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
   if (slot >= nslot) return;
   const int li = slot / T.nterms, k = slot % T.nterms;
   const int ii = ilist[li];
+  if (!on_route(plan[ii], 2)) return;
   const InstDesc D = inst[ii];
   const int n = D.n, np = D.npad;
   const int tr = sub % ntile1, tc = sub / ntile1;
@@ -118,12 +119,13 @@ __device__ __forceinline__ void ln_gj64(double *Dl, int pr0, int pc0) {
 
 __global__ void __launch_bounds__(256)
 ln_dinv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nslot, Terms T,
-               double *__restrict__ wsd, int J) {
+               double *__restrict__ wsd, int J, const PlanRec *__restrict__ plan) {
   constexpr int LDD = kLB + 1;
   __shared__ double Dl[kLB * LDD];
   const int slot = blockIdx.x;
   if (slot >= nslot) return;
   const int li = slot / T.nterms, k = slot % T.nterms;
+  if (!on_route(plan[ilist[li]], 2)) return;
   const InstDesc D = inst[ilist[li]];
   const int np = D.npad, nJ = np / kLB;
   if (J >= nJ) return;
@@ -147,7 +149,7 @@ ln_dinv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
 
 __global__ void __launch_bounds__(256)
 ln_row_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nslot, int nJmax,
-              Terms T, double *__restrict__ wsd, int J) {
+              Terms T, double *__restrict__ wsd, int J, const PlanRec *__restrict__ plan) {
   constexpr int LDD = kLB + 1;
   __shared__ double Dl[kLB * LDD];
   __shared__ double Cl[kLB * LDD];
@@ -155,6 +157,7 @@ ln_row_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   xcd_map(blockIdx.x, nJmax, slot, C);
   if (slot >= nslot) return;
   const int li = slot / T.nterms, k = slot % T.nterms;
+  if (!on_route(plan[ilist[li]], 2)) return;
   const InstDesc D = inst[ilist[li]];
   const int np = D.npad, nJ = np / kLB;
   if (J >= nJ || C >= nJ) return;
@@ -214,7 +217,7 @@ ln_row_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
 
 __global__ void __launch_bounds__(256)
 ln_upd_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nslot, int nJmax,
-              int nRmax, Terms T, double *__restrict__ wsd, int J) {
+              int nRmax, Terms T, double *__restrict__ wsd, int J, const PlanRec *__restrict__ plan) {
   constexpr int LDB = 80;  // == 16 mod 32 doubles
   __shared__ double Bl[kLB * LDB];
   int slot, sub;
@@ -222,6 +225,7 @@ ln_upd_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   if (slot >= nslot) return;
   const int C = sub / nRmax, rc = sub % nRmax;
   const int li = slot / T.nterms, k = slot % T.nterms;
+  if (!on_route(plan[ilist[li]], 2)) return;
   const InstDesc D = inst[ilist[li]];
   const int np = D.npad, nJ = np / kLB;
   if (J >= nJ || C >= nJ || rc * kLRows >= np) return;
@@ -294,7 +298,8 @@ __host__ __device__ inline int64_t ln_vchain(int np, int p) { return 3 * (int64_
 // U[0] of each chain <- V (zero padded).  Grid: x = 64-row chunk, y = instance in list.
 __global__ void __launch_bounds__(256)
 ln_vprep_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, int nchain,
-                double *__restrict__ wsd) {
+                double *__restrict__ wsd, const PlanRec *__restrict__ plan) {
+  if (!on_route(plan[ilist[blockIdx.y]], 2)) return;
   const InstDesc D = inst[ilist[blockIdx.y]];
   const int np = D.npad, pp = ln_pp(D.p);
   const int r0 = blockIdx.x * 64;
@@ -325,6 +330,7 @@ ln_gemv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
   xcd_map(blockIdx.x, nsub, slot, sub);
   if (slot >= nl) return;
   const int ii = ilist[slot];
+  if (!on_route(plan[ii], 2)) return;
   const InstDesc D = inst[ii];
   if (step > plan[ii].s) return;
   const int np = D.npad, nr = D.n, hn = D.hn, emb = D.emb;
@@ -373,6 +379,7 @@ ln_vreduce_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ili
                   const PlanRec *__restrict__ plan, double *__restrict__ wsd, int step, int chain,
                   int out_buf, double scale_first, int phi) {
   const int ii = ilist[blockIdx.y];
+  if (!on_route(plan[ii], 2)) return;
   const InstDesc D = inst[ii];
   const int N = plan[ii].s;
   if (step > N) return;
@@ -431,6 +438,7 @@ ln_steps_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist
   const int ch = sub / nslab, slab = sub % nslab;
   const bool phi = ch == 1 || !want_exp;
   const int ii = ilist[slot];
+  if (!on_route(plan[ii], 2)) return;
   const InstDesc D = inst[ii];
   const int np = D.npad, nr = D.n, hn = D.hn, emb = D.emb, p = D.p;
   const int c0 = slab * 16;

@@ -61,6 +61,7 @@ lu_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist,
   xcd_map(blockIdx.x, T.nterms, slot, k);
   if (slot >= nlist) return;
   const int ii = ilist[slot];
+  if (!on_route(plan[ii], 0)) return;  // the device chose another route (uniform per workgroup)
   const InstDesc D = inst[ii];
   const int n = D.n, np = D.npad;
   if (np > NPMAX || (np & 15) || n > np || n < 1) return;  // sizes the host never sends

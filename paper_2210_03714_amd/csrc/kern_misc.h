@@ -186,13 +186,43 @@ embed_kernel(const InstDesc *__restrict__ inst, double *__restrict__ wsd) {
   }
 }
 
-// status |= bits, and route = route (if >= 0), for the listed instances
-__global__ void mark_status_kernel(PlanRec *__restrict__ plan, const int *__restrict__ list, int n, int bits,
-                                   int route) {
+// The route of every instance, from its plan, on the device (the host reads
+// nothing back).  With |c_k| ||B||_1 <= 1/2 for every shift, each
+// I - c_k B is strictly column diagonally dominant, partial pivoting would
+// never interchange rows, and the inverses are formed by Gauss-Jordan:
+//   - the multi-workgroup route (2) for instances that may take it (action or
+//     complex above the threshold, or n > 512), with the dominance test on
+//     the real matrix the kernels see (||emb(B)||_1 <= sqrt(2) ||B||_1);
+//     an instance above 512 that fails it is not computed (no other route);
+//   - the single-workgroup Gauss-Jordan route (1) where the call allows it;
+//   - else the pivoting LU route (0).  The hybrid set of §4.3 has no LU-route
+//     form: such an instance is not computed.
+// Plans above the caps (kSCap squarings, kNCap steps) are not computed
+// either.
+__global__ void __launch_bounds__(256)
+route_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan, int batch, int action, double cmax,
+             int hybrid) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  plan[list[i]].status |= bits;
-  if (route >= 0) plan[list[i]].route = route;
+  if (i >= batch) return;
+  const InstDesc D = inst[i];
+  PlanRec P = plan[i];
+  const bool finite = !(P.status & PFM_NONFINITE);
+  const double bn = action ? P.eta / (double)(P.s > 1 ? P.s : 1) : ldexp(P.eta, -(P.s < 1023 ? P.s : 1023));
+  const bool ln_dom = finite && cmax * bn * (D.emb ? 1.4142135623730951 : 1.0) <= 0.5;
+  const bool dom = finite && cmax * bn <= 0.5;
+  int route = 0;
+  if (D.rflags & kRfLarge) {
+    route = 2;
+    if (!ln_dom) P.status |= PFM_NOT_COMPUTED;
+  } else if ((D.rflags & kRfMayLn) && ln_dom) {
+    route = 2;
+  } else if ((D.rflags & kRfGj) && dom) {
+    route = 1;
+  }
+  if (hybrid && route == 0) P.status |= PFM_NOT_COMPUTED;
+  if (action ? P.s > kNCap : P.s > kSCap) P.status |= PFM_NOT_COMPUTED;
+  P.route = route;
+  plan[i] = P;
 }
 
 struct InfoRec {  // mirrors pfm_info

@@ -16,6 +16,7 @@
 // load, emb(R)[:, hn + j] = J emb(R)[:, j], and only hn columns are produced.
 #pragma once
 #include "kern_common.h"
+#include "pfm.h"
 
 namespace pfm {
 
@@ -38,12 +39,13 @@ struct SqTask {
 // MODE 2: B T for the large instances: T from buffer 1 (3), B from the
 //         row-major A as in MODE 1, output in the factor buffer slot 0 (1),
 //         all npad columns.
+// One output tile of one product (the body shared by the per-level launches
+// and the persistent queue of kern_sched.h).  Ends with a barrier after its
+// last LDS read, so a caller may reuse the LDS right away.
 template <int MODE, int TILE>
-__global__ void __launch_bounds__(256, 2)
-square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restrict__ tasks,
-                        int ntasks, int level, double *__restrict__ wsd,
-                        const PlanRec *__restrict__ plan, double a0e, double a0p,
-                        double a1e = 0.0, double a1p = 0.0) {
+__device__ __forceinline__ void sq_tile(const InstDesc *__restrict__ inst, const SqTask tk, int level,
+                                        double *__restrict__ wsd, const PlanRec *__restrict__ plan, double a0e,
+                                        double a0p, double a1e, double a1p) {
   static_assert(TILE == 64 || TILE == 128, "tile");
   constexpr int LDA = TILE + 16, LDB = TILE + 16;  // == 16 mod 32 doubles: conflict-free fragment reads
   constexpr int NP = TILE / 64;   // staging passes per operand
@@ -51,10 +53,6 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
   constexpr int NT = WT / 16;     // MFMA tiles per wave and dimension
   __shared__ double As[16 * LDA];
   __shared__ double Bs[16 * LDB];
-  const int q = blockIdx.x;
-  if (q >= ntasks) return;
-  const SqTask tk = tasks[q];
-  if (tk.inst < 0) return;
   const InstDesc D = inst[tk.inst];
   const int np = D.npad, nr = D.n, ncol = D.ncol, hn = D.hn, emb = D.emb;
   const int which = tk.tile >> 20;
@@ -192,6 +190,27 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
         *reinterpret_cast<v4d *>(Cdst + r + (int64_t)c * np) = o;
       }
     }
+}
+
+// One launch over a task list.  Every candidate instance is listed (the host
+// does not know the plans): MODE 0 tasks of instances with s < level, and
+// MODE 1 / 2 tasks of instances on another route, return at once.
+template <int MODE, int TILE>
+__global__ void __launch_bounds__(256, 2)
+square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restrict__ tasks,
+                        int ntasks, int level, double *__restrict__ wsd,
+                        const PlanRec *__restrict__ plan, double a0e, double a0p,
+                        double a1e = 0.0, double a1p = 0.0) {
+  const int q = blockIdx.x;
+  if (q >= ntasks) return;
+  const SqTask tk = tasks[q];
+  if (tk.inst < 0) return;
+  const PlanRec &P = plan[tk.inst];
+  if (P.status & PFM_NOT_COMPUTED) return;
+  if (MODE == 0 && P.s < level) return;
+  if (MODE == 1 && P.route == 0) return;
+  if (MODE == 2 && P.route != 2) return;
+  sq_tile<MODE, TILE>(inst, tk, level, wsd, plan, a0e, a0p, a1e, a1p);
 }
 
 }  // namespace pfm

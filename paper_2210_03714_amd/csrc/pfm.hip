@@ -1,10 +1,14 @@
 // libpfm host runtime: the C ABI of include/pfm.h on top of the gfx950 kernels.
 //
-// A call of pfm_eval_batched validates on the host, lays out the workspace,
-// computes the per-instance plan (s or N) on the device from ||A||_1, reads
-// the plans back once (one stream synchronisation per call: the host sizes
-// the squaring / step launches and routes each instance from them), then
-// enqueues the rest of the path without further waits.
+// A call of pfm_eval_batched validates on the host, lays out the workspace
+// from the sizes alone, and enqueues the whole path: the per-instance plan
+// (s or N) and route are decided on the device from ||A||_1, the kernels of
+// every route are launched over all instances that may take it (the others
+// return at once), and the squarings run as a fixed number of per-level
+// launches followed by a persistent queue for any further levels
+// (kern_sched.h).  Nothing is read back, so the call does not wait for the
+// GPU (except to grow the workspace, or for the step count of an action on
+// an instance above 512).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,9 +37,11 @@
 #include "kern_large.h"
 #include "kern_tri.h"
 #include "kern_band.h"
+#include "kern_sched.h"
 
 using namespace pfm;
 static_assert(kNCap == PFM_MAX_STEPS, "the device-side step cap is the documented one");
+static_assert(kSCap == PFM_MAX_SQUARINGS, "the device-side squaring cap is the documented one");
 
 // phases timed by pfm_profile: LU, solve+combine, squaring, store
 constexpr int kNumPhases = 4;
@@ -61,6 +67,14 @@ struct pfm_ctx {
   // action / complex instances may take the multi-workgroup route
   int gj = 1;
   int ln_min = kLnMin;
+  // squaring levels launched one by one; the rest run from the persistent
+  // queue (kern_sched.h)
+  int sq_direct = 8;
+  bool sched_explicit = false;  // set by pfm_set_schedule: a tuned schedule does not override it
+  // the bytes (pointers, descriptors, lists, task lists) of the last upload
+  // of pfm_eval_batched, valid while nothing else has written the workspace
+  std::vector<char> up_key;
+  bool up_valid = false;
   // autotuned policies per batch key (pfm_tune); force_policy >= 0 while
   // tuning
   std::map<uint64_t, int> tuned;
@@ -183,13 +197,22 @@ int prof_harvest(pfm_ctx *ctx) {
   return PFM_OK;
 }
 
-// Route policies the autotuner chooses between.
+// Policies the autotuner chooses between: a route policy and a squaring
+// schedule (policy index = route + kNumRoutePolicies * schedule).
 struct Policy {
   int gj;      // single-workgroup Gauss-Jordan route for dominant real full matrices
   int ln_min;  // action / complex instances above this size may take the multi-workgroup route
 };
 constexpr Policy kPolicies[] = {{1, kLnMin}, {0, kLnMin}, {1, 512}, {0, 512}};
-constexpr int kNumPolicies = 4;
+constexpr int kNumRoutePolicies = 4;
+// squaring levels launched one by one before the persistent queue takes the
+// rest: 8 (enough for ||A||_1 up to 2^8 θ), or 0 (the queue runs them all)
+constexpr int kSqDirect[] = {8, 0};
+constexpr int kNumSchedules = 2;
+// smallest npad whose product tiles are 128 x 128 (else 64 x 64)
+constexpr int kTile128Min[] = {256, 1 << 30};
+constexpr int kNumTiles = 2;
+constexpr int kNumPolicies = kNumRoutePolicies * kNumSchedules * kNumTiles;
 
 // Tuning key of a batch: mode, complex, precision, size bucket of its
 // largest real dimension (2n for complex), batch-size bucket.
@@ -239,6 +262,16 @@ int pfm_set_route(pfm_ctx *ctx, int route) {
   return PFM_OK;
 }
 
+int pfm_set_schedule(pfm_ctx *ctx, int direct_levels) {
+  if (!ctx) return PFM_ERR_INVALID;
+  if (direct_levels < 0 || direct_levels > PFM_MAX_SQUARINGS)
+    return set_err(ctx, PFM_ERR_INVALID, "pfm_set_schedule: %d levels not in [0, %d]", direct_levels,
+                   PFM_MAX_SQUARINGS);
+  ctx->sq_direct = direct_levels;
+  ctx->sched_explicit = true;
+  return PFM_OK;
+}
+
 int pfm_profile(pfm_ctx *ctx, int enable) {
   if (!ctx) return PFM_ERR_INVALID;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -284,14 +317,19 @@ size_t pfm_workspace_bytes(int f, int m, int prec, int dtype, int batch, const p
     if (nk > 512 && (mixed || pairs || nk > kLargeMax || P.p > 64)) return 0;
     const int64_t np = (nk + 63) / 64 * 64, nn = np * np;
     const bool large = nk > 512;
+    const bool may_ln = large || (!mixed && !pairs && nk > kLnMin && (act || emb));
     d += nterms * nn + 4 * nn + 6 * 64;
-    d += large ? nterms * ln_stride((int)np) : nterms * 2 * (np / 16) * 256;
-    if (emb || mixed) d += nn;
-    if (large && P.p > 0) d += 2 * ln_vchain((int)np, P.p) + (int64_t)ln_ks((int)nk) * np * ln_pp(P.p);
+    if (may_ln) {
+      d += nterms * ln_stride((int)np);
+      if (P.p > 0) d += 2 * ln_vchain((int)np, P.p) + (int64_t)ln_ks((int)nk) * np * ln_pp(P.p);
+    }
+    if (!large) d += nterms * 2 * (np / 16) * 256;
+    if (emb || mixed) d += std::max(nk, np) * np;
     ints += large ? 0 : 2 * nterms * np + 128;
-    d += (sizeof(PlanRec) + sizeof(InstDesc) + 2 * sizeof(int) + 7) / 8;
+    // plan, descriptor, list entries and squaring-queue entries
+    d += (sizeof(PlanRec) + sizeof(InstDesc) + 4 * sizeof(int) + 16 + 7) / 8;
   }
-  return (size_t)(d * 8 + ints * 4 + 3 * 256);
+  return (size_t)(d * 8 + ints * 4 + 2 * (kSCap + 2) * 8 + 16 * 256 + 4096);
 }
 
 const char *pfm_version(void) { return "pfm 0.2 (gfx950)"; }
@@ -528,6 +566,7 @@ int tri_launch(pfm_ctx *ctx, const TriTerms &T, int order, int batch, const TriD
 
 // Grow the context's workspace to at least `need` bytes.
 int ws_reserve(pfm_ctx *ctx, int64_t need, hipStream_t stream) {
+  ctx->up_valid = false;  // this call writes its descriptors at the workspace's start
   if (ctx->budget && (size_t)need > ctx->budget)
     return set_err(ctx, PFM_ERR_BUDGET, "workspace %lld bytes exceeds budget %zu", (long long)need, ctx->budget);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -896,23 +935,32 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   const int nterms = T.nterms;
 
   // route policy: the context's, unless a tuned one exists for this batch
-  int pol_gj = ctx->gj, pol_ln = ctx->ln_min;
+  int pol_gj = ctx->gj, pol_ln = ctx->ln_min, pol_direct = ctx->sq_direct, pol_t128 = kTile128Min[0];
   {
     const int pidx = ctx->force_policy >= 0 ? ctx->force_policy
                                             : [&] {
                                                 auto it = ctx->tuned.find(batch_key(action, emb, mixed, batch, probs));
                                                 return it == ctx->tuned.end() ? -1 : it->second;
                                               }();
-    if (pidx >= 0 && ctx->gj && !hybrid) {  // an explicit PFM_ROUTE_LU stays authoritative
-      pol_gj = kPolicies[pidx].gj;
-      pol_ln = kPolicies[pidx].ln_min;
+    if (pidx >= 0) {
+      if (ctx->gj && !hybrid) {  // an explicit PFM_ROUTE_LU stays authoritative
+        pol_gj = kPolicies[pidx % kNumRoutePolicies].gj;
+        pol_ln = kPolicies[pidx % kNumRoutePolicies].ln_min;
+      }
+      if (!ctx->sched_explicit) pol_direct = kSqDirect[(pidx / kNumRoutePolicies) % kNumSchedules];
+      pol_t128 = kTile128Min[pidx / (kNumRoutePolicies * kNumSchedules)];
     }
   }
   const bool gj_call = pol_gj && !action && !emb && !mixed;
-  // workspace layout
+  if (hybrid && !gj_call)
+    for (int i = 0; i < batch; ++i)
+      if (probs[i].n <= 512)
+        return set_err(ctx, PFM_ERR_UNSUPPORTED,
+                       "m = %d needs the Gauss-Jordan routes, which PFM_ROUTE_LU turns off (instance %d)", m, i);
+  // workspace layout: from the sizes alone (the device routes each instance
+  // after its plan, so every route an instance may take is laid out)
   std::vector<InstDesc> desc(batch);
   std::vector<int> cls_list[4];
-  std::vector<char> may_ln_v(batch, 0);
   int64_t dofs = 0, iofs = 0;
   for (int i = 0; i < batch; ++i) {
     const pfm_problem &P = probs[i];
@@ -933,13 +981,13 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     D.ncol = P.n;
     // Routes: real FP64 full-matrix instances may take the single-workgroup
     // Gauss-Jordan path (64-wide blocks); instances above 512 must take the
-    // multi-workgroup one (class 3); action and complex instances above 128
-    // take it when the shifted matrices are dominant and keep the pivoting
-    // LU route otherwise, so both workspaces are laid out for them.
+    // multi-workgroup one (class 3); action and complex instances above the
+    // threshold take it when the shifted matrices are dominant and keep the
+    // pivoting LU route otherwise, so both workspaces are laid out for them.
     const bool large = D.n > 512;
     const bool may_ln = large || (!mixed && !pairs && D.n > pol_ln && (action || emb));
-    may_ln_v[i] = may_ln;
     D.npad = (gj_call || may_ln) ? (D.n + 63) / 64 * 64 : (D.n + 15) / 16 * 16;
+    D.rflags = (may_ln ? kRfMayLn : 0) | (large ? kRfLarge : 0) | (gj_call && !large ? kRfGj : 0);
     D.p = P.p;
     D.cls = large ? 3 : (D.npad <= 128 ? 0 : (D.npad <= 256 ? 1 : 2));
     const int64_t np = D.npad, nn = np * np;
@@ -970,154 +1018,26 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     }
     cls_list[D.cls].push_back(i);
   }
-  const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
-  const int64_t desc_bytes = align_up((int64_t)batch * sizeof(InstDesc), 256);
-  const int64_t list_bytes = align_up((int64_t)2 * batch * sizeof(int), 256);
-  const int64_t need = dofs * 8 + iofs * 4 + plan_bytes + desc_bytes + list_bytes + 4096;
-  if (ctx->budget && (size_t)need > ctx->budget)
-    return set_err(ctx, PFM_ERR_BUDGET, "workspace %lld bytes exceeds budget %zu", (long long)need,
-                   ctx->budget);
 
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  if ((size_t)need > ctx->ws_bytes) {
-    if (ctx->ws) {
-      HIP_TRY(ctx, hipStreamSynchronize(stream));
-      HIP_TRY(ctx, hipFree(ctx->ws));
-      ctx->ws = nullptr;
-      ctx->ws_bytes = 0;
-    }
-    HIP_TRY(ctx, hipMalloc(&ctx->ws, (size_t)need));
-    ctx->ws_bytes = (size_t)need;
-  }
-  char *base = (char *)ctx->ws;
-  double *wsd = (double *)base;
-  int *wsi = (int *)(base + dofs * 8);
-  char *tail = base + dofs * 8 + align_up(iofs * 4, 256);
-  PlanRec *d_plan = (PlanRec *)tail;
-  InstDesc *d_desc = (InstDesc *)(tail + plan_bytes);
-  int *d_list = (int *)(tail + plan_bytes + desc_bytes);
-
-  for (int i = 0; i < batch; ++i)
-    if (desc[i].emb) desc[i].A = wsd + desc[i].e_off;
-
-  // descriptors through pinned staging
-  char *pin = nullptr;
-  int rcs = staging(ctx, desc_bytes + plan_bytes, &pin);
-  if (rcs) return rcs;
-  InstDesc *h_desc = (InstDesc *)pin;
-  PlanRec *h_plan = (PlanRec *)(pin + desc_bytes);
-  memcpy(h_desc, desc.data(), batch * sizeof(InstDesc));
-  HIP_TRY(ctx, hipMemcpyAsync(d_desc, h_desc, batch * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
-
-  if (emb) {
-    int maxk = 0;
-    for (int i = 0; i < batch; ++i) maxk = std::max(maxk, desc[i].n);
-    const int te = (maxk + 31) / 32;
-    hipLaunchKernelGGL(embed_kernel, dim3(te * te, batch), dim3(256), 0, stream, d_desc, wsd);
-  }
-  // 1. norm and plan on the device; the host reads the plans back once (it
-  //    needs max s to size the squaring launches and routes each instance)
-  {
-    int maxc = 0;
-    for (int i = 0; i < batch; ++i) maxc = std::max(maxc, probs[i].n);
-    const int nb = (batch + 255) / 256;
-    hipLaunchKernelGGL(plan_init_kernel, dim3(nb), dim3(256), 0, stream, d_plan, batch);
-    hipLaunchKernelGGL(norm_kernel, dim3((maxc + 63) / 64, batch), dim3(256), 0, stream, d_desc, d_plan);
-    hipLaunchKernelGGL(plan_finish_kernel, dim3(nb), dim3(256), 0, stream, d_desc, d_plan, batch,
-                       action ? 1 : 0, force_plan, log1m ? 1 : 0);
-  }
-  HIP_TRY(ctx, hipGetLastError());
-  HIP_TRY(ctx, hipMemcpyAsync(h_plan, d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(ctx, hipStreamSynchronize(stream));
-  {
-    int rcp = prof_harvest(ctx);
-    if (rcp) return rcp;
-  }
-  // the pinned staging area is reused below for the lists: keep a copy
-  std::vector<PlanRec> hplan(h_plan, h_plan + batch);
-  h_plan = hplan.data();
-  std::vector<int> svec(batch);
-  int smax = 0;
-  for (int i = 0; i < batch; ++i) {
-    svec[i] = std::max(0, std::min(h_plan[i].s, kSCap));
-    smax = std::max(smax, svec[i]);
-  }
-  if (action)
-    for (int i = 0; i < batch; ++i)
-      if (h_plan[i].s > kNCap)
-        return set_err(ctx, PFM_ERR_INVALID, "instance %d needs N = %d steps (cap %d)", i,
-                       h_plan[i].s, kNCap);
-  if (!action)
-    for (int i = 0; i < batch; ++i)
-      if (h_plan[i].s > kSCap) {
-        return set_err(ctx, PFM_ERR_INVALID, "instance %d needs s = %d squarings (cap %d)", i,
-                       h_plan[i].s, kSCap);
-      }
-
-  // Routing: with |c_k| ||B||_1 <= 1/2 every M_k is strictly column diagonally
-  // dominant, partial pivoting would never interchange rows, and the inverse
-  // is formed by Gauss-Jordan; everything else takes the pivoting LU path.
-  double cmax = 0.0;
-  for (int k = 0; k < nterms; ++k) cmax = std::max(cmax, std::hypot(T.c_re[k], T.c_im[k]));
-  std::vector<int> fast_list[3], slow_list[3];
-  std::vector<char> is_fast(batch, 0);
-  // the dominance test of the multi-workgroup route (||emb(B)||_1 <=
-  // sqrt(2) ||B||_1 for the real matrix the kernels see)
-  auto ln_dominant = [&](int i) {
-    const double bn = action ? h_plan[i].eta / (double)std::max(1, h_plan[i].s)
-                             : std::ldexp(h_plan[i].eta, -svec[i]);
-    return !(h_plan[i].status & 2) && cmax * bn * (desc[i].emb ? std::sqrt(2.0) : 1.0) <= 0.5;
-  };
-  std::vector<int> ln_list, skip_list;
-  std::vector<char> skip(batch, 0);
-  for (int c = 0; c < 3; ++c)
-    for (int i : cls_list[c]) {
-      if (may_ln_v[i] && ln_dominant(i)) {
-        ln_list.push_back(i);
-        is_fast[i] = 1;
-        continue;
-      }
-      const bool fast = gj_call && (desc[i].npad % kGJ) == 0 && !(h_plan[i].status & 2) &&
-                        cmax * std::ldexp(h_plan[i].eta, -svec[i]) <= 0.5;
-      (fast ? fast_list : slow_list)[c].push_back(i);
-      is_fast[i] = fast;
-    }
-  if (hybrid)
-    for (int c = 0; c < 3; ++c)
-      if (!slow_list[c].empty())
-        return set_err(ctx, PFM_ERR_UNSUPPORTED,
-                       "m = %d needs |c_k| ||B||_1 <= 1/2 for every instance (the Gauss-Jordan route); "
-                       "instance %d is on the pivoting LU route (forced plan, PFM_ROUTE_LU or non-finite input)",
-                       m, slow_list[c][0]);
-  int fast_off[3], slow_off[3];
+  // Instance lists (all from the sizes): per class for the single-workgroup
+  // kernels; the multi-workgroup candidates by class; their action step
+  // groups; the squaring groups by tile edge.  Kernels skip the instances the
+  // device routed elsewhere.
   std::vector<int> lists;
+  int cls_off[3];
   for (int c = 0; c < 3; ++c) {
-    fast_off[c] = (int)lists.size();
-    lists.insert(lists.end(), fast_list[c].begin(), fast_list[c].end());
+    cls_off[c] = (int)lists.size();
+    lists.insert(lists.end(), cls_list[c].begin(), cls_list[c].end());
   }
-  for (int c = 0; c < 3; ++c) {
-    slow_off[c] = (int)lists.size();
-    lists.insert(lists.end(), slow_list[c].begin(), slow_list[c].end());
-  }
-  // instances above 512 have no other route: not computed if not dominant
-  for (int i : cls_list[3]) {
-    const bool ok = ln_dominant(i);
-    (ok ? ln_list : skip_list).push_back(i);
-    is_fast[i] = ok;
-    skip[i] = !ok;
-  }
-  // multi-workgroup-route instances, ordered by size class: those with
-  // npad <= 512 are inverted by the single-workgroup Gauss-Jordan kernel of
-  // their class, the rest block step by block step
-  std::stable_sort(ln_list.begin(), ln_list.end(), [&](int a, int b) { return desc[a].cls < desc[b].cls; });
+  std::vector<int> ln_list;
+  for (int c = 0; c < 4; ++c)
+    for (int i : cls_list[c])
+      if (desc[i].rflags & kRfMayLn) ln_list.push_back(i);
   int ln_cls_off[5] = {0, 0, 0, 0, 0};
   for (int i : ln_list) ln_cls_off[desc[i].cls + 1]++;
   for (int c = 0; c < 4; ++c) ln_cls_off[c + 1] += ln_cls_off[c];
   const int ln_off_l = (int)lists.size();
   lists.insert(lists.end(), ln_list.begin(), ln_list.end());
-  // action steps: npad <= 256 / 512 run all steps in one workgroup per
-  // (instance, function, column slab); larger ones step by step over many
-  // workgroups (one workgroup would hold a CU for too long)
   std::vector<int> act_list[4];
   int act_off[4] = {0, 0, 0, 0};
   if (action) {
@@ -1130,18 +1050,28 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
       lists.insert(lists.end(), act_list[c].begin(), act_list[c].end());
     }
   }
-  const int skip_off_l = (int)lists.size();
-  lists.insert(lists.end(), skip_list.begin(), skip_list.end());
-  bool any_fast = false;
-  for (int i = 0; i < batch; ++i) any_fast |= is_fast[i] != 0;
+  auto tile_of = [&](int i) { return desc[i].npad >= pol_t128 || desc[i].cls == 3 ? 1 : 0; };
+  std::vector<int> sq_group[2];
+  int sq_off[2] = {0, 0};
+  if (!action) {
+    for (int i = 0; i < batch; ++i) sq_group[tile_of(i)].push_back(i);
+    for (int g = 0; g < 2; ++g) {
+      sq_off[g] = (int)lists.size();
+      lists.insert(lists.end(), sq_group[g].begin(), sq_group[g].end());
+    }
+  }
+  std::vector<int> gj_cand;  // instances that may take a Gauss-Jordan route
+  for (int i = 0; i < batch; ++i)
+    if (desc[i].rflags & (kRfGj | kRfMayLn)) gj_cand.push_back(i);
+  const bool any_gj = !gj_cand.empty();
 
-  // GEMM task lists: level 0 = R = a0 I + S B for the Gauss-Jordan instances,
-  // levels 1..smax = squarings, and the B T products of the multi-workgroup
-  // route; per level one list per tile size (128 for npad >= 256, else 64).
+  // GEMM task lists: level 0 = R = a0 I + S B of the Gauss-Jordan
+  // candidates, the B T products of the multi-workgroup candidates, and one
+  // list of every instance's tiles that each directly launched squaring level
+  // reuses; per list one part per tile size (128 for npad >= 256, else 64).
   // All tiles of one instance go to one XCD.
   std::vector<SqTask> all;
   using LevelLists = std::array<std::pair<int64_t, int>, 2>;  // (offset, count) per tile size
-  auto tile_of = [&](int i) { return desc[i].npad >= 256 ? 1 : 0; };
   auto build = [&](const std::vector<int> &ids, int tc, bool all_cols) {
     std::vector<std::vector<SqTask>> qx(8);
     int x = 0;
@@ -1161,16 +1091,12 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
       for (int xx = 0; xx < 8; ++xx) all.push_back(qq < qx[xx].size() ? qx[xx][qq] : SqTask{-1, 0});
     return std::make_pair(off, (int)(mx * 8));
   };
-  std::vector<LevelLists> lv;
-  const int jtop = action ? 0 : smax;  // the action has no squarings
-  for (int j = 0; j <= jtop; ++j) {
-    std::vector<int> ids;
-    for (int i = 0; i < batch; ++i)
-      if (!skip[i] && (j == 0 ? is_fast[i] != 0 : svec[i] >= j)) ids.push_back(i);
-    lv.push_back(LevelLists{build(ids, 0, false), build(ids, 1, false)});
-  }
-  // B T products (all npad columns) of the large instances, before level 0
+  const LevelLists lv0{build(gj_cand, 0, false), build(gj_cand, 1, false)};
   const LevelLists lvbt{build(ln_list, 0, true), build(ln_list, 1, true)};
+  std::vector<int> every(batch);
+  for (int i = 0; i < batch; ++i) every[i] = i;
+  LevelLists lvsq{std::make_pair((int64_t)0, 0), std::make_pair((int64_t)0, 0)};
+  if (!action) lvsq = LevelLists{build(every, 0, false), build(every, 1, false)};
   // alpha1 = sum_k w_k of the binary64 weights, summed in extended precision
   double a1e = 0.0, a1p = 0.0;
   {
@@ -1179,39 +1105,149 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     a1e = (double)se + T.d1e;  // the hybrid set's d1 B joins alpha1 B
     a1p = (double)sp;
   }
+
+  // workspace tail: plans, descriptors, lists, the squaring queues
+  const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
+  const int64_t desc_bytes = align_up((int64_t)batch * sizeof(InstDesc), 256);
+  const int64_t list_bytes = align_up((int64_t)std::max<size_t>(lists.size(), 1) * sizeof(int), 256);
+  auto queue_bytes = [&](int ng) {
+    return align_up(sizeof(SqQueue), 64) + align_up((int64_t)ng * 4, 64) + align_up((int64_t)(ng + 1) * 8, 64) +
+           align_up((int64_t)(kSCap + 2) * 8, 64) + align_up((int64_t)ng * 4, 64);
+  };
+  const int64_t q_bytes = align_up(queue_bytes((int)sq_group[0].size()), 256) +
+                          align_up(queue_bytes((int)sq_group[1].size()), 256);
+  const int64_t need = dofs * 8 + align_up(iofs * 4, 256) + plan_bytes + desc_bytes + list_bytes + q_bytes + 4096;
+  if (ctx->budget && (size_t)need > ctx->budget)
+    return set_err(ctx, PFM_ERR_BUDGET, "workspace %lld bytes exceeds budget %zu", (long long)need,
+                   ctx->budget);
   const size_t tb = all.size() * sizeof(SqTask);
+
+  // a call recorded into the caller's stream capture: nothing may allocate,
+  // synchronise or read host memory that a later call may change
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (stream) HIP_TRY(ctx, hipStreamIsCapturing(stream, &cap));
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if (capturing && ((size_t)need > ctx->ws_bytes || tb > ctx->tasks_bytes || ctx->prof))
+    return set_err(ctx, PFM_ERR_INVALID,
+                   "a captured call must not grow the workspace or time phases: run the same call eagerly once "
+                   "first, with pfm_profile off");
+
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((size_t)need > ctx->ws_bytes) {
+    if (ctx->ws) {
+      HIP_TRY(ctx, hipStreamSynchronize(stream));
+      HIP_TRY(ctx, hipFree(ctx->ws));
+      ctx->ws = nullptr;
+      ctx->ws_bytes = 0;
+    }
+    ctx->up_valid = false;
+    HIP_TRY(ctx, hipMalloc(&ctx->ws, (size_t)need));
+    ctx->ws_bytes = (size_t)need;
+  }
   if (tb > ctx->tasks_bytes) {
-    if (ctx->tasks) HIP_TRY(ctx, hipFree(ctx->tasks));
+    if (ctx->tasks) {
+      HIP_TRY(ctx, hipStreamSynchronize(stream));
+      HIP_TRY(ctx, hipFree(ctx->tasks));
+    }
     ctx->tasks = nullptr;
     ctx->tasks_bytes = 0;
+    ctx->up_valid = false;
     HIP_TRY(ctx, hipMalloc(&ctx->tasks, std::max<size_t>(tb, 256)));
     ctx->tasks_bytes = std::max<size_t>(tb, 256);
   }
+  char *base = (char *)ctx->ws;
+  double *wsd = (double *)base;
+  int *wsi = (int *)(base + dofs * 8);
+  char *tail = base + dofs * 8 + align_up(iofs * 4, 256);
+  PlanRec *d_plan = (PlanRec *)tail;
+  InstDesc *d_desc = (InstDesc *)(tail + plan_bytes);
+  int *d_list = (int *)(tail + plan_bytes + desc_bytes);
+  char *qbase = tail + plan_bytes + desc_bytes + list_bytes;
+  struct QPtr {
+    SqQueue *q;
+    int *ord;
+    long long *pre, *lstart;
+    int *done;
+  } qp[2];
   {
-    // the staging area is free again: the stream was synchronised above
-    const size_t lb = align_up((int64_t)lists.size() * sizeof(int), 256);
-    char *pin2 = nullptr;
-    rcs = staging(ctx, lb + tb + 256, &pin2);
-    if (rcs) return rcs;
-    memcpy(pin2, lists.data(), lists.size() * sizeof(int));
-    if (tb) memcpy(pin2 + lb, all.data(), tb);
-    HIP_TRY(ctx, hipMemcpyAsync(d_list, pin2, lists.size() * sizeof(int), hipMemcpyHostToDevice, stream));
-    if (tb) HIP_TRY(ctx, hipMemcpyAsync(ctx->tasks, pin2 + lb, tb, hipMemcpyHostToDevice, stream));
-    HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
-    ctx->pin_pending = true;
+    char *c = qbase;
+    for (int g = 0; g < 2; ++g) {
+      const int ng = (int)sq_group[g].size();
+      char *c0 = c;
+      qp[g].q = (SqQueue *)c;  c += align_up(sizeof(SqQueue), 64);
+      qp[g].ord = (int *)c;    c += align_up((int64_t)ng * 4, 64);
+      qp[g].pre = (long long *)c; c += align_up((int64_t)(ng + 1) * 8, 64);
+      qp[g].lstart = (long long *)c; c += align_up((int64_t)(kSCap + 2) * 8, 64);
+      qp[g].done = (int *)c;
+      c = c0 + align_up(queue_bytes(ng), 256);
+    }
+  }
+  for (int i = 0; i < batch; ++i)
+    if (desc[i].emb) desc[i].A = wsd + desc[i].e_off;
+
+  // descriptors, lists and task lists: uploaded through the pinned staging
+  // area unless the device already holds exactly these bytes at these
+  // addresses (then a captured call has no copy node at all)
+  {
+    const size_t nd = batch * sizeof(InstDesc), nl = lists.size() * sizeof(int);
+    std::vector<char> key(nd + nl + tb + 4 * sizeof(void *));
+    char *kp = key.data();
+    const void *ptrs[4] = {ctx->ws, ctx->tasks, d_desc, d_list};
+    memcpy(kp, ptrs, sizeof ptrs);
+    memcpy(kp + sizeof ptrs, desc.data(), nd);
+    memcpy(kp + sizeof ptrs + nd, lists.data(), nl);
+    if (tb) memcpy(kp + sizeof ptrs + nd + nl, all.data(), tb);
+    if (!(ctx->up_valid && ctx->up_key == key)) {
+      if (capturing)
+        return set_err(ctx, PFM_ERR_INVALID,
+                       "a captured call must repeat the previous call on this context (same problems and "
+                       "arguments): run it eagerly once first");
+      const size_t a_nd = align_up(nd, 256), a_nl = align_up(nl, 256);
+      char *pin = nullptr;
+      const int rcs = staging(ctx, a_nd + a_nl + tb + 256, &pin);
+      if (rcs) return rcs;
+      memcpy(pin, desc.data(), nd);
+      if (nl) memcpy(pin + a_nd, lists.data(), nl);
+      if (tb) memcpy(pin + a_nd + a_nl, all.data(), tb);
+      ctx->up_valid = false;
+      HIP_TRY(ctx, hipMemcpyAsync(d_desc, pin, nd, hipMemcpyHostToDevice, stream));
+      if (nl) HIP_TRY(ctx, hipMemcpyAsync(d_list, pin + a_nd, nl, hipMemcpyHostToDevice, stream));
+      if (tb) HIP_TRY(ctx, hipMemcpyAsync(ctx->tasks, pin + a_nd + a_nl, tb, hipMemcpyHostToDevice, stream));
+      HIP_TRY(ctx, hipEventRecord(ctx->pin_ev, stream));
+      ctx->pin_pending = true;
+      ctx->up_key.swap(key);
+      ctx->up_valid = true;
+    }
+  }
+  if (!capturing) {
+    const int rcp = prof_harvest(ctx);
+    if (rcp) return rcp;
   }
   const SqTask *dt = (const SqTask *)ctx->tasks;
-  const int nln = (int)ln_list.size();
-  int ln_npm = 0, ln_nmax = 0, ln_big_npm = 0;
+  int ln_npm = 0, ln_big_npm = 0;
   for (int i : ln_list) {
     ln_npm = std::max(ln_npm, desc[i].npad);
-    ln_nmax = std::max(ln_nmax, action ? h_plan[i].s : 0);
     if (desc[i].cls == 3) ln_big_npm = std::max(ln_big_npm, desc[i].npad);
   }
+  double cmax = 0.0;
+  for (int k = 0; k < nterms; ++k) cmax = std::max(cmax, std::hypot(T.c_re[k], T.c_im[k]));
+  int maxc = 0, maxn = 0, maxp = 0;
+  for (int i = 0; i < batch; ++i) {
+    maxc = std::max(maxc, probs[i].n);
+    maxn = std::max(maxn, desc[i].npad);
+    maxp = std::max(maxp, probs[i].p);
+  }
+  // resident workgroups of the persistent squaring kernels (their grids)
+  int occ[2] = {0, 0};
+  HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], sq_persist_kernel<64>, 256, 0));
+  HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], sq_persist_kernel<128>, 256, 0));
+  // the large action route's steps are launched one by one: the host needs
+  // their count, the one case in which a call reads the plans back
+  const bool big_action = action && !act_list[3].empty();
+  if (big_action && capturing)
+    return set_err(ctx, PFM_ERR_UNSUPPORTED,
+                   "an action on an instance above 512 (complex: 256) reads its step count back: not capturable");
 
-  // Everything from here on depends only on what the host has decided (the
-  // descriptors, plans, lists and task lists); a call that repeats all of it
-  // replays a captured graph of this sequence.
   // one launch per tile size with tasks
 #define PFM_SQ(MODE, LL, LEVEL)                                                                     \
   do {                                                                                              \
@@ -1224,21 +1260,53 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
                          stream, d_desc, dt + (LL)[1].first, (LL)[1].second, LEVEL, wsd, d_plan, T.a0e,     \
                          T.a0p, a1e, a1p);                                                          \
   } while (0)
+  // Everything from here on depends only on what the host has decided (the
+  // descriptors, lists and task lists); a call that repeats all of it
+  // replays a captured graph of this sequence.
+  // 1. embedding, norm, plan and route, on the device
+  auto enqueue_plan = [&]() -> int {
+  if (emb) {
+    const int te = (maxn + 31) / 32;
+    hipLaunchKernelGGL(embed_kernel, dim3(te * te, batch), dim3(256), 0, stream, d_desc, wsd);
+  }
+  {
+    const int nb = (batch + 255) / 256;
+    hipLaunchKernelGGL(plan_init_kernel, dim3(nb), dim3(256), 0, stream, d_plan, batch);
+    hipLaunchKernelGGL(norm_kernel, dim3((maxc + 63) / 64, batch), dim3(256), 0, stream, d_desc, d_plan);
+    hipLaunchKernelGGL(plan_finish_kernel, dim3(nb), dim3(256), 0, stream, d_desc, d_plan, batch,
+                       action ? 1 : 0, force_plan, log1m ? 1 : 0);
+    hipLaunchKernelGGL(route_kernel, dim3(nb), dim3(256), 0, stream, d_desc, d_plan, batch, action ? 1 : 0, cmax,
+                       hybrid ? 1 : 0);
+  }
+  return PFM_OK;
+  };
+  // The large action route's steps are launched one by one: the host reads
+  // their count back after the plan (the one read-back of a call) and the
+  // rest of the sequence depends on it.
+  int big_nmax = 0;
+  if (big_action) {
+    const int rcp = enqueue_plan();
+    if (rcp) return rcp;
+    HIP_TRY(ctx, hipGetLastError());
+    std::vector<PlanRec> hp(batch);
+    HIP_TRY(ctx, hipMemcpyAsync(hp.data(), d_plan, batch * sizeof(PlanRec), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    for (int i : act_list[3])
+      if (on_route(hp[i], 2)) big_nmax = std::max(big_nmax, hp[i].s);
+  }
   auto enqueue = [&]() -> int {
-  if (!skip_list.empty())
-    hipLaunchKernelGGL(mark_status_kernel, dim3(((int)skip_list.size() + 255) / 256), dim3(256), 0, stream,
-                       d_plan, d_list + skip_off_l, (int)skip_list.size(), PFM_NOT_COMPUTED, -1);
-  if (nln)
-    hipLaunchKernelGGL(mark_status_kernel, dim3((nln + 255) / 256), dim3(256), 0, stream, d_plan,
-                       d_list + ln_off_l, nln, 0, 2);
+  if (!big_action) {
+    const int rcp = enqueue_plan();
+    if (rcp) return rcp;
+  }
   for (int p = 0; p < kNumPhases; ++p) ctx->cur_launches[p] = 0;
   prof_mark(ctx, 0, stream);
-  // 2. shifted factorisations: Gauss-Jordan inverses (fast instances) and
-  //    pivoting LU (the rest), all (instance, shift) pairs of a class per launch
-  for (int c = 0; c < 3; ++c) {
-    const int nl = (int)fast_list[c].size();
+  // 2. shifted factorisations: Gauss-Jordan inverses (route 1) and pivoting
+  //    LU (route 0), all (instance, shift) pairs of a class per launch
+  for (int c = 0; c < 3 && gj_call; ++c) {
+    const int nl = (int)cls_list[c].size();
     if (!nl) continue;
-    const int *dl = d_list + fast_off[c];
+    const int *dl = d_list + cls_off[c];
     const dim3 gg(xcd_grid(nl, nterms));
     if (c == 0) hipLaunchKernelGGL((gj_inv_kernel<128, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 1);
     if (c == 1) hipLaunchKernelGGL((gj_inv_kernel<256, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 1);
@@ -1246,9 +1314,9 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     ctx->cur_launches[0]++;
   }
   for (int c = 0; c < 3; ++c) {
-    const int nl = (int)slow_list[c].size();
+    const int nl = (int)cls_list[c].size();
     if (!nl) continue;
-    const int *dl = d_list + slow_off[c];
+    const int *dl = d_list + cls_off[c];
     const dim3 glu(xcd_grid(nl, nterms));
     const int am = action ? 1 : 0;
 #define PFM_LU(NPM)                                                                            \
@@ -1275,9 +1343,9 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
 #define PFM_GJ_LN(NPM)                                                                             \
   do {                                                                                             \
     if (action)                                                                                    \
-      hipLaunchKernelGGL((gj_inv_kernel<NPM, true>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, -1); \
+      hipLaunchKernelGGL((gj_inv_kernel<NPM, true>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 2); \
     else                                                                                           \
-      hipLaunchKernelGGL((gj_inv_kernel<NPM, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, -1); \
+      hipLaunchKernelGGL((gj_inv_kernel<NPM, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 2); \
   } while (0)
     if (c == 0) PFM_GJ_LN(128);
     if (c == 1) PFM_GJ_LN(256);
@@ -1296,28 +1364,23 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     hipLaunchKernelGGL(ln_load_kernel, dim3(xcd_grid(nslot, t1 * t1)), dim3(256), 0, stream, d_desc, dl,
                        nslot, t1, d_plan, T, wsd, action ? 1 : 0);
     for (int J = 0; J < t1; ++J) {
-      hipLaunchKernelGGL(ln_dinv_kernel, dim3(nslot), dim3(256), 0, stream, d_desc, dl, nslot, T, wsd, J);
+      hipLaunchKernelGGL(ln_dinv_kernel, dim3(nslot), dim3(256), 0, stream, d_desc, dl, nslot, T, wsd, J, d_plan);
       hipLaunchKernelGGL(ln_row_kernel, dim3(xcd_grid(nslot, t1)), dim3(256), 0, stream, d_desc, dl, nslot,
-                         t1, T, wsd, J);
+                         t1, T, wsd, J, d_plan);
       hipLaunchKernelGGL(ln_upd_kernel, dim3(xcd_grid(nslot, t1 * nR)), dim3(256), 0, stream, d_desc, dl,
-                         nslot, t1, nR, T, wsd, J);
+                         nslot, t1, nR, T, wsd, J, d_plan);
     }
     ctx->cur_launches[0] += 1 + 3 * t1;
   }
   prof_mark(ctx, 1, stream);
   if (action) {
     // 3'. B = A / N column-major, then the N-step recurrence per column slab
-    int maxn = 0, maxp = 0;
-    for (int i = 0; i < batch; ++i) {
-      maxn = std::max(maxn, desc[i].npad);
-      maxp = std::max(maxp, probs[i].p);
-    }
     const int tnb = (maxn + 31) / 32;
     hipLaunchKernelGGL(prep_bt_kernel, dim3(tnb * tnb, batch), dim3(256), 0, stream, d_desc, d_plan, wsd, 1);
     for (int c = 0; c < 3; ++c) {
-      const int nl = (int)slow_list[c].size();
+      const int nl = (int)cls_list[c].size();
       if (!nl) continue;
-      const int *dl = d_list + slow_off[c];
+      const int *dl = d_list + cls_off[c];
 #define PFM_ACT(NPM, SWW)                                                                       \
   do {                                                                                          \
     const int ns = (maxp + SWW - 1) / SWW;                                                      \
@@ -1335,6 +1398,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
 #undef PFM_ACT
       ctx->cur_launches[1] += T.want_exp + T.want_phi;
     }
+    const int nln = (int)ln_list.size();
     if (nln) {
       // large instances: S = sum_k w_k X_k, R = a0 I + S B and P (phi1),
       // then the N steps U <- R U (+ U1) as K-split GEMMs
@@ -1342,14 +1406,14 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
       const int *dl = d_list + ln_off_l;
       hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nln), dim3(256), 0, stream, d_desc, dl, T, wsd, d_plan);
       PFM_SQ(2, lvbt, 1);  // level argument 1: B = A / N
-      PFM_SQ(1, lv[0], 1);
+      PFM_SQ(1, lv0, 1);
       const int nchain = T.want_exp + T.want_phi;
-      for (int c = 0; c < 3; ++c) {  // one launch runs all N steps
+      for (int c = 0; c < 2; ++c) {  // one launch runs all N steps
         const int nl = (int)act_list[c].size();
         if (!nl) continue;
-        int maxp = 1;
-        for (int i : act_list[c]) maxp = std::max(maxp, desc[i].p);
-        const int nslab = (maxp + 15) / 16;
+        int mp = 1;
+        for (int i : act_list[c]) mp = std::max(mp, desc[i].p);
+        const int nslab = (mp + 15) / 16;
         const int *dla = d_list + act_off[c];
         const dim3 gs(xcd_grid(nl, nchain * nslab));
         if (c == 0)
@@ -1361,36 +1425,35 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
         ctx->cur_launches[1]++;
       }
       const int nbig = (int)act_list[3].size();
-      const int *dlb = d_list + act_off[3];
-      int big_npm = 0, big_nmax = 0;
-      for (int i : act_list[3]) {
-        big_npm = std::max(big_npm, desc[i].npad);
-        big_nmax = std::max(big_nmax, h_plan[i].s);
-      }
-      if (nbig)
+      if (nbig) {
+        // the large action instances, big_nmax steps (read back above)
+        const int *dlb = d_list + act_off[3];
+        int big_npm = 0;
+        for (int i : act_list[3]) big_npm = std::max(big_npm, desc[i].npad);
         hipLaunchKernelGGL(ln_vprep_kernel, dim3(big_npm / 64, nbig), dim3(256), 0, stream, d_desc, dlb, nchain,
-                           wsd);
-      int ppmask = 0, ksmax = 1;
-      for (int i : act_list[3]) {
-        ppmask |= 1 << (ln_pp(desc[i].p) / 16 - 1);
-        ksmax = std::max(ksmax, ln_ks(desc[i].n));
-      }
-      const int nsub = (big_npm / 64) * ksmax;
-      const dim3 gv(xcd_grid(nbig, nsub));
-      for (int j = 1; nbig && j <= big_nmax; ++j) {
-        for (int ch = 0; ch < nchain; ++ch) {
-          const int phi = (ch == 1 || !T.want_exp) ? 1 : 0;
-          const int use_p = phi && j == 1;
-          const int inb = (j - 1) & 1, outb = j & 1;
+                           wsd, d_plan);
+        int ppmask = 0, ksmax = 1;
+        for (int i : act_list[3]) {
+          ppmask |= 1 << (ln_pp(desc[i].p) / 16 - 1);
+          ksmax = std::max(ksmax, ln_ks(desc[i].n));
+        }
+        const int nsub = (big_npm / 64) * ksmax;
+        const dim3 gv(xcd_grid(nbig, nsub));
+        for (int j = 1; j <= big_nmax; ++j) {
+          for (int ch = 0; ch < nchain; ++ch) {
+            const int phi = (ch == 1 || !T.want_exp) ? 1 : 0;
+            const int use_p = phi && j == 1;
+            const int inb = (j - 1) & 1, outb = j & 1;
 #define PFM_GEMV(PPV)                                                                              \
   if (ppmask & (1 << (PPV / 16 - 1)))                                                            \
     hipLaunchKernelGGL(ln_gemv_kernel<PPV>, gv, dim3(256), 0, stream, d_desc, dlb, nbig, nsub, d_plan, \
                        wsd, j, ch, use_p, inb);
-          PFM_GEMV(16) PFM_GEMV(32) PFM_GEMV(48) PFM_GEMV(64)
+            PFM_GEMV(16) PFM_GEMV(32) PFM_GEMV(48) PFM_GEMV(64)
 #undef PFM_GEMV
-          hipLaunchKernelGGL(ln_vreduce_kernel, dim3(big_npm / 64, nbig), dim3(256), 0, stream, d_desc, dlb,
-                             d_plan, wsd, j, ch, outb, 1.0, phi);
-          ctx->cur_launches[1] += 2;
+            hipLaunchKernelGGL(ln_vreduce_kernel, dim3(big_npm / 64, nbig), dim3(256), 0, stream, d_desc, dlb,
+                               d_plan, wsd, j, ch, outb, 1.0, phi);
+            ctx->cur_launches[1] += 2;
+          }
         }
       }
       ctx->cur_launches[1] += 3;
@@ -1407,8 +1470,6 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   }
   // 3. solves fused with the combination
   if (mixed) {
-    int maxn = 0;
-    for (int i = 0; i < batch; ++i) maxn = std::max(maxn, desc[i].npad);
     const int tnb = (maxn + 31) / 32;
     hipLaunchKernelGGL(prep_bt_kernel, dim3(tnb * tnb, batch), dim3(256), 0, stream, d_desc, d_plan, wsd, 0);
     double sw = 0.0, swp = 0.0;
@@ -1416,9 +1477,9 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     const double irtol = tol / (4.0 * std::max(sw, T.want_phi ? swp : 0.0));
     const int maxit = 3;
     for (int c = 0; c < 3; ++c) {
-      const int nl = (int)slow_list[c].size();
+      const int nl = (int)cls_list[c].size();
       if (!nl) continue;
-      const int *dl = d_list + slow_off[c];
+      const int *dl = d_list + cls_off[c];
 #define PFM_MIX(NPM, SWW)                                                                         \
   do {                                                                                            \
     const dim3 gs(xcd_grid(nl, NPM / SWW));                                                       \
@@ -1436,29 +1497,29 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
       ctx->cur_launches[1]++;
     }
   }
-  if (any_fast) {
+  if (any_gj) {
     // S = sum_k w_k X_k, then R = a0 I + S B (and Phi) for the Gauss-Jordan instances
     int maxnp = 0;
-    for (int i = 0; i < batch; ++i)
-      if (is_fast[i]) maxnp = std::max(maxnp, desc[i].npad);
+    for (int i : gj_cand) maxnp = std::max(maxnp, desc[i].npad);
     const int chunks = (int)(((int64_t)maxnp * maxnp / 4 + 255) / 256);
-    for (int c = 0; c < 3; ++c) {
-      const int nl = (int)fast_list[c].size();
+    for (int c = 0; c < 3 && gj_call; ++c) {
+      const int nl = (int)cls_list[c].size();
       if (!nl) continue;
       hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nl), dim3(256), 0, stream, d_desc,
-                         d_list + fast_off[c], T, wsd, d_plan);
+                         d_list + cls_off[c], T, wsd, d_plan);
     }
+    const int nln = (int)ln_list.size();
     if (nln)
       hipLaunchKernelGGL(combine_inv_kernel, dim3(chunks, nln), dim3(256), 0, stream, d_desc,
                          d_list + ln_off_l, T, wsd, d_plan);
     PFM_SQ(2, lvbt, 0);
-    PFM_SQ(1, lv[0], 0);
+    PFM_SQ(1, lv0, 0);
     ctx->cur_launches[1] += 2;
   }
   for (int c = 0; c < 3 && !mixed; ++c) {
-    const int nl = (int)slow_list[c].size();
+    const int nl = (int)cls_list[c].size();
     if (!nl) continue;
-    const int *dl = d_list + slow_off[c];
+    const int *dl = d_list + cls_off[c];
 #define PFM_SOLVE(NPM, SWW)                                                                      \
   do {                                                                                           \
     const dim3 gs(xcd_grid(nl, NPM / SWW));                                                      \
@@ -1476,16 +1537,32 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     ctx->cur_launches[1]++;
   }
   prof_mark(ctx, 2, stream);
-  // 4. squaring levels, one launch per level
-  for (int j = 1; j <= smax; ++j) {
-    PFM_SQ(0, lv[j], j);
+  // 4. squaring levels: the first pol_direct levels one launch each over
+  //    every instance's tiles (tiles of instances with s < level return at
+  //    once), the rest, whatever s is, from the persistent queue
+  for (int j = 1; j <= pol_direct; ++j) {
+    PFM_SQ(0, lvsq, j);
     ctx->cur_launches[2]++;
+  }
+  for (int g = 0; g < 2; ++g) {
+    const int ng = (int)sq_group[g].size();
+    if (!ng) continue;
+    const int *gl = d_list + sq_off[g];
+    hipLaunchKernelGGL(sq_queue_kernel, dim3(1), dim3(kQueueThreads), 0, stream, d_desc, d_plan, gl, ng,
+                       g ? 128 : 64, 1 + T.want_phi, pol_direct + 1, qp[g].q, qp[g].ord, qp[g].pre, qp[g].lstart,
+                       qp[g].done);
+    const int grid = std::max(1, occ[g] * ctx->num_cu);
+    if (g == 0)
+      hipLaunchKernelGGL(sq_persist_kernel<64>, dim3(grid), dim3(256), 0, stream, d_desc, d_plan, gl,
+                         1 + T.want_phi, qp[g].q, qp[g].ord, qp[g].pre, qp[g].lstart, qp[g].done, wsd, ctx->d_err);
+    else
+      hipLaunchKernelGGL(sq_persist_kernel<128>, dim3(grid), dim3(256), 0, stream, d_desc, d_plan, gl,
+                         1 + T.want_phi, qp[g].q, qp[g].ord, qp[g].pre, qp[g].lstart, qp[g].done, wsd, ctx->d_err);
+    ctx->cur_launches[2] += 2;
   }
   prof_mark(ctx, 3, stream);
   // 5. results to the caller's row-major buffers, then the info records
-  int maxn = 0;
-  for (int i = 0; i < batch; ++i) maxn = std::max(maxn, probs[i].n);
-  const int tn = (maxn + 31) / 32;  // stores run over the caller's n
+  const int tn = (maxc + 31) / 32;  // stores run over the caller's n
   hipLaunchKernelGGL(store_full_kernel, dim3(tn * tn, batch), dim3(256), 0, stream, d_desc, d_plan,
                      wsd, T.want_exp, T.want_phi);
   ctx->cur_launches[3]++;
@@ -1497,12 +1574,15 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   HIP_TRY(ctx, hipGetLastError());
   return PFM_OK;
   };
+#undef PFM_SQ
 
   // hipGraph reuse: eager the first time a launch sequence is seen; captured
   // and instantiated when the same sequence comes a second time in a row;
-  // replayed from then on.  Not on the null stream (it cannot be captured)
-  // or while phase timing is on.
-  if (!ctx->graphs || ctx->prof || stream == nullptr) return enqueue();
+  // replayed from then on (for a large action, the sequence after the
+  // read-back, with its step count in the signature).  Not on the null
+  // stream (it cannot be captured), while phase timing is on, or inside the
+  // caller's own capture.
+  if (!ctx->graphs || ctx->prof || stream == nullptr || capturing) return enqueue();
   uint64_t sig = 1469598103934665603ull;
   auto mix = [&](const void *p, size_t nbytes) {  // 64-bit words, then the tail bytes
     const unsigned char *b = (const unsigned char *)p;
@@ -1515,9 +1595,10 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     }
     for (; q < nbytes; ++q) sig = (sig ^ b[q]) * 1099511628211ull;
   };
-  const void *ptrs[6] = {ctx->ws, ctx->tasks, info, stream, d_desc, d_list};
-  const int64_t ints[10] = {f, m, prec, dtype, batch, force_plan, pol_gj, smax, ln_nmax, (int64_t)lists.size()};
-  const double dbls[5] = {tol, theta, a1e, a1p, T.a0e};
+  const void *ptrs[7] = {ctx->ws, ctx->tasks, info, stream, d_desc, d_list, ctx->d_err};
+  const int64_t ints[12] = {f, m, prec, dtype, batch, force_plan, pol_gj, pol_direct, pol_t128, ctx->num_cu,
+                            (int64_t)lists.size(), big_nmax};
+  const double dbls[6] = {tol, theta, a1e, a1p, T.a0e, cmax};
   mix(ptrs, sizeof ptrs);
   mix(ints, sizeof ints);
   mix(dbls, sizeof dbls);
@@ -1525,7 +1606,6 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   mix(desc.data(), desc.size() * sizeof(InstDesc));
   mix(lists.data(), lists.size() * sizeof(int));
   mix(all.data(), all.size() * sizeof(SqTask));
-  mix(svec.data(), svec.size() * sizeof(int));
   if (ctx->gexec && sig == ctx->gsig) {
     HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, stream));
     ++ctx->graph_replays;
@@ -1578,10 +1658,19 @@ int pfm_tune(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype, int ba
   const bool action = probs[0].p > 0;
   const bool emb = dtype == PFM_C128 || ee->pair != 0;
   const bool mixed = prec == PFM_MIXED;
-  // candidates that can differ for this kind of batch
+  // candidates that can differ for this kind of batch: the route policy
+  // (full real matrices: Gauss-Jordan vs LU; action or complex: the
+  // multi-workgroup route above 128 vs above 512), and for full matrices the
+  // squaring schedule (levels launched one by one, or all from the
+  // persistent queue) and the product tile (128 from npad 256 on, or 64)
+  std::vector<int> routes = (!action && !emb) ? std::vector<int>{0, 1} : std::vector<int>{0, 2};
+  // the tile choice only differs for a padded size of 256 or more
+  bool tile_matters = false;
+  for (int i = 0; i < batch; ++i) tile_matters |= (emb ? 2 * probs[i].n : probs[i].n) > 192;
   std::vector<int> cand;
-  if (!action && !emb) cand = {0, 1};  // Gauss-Jordan vs LU
-  else cand = {0, 2};                  // multi-workgroup route above 128 vs above 512
+  for (int tl = 0; tl < (action || !tile_matters ? 1 : kNumTiles); ++tl)
+    for (int sc = 0; sc < (action ? 1 : kNumSchedules); ++sc)
+      for (int r : routes) cand.push_back(r + kNumRoutePolicies * (sc + kNumSchedules * tl));
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipEvent_t e0, e1;
   HIP_TRY(ctx, hipEventCreate(&e0));

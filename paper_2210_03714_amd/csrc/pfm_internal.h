@@ -1,5 +1,6 @@
 // Internal structures shared by the host runtime and the kernels of libpfm.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace pfm {
@@ -42,7 +43,15 @@ struct InstDesc {
   int64_t v_off;     // large action instances: step vectors and partial products
   int64_t perm_ioff; // nterms * npad : row permutation of each factorisation
   int64_t ipiv_ioff; // nterms * npad : LAPACK-style pivot sequence
+  int32_t rflags;    // kRf* bits: the routes this instance may take (from its size alone)
+  int32_t rpad_;
 };
+
+// Routes an instance may take, fixed by the host from the sizes; the device
+// picks among them after the plan (route_kernel).
+constexpr int kRfMayLn = 1;  // the multi-workgroup Gauss-Jordan route (action / complex above the threshold)
+constexpr int kRfLarge = 2;  // n > 512: that route only
+constexpr int kRfGj = 4;     // the single-workgroup Gauss-Jordan route (real full matrices)
 
 // Device-side plan of one instance.
 struct PlanRec {
@@ -50,11 +59,15 @@ struct PlanRec {
   int32_t status;     // PFM_* status bits
   int32_t bad_shift;  // smallest shift index with a zero pivot (0x7fffffff: none)
   int32_t ir_iters;
-  int32_t route;      // 1: Gauss-Jordan inverse route, 0: pivoting LU route
+  int32_t route;      // 0: pivoting LU route, 1: Gauss-Jordan inverses, 2: the multi-workgroup route
   int32_t pad_;
   double eta;         // ||A||_1
   double resid;
 };
+
+// The instance takes route r and is computed (kernels of every route are
+// launched over all candidates; the others return at once).
+__host__ __device__ inline bool on_route(const PlanRec &P, int r) { return P.route == r && !(P.status & 8); }
 
 // The shift/weight list of a call (passed by value to kernels).
 // Real weights (fold = 0): Z_k is accumulated as we_k Z_k and wp_k Z_k.

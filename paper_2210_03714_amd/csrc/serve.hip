@@ -2,7 +2,7 @@
 // pfm_eval_batched (pfm_srv_* in pfm.h).
 //
 // One scheduler thread owns `lanes` lanes; a lane is a context (its own
-// workspace, pinned staging and plan read-back) plus a stream and a
+// workspace and pinned staging) plus a stream and a
 // completion event, so up to `lanes` batches are in flight on the GPU at
 // once.  Each scheduler pass:
 //   1. retires lanes whose completion event has fired: their requests
@@ -259,8 +259,8 @@ int launch(pfm_server *S, Lane &L, std::vector<Req *> &batch) {
 }
 
 // One thread per lane: launches the batches the scheduler hands over, so
-// that one lane waiting for its plan read-back (the GPU may be busy with
-// other lanes' work) never holds up the dispatch of the others.
+// that one lane whose call waits (to grow its workspace, or for the step
+// count of a large action) never holds up the dispatch of the others.
 void lane_main(pfm_server *S, Lane *L) {
   (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);

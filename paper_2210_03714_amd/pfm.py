@@ -94,6 +94,7 @@ def lib():
         L.pfm_selftest_mfma.argtypes = [i32, dp]
         L.pfm_profile.argtypes = [vp, i32]
         L.pfm_set_route.argtypes = [vp, i32]
+        L.pfm_set_schedule.argtypes = [vp, i32]
         L.pfm_set_graphs.argtypes = [vp, i32]
         L.pfm_eval_batched_tols.argtypes = [vp, i32, i32, dp, dbl, i32, i32, i32, ctypes.POINTER(Problem), vp,
                                             i32, vp]
@@ -204,6 +205,13 @@ class Context:
         """ROUTE_AUTO (Gauss-Jordan where pivoting provably never swaps) or
         ROUTE_LU (pivoting LU for every instance)."""
         rc = lib().pfm_set_route(self._h, int(route))
+        if rc:
+            raise PfmError(rc, self.last_error())
+
+    def set_schedule(self, direct_levels):
+        """Squaring levels launched one by one before the persistent queue
+        takes the rest (0: all from the queue)."""
+        rc = lib().pfm_set_schedule(self._h, int(direct_levels))
         if rc:
             raise PfmError(rc, self.last_error())
 

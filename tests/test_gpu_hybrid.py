@@ -124,10 +124,13 @@ def test_unsupported_combinations(torch_dev):
     with pytest.raises(pfm.PfmError) as e:
         pfm.expm([At.to(torch.complex128)], ("exp",), m=10)
     assert e.value.code == pfm.ERR_UNSUPPORTED
-    # a forced s = 0 leaves |c_k| ||B||_1 = 1 > 1/2: no Gauss-Jordan route
-    with pytest.raises(pfm.PfmError) as e:
-        pfm.expm([At], ("exp",), m=10, force_plan=0)
-    assert e.value.code == pfm.ERR_UNSUPPORTED
+    # a forced s = 0 leaves |c_k| ||B||_1 = 1 > 1/2: no Gauss-Jordan route;
+    # the device finds that after the plan and does not compute the instance
+    out = {"exp": [torch.full_like(At, 7.25)]}
+    res, info = pfm.expm([At], ("exp",), m=10, force_plan=0, out=out)
+    torch.cuda.synchronize()
+    assert info[0]["status"] & pfm.NOT_COMPUTED
+    assert torch.all(res["exp"][0] == 7.25)
     ctx = pfm.Context(0)
     ctx.set_route(pfm.ROUTE_LU)
     with pytest.raises(pfm.PfmError) as e:
