@@ -155,8 +155,10 @@ const char *pfm_last_error(const pfm_ctx *ctx);
  * solve eq. (4) with a_k = 1/(k+1)! on the same shifts.  m = 10 (exp only):
  * the hybrid 10th-order set of §4.3 with the smaller coefficients
  * (c = -+1/8, -+1/10, ..., -+1/16; b_9 = 2000, b_10 = -3500), whose
- * polynomial part pfm_poly returns (a0 = d0 + sum_k b_k).  Arrays must hold
- * 16 entries.  Returns PFM_ERR_UNSUPPORTED for an unknown (f, m). */
+ * polynomial part pfm_poly returns (a0 = d0 + sum_k b_k); m = PFM_R10STAR
+ * (exp only): the other one, R*10 (c_i = 1/(6 + i), b_9 = -5 10^4,
+ * b_10 = 3.5 10^5).  Arrays must hold 16 entries.  Returns
+ * PFM_ERR_UNSUPPORTED for an unknown (f, m). */
 int pfm_coeffs(int f, int m, int *n_terms, double *c_re, double *c_im,
                double *w_re, double *w_im, double *a0, int *order,
                int *is_pair);
@@ -176,13 +178,25 @@ int pfm_theta(int f, int m, double tol, double *theta);
  * PFM_NOT_COMPUTED). */
 #define PFM_MAX_SQUARINGS 1000
 
+/* The solve count that selects the other hybrid 10th-order set of §4.3,
+ * R*10 (eqs. Frac10ciNO-Frac10biNO: c_i = 1/(6 + i), i = 1..10, b_9 = -5 10^4,
+ * b_10 = 3.5 10^5), the set the θ_10 of §5.1 (Table 2) is computed for.
+ * Ten shifted solves, exp only, like m = 10; its weights are large
+ * (sum |w_k| about 1.3e6), so its rounding floor (pfm_eval_batched) is about
+ * 2e-10: tolerances below it are refused. */
+#define PFM_R10STAR 110
+
 /* Evaluate a batch of problems.
  *   f          PFM_EXP, PFM_PHI1 or both
  *   m          number of shifted solves: 1, 4, 5 or 8; or 10, the hybrid set
  *              of §4.3, for PFM_EXP of real full matrices in binary64 on the
  *              Gauss-Jordan routes (every |c_k| ||B||_1 <= 1/2, which planned
- *              steps meet; PFM_ERR_UNSUPPORTED otherwise)
- *   tol        target of the forward bound per scaled step, in (0, 1)
+ *              steps meet; PFM_ERR_UNSUPPORTED otherwise); or PFM_R10STAR,
+ *              the other hybrid set, likewise
+ *   tol        target of the forward bound per scaled step, in (0, 1), and
+ *              not below the set's rounding floor (sum_k |w_k| + |d1| + |d2|)
+ *              θ(tol) 2^-53, which the round-off form cannot go under
+ *              (PFM_ERR_UNSUPPORTED: only R*10 has a floor above 1e-12)
  *   prec       PFM_FP64 or PFM_MIXED
  *   dtype      PFM_R64 or PFM_C128 (for A, V and outputs)
  *   batch      number of problems, >= 1
@@ -211,6 +225,31 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec,
 int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int prec, int dtype,
                           int batch, const pfm_problem *probs, pfm_info *info, int force_plan,
                           pfm_stream_t stream);
+
+/* A caller-given partial-fraction decomposition (§2: a rational function
+ * with simple poles, r(x) = d0 + sum_k b_k / (1 - c_k x), each pole 1/c_k real
+ * or complex): r(A) (p == 0; F_exp receives it) or r(A) V (p >= 1; one step,
+ * F_exp), evaluated in the round-off form of §4.3 as
+ *     a0 I + sum_k w_k (I - c_k A)^{-1} A,   w_k = b_k c_k,  a0 = d0 + sum_k b_k,
+ * with no scaling (s = 0, N = 1: choose the norm range of A beforehand) and
+ * every shifted solve independent.  c_k = c_re[k] + i c_im[k] and
+ * w_k = w_re[k] + i w_im[k] (c_im, w_im may be NULL: all real).  With
+ * conj_pairs != 0 every term with c_im[k] != 0 stands for itself and its
+ * conjugate (c_k*, w_k*), so that a real A gives a real r(A); complex shifts on
+ * real A require it.  A real shift needs a real weight on real A.
+ *   nterms     1..16 terms (16 solves at most, conjugates included, for
+ *              complex A)
+ *   dtype      PFM_R64 or PFM_C128 (A, V and F_exp); the problems as for
+ *              pfm_eval_batched, F_phi1 ignored
+ * Real shifts on real A take the real routes (Gauss-Jordan where every
+ * |c_k| ||A||_1 <= 1/2, else pivoting LU), anything complex the embedded
+ * route (complex: n <= 256).  binary64 only.  pfm_info.plan is 0 (full) or
+ * 1 (action), order 0, theta +inf (no bound is known for the set).
+ * PFM_ERR_INVALID for a bad term, PFM_ERR_UNSUPPORTED for complex shifts on
+ * real A without conj_pairs. */
+int pfm_eval_rational(pfm_ctx *ctx, int nterms, const double *c_re, const double *c_im, const double *w_re,
+                      const double *w_im, double a0, int conj_pairs, int dtype, int batch,
+                      const pfm_problem *probs, pfm_info *info, pfm_stream_t stream);
 
 /* ------------------------------------------------------------------------
  * Tridiagonal A (§2.1, §5): the action f(A)V for real A given by its three
@@ -253,8 +292,9 @@ typedef struct {
  *              |c_k| ||B||_1 >= 1 may meet a zero pivot, reported as
  *              PFM_SINGULAR_SHIFT, since the sweeps do not interchange rows)
  *   m          4, 5 or 8 (the real shift sets; PFM_ERR_UNSUPPORTED for m = 1),
- *              or 10: the hybrid set of §4.3 in the round-off form (R10' of
- *              §5), exp only (PFM_ERR_UNSUPPORTED with PFM_PHI1)
+ *              or 10 / PFM_R10STAR: the hybrid sets of §4.3 in the round-off
+ *              form (R10' of §5), exp only (PFM_ERR_UNSUPPORTED with
+ *              PFM_PHI1 or a tol below the set's rounding floor)
  * pfm_info.route is 3.  With pfm_profile on, phase 0 times the
  * factorisations and phase 1 the N steps.  The call only enqueues work on
  * `stream` (nothing is read back): an instance whose N would exceed

@@ -209,7 +209,7 @@ REAL_SETS = {4: shifts_R4, 5: shifts_R5, 8: shifts_R8}
 LOG1M_SETS = {5: shifts_frac4}
 # m = 10: the hybrid set of §4.3 with the smaller coefficients (R10), for
 # the exponential (the paper gives no phi1 weights for it)
-HYBRID_SETS = {10: "R10"}
+HYBRID_SETS = {10: "R10", 110: "R10*"}  # registry keys of the two sets (110: R*10)
 
 
 def real_set(func, m):

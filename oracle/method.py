@@ -293,6 +293,42 @@ def action_normal(mu, U, V, funcs=("exp",), m=8, N=1, exact_scalars=False):
     return res
 
 
+def rational(A, c, w, a0, conj_pairs=True, V=None):
+    """A caller-given partial-fraction set (§2, a rational function with simple
+    poles 1/c_k), in the round-off form of §4.3 with no scaling:
+        r(A) = a0 I + sum_k w_k (I - c_k A)^{-1} A        (V is None), or
+        r(A) V = a0 V + sum_k w_k (I - c_k A)^{-1} (A V)  (one step).
+    With conj_pairs every term with a complex shift also stands for its
+    conjugate (c_k*, w_k*); on real A and V the pair is then 2 Re(w_k Z_k)
+    (the conjugate solve is the conjugate of Z_k) and the result is real.  One
+    LAPACK getrf/getrs per solve, the terms summed in the listed order."""
+    A = np.asarray(A)
+    n = A.shape[0]
+    c = [complex(x) for x in c]
+    w = [complex(x) for x in w]
+    real_in = not np.iscomplexobj(A) and (V is None or not np.iscomplexobj(V))
+    if real_in and not conj_pairs and any(x.imag != 0.0 for x in c + w):
+        raise ValueError("complex terms on real A need the conjugates for a real result")
+    out_complex = not real_in
+    dt = np.complex128 if (out_complex or any(x.imag != 0.0 for x in c)) else np.float64
+    I = np.eye(n)
+    rhs = A if V is None else A @ np.asarray(V)
+    acc = (a0 * (I if V is None else np.asarray(V))).astype(np.complex128 if out_complex else np.float64)
+    for ck, wk in zip(c, w):
+        shift = ck if (out_complex or ck.imag != 0.0) else ck.real
+        Z = sla.lu_solve(sla.lu_factor(I - shift * A), rhs.astype(dt))
+        if out_complex:
+            acc = acc + wk * Z
+            if conj_pairs and ck.imag != 0.0:
+                Zc = sla.lu_solve(sla.lu_factor(I - ck.conjugate() * A), rhs.astype(dt))
+                acc = acc + wk.conjugate() * Zc
+        elif ck.imag != 0.0:
+            acc = acc + 2.0 * (wk * Z).real
+        else:
+            acc = acc + wk.real * Z.real
+    return acc
+
+
 def rel_fro(X, Xref):
     """Relative Frobenius error ||X - Xref||_F / ||Xref||_F."""
     X = np.asarray(X)

@@ -9,8 +9,9 @@ constants each rounded once from an exact value:
 * the order of the approximation,
 * the forward-bound series coefficients d_k = |a_k - alpha_k| (§3), from
   which the library finds θ(tol) at run time by bisection,
-* for the hybrid 10th-order set of §4.3 (m = 10, the exponential), the
-  polynomial part d_1 x + d_2 x^2 of r(x) = d_0 + d_1 x + d_2 x^2 +
+* for the two hybrid 10th-order sets of §4.3 (the exponential: m = 10,
+  the one with the smaller coefficients, and m = 110 for the other, R*10),
+  the polynomial part d_1 x + d_2 x^2 of r(x) = d_0 + d_1 x + d_2 x^2 +
   sum b_i / (1 - c_i x); its d_0 is in a0 = d_0 + sum b_i.
 
 Weights come from the transposed Vandermonde system of §2 (eq. 4), solved here
@@ -95,15 +96,21 @@ def real_entry(func, m):
     return {"a0": a[0], "order": len(c) - 1, "terms": terms, "pair": 0, "d": d}
 
 
-def hybrid_entry():
-    """§4.3, the set with c_{2i-1} = -1/(6+2i), c_{2i} = 1/(6+2i) and b_9 = 2000,
-    b_10 = -3500: b_1..b_8 from sum_i b_i c_i^k = 1/k!, k = 3..10, through
-    the Lagrange basis of the first eight shifts (x^3 times it gives the
-    rows k = 3..10), then d_k = 1/k! - sum_i b_i c_i^k, k = 0..2."""
+def hybrid_entry(star=False):
+    """§4.3: star = False, the set with c_{2i-1} = -1/(6+2i), c_{2i} = 1/(6+2i)
+    and b_9 = 2000, b_10 = -3500; star = True, the set with c_i = 1/(6+i),
+    i = 1..10, and b_9 = -5 10^4, b_10 = 3.5 10^5.  b_1..b_8 from
+    sum_i b_i c_i^k = 1/k!, k = 3..10, through the Lagrange basis of the first
+    eight shifts (x^3 times it gives the rows k = 3..10), then
+    d_k = 1/k! - sum_i b_i c_i^k, k = 0..2."""
     c = []
-    for i in range(1, 6):
-        c += [Q(-1, 6 + 2 * i), Q(1, 6 + 2 * i)]
-    b9, b10 = Q(2000), Q(-3500)
+    if star:
+        c = [Q(1, 6 + i) for i in range(1, 11)]
+        b9, b10 = Q(-50000), Q(350000)
+    else:
+        for i in range(1, 6):
+            c += [Q(-1, 6 + 2 * i), Q(1, 6 + 2 * i)]
+        b9, b10 = Q(2000), Q(-3500)
     a = series("exp", KBOUND)
     # sum_{i<8} (b_i c_i^3) c_i^j = a_{j+3} - b9 c9^{j+3} - b10 c10^{j+3}, j = 0..7
     rhs = [a[j + 3] - b9 * c[8] ** (j + 3) - b10 * c[9] ** (j + 3) for j in range(8)]
@@ -180,6 +187,7 @@ def emit(path):
             e = pair_entry(func) if m == 1 else real_entry(func, m)
             entries.append((m, fi, e))
     entries.append((10, 0, hybrid_entry()))  # the exponential only
+    entries.append((110, 0, hybrid_entry(star=True)))  # R*10, the exponential only
     entries.append((5, 2, real_entry("log1m", 5)))  # log(1 - x), evaluated at s = 0
     lines = ["/* Generated by gen_tables.py -- do not edit. */",
              "#define PFM_KBOUND %d" % KBOUND,

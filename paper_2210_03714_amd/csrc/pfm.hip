@@ -129,6 +129,8 @@ int set_err(pfm_ctx *ctx, int code, const char *fmt, ...) {
       return set_err(ctx, PFM_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
   } while (0)
 
+inline bool T_want_phi(int f) { return f != PFM_LOG1M && (f & PFM_PHI1); }
+
 // table index of a single function bit (PFM_EXP 0, PFM_PHI1 1, PFM_LOG1M 2)
 inline int func_index(int f) { return f == PFM_EXP ? 0 : (f == PFM_PHI1 ? 1 : 2); }
 
@@ -157,6 +159,18 @@ double theta_of(const PfmSetEntry *e, double tol) {
   double v = (double)lo;
   if ((long double)v > lo) v = std::nextafter(v, 0.0);
   return v;
+}
+
+// The rounding floor of the round-off form (§4.3): a scaled step's result
+// carries rounding of about (sum_k |w_k| + |d1| + |d2|) θ u (u = 2^-53), which
+// the cancellation in the sum does not remove, so a tolerance below it cannot
+// be met.  It is below 1e-14 for the partial-fraction sets, about 6e-13 for
+// the hybrid set m = 10 at 1e-12, and about 2e-10 for R*10 (m = 110).
+double rounding_floor(const PfmSetEntry *e, double theta) {
+  if (!e) return 0.0;
+  long double s = fabsl((long double)e->poly[0]) + fabsl((long double)e->poly[1]);
+  for (int k = 0; k < e->nterms; ++k) s += (e->pair ? 2.0L : 1.0L) * (long double)std::hypot(e->w_re[k], e->w_im[k]);
+  return (double)(s * (long double)theta * 0x1p-53L);
 }
 
 inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -451,6 +465,11 @@ int sparse_terms(pfm_ctx *ctx, const char *what, int f, int m, double tol, TriTe
     return set_err(ctx, PFM_ERR_UNSUPPORTED, "the hybrid set is provided for the exponential only");
   const int rc = pfm_theta(f, m, tol, theta);
   if (rc) return set_err(ctx, rc, "theta failed");
+  {
+    const double fl = std::max(rounding_floor(ee, *theta), (f & PFM_PHI1) ? rounding_floor(ep, *theta) : 0.0);
+    if (tol < fl)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED, "tol %g is below the rounding floor %.2g of the m = %d set", tol, fl, m);
+  }
   memset(T, 0, sizeof *T);
   T->nterms = ee->nterms;
   T->nf = 0;
@@ -806,11 +825,24 @@ int pfm_eval_batched(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype
   return pfm_eval_batched_tols(ctx, f, m, nullptr, tol, prec, dtype, batch, probs, info, force_plan, stream);
 }
 
-int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int prec, int dtype,
-                          int batch, const pfm_problem *probs, pfm_info *info, int force_plan,
-                          pfm_stream_t stream_) {
+}  // extern "C"
+
+namespace {
+
+// A caller-given partial-fraction set (pfm_eval_rational): the terms as the
+// kernels take them, and whether any shift is complex.
+struct CustomSet {
+  Terms T;
+  bool complex_shift;
+};
+
+int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int prec, int dtype, int batch,
+              const pfm_problem *probs, pfm_info *info, int force_plan, pfm_stream_t stream_,
+              const CustomSet *cs) {
   if (!ctx) return PFM_ERR_INVALID;
   const bool log1m = f == PFM_LOG1M;
+  // a caller-given set: no scaling identity, r(A) itself (s = 0) or one step
+  // of the action (N = 1)
   if ((f < 1 || f > 3) && !log1m) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
   if (tols) {  // per-instance tolerances: the scalar is their minimum
     if (batch < 1) return set_err(ctx, PFM_ERR_INVALID, "empty batch");
@@ -839,26 +871,36 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     if (misaligned(P.A) || misaligned(P.V) || misaligned(P.F_exp) || misaligned(P.F_phi1))
       return set_err(ctx, PFM_ERR_INVALID, "problem %d: an array is not 8-byte aligned", i);
   }
-  const PfmSetEntry *ee = find_set(m, log1m ? 2 : 0), *ep = find_set(m, 1);
-  if (log1m) {
-    // log(1 - A): its own set, evaluated at s = 0 (no scaling identity)
-    if (!ee) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no log(1 - x) set for m = %d", m);
-    if (prec != PFM_FP64 || dtype != PFM_R64 || action)
-      return set_err(ctx, PFM_ERR_UNSUPPORTED, "log(1 - A) is provided for real full matrices in binary64");
-    ep = ee;  // the phi1 slot is never read (want_phi = 0)
-  }
-  const bool hybrid = ee && (ee->poly[0] != 0.0 || ee->poly[1] != 0.0);
-  if (!ee || (!ep && !hybrid)) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
-  if (hybrid) {
-    // the hybrid set of §4.3: the exponential of real matrices in binary64,
-    // on the Gauss-Jordan routes (checked after the plan)
-    if (f != PFM_EXP || prec != PFM_FP64 || dtype != PFM_R64 || action)
-      return set_err(ctx, PFM_ERR_UNSUPPORTED,
-                     "m = %d (the hybrid set) is provided for exp(A) of real matrices in binary64", m);
-    ep = ee;  // no phi1 weights; never read (want_phi = 0)
+  const PfmSetEntry *ee = nullptr, *ep = nullptr;
+  bool hybrid = false, pairs = false;
+  if (cs) {
+    if (prec != PFM_FP64)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED, "a caller-given set is evaluated in binary64 only");
+    pairs = cs->complex_shift;  // complex shifts: the embedded route
+  } else {
+    ee = find_set(m, log1m ? 2 : 0);
+    ep = find_set(m, 1);
+    if (log1m) {
+      // log(1 - A): its own set, evaluated at s = 0 (no scaling identity)
+      if (!ee) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no log(1 - x) set for m = %d", m);
+      if (prec != PFM_FP64 || dtype != PFM_R64 || action)
+        return set_err(ctx, PFM_ERR_UNSUPPORTED, "log(1 - A) is provided for real full matrices in binary64");
+      ep = ee;  // the phi1 slot is never read (want_phi = 0)
+    }
+    hybrid = ee && (ee->poly[0] != 0.0 || ee->poly[1] != 0.0);
+    if (!ee || (!ep && !hybrid)) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
+    if (hybrid) {
+      // the hybrid set of §4.3: the exponential of real matrices in binary64,
+      // on the Gauss-Jordan routes (checked after the plan)
+      if (f != PFM_EXP || prec != PFM_FP64 || dtype != PFM_R64 || action)
+        return set_err(ctx, PFM_ERR_UNSUPPORTED,
+                       "m = %d (the hybrid set) is provided for exp(A) of real matrices in binary64", m);
+      ep = ee;  // no phi1 weights; never read (want_phi = 0)
+    }
+    pairs = ee->pair != 0;
   }
   const bool cplx = dtype == PFM_C128;
-  const bool pairs = ee->pair != 0;
+  const int order_v = cs ? 0 : ee->order;
   const bool mixed = prec == PFM_MIXED;
   if (mixed && (cplx || pairs || action))
     return set_err(ctx, PFM_ERR_UNSUPPORTED,
@@ -871,7 +913,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     if (mixed || pairs)
       return set_err(ctx, PFM_ERR_UNSUPPORTED,
                      "problem %d: n = %d needs the large-instance route, which has no %s", i, probs[i].n,
-                     mixed ? "mixed-precision variant" : "conjugate-pair (m = 1) variant");
+                     mixed ? "mixed-precision variant" : "conjugate-pair (complex shift) variant");
     if (nk > kLargeMax)
       return set_err(ctx, PFM_ERR_UNSUPPORTED, "problem %d: n = %d exceeds the largest size (%s%d)", i,
                      probs[i].n, emb ? "complex: n <= " : "n <= ", emb ? kLargeMax / 2 : kLargeMax);
@@ -879,11 +921,13 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
       return set_err(ctx, PFM_ERR_UNSUPPORTED, "problem %d: p = %d > 64 at n > 512 (split V)", i, probs[i].p);
   }
 
-  double theta;
-  int rc = pfm_theta(f, m, tol, &theta);
-  if (rc) return set_err(ctx, rc, "theta failed");
+  double theta = INFINITY;  // a caller-given set has no bound: the caller scales A
+  if (!cs) {
+    const int rc = pfm_theta(f, m, tol, &theta);
+    if (rc) return set_err(ctx, rc, "theta failed");
+  }
   std::vector<double> thetas(batch, theta);
-  if (tols) {
+  if (tols && !cs) {
     std::map<double, double> seen;
     for (int i = 0; i < batch; ++i) {
       auto it = seen.find(tols[i]);
@@ -895,9 +939,18 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
       thetas[i] = it->second;
     }
   }
+  for (int i = 0; i < (cs ? 0 : tols ? batch : 1); ++i) {
+    const double ti = tols ? tols[i] : tol, th = thetas[i];
+    const double fl = std::max(rounding_floor(ee, th), T_want_phi(f) ? rounding_floor(ep, th) : 0.0);
+    if (ti < fl)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED, "tol %g is below the rounding floor %.2g of the m = %d set", ti, fl, m);
+  }
 
   Terms T;
   memset(&T, 0, sizeof T);
+  if (cs) {
+    T = cs->T;
+  } else {
   T.want_exp = ((f & PFM_EXP) || log1m) ? 1 : 0;  // log(1 - A) runs in the exp slot
   T.want_phi = (f & PFM_PHI1) ? 1 : 0;
   T.a0e = ee->a0;
@@ -931,6 +984,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     }
     T.nterms = k;
     T.pair_real = cplx ? 0 : 1;
+  }
   }
   const int nterms = T.nterms;
 
@@ -1274,7 +1328,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     hipLaunchKernelGGL(plan_init_kernel, dim3(nb), dim3(256), 0, stream, d_plan, batch);
     hipLaunchKernelGGL(norm_kernel, dim3((maxc + 63) / 64, batch), dim3(256), 0, stream, d_desc, d_plan);
     hipLaunchKernelGGL(plan_finish_kernel, dim3(nb), dim3(256), 0, stream, d_desc, d_plan, batch,
-                       action ? 1 : 0, force_plan, log1m ? 1 : 0);
+                       action ? 1 : 0, cs && action ? 1 : force_plan, (log1m || (cs && !action)) ? 1 : 0);
     hipLaunchKernelGGL(route_kernel, dim3(nb), dim3(256), 0, stream, d_desc, d_plan, batch, action ? 1 : 0, cmax,
                        hybrid ? 1 : 0);
   }
@@ -1464,7 +1518,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
     if (ctx->prof) ctx->prof_pending = true;
     if (info)
       hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_desc, d_plan,
-                         (InfoRec *)info, batch, ee->order);
+                         (InfoRec *)info, batch, order_v);
     HIP_TRY(ctx, hipGetLastError());
     return PFM_OK;
   }
@@ -1570,7 +1624,7 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   if (ctx->prof) ctx->prof_pending = true;
   if (info)
     hipLaunchKernelGGL(info_kernel, dim3((batch + 255) / 256), dim3(256), 0, stream, d_desc, d_plan,
-                       (InfoRec *)info, batch, ee->order);
+                       (InfoRec *)info, batch, order_v);
   HIP_TRY(ctx, hipGetLastError());
   return PFM_OK;
   };
@@ -1634,6 +1688,83 @@ int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double
   HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, stream));
   ++ctx->graph_captures;
   return PFM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pfm_eval_batched_tols(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int prec, int dtype,
+                          int batch, const pfm_problem *probs, pfm_info *info, int force_plan,
+                          pfm_stream_t stream) {
+  return eval_impl(ctx, f, m, tols, tol, prec, dtype, batch, probs, info, force_plan, stream, nullptr);
+}
+
+int pfm_eval_rational(pfm_ctx *ctx, int nterms, const double *c_re, const double *c_im, const double *w_re,
+                      const double *w_im, double a0, int conj_pairs, int dtype, int batch,
+                      const pfm_problem *probs, pfm_info *info, pfm_stream_t stream) {
+  if (!ctx) return PFM_ERR_INVALID;
+  if (nterms < 1 || nterms > kMaxTerms || !c_re || !w_re)
+    return set_err(ctx, PFM_ERR_INVALID, "nterms must lie in [1, %d], with c_re and w_re given", kMaxTerms);
+  if (dtype != PFM_R64 && dtype != PFM_C128) return set_err(ctx, PFM_ERR_INVALID, "bad dtype");
+  if (!std::isfinite(a0)) return set_err(ctx, PFM_ERR_INVALID, "a0 is not finite");
+  bool any_complex = false;
+  for (int k = 0; k < nterms; ++k) {
+    const double ci = c_im ? c_im[k] : 0.0, wi = w_im ? w_im[k] : 0.0;
+    if (!std::isfinite(c_re[k]) || !std::isfinite(ci) || !std::isfinite(w_re[k]) || !std::isfinite(wi))
+      return set_err(ctx, PFM_ERR_INVALID, "term %d is not finite", k);
+    if (ci == 0.0 && wi != 0.0 && dtype == PFM_R64)
+      return set_err(ctx, PFM_ERR_INVALID, "term %d: a real shift with a complex weight on real A", k);
+    any_complex |= ci != 0.0;
+  }
+  if (any_complex && dtype == PFM_R64 && !conj_pairs)
+    return set_err(ctx, PFM_ERR_UNSUPPORTED,
+                   "complex shifts on real A give a complex r(A): pass conj_pairs, or complex A and outputs");
+  CustomSet cs;
+  memset(&cs, 0, sizeof cs);
+  Terms &T = cs.T;
+  T.want_exp = 1;
+  T.a0e = a0;
+  const bool emb = any_complex || dtype == PFM_C128;
+  if (!emb) {
+    // real shifts and weights on real A: the real routes
+    T.nterms = nterms;
+    for (int k = 0; k < nterms; ++k) {
+      T.c_re[k] = c_re[k];
+      T.we_re[k] = w_re[k];
+    }
+  } else {
+    // the embedded route, each weight folded into its solve's right-hand
+    // side; on real A every term counts 2 Re(w_k Z_k): a complex shift for
+    // itself and its conjugate, a real one with half its weight (exact)
+    const bool pr = dtype == PFM_R64;
+    int k2 = 0;
+    auto add = [&](double cr, double ci, double wr, double wi) -> bool {
+      if (k2 >= kMaxTerms) return false;
+      T.c_re[k2] = cr;
+      T.c_im[k2] = ci;
+      T.we_re[k2] = wr;
+      T.we_im[k2] = wi;
+      T.fold[k2] = 1;
+      T.fn[k2] = 0;
+      ++k2;
+      return true;
+    };
+    for (int k = 0; k < nterms; ++k) {
+      const double ci = c_im ? c_im[k] : 0.0, wi = w_im ? w_im[k] : 0.0;
+      bool ok;
+      if (pr) ok = ci != 0.0 ? add(c_re[k], ci, w_re[k], wi) : add(c_re[k], 0.0, 0.5 * w_re[k], 0.0);
+      else {
+        ok = add(c_re[k], ci, w_re[k], wi);
+        if (ok && conj_pairs && ci != 0.0) ok = add(c_re[k], -ci, w_re[k], -wi);
+      }
+      if (!ok) return set_err(ctx, PFM_ERR_INVALID, "more than %d solves with the conjugates", kMaxTerms);
+    }
+    T.nterms = k2;
+    T.pair_real = pr ? 1 : 0;
+  }
+  cs.complex_shift = emb;
+  return eval_impl(ctx, PFM_EXP, 0, nullptr, 0.5, PFM_FP64, dtype, batch, probs, info, -1, stream, &cs);
 }
 
 int pfm_set_graphs(pfm_ctx *ctx, int enable) {

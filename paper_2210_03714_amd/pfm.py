@@ -31,6 +31,7 @@ ERR_BUDGET = -3
 ERR_HIP = -4
 ERR_DEVICE = -5
 
+R10STAR = 110                       # PFM_R10STAR: the hybrid set R*10 of §4.3
 MAX_STEPS = 1 << 20                 # PFM_MAX_STEPS: more action steps are PFM_NOT_COMPUTED
 NOALLOC_MAX_BYTES = 64 << 20        # PFM_NOALLOC_MAX_BYTES
 NOALLOC_MAX_BATCH = 1024            # PFM_NOALLOC_MAX_BATCH
@@ -115,6 +116,8 @@ def lib():
         L.pfm_srv_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p, dp]
         L.pfm_profile_read.argtypes = [vp, dp, ip, ip]
         L.pfm_tri_action.argtypes = [vp, i32, i32, dbl, i32, ctypes.POINTER(TriProblem), vp, i32, vp]
+        L.pfm_eval_rational.argtypes = [vp, i32, dp, dp, dp, dp, dbl, i32, i32, i32, ctypes.POINTER(Problem), vp,
+                                        vp]
         L.pfm_tri_action_noalloc.argtypes = [vp, i32, i32, dbl, i32, ctypes.POINTER(TriProblem), vp, i32, vp]
         L.pfm_band_action.argtypes = [vp, i32, i32, dbl, i32, i32, ctypes.POINTER(BandProblem), vp, i32, vp]
         _lib = L
@@ -444,6 +447,56 @@ def action(A, V, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx
     info = _info_buffer(info_out, len(mats), mats[0].device)
     rc = ctx.eval_batched(probs, fm, m, tol, {"fp64": FP64, "mixed": MIXED}[prec],
                           C128 if cplx else R64, info, force_plan, stream)
+    if rc:
+        raise PfmError(rc, ctx.last_error())
+    return out, _Info(info)
+
+
+def rational(A, c, w, a0, conj_pairs=True, V=None, ctx=None, stream=None, out=None, info_out=None):
+    """r(A) (V None) or r(A) V for a caller-given partial-fraction set
+    (pfm_eval_rational): r(x) = a0 + sum_k w_k x / (1 - c_k x), with c and w
+    sequences of (complex) numbers; with ``conj_pairs`` each complex shift
+    also stands for its conjugate.  ``A`` (and ``V``) are lists of CUDA
+    tensors, float64 or complex128.  Returns (list of results, info)."""
+    import torch
+    mats = list(A)
+    vecs = None if V is None else list(V)
+    for a in mats + (vecs or []):
+        _require_gpu(a)
+        if a.dtype not in (torch.float64, torch.complex128) or a.stride(-1) != 1:
+            raise ValueError("A and V must be float64 or complex128 with unit column stride")
+    cplx = any(t.is_complex() for t in mats + (vecs or []))
+    if cplx:
+        mats = [a.to(torch.complex128) for a in mats]
+        vecs = None if vecs is None else [v.to(torch.complex128) for v in vecs]
+    like = mats if vecs is None else vecs
+    if out is None:
+        out = [torch.empty_like(x) for x in like]
+    probs = []
+    for i, a in enumerate(mats):
+        if a.dim() != 2 or a.shape[0] != a.shape[1]:
+            raise ValueError("each A must be square")
+        v = None if vecs is None else vecs[i]
+        if v is not None and (v.dim() != 2 or v.shape[0] != a.shape[0]):
+            raise ValueError("each V must be (n, p)")
+        o = out[i]
+        if o.shape != like[i].shape or o.dtype != like[i].dtype or o.stride(-1) != 1:
+            raise ValueError("outputs must match A (or V) in shape and dtype")
+        probs.append(Problem(a.shape[0], 0 if v is None else v.shape[1], a.stride(0), 0 if v is None else v.stride(0),
+                             o.stride(0), a.data_ptr(), None if v is None else v.data_ptr(), o.data_ptr(), None))
+    k = len(c)
+    if k != len(w):
+        raise ValueError("one weight per shift")
+    arr = lambda xs: (ctypes.c_double * max(1, k))(*xs)
+    cr, ci = arr([complex(x).real for x in c]), arr([complex(x).imag for x in c])
+    wr, wi = arr([complex(x).real for x in w]), arr([complex(x).imag for x in w])
+    ctx = ctx or default_context(mats[0].device.index or 0)
+    info = _info_buffer(info_out, len(mats), mats[0].device)
+    pa = (Problem * len(probs))(*probs)
+    cast = lambda a: ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+    rc = lib().pfm_eval_rational(ctx.handle, k, cast(cr), cast(ci), cast(wr), cast(wi), float(a0),
+                                 1 if conj_pairs else 0, C128 if cplx else R64, len(probs), pa,
+                                 ctypes.c_void_p(info.data_ptr()), _stream_ptr(stream))
     if rc:
         raise PfmError(rc, ctx.last_error())
     return out, _Info(info)

@@ -136,3 +136,24 @@ def test_log1m_set_bitwise_equal_oracle(L):
     out = ctypes.c_double()
     assert L.pfm_theta(pfm.LOG1M, 8, 1e-12, ctypes.byref(out)) == pfm.ERR_UNSUPPORTED
     assert L.pfm_eval_batched(None, pfm.LOG1M | pfm.EXP, 5, 1e-12, 0, 0, 1, None, None, -1, None) == pfm.ERR_INVALID
+
+
+def test_r10star_set_bitwise_equal_oracle(L):
+    """m = PFM_R10STAR (110): R*10 of §4.3 (c_i = 1/(6 + i), b_9 = -5e4,
+    b_10 = 3.5e5): shifts, weights, a0 and the polynomial part equal the
+    oracle's exact solve; θ likewise, including Table 2's θ_10 = 1.734 at
+    u = 2^-24 (to the printed digits)."""
+    c, w, a0, order, pair = pfm.coeffs(pfm.EXP, pfm.R10STAR)
+    a0o, terms = co.roundoff_terms("exp", 110)
+    assert not pair and order == co.order_of(110) == 10 and a0 == a0o == 1.0
+    assert list(c.real) == [t[0] for t in terms] == [1.0 / (6 + i) for i in range(1, 11)]
+    assert list(w.real) == [t[1] for t in terms]
+    assert pfm.poly(pfm.EXP, pfm.R10STAR) == co.poly_terms("exp", 110)
+    assert sum(abs(x) for x in w.real) > 1e6  # the cancellation the paper notes for this set
+    for tol in (2.0 ** -24, 1e-8):
+        lib_t = pfm.theta(pfm.EXP, pfm.R10STAR, tol)
+        orc_t = th.theta_set("exp", 110, tol)
+        assert abs(lib_t - orc_t) <= 1e-13 * orc_t, (tol, lib_t, orc_t)
+    assert round(pfm.theta(pfm.EXP, pfm.R10STAR, 2.0 ** -24), 3) == 1.734
+    with pytest.raises(ValueError):
+        pfm.coeffs(pfm.PHI1, pfm.R10STAR)

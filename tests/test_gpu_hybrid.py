@@ -137,3 +137,62 @@ def test_unsupported_combinations(torch_dev):
         pfm.expm([At], ("exp",), m=10, ctx=ctx)
     assert e.value.code == pfm.ERR_UNSUPPORTED
     ctx.close()
+
+
+def _bar_set(m, n, s, theta):
+    """The bar of this module for set m (10 or 110)."""
+    _, terms = co.roundoff_terms("exp", m)
+    sw = sum(abs(w) for _, w, _ in terms)
+    cmax = max(abs(c) for c, _, _ in terms)
+    return 2 * 2 ** s * math.sqrt(n) * sw * theta / (1 - cmax * theta) * U
+
+
+def test_r10star_full_and_tridiagonal(torch_dev):
+    """R*10 (m = PFM_R10STAR, §4.3 eqs. Frac10ciNO-Frac10biNO) at tol 1e-8:
+    full matrices on the Gauss-Jordan route and the tridiagonal action
+    (R*10' of §5), against the oracle at the same plan, within the bars of
+    this module and of the tridiagonal tests (its weights, sum |w| ~ 1.3e6,
+    set the rounding).  Below its rounding floor (tol 1e-12) it is refused."""
+    torch, dev = torch_dev
+    from oracle import banded as bd
+    from paper_2210_03714_amd import pfm
+    m, tol = pfm.R10STAR, 1e-8
+    mats = wl.gaussian_uneven(6, [40, 64, 130, 256], 0.5, 8.0, wl.SEED_BASE + 710)
+    _say("case R*10 full matrices")
+    res, info = pfm.expm([torch.from_numpy(a).to(dev) for a in mats], ("exp",), m=m, tol=tol)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, A in enumerate(mats):
+        s = int(info[i]["plan"])
+        own = me.expm_full(A, ("exp",), 110, tol, force_plan=s)
+        assert info[i]["status"] == 0 and info[i]["order"] == 10 and info[i]["route"] == 1
+        err = me.rel_fro(res["exp"][i].cpu().numpy(), own["exp"])
+        bar = _bar_set(110, A.shape[0], s, own["theta"])
+        worst = max(worst, err / bar)
+        assert err <= bar, (i, A.shape[0], s, err, bar)
+    _say("  worst err / bar %.2e" % worst)
+    tris = [wl.tri_gaussian_batch(1, d, 0.5, 8.0, wl.SEED_BASE + 720 + d)[0] for d in (17, 300)]
+    vecs = [wl.vectors(d, p, wl.SEED_BASE + 730 + d) for d, p in ((17, 3), (300, 70))]
+    _say("case R*10' tridiagonal")
+    dl = [torch.from_numpy(np.ascontiguousarray(t[0])).to(dev) for t in tris]
+    dd = [torch.from_numpy(np.ascontiguousarray(t[1])).to(dev) for t in tris]
+    du = [torch.from_numpy(np.ascontiguousarray(t[2])).to(dev) for t in tris]
+    Vt = [torch.from_numpy(v).to(dev) for v in vecs]
+    rt, it = pfm.tri_action(dl, dd, du, Vt, ("exp",), m=m, tol=tol)
+    torch.cuda.synchronize()
+    _, terms = co.roundoff_terms("exp", 110)
+    d1, d2 = co.poly_terms("exp", 110)
+    amp = 1 + sum(abs(w) for _, w, _ in terms) + abs(d1) + abs(d2)
+    for i, ((a, b, c), V) in enumerate(zip(tris, vecs)):
+        N = int(it[i]["plan"])
+        own = bd.tri_action(a, b, c, V, ("exp",), 110, tol, force_plan=N)
+        err = me.rel_fro(rt["exp"][i].cpu().numpy(), own["exp"])
+        assert err <= 2 * 16 * N * amp * U, (i, N, err)
+    A0 = torch.from_numpy(mats[0]).to(dev)
+    for t in (1e-12, 1e-10):
+        with pytest.raises(pfm.PfmError) as e:
+            pfm.expm([A0], ("exp",), m=m, tol=t)
+        assert e.value.code == pfm.ERR_UNSUPPORTED
+        with pytest.raises(pfm.PfmError) as e:
+            pfm.tri_action(dl[:1], dd[:1], du[:1], Vt[:1], ("exp",), m=m, tol=t)
+        assert e.value.code == pfm.ERR_UNSUPPORTED
