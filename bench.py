@@ -670,7 +670,9 @@ def main():
     per_launch_ms = tot_ms / max(1, launches)
     flops_per_launch = flops[dom] * calls / max(1, launches)
     achieved = flops_per_launch / (per_launch_ms * 1e-3)
-    kname = {"lu": "gj_inv_kernel<256,false>" if n_lu == 0 else "lu_kernel<256,double>",
+    # n = 256 pads to 256: the 128-wide pivot block kernel (the default policy)
+    gj_name = "gj2_inv_kernel<false>" if n == 256 else "gj_inv_kernel<256,false>"
+    kname = {"lu": gj_name if n_lu == 0 else "lu_kernel<256,double>",
              "solve_combine": "square_level_f64_kernel<1,128>" if n_lu == 0 else "solve_full_f64_kernel<256,16>",
              "square": "square_level_f64_kernel<0,128>"}[dom]
 

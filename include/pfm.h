@@ -433,17 +433,19 @@ int pfm_graph_stats(pfm_ctx *ctx, int *captures, int *replays);
  * `reps` calls of each with hipEvents on `stream` after one warm-up call,
  * and keeps the fastest for the batch's key (mode, complex, precision, size
  * bucket of the largest instance, batch-size bucket).  A policy is
- * route + 4 (schedule + 2 tile):
+ * route + 4 (schedule + 2 (tile + 2 block)):
  *   route    real full matrices: 0 single-workgroup Gauss-Jordan inverses
  *            where dominant, 1 the pivoting LU route; action or complex: 0
  *            the multi-workgroup route for sizes above 128, 2 only above 512;
  *   schedule full matrices: 0 the first 8 squaring levels launched one by
  *            one, 1 every level from the persistent queue (pfm_set_schedule);
  *   tile     full matrices: 0 128 x 128 product tiles from npad 256 on, 1
- *            64 x 64 tiles for every size up to 512.
+ *            64 x 64 tiles for every size up to 512;
+ *   block    Gauss-Jordan inverses of padded size 256: 0 128-wide pivot
+ *            blocks (two passes over each matrix), 1 64-wide (four passes).
  * Later calls with the same key use it (an explicit PFM_ROUTE_LU or
  * pfm_set_schedule still wins).  Synchronises the stream.  *policy and *ms
- * (may be NULL) receive the choice (0..15) and its time per call. */
+ * (may be NULL) receive the choice (0..31) and its time per call. */
 int pfm_tune(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype, int batch, const pfm_problem *probs,
              int reps, pfm_stream_t stream, int *policy, double *ms);
 

@@ -34,6 +34,7 @@
 #include "kern_action.h"
 #include "kern_mixed.h"
 #include "kern_gj.h"
+#include "kern_gj2.h"
 #include "kern_large.h"
 #include "kern_tri.h"
 #include "kern_band.h"
@@ -226,7 +227,11 @@ constexpr int kNumSchedules = 2;
 // smallest npad whose product tiles are 128 x 128 (else 64 x 64)
 constexpr int kTile128Min[] = {256, 1 << 30};
 constexpr int kNumTiles = 2;
-constexpr int kNumPolicies = kNumRoutePolicies * kNumSchedules * kNumTiles;
+// Gauss-Jordan pivot block of npad = 256 instances: 128 (gj2_inv_kernel,
+// two passes over the matrix) or 64 (gj_inv_kernel, four passes)
+constexpr int kGjBlock[] = {128, 64};
+constexpr int kNumGjBlocks = 2;
+constexpr int kNumPolicies = kNumRoutePolicies * kNumSchedules * kNumTiles * kNumGjBlocks;
 
 // Tuning key of a batch: mode, complex, precision, size bucket of its
 // largest real dimension (2n for complex), batch-size bucket.
@@ -990,6 +995,7 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
 
   // route policy: the context's, unless a tuned one exists for this batch
   int pol_gj = ctx->gj, pol_ln = ctx->ln_min, pol_direct = ctx->sq_direct, pol_t128 = kTile128Min[0];
+  int pol_gjb = kGjBlock[0];
   {
     const int pidx = ctx->force_policy >= 0 ? ctx->force_policy
                                             : [&] {
@@ -1002,7 +1008,8 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
         pol_ln = kPolicies[pidx % kNumRoutePolicies].ln_min;
       }
       if (!ctx->sched_explicit) pol_direct = kSqDirect[(pidx / kNumRoutePolicies) % kNumSchedules];
-      pol_t128 = kTile128Min[pidx / (kNumRoutePolicies * kNumSchedules)];
+      pol_t128 = kTile128Min[(pidx / (kNumRoutePolicies * kNumSchedules)) % kNumTiles];
+      pol_gjb = kGjBlock[pidx / (kNumRoutePolicies * kNumSchedules * kNumTiles)];
     }
   }
   const bool gj_call = pol_gj && !action && !emb && !mixed;
@@ -1071,6 +1078,13 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
       D.ipiv_ioff = iofs; iofs += align_up(nterms * np, 64);
     }
     cls_list[D.cls].push_back(i);
+  }
+  // class 1: the npad = 256 instances first, so that the 128-block kernel
+  // takes a prefix of the list and the 64-block one the rest
+  int n_wide = 0;
+  if (gj_call && pol_gjb == 128) {
+    std::stable_partition(cls_list[1].begin(), cls_list[1].end(), [&](int i) { return desc[i].npad == 256; });
+    for (int i : cls_list[1]) n_wide += desc[i].npad == 256;
   }
 
   // Instance lists (all from the sizes): per class for the single-workgroup
@@ -1363,7 +1377,14 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
     const int *dl = d_list + cls_off[c];
     const dim3 gg(xcd_grid(nl, nterms));
     if (c == 0) hipLaunchKernelGGL((gj_inv_kernel<128, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 1);
-    if (c == 1) hipLaunchKernelGGL((gj_inv_kernel<256, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 1);
+    if (c == 1) {
+      if (n_wide)
+        hipLaunchKernelGGL((gj2_inv_kernel<false>), dim3(xcd_grid(n_wide, nterms)), dim3(512), 0, stream, d_desc, dl,
+                           n_wide, d_plan, T, wsd, 1);
+      if (nl > n_wide)
+        hipLaunchKernelGGL((gj_inv_kernel<256, false>), dim3(xcd_grid(nl - n_wide, nterms)), dim3(256), 0, stream,
+                           d_desc, dl + n_wide, nl - n_wide, d_plan, T, wsd, 1);
+    }
     if (c == 2) hipLaunchKernelGGL((gj_inv_kernel<512, false>), gg, dim3(256), 0, stream, d_desc, dl, nl, d_plan, T, wsd, 1);
     ctx->cur_launches[0]++;
   }
@@ -1650,8 +1671,8 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
     for (; q < nbytes; ++q) sig = (sig ^ b[q]) * 1099511628211ull;
   };
   const void *ptrs[7] = {ctx->ws, ctx->tasks, info, stream, d_desc, d_list, ctx->d_err};
-  const int64_t ints[12] = {f, m, prec, dtype, batch, force_plan, pol_gj, pol_direct, pol_t128, ctx->num_cu,
-                            (int64_t)lists.size(), big_nmax};
+  const int64_t ints[13] = {f, m, prec, dtype, batch, force_plan, pol_gj, pol_direct, pol_t128, ctx->num_cu,
+                            (int64_t)lists.size(), big_nmax, pol_gjb};
   const double dbls[6] = {tol, theta, a1e, a1p, T.a0e, cmax};
   mix(ptrs, sizeof ptrs);
   mix(ints, sizeof ints);
@@ -1796,12 +1817,19 @@ int pfm_tune(pfm_ctx *ctx, int f, int m, double tol, int prec, int dtype, int ba
   // persistent queue) and the product tile (128 from npad 256 on, or 64)
   std::vector<int> routes = (!action && !emb) ? std::vector<int>{0, 1} : std::vector<int>{0, 2};
   // the tile choice only differs for a padded size of 256 or more
-  bool tile_matters = false;
-  for (int i = 0; i < batch; ++i) tile_matters |= (emb ? 2 * probs[i].n : probs[i].n) > 192;
+  bool tile_matters = false, block_matters = false;
+  for (int i = 0; i < batch; ++i) {
+    tile_matters |= (emb ? 2 * probs[i].n : probs[i].n) > 192;
+    block_matters |= !action && !emb && !mixed && probs[i].n > 192 && probs[i].n <= 256;
+  }
   std::vector<int> cand;
-  for (int tl = 0; tl < (action || !tile_matters ? 1 : kNumTiles); ++tl)
-    for (int sc = 0; sc < (action ? 1 : kNumSchedules); ++sc)
-      for (int r : routes) cand.push_back(r + kNumRoutePolicies * (sc + kNumSchedules * tl));
+  for (int gb = 0; gb < (block_matters ? kNumGjBlocks : 1); ++gb)
+    for (int tl = 0; tl < (action || !tile_matters ? 1 : kNumTiles); ++tl)
+      for (int sc = 0; sc < (action ? 1 : kNumSchedules); ++sc)
+        for (int r : routes) {
+          if (gb && !kPolicies[r].gj) continue;  // the pivot block only matters on the Gauss-Jordan route
+          cand.push_back(r + kNumRoutePolicies * (sc + kNumSchedules * (tl + kNumTiles * gb)));
+        }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipEvent_t e0, e1;
   HIP_TRY(ctx, hipEventCreate(&e0));

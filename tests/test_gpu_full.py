@@ -231,3 +231,36 @@ def test_per_instance_tolerances(torch_dev):
             assert torch.equal(res["exp"][i], r1["exp"][j])
             assert info[i]["theta"] == i1[j]["theta"] == pfm.theta(pfm.EXP, 8, t)
             assert info[i]["plan"] == i1[j]["plan"]
+
+
+def test_gauss_jordan_pivot_blocks(torch_dev):
+    """Padded sizes 192 and 256 in one call (n = 130..256, both pivot-block
+    kernels of the inverse route in one launch sequence): the 128-wide
+    pivot blocks (npad 256, the default) and the 64-wide ones (the tuner's
+    other choice) each meet the oracle at 1e-12, with identical plans and
+    routes, and agree with each other to the same bar."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    sizes = [256, 193, 200, 256, 130, 255, 192, 241, 256, 224]
+    rng = np.random.default_rng(wl.SEED_BASE + 60)
+    mats = [wl.gaussian(n, float(rng.uniform(0.5, 8.0)), wl.SEED_BASE + 61 + i) for i, n in enumerate(sizes)]
+    At = [torch.from_numpy(a).to(dev) for a in mats]
+    ctx = pfm.Context(0)
+    pfm.tune(At, None, ("exp", "phi1"), ctx=ctx, reps=1)
+    key = ctx.tune_export().split()[0]
+    out = {}
+    for blk, pol in (("128", 0), ("64", 16)):
+        ctx.tune_import("%s %d\n" % (key, pol))
+        _say("case pivot block %s" % blk)
+        res, info = pfm.expm(At, ("exp", "phi1"), m=8, tol=1e-12, ctx=ctx)
+        torch.cuda.synchronize()
+        assert all(info[i]["route"] == 1 for i in range(len(sizes)))
+        w = _check_instances(mats, res, info, ("exp", "phi1"), 8, 1e-12)
+        _say("  worst rel err %.3e" % w)
+        out[blk] = res
+    for f in ("exp", "phi1"):
+        for i in range(len(sizes)):
+            a, b = out["128"][f][i].cpu().numpy(), out["64"][f][i].cpu().numpy()
+            assert me.rel_fro(a, b) <= 1e-12, (f, i)
+    ctx.check()
+    ctx.close()

@@ -78,9 +78,9 @@ def test_tune_action_complex(torch_dev):
 
 def test_tune_full_256_every_policy(torch_dev):
     """n = 256 and 300 (padded sizes 256 and 320, where the product tile
-    choice matters): the tuner tries routes x squaring schedules x tiles; then
-    every full-matrix policy is imported for the same key and gives the
-    oracle's result."""
+    and the Gauss-Jordan pivot block choices matter): the tuner tries routes x
+    squaring schedules x tiles x pivot blocks; then every full-matrix policy
+    is imported for the same key and gives the oracle's result."""
     torch, dev = torch_dev
     from paper_2210_03714_amd import pfm
     mats_np = [wl.gaussian(n, t, wl.SEED_BASE + 650 + i) for i, (n, t) in enumerate([(256, 7.5), (300, 3.0),
@@ -89,10 +89,10 @@ def test_tune_full_256_every_policy(torch_dev):
     ctx = pfm.Context(0)
     pol, ms = pfm.tune(mats, None, ("exp", "phi1"), ctx=ctx)
     _say("  tuned full n=256/300 x4: policy %d, %.3f ms" % (pol, ms))
-    assert pol % 4 in (0, 1) and 0 <= pol < 16
+    assert pol % 4 in (0, 1) and 0 <= pol < 32
     key = ctx.tune_export().split()[0]
     refs = [me.expm_full(a, ("exp", "phi1"), 8, 1e-12) for a in mats_np]
-    for p in range(16):
+    for p in range(32):
         if p % 4 not in (0, 1):
             continue
         ctx.tune_import("%s %d\n" % (key, p))
