@@ -49,26 +49,45 @@ def _problem_array(np, A, outs, ldf):
     return arr
 
 
-def kernel_source_hash():
+# the sources each kernel is built from (besides the common headers), so
+# that a counter summary stays attached to the kernel it measured
+_KERNEL_SOURCES = [
+    ("gj2_inv_kernel", ["kern_gj2.h", "kern_gj.h"]),
+    ("gj_inv_kernel", ["kern_gj.h"]), ("combine_inv_kernel", ["kern_gj.h"]),
+    ("square_level", ["kern_square.h"]), ("sq_", ["kern_sched.h", "kern_square.h"]),
+    ("lu_kernel", ["kern_lu.h"]), ("solve_full", ["kern_solve.h"]),
+    ("solve_mixed", ["kern_mixed.h", "kern_solve.h"]), ("prep_bt", ["kern_mixed.h"]),
+    ("tri_", ["kern_tri.h"]), ("band_", ["kern_band.h", "kern_tri.h"]),
+    ("ln_", ["kern_large.h"]), ("act", ["kern_action.h", "kern_solve.h"]),
+]
+
+
+def kernel_sources(kernel):
+    for prefix, files in _KERNEL_SOURCES:
+        if kernel.startswith(prefix):
+            return ["kern_common.h", "pfm_internal.h"] + files
+    return ["kern_common.h", "pfm_internal.h", "kern_misc.h"]
+
+
+def kernel_source_hash(files):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2210_03714_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, fn), "rb") as f:
-                h.update(f.read())
+    for fn in files:
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def traffic_from_profile(kernel):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel sources."""
+    if it was taken on the kernel's current sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     k = rec.get("kernels", {}).get(kernel)
-    if not k or rec.get("source_hash") != kernel_source_hash():
+    if not k or k.get("source_hash") != kernel_source_hash(k.get("sources", [])):
         return None
     return k.get("bytes_per_launch")
 
