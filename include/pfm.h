@@ -458,6 +458,24 @@ int pfm_tune_export(const pfm_ctx *ctx, char *buf, size_t size);
  * PFM_ERR_INVALID (table unchanged) for unreadable text. */
 int pfm_tune_import(pfm_ctx *ctx, const char *text);
 
+/* The pivoting LU factorisation of shift `shift` (0-based, in the order of
+ * pfm_coeffs) of instance `instance` of the most recent pfm_eval_batched
+ * call on ctx (§8(a3): M_k = I - c_k B = P L U, partial pivoting, pivot = the
+ * first index of the largest |.| in the column), as the solve kernels store
+ * it.  lu (host, column-major, npad x npad with leading dimension
+ * ldlu >= npad) receives the padded matrix's factors (npad = n rounded up to
+ * a multiple of 16, the padding being the identity): L unit lower below the
+ * diagonal, U on and above it, except that every off-diagonal 16 x 16 block
+ * is stored multiplied by the inverse of the diagonal block of its block
+ * column, L_ij L_jj^{-1} (i > j) and U_ij U_jj^{-1} (i < j); binary32
+ * factors (PFM_MIXED) are widened.  ipiv (host, npad entries) receives the
+ * LAPACK-style pivot sequence, 0-based: at step r rows r and ipiv[r] were
+ * interchanged.  *npad (may be NULL) receives npad; with lu and ipiv both
+ * NULL only npad is returned.  Synchronises the device.  PFM_ERR_INVALID if
+ * there is no such factorisation (the instance took another route, the
+ * indices are out of range, or a later call reused the workspace). */
+int pfm_lu_factors(pfm_ctx *ctx, int instance, int shift, double *lu, int64_t ldlu, int32_t *ipiv, int32_t *npad);
+
 /* Upper bound of the workspace bytes pfm_eval_batched would allocate for
  * this batch (host only; probs may hold NULL data pointers).  Returns 0 for
  * an invalid or unsupported batch. */

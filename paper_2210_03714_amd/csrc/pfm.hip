@@ -94,6 +94,14 @@ struct pfm_ctx {
   int prof_launches[kNumPhases] = {};
   int prof_calls = 0;
   int cur_launches[kNumPhases] = {};
+  // where the last pfm_eval_batched call left its factorisations
+  // (pfm_lu_factors); cleared whenever another call reuses the workspace
+  std::vector<InstDesc> fac_desc;
+  int fac_nterms = 0;
+  bool fac_mixed = false;
+  const double *fac_wsd = nullptr;
+  const int *fac_wsi = nullptr;
+  const PlanRec *fac_plan = nullptr;
   std::string err;
 };
 
@@ -591,6 +599,7 @@ int tri_launch(pfm_ctx *ctx, const TriTerms &T, int order, int batch, const TriD
 // Grow the context's workspace to at least `need` bytes.
 int ws_reserve(pfm_ctx *ctx, int64_t need, hipStream_t stream) {
   ctx->up_valid = false;  // this call writes its descriptors at the workspace's start
+  ctx->fac_desc.clear();
   if (ctx->budget && (size_t)need > ctx->budget)
     return set_err(ctx, PFM_ERR_BUDGET, "workspace %lld bytes exceeds budget %zu", (long long)need, ctx->budget);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -1228,6 +1237,12 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
   int *wsi = (int *)(base + dofs * 8);
   char *tail = base + dofs * 8 + align_up(iofs * 4, 256);
   PlanRec *d_plan = (PlanRec *)tail;
+  ctx->fac_desc = desc;
+  ctx->fac_nterms = nterms;
+  ctx->fac_mixed = mixed;
+  ctx->fac_wsd = wsd;
+  ctx->fac_wsi = wsi;
+  ctx->fac_plan = d_plan;
   InstDesc *d_desc = (InstDesc *)(tail + plan_bytes);
   int *d_list = (int *)(tail + plan_bytes + desc_bytes);
   char *qbase = tail + plan_bytes + desc_bytes + list_bytes;
@@ -1881,6 +1896,40 @@ int pfm_tune_export(const pfm_ctx *ctx, char *buf, size_t size) {
     buf[k] = 0;
   }
   return (int)s.size() + 1;
+}
+
+int pfm_lu_factors(pfm_ctx *ctx, int instance, int shift, double *lu, int64_t ldlu, int32_t *ipiv, int32_t *npad) {
+  if (!ctx) return PFM_ERR_INVALID;
+  if (instance < 0 || instance >= (int)ctx->fac_desc.size() || shift < 0 || shift >= ctx->fac_nterms)
+    return set_err(ctx, PFM_ERR_INVALID, "pfm_lu_factors: no factorisation (%d, %d) from the last call", instance, shift);
+  const InstDesc &D = ctx->fac_desc[instance];
+  const int np = D.npad;
+  if (npad) *npad = np;
+  if (!lu && !ipiv) return PFM_OK;
+  if (!lu || !ipiv || ldlu < np)
+    return set_err(ctx, PFM_ERR_INVALID, "pfm_lu_factors: lu (ld >= %d) and ipiv are required", np);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  PlanRec P;
+  HIP_TRY(ctx, hipMemcpy(&P, ctx->fac_plan + instance, sizeof P, hipMemcpyDeviceToHost));
+  if (!on_route(P, 0))
+    return set_err(ctx, PFM_ERR_INVALID, "pfm_lu_factors: instance %d did not take the pivoting LU route", instance);
+  const int64_t nn = (int64_t)np * np;
+  std::vector<double> w(nn);
+  if (ctx->fac_mixed) {
+    std::vector<float> wf(nn);
+    const float *src = reinterpret_cast<const float *>(ctx->fac_wsd + D.fac_off) + (int64_t)shift * nn;
+    HIP_TRY(ctx, hipMemcpy(wf.data(), src, nn * sizeof(float), hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < nn; ++e) w[e] = wf[e];
+  } else {
+    HIP_TRY(ctx, hipMemcpy(w.data(), ctx->fac_wsd + D.fac_off + (int64_t)shift * nn, nn * sizeof(double),
+                           hipMemcpyDeviceToHost));
+  }
+  for (int c = 0; c < np; ++c)
+    for (int r = 0; r < np; ++r) lu[r + (int64_t)c * ldlu] = w[r + (int64_t)c * np];
+  HIP_TRY(ctx, hipMemcpy(ipiv, ctx->fac_wsi + D.ipiv_ioff + (int64_t)shift * np, np * sizeof(int32_t),
+                         hipMemcpyDeviceToHost));
+  return PFM_OK;
 }
 
 int pfm_tune_import(pfm_ctx *ctx, const char *text) {

@@ -102,6 +102,7 @@ def lib():
         L.pfm_tune.argtypes = [vp, i32, i32, dbl, i32, i32, i32, ctypes.POINTER(Problem), i32, vp, ip, dp]
         L.pfm_tune_export.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
         L.pfm_tune_import.argtypes = [vp, ctypes.c_char_p]
+        L.pfm_lu_factors.argtypes = [vp, i32, i32, dp, ctypes.c_int64, ip, ip]
         L.pfm_graph_stats.argtypes = [vp, ip, ip]
         u64p = ctypes.POINTER(ctypes.c_uint64)
         L.pfm_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(Problem)]
@@ -239,6 +240,24 @@ class Context:
         rc = lib().pfm_tune_import(self._h, text.encode())
         if rc:
             raise PfmError(rc, self.last_error())
+
+    def lu_factors(self, instance, shift):
+        """(lu, ipiv): the stored pivoting-LU factors of one (instance, shift)
+        of the last eval call, npad x npad (row index first; off-diagonal
+        16 x 16 blocks multiplied by the inverse of their column's diagonal
+        block, as pfm_lu_factors documents) and the 0-based LAPACK pivots."""
+        npad = ctypes.c_int32(0)
+        rc = lib().pfm_lu_factors(self._h, instance, shift, None, 0, None, ctypes.byref(npad))
+        if rc:
+            raise PfmError(rc, self.last_error())
+        np_ = npad.value
+        lu = np.zeros(np_ * np_, dtype=np.float64)
+        ipiv = np.zeros(np_, dtype=np.int32)
+        rc = lib().pfm_lu_factors(self._h, instance, shift, lu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), np_,
+                                  ipiv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None)
+        if rc:
+            raise PfmError(rc, self.last_error())
+        return lu.reshape(np_, np_).T.copy(), ipiv
 
     def set_graphs(self, enable):
         """Capture and replay repeated launch sequences as hipGraphs."""
