@@ -57,6 +57,16 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
  * identity, so r(A) is evaluated directly (s = 0); the bound of §3 holds for
  * ||A||_1 <= θ (PFM_OUT_OF_RANGE otherwise).  The result goes to F_exp. */
 #define PFM_LOG1M 4
+/* phi2(A) = sum_k A^k / (k + 2)! (§1's phi_k with k = 2, the Taylor
+ * polynomial of degree k - 1 removed): weights solving eq. (4) with
+ * a_k = 1/(k + 2)! on the exponential's shifts, and the doubling
+ * phi2(2B) = (phi1(B)^2 + 2 phi2(B)) / 4 between the squarings (the phi1
+ * chain is computed for it even when F_phi1 is not requested).  Combines
+ * with PFM_EXP and PFM_PHI1; real full matrices up to n = 512 in binary64
+ * with m = 4, 5 or 8 (PFM_ERR_UNSUPPORTED otherwise: action, complex,
+ * mixed, the hybrid sets, larger n, the tridiagonal / banded paths and the
+ * serving queue). */
+#define PFM_PHI2 8
 
 /* element types */
 #define PFM_R64 0  /* real binary64 */
@@ -97,7 +107,7 @@ typedef void *pfm_stream_t; /* a hipStream_t; NULL is the null stream */
 #define PFM_OUT_OF_RANGE 16  /* PFM_LOG1M: ||A||_1 > θ, so the tolerance is not
                                 guaranteed (the result is still computed) */
 
-/* One problem instance.  p == 0: full matrix, F_exp / F_phi1 are n x n with
+/* One problem instance.  p == 0: full matrix, F_exp / F_phi1 / F_phi2 are n x n with
  * leading dimension ldf.  p >= 1: action on the n x p block V (leading
  * dimension ldv), F_exp / F_phi1 are n x p with leading dimension ldf.
  * Outputs not requested by the function mask may be NULL.  Every array is
@@ -113,6 +123,7 @@ typedef struct {
   const void *V;
   void *F_exp;
   void *F_phi1;
+  void *F_phi2;  /* PFM_PHI2 output (full matrices), else ignored */
 } pfm_problem;
 
 /* Per-instance report, written to device memory by pfm_eval_batched. */
@@ -145,14 +156,15 @@ int pfm_destroy(pfm_ctx *ctx);
 /* Text of the last error on this context (never NULL). */
 const char *pfm_last_error(const pfm_ctx *ctx);
 
-/* Host only.  Coefficients of the set used for function `f` (PFM_EXP or
- * PFM_PHI1, not both) with m solves: the round-off form of §4.3,
+/* Host only.  Coefficients of the set used for function `f` (PFM_EXP,
+ * PFM_PHI1, PFM_PHI2 or PFM_LOG1M, one of them) with m solves: the round-off form of §4.3,
  * r(x) = a0 + sum_k w_k x / (1 - c_k x), with w_k = b_k c_k and b_k the
  * solution of eq. (4) (§2).  m = 1: the 4th-order Padé pair of eq. (5) (exp)
  * or eq. (6) (phi1) written in this form, one conjugate pair (the conjugate
  * term is implied, *is_pair = 1).  m = 4: the set of §4.1 with alpha = 5;
  * m = 5: the set of §5.1; m = 8: the set of §4.2 with alpha = 5.  phi1 weights
- * solve eq. (4) with a_k = 1/(k+1)! on the same shifts.  m = 10 (exp only):
+ * solve eq. (4) with a_k = 1/(k+1)! on the same shifts, phi2 weights
+ * (m = 4, 5, 8) with a_k = 1/(k+2)!.  m = 10 (exp only):
  * the hybrid 10th-order set of §4.3 with the smaller coefficients
  * (c = -+1/8, -+1/10, ..., -+1/16; b_9 = 2000, b_10 = -3500), whose
  * polynomial part pfm_poly returns (a0 = d0 + sum_k b_k); m = PFM_R10STAR
@@ -170,8 +182,10 @@ int pfm_coeffs(int f, int m, int *n_terms, double *c_re, double *c_im,
 int pfm_poly(int f, int m, double *d1, double *d2);
 
 /* Host only.  θ(f, m, tol): the largest x with sum_k |a_k - alpha_k| x^k <=
- * tol (forward bound of §3; absolute, any consistent norm).  For
- * f = PFM_EXP|PFM_PHI1 the minimum of the two. */
+ * tol (forward bound of §3; absolute, any consistent norm).  For a mask
+ * with several functions the minimum; PFM_PHI2 brings in the exponential's
+ * and phi1's bounds too (its doubling squares phi1, whose doubling applies
+ * e^B). */
 int pfm_theta(int f, int m, double tol, double *theta);
 
 /* Largest squaring count s of the full-matrix path (above it the instance is
@@ -187,7 +201,7 @@ int pfm_theta(int f, int m, double tol, double *theta);
 #define PFM_R10STAR 110
 
 /* Evaluate a batch of problems.
- *   f          PFM_EXP, PFM_PHI1 or both
+ *   f          PFM_EXP, PFM_PHI1, PFM_PHI2 (any combination), or PFM_LOG1M
  *   m          number of shifted solves: 1, 4, 5 or 8; or 10, the hybrid set
  *              of §4.3, for PFM_EXP of real full matrices in binary64 on the
  *              Gauss-Jordan routes (every |c_k| ||B||_1 <= 1/2, which planned

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Full matrix, f in {exp, phi1} (§1, §2, §4.3):
+Full matrix, f in {exp, phi1, phi2} (§1, §2, §4.3):
   1. eta = ||A||_1 (max column sum of |a_ij|; §5 names the 1-norm as the usual
      choice) and θ = θ(f, m, tol) from the forward bound of §3.
   2. s = smallest integer s >= 0 with eta * 2^-s <= θ; B = A * 2^-s (exact).
@@ -17,6 +17,11 @@ Full matrix, f in {exp, phi1} (§1, §2, §4.3):
      The phi1 step is the doubling identity of §1 written for B:
      phi1(2B) = (e^B + I) phi1(B) / 2 (the form printed in §1 lacks the
      factor t that phi1(tA) carries), and it uses R *before* it is squared.
+     phi2 (§1's phi_k with k = 2: (e^x - 1 - x) / x^2, weights for
+     a_k = 1/(k+2)! on the same shifts) doubles as
+     phi2(2B) = (phi1(B)^2 + 2 phi2(B)) / 4, which follows from
+     e^{2x} - 1 - 2x = x^2 phi1(x)^2 + 2 x^2 phi2(x); it uses Phi before
+     Phi's own step, so phi2 always carries the phi1 chain.
 
 Action on a block V (n x p) (§1, §2):
   1. eta, θ as above; N = max(1, ceil(eta / θ)) (correctly rounded quotient);
@@ -51,10 +56,13 @@ def norm1(A):
 def theta_for(funcs, m, tol):
     """θ used by the plan.  phi1 always needs the exponential approximant as
     well (its doubling step and its N-step recurrence both apply e^B), so a
-    request containing phi1 takes min(θ_exp, θ_phi1)."""
+    request containing phi1 takes min(θ_exp, θ_phi1); phi2's doubling squares
+    phi1, so a request containing phi2 takes min(θ_exp, θ_phi1, θ_phi2)."""
     key = (tuple(sorted(funcs)), m, float(tol))
     if key not in _THETA_CACHE:
         need = set(funcs) if "log1m" in funcs else {"exp"} | set(funcs)
+        if "phi2" in need:
+            need.add("phi1")
         _THETA_CACHE[key] = min(th.theta_set(f, m, tol) for f in need)
     return _THETA_CACHE[key]
 
@@ -90,10 +98,13 @@ def build_terms(funcs, m, complex_A):
             raise ValueError("log1m is evaluated on its own")
         a0l, tl = co.roundoff_terms("log1m", m)
         return {"log1m": a0l}, [(c, {"log1m": w}, pair) for c, w, pair in tl]
-    need = ["exp"] + (["phi1"] if "phi1" in funcs else [])
+    need = ["exp"] + (["phi1"] if ("phi1" in funcs or "phi2" in funcs) else []) + \
+        (["phi2"] if "phi2" in funcs else [])
     a0 = {}
     terms = []
     if m == 1:
+        if "phi2" in funcs:
+            raise NotImplementedError("the m = 1 Padé pairs are given for exp and phi1 only")
         for f in need:
             a0[f], tl = co.roundoff_terms(f, 1)
             (c, w, _), = tl
@@ -122,8 +133,18 @@ def _accumulate(acc, Z, w, pair):
         acc += w * Z
 
 
+def doubling_step(R, Phi, Phi2, I):
+    """One undoing of the scaling (§1) for B -> 2B: phi2 from phi1 and phi2,
+    phi1 from e^B and phi1 (both before their own step), then R <- R R."""
+    if Phi2 is not None:
+        Phi2 = 0.25 * (Phi @ Phi) + 0.5 * Phi2
+    if Phi is not None:
+        Phi = 0.5 * ((R + I) @ Phi)
+    return R @ R, Phi, Phi2
+
+
 def expm_full(A, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
-    """f(A) for f in ``funcs`` (subset of {"exp", "phi1"}) by the full-matrix
+    """f(A) for f in ``funcs`` (subset of {"exp", "phi1", "phi2"}) by the full-matrix
     algorithm in the module docstring.  Returns a dict with the requested
     results and the plan (s, θ, eta)."""
     A = np.asarray(A)
@@ -154,15 +175,16 @@ def expm_full(A, funcs=("exp",), m=8, tol=1e-12, force_plan=None):
         return {"plan": 0, "theta": theta, "eta": eta, "log1m": acc["log1m"]}
     R = acc["exp"]
     Phi = acc.get("phi1")
+    Phi2 = acc.get("phi2")
     for _ in range(s):
-        if Phi is not None:
-            Phi = 0.5 * ((R + I) @ Phi)
-        R = R @ R
+        R, Phi, Phi2 = doubling_step(R, Phi, Phi2, I)
     res = {"plan": s, "theta": theta, "eta": eta}
     if "exp" in funcs:
         res["exp"] = R
     if "phi1" in funcs:
         res["phi1"] = Phi
+    if "phi2" in funcs:
+        res["phi2"] = Phi2
     return res
 
 

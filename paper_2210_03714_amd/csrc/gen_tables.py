@@ -39,6 +39,8 @@ def series(func, K):
         return [Q(1, factorial(k)) for k in range(K)]
     if func == "phi1":
         return [Q(1, factorial(k + 1)) for k in range(K)]
+    if func == "phi2":  # phi2(x) = (e^x - 1 - x) / x^2 (§1, degree-1 polynomial removed)
+        return [Q(1, factorial(k + 2)) for k in range(K)]
     if func == "log1m":  # log(1 - x) = -sum_{k >= 1} x^k / k
         return [Q(0)] + [Q(-1, k) for k in range(1, K)]
     raise ValueError(func)
@@ -189,6 +191,8 @@ def emit(path):
     entries.append((10, 0, hybrid_entry()))  # the exponential only
     entries.append((110, 0, hybrid_entry(star=True)))  # R*10, the exponential only
     entries.append((5, 2, real_entry("log1m", 5)))  # log(1 - x), evaluated at s = 0
+    for m in (4, 5, 8):  # phi2 on the exponential's real shift sets (index 3)
+        entries.append((m, 3, real_entry("phi2", m)))
     lines = ["/* Generated by gen_tables.py -- do not edit. */",
              "#define PFM_KBOUND %d" % KBOUND,
              "struct PfmSetEntry { int m; int func; int pair; int order; int nterms; double a0;",

@@ -303,7 +303,8 @@ gj_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ilist, 
   for (int J = 1; J < nJ; ++J) step(J, std::false_type{});
 }
 
-// S_e = sum_k we_k X_k, S_p = sum_k wp_k X_k (binary64, fixed order k = 0..),
+// S_e = sum_k we_k X_k, S_p = sum_k wp_k X_k (and S_q = sum_k wq_k X_k for
+// phi2) (binary64, fixed order k = 0..),
 // into the level-1 squaring buffers (free at this point).  Large instances
 // (route 2) take the weights w_k c_k instead: T = sum_k w_k c_k X_k for the
 // form R = a0 I + alpha1 B + B T B (see square_level_f64_kernel).  The
@@ -321,15 +322,17 @@ combine_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ il
   if (e0 >= nn) return;
   const double *X = wsd + D.fac_off;
   const bool q1 = plan[ii].route == 2;
-  v4d se = zero4(), sp = zero4();
+  v4d se = zero4(), sp = zero4(), sq = zero4();
   for (int k = 0; k < T.nterms; ++k) {
     const v4d x = *reinterpret_cast<const v4d *>(X + (int64_t)k * nn + e0);
     const double we = q1 ? T.we_re[k] * T.c_re[k] : T.we_re[k];
     const double wp = q1 ? T.wp_re[k] * T.c_re[k] : T.wp_re[k];
+    const double wq = T.wq_re[k];  // phi2: real full instances on route 1 only
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       se[v] = fma(we, x[v], se[v]);
       sp[v] = fma(wp, x[v], sp[v]);
+      sq[v] = fma(wq, x[v], sq[v]);
     }
   }
   if (T.d1e != 0.0 || T.d2e != 0.0) {
@@ -349,6 +352,7 @@ combine_inv_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ il
   double *base = wsd + D.r_off;
   *reinterpret_cast<v4d *>(base + nn + e0) = se;                    // R buffer 1
   if (T.want_phi) *reinterpret_cast<v4d *>(base + 3 * nn + e0) = sp;  // Phi buffer 1
+  if (T.want_phi2) *reinterpret_cast<v4d *>(base + 5 * nn + e0) = sq; // Phi2 buffer 1
 }
 
 }  // namespace pfm

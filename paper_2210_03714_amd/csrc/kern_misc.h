@@ -109,7 +109,7 @@ plan_finish_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan
 // y = instance.
 __global__ void __launch_bounds__(256)
 store_full_kernel(const InstDesc *__restrict__ inst, const PlanRec *__restrict__ plan,
-                  const double *__restrict__ wsd, int want_exp, int want_phi) {
+                  const double *__restrict__ wsd, int want_exp, int want_phi, int want_phi2) {
   __shared__ double tile[2][32][33];
   const int ii = blockIdx.y;
   const InstDesc D = inst[ii];
@@ -124,11 +124,12 @@ store_full_kernel(const InstDesc *__restrict__ inst, const PlanRec *__restrict__
   const int64_t nn = (int64_t)np * np;
   const int t = threadIdx.x;
   const bool cplx_out = D.emb && D.cin;
-  for (int which = 0; which < 2; ++which) {
+  for (int which = 0; which < 3; ++which) {
     if (which == 0 && !want_exp) continue;
     if (which == 1 && !want_phi) continue;
+    if (which == 2 && !want_phi2) continue;
     const double *src = wsd + D.r_off + (which * 2 + (s & 1)) * nn;
-    double *dst = which ? D.Fp : D.Fe;
+    double *dst = which == 2 ? D.Fq : (which ? D.Fp : D.Fe);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int r = r0 + (t & 7) * 4 + u, c = c0 + (t >> 3);

@@ -252,6 +252,34 @@ solve_full_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__
           if constexpr (PHI) Ap[rb][ct][v] = fold ? (fp ? Ap[rb][ct][v] + zf : Ap[rb][ct][v]) : fma(wp, z, Ap[rb][ct][v]);
         }
       }
+    if constexpr (PHI) {
+      if (T.want_phi2) {
+        // phi2 (real shift sets, never folded): sum_k wq_k Z_k accumulates in
+        // its level-0 buffer, shift by shift in the order k = 0, 1, ...
+        // (this workgroup's columns; no registers held across shifts)
+        double *Q0 = wsd + D.r_off + 4 * (int64_t)np * np;
+        const bool last = k + 1 == T.nterms;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const int b = wave + 4 * rb;
+          if (b >= nblk) continue;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            const int col = c0 + 16 * ct + i16;
+            if (col >= ncol) continue;
+            const int r = 16 * b + 4 * g;
+            v4d *pq = reinterpret_cast<v4d *>(Q0 + r + (int64_t)col * np);
+            v4d o = k == 0 ? zero4() : *pq;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = fma(T.wq_re[k], Z[rb][ct][v], o[v]);
+            if (last)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) o[v] += (r + v == col ? T.a0q : 0.0);
+            *pq = o;
+          }
+        }
+      }
+    }
     __syncthreads();
   }
 

@@ -1,6 +1,9 @@
 // Undoing the scaling (§1): s squarings R <- R R, preceded for phi1 by the
 // doubling step Phi <- (R + I) Phi / 2, which uses R before it is squared
-// (phi1(2B) = (e^B + I) phi1(B) / 2).
+// (phi1(2B) = (e^B + I) phi1(B) / 2), and for phi2 by
+// Phi2 <- (Phi Phi + 2 Phi2) / 4 with Phi before its own step
+// (phi2(2z) = (phi1(z)^2 + 2 phi2(z)) / 4, from e^{2z} - 1 - 2z =
+// z^2 phi1(z)^2 + 2 z^2 phi2(z)).
 //
 // Every instance has its own s.  Level j (j = 1..max s) is one launch per
 // tile size over the output tiles of the instances with s >= j (128 x 128
@@ -22,9 +25,11 @@ namespace pfm {
 
 struct SqTask {
   int32_t inst;  // -1: padding
-  int32_t tile;  // tile index; + (1 << 20) for the Phi product
+  int32_t tile;  // tile index; + (1 << 20) for the Phi product, + (2 << 20) for Phi2's
 };
 
+// Buffers of an instance (np^2 doubles each, from D.r_off): R in 0 / 1, Phi
+// in 2 / 3, Phi2 in 4 / 5 (level j writes j mod 2).
 // MODE 0: squaring level `level` as described above.
 // MODE 1: the combination's product for the Gauss-Jordan path,
 //         R = a0 I + S B (S in buffer 1, B read from the row-major A: A 2^-s,
@@ -45,7 +50,7 @@ struct SqTask {
 template <int MODE, int TILE>
 __device__ __forceinline__ void sq_tile(const InstDesc *__restrict__ inst, const SqTask tk, int level,
                                         double *__restrict__ wsd, const PlanRec *__restrict__ plan, double a0e,
-                                        double a0p, double a1e, double a1p) {
+                                        double a0p, double a1e, double a1p, double a0q = 0.0) {
   static_assert(TILE == 64 || TILE == 128, "tile");
   constexpr int LDA = TILE + 16, LDB = TILE + 16;  // == 16 mod 32 doubles: conflict-free fragment reads
   constexpr int NP = TILE / 64;   // staging passes per operand
@@ -72,14 +77,22 @@ __device__ __forceinline__ void sq_tile(const InstDesc *__restrict__ inst, const
   const bool act = MODE != 0 && level == 1;
   const bool q1 = MODE == 1 && plan[tk.inst].route == 2;
   double *facb = wsd + D.fac_off + (which ? nn : 0);
+  const double *Qold = nullptr;  // Phi2_{j-1} (MODE 0, which 2)
   if (MODE == 0) {
-    Asrc = base + ((level - 1) & 1) * nn;   // R_{j-1}
-    Bsrc = which ? base + (2 + ((level - 1) & 1)) * nn : Asrc;
-    Cdst = which ? base + (2 + (level & 1)) * nn : base + (level & 1) * nn;
+    if (which == 2) {
+      Asrc = base + (2 + ((level - 1) & 1)) * nn;  // Phi_{j-1} Phi_{j-1}
+      Bsrc = Asrc;
+      Qold = base + (4 + ((level - 1) & 1)) * nn;
+      Cdst = base + (4 + (level & 1)) * nn;
+    } else {
+      Asrc = base + ((level - 1) & 1) * nn;   // R_{j-1}
+      Bsrc = which ? base + (2 + ((level - 1) & 1)) * nn : Asrc;
+      Cdst = which ? base + (2 + (level & 1)) * nn : base + (level & 1) * nn;
+    }
   } else if (MODE == 1) {
-    Asrc = q1 ? facb : base + (which ? 3 : 1) * nn;  // B T, or S_e / S_p
+    Asrc = q1 ? facb : base + (2 * which + 1) * nn;  // B T, or S_e / S_p / S_p2
     Bsrc = nullptr;
-    Cdst = base + (which ? 2 : 0) * nn;
+    Cdst = base + 2 * which * nn;
     sdiv = plan[tk.inst].s;
   } else {
     Asrc = nullptr;
@@ -120,7 +133,7 @@ __device__ __forceinline__ void sq_tile(const InstDesc *__restrict__ inst, const
           else
             a = r < hn ? -Asrc[(r + hn) + (int64_t)(kc - hn) * np] : Asrc[(r - hn) + (int64_t)(kc - hn) * np];
         }
-        if (MODE == 0 && which && r == kc) a += 1.0;  // (R + I) for the phi1 doubling
+        if (MODE == 0 && which == 1 && r == kc) a += 1.0;  // (R + I) for the phi1 doubling
         ra[ps][u] = a;
         if (MODE == 0) {
           const int c = no + bc;
@@ -168,8 +181,8 @@ __device__ __forceinline__ void sq_tile(const InstDesc *__restrict__ inst, const
     }
     __syncthreads();
   }
-  const double scl = (MODE == 0 && which) ? 0.5 : 1.0;
-  const double dia = MODE == 1 ? (which ? a0p : a0e) : 0.0;
+  const double scl = MODE == 0 ? (which == 2 ? 0.25 : (which ? 0.5 : 1.0)) : 1.0;
+  const double dia = MODE == 1 ? (which == 2 ? a0q : (which ? a0p : a0e)) : 0.0;
   const double lin = q1 ? (which ? a1p : a1e) : 0.0;
   const int oc = MODE == 2 ? np : ncol;  // computed columns
 #pragma unroll
@@ -180,6 +193,11 @@ __device__ __forceinline__ void sq_tile(const InstDesc *__restrict__ inst, const
       const int r = m0 + WT * wm + 16 * a + 4 * g;
       if (c < oc && r < np) {
         v4d o = acc[a][b] * scl;
+        if (MODE == 0 && which == 2) {
+          const v4d q = *reinterpret_cast<const v4d *>(Qold + r + (int64_t)c * np);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) o[v] = fma(0.5, q[v], o[v]);
+        }
         if (MODE == 1) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -200,7 +218,7 @@ __global__ void __launch_bounds__(256, 2)
 square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restrict__ tasks,
                         int ntasks, int level, double *__restrict__ wsd,
                         const PlanRec *__restrict__ plan, double a0e, double a0p,
-                        double a1e = 0.0, double a1p = 0.0) {
+                        double a1e = 0.0, double a1p = 0.0, double a0q = 0.0) {
   const int q = blockIdx.x;
   if (q >= ntasks) return;
   const SqTask tk = tasks[q];
@@ -210,7 +228,7 @@ square_level_f64_kernel(const InstDesc *__restrict__ inst, const SqTask *__restr
   if (MODE == 0 && P.s < level) return;
   if (MODE == 1 && P.route == 0) return;
   if (MODE == 2 && P.route != 2) return;
-  sq_tile<MODE, TILE>(inst, tk, level, wsd, plan, a0e, a0p, a1e, a1p);
+  sq_tile<MODE, TILE>(inst, tk, level, wsd, plan, a0e, a0p, a1e, a1p, a0q);
 }
 
 }  // namespace pfm

@@ -138,10 +138,15 @@ int set_err(pfm_ctx *ctx, int code, const char *fmt, ...) {
       return set_err(ctx, PFM_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
   } while (0)
 
-inline bool T_want_phi(int f) { return f != PFM_LOG1M && (f & PFM_PHI1); }
+inline bool T_want_phi(int f) { return f != PFM_LOG1M && (f & (PFM_PHI1 | PFM_PHI2)); }
 
-// table index of a single function bit (PFM_EXP 0, PFM_PHI1 1, PFM_LOG1M 2)
-inline int func_index(int f) { return f == PFM_EXP ? 0 : (f == PFM_PHI1 ? 1 : 2); }
+// table index of a single function bit (PFM_EXP 0, PFM_PHI1 1, PFM_LOG1M 2,
+// PFM_PHI2 3)
+inline int func_index(int f) { return f == PFM_EXP ? 0 : (f == PFM_PHI1 ? 1 : (f == PFM_LOG1M ? 2 : 3)); }
+
+// a function mask pfm_eval_batched accepts: PFM_LOG1M alone, or a nonempty
+// combination of PFM_EXP, PFM_PHI1 and PFM_PHI2
+inline bool valid_mask(int f) { return f == PFM_LOG1M || (f > 0 && (f & ~(PFM_EXP | PFM_PHI1 | PFM_PHI2)) == 0); }
 
 const PfmSetEntry *find_set(int m, int func) {
   for (int i = 0; i < kPfmNumSets; ++i)
@@ -325,9 +330,10 @@ int pfm_profile_read(pfm_ctx *ctx, double *ms, int *launches, int *calls) {
 }
 
 size_t pfm_workspace_bytes(int f, int m, int prec, int dtype, int batch, const pfm_problem *probs) {
-  if (f < 1 || f > 3 || batch < 1 || !probs) return 0;
+  if (!valid_mask(f) || f == PFM_LOG1M || batch < 1 || !probs) return 0;
   const PfmSetEntry *ee = find_set(m, 0), *ep = find_set(m, 1);
-  if (!ee || (!ep && (f & PFM_PHI1))) return 0;
+  if (!ee || (!ep && (f & (PFM_PHI1 | PFM_PHI2))) || ((f & PFM_PHI2) && !find_set(m, 3))) return 0;
+  const int64_t rbufs = (f & PFM_PHI2) ? 6 : 4;
   const bool cplx = dtype == PFM_C128, pairs = ee->pair != 0, mixed = prec == PFM_MIXED;
   const bool emb = cplx || pairs;
   const bool phi = (f & PFM_PHI1) != 0;
@@ -345,7 +351,7 @@ size_t pfm_workspace_bytes(int f, int m, int prec, int dtype, int batch, const p
     const int64_t np = (nk + 63) / 64 * 64, nn = np * np;
     const bool large = nk > 512;
     const bool may_ln = large || (!mixed && !pairs && nk > kLnMin && (act || emb));
-    d += nterms * nn + 4 * nn + 6 * 64;
+    d += nterms * nn + rbufs * nn + 6 * 64;
     if (may_ln) {
       d += nterms * ln_stride((int)np);
       if (P.p > 0) d += 2 * ln_vchain((int)np, P.p) + (int64_t)ln_ks((int)nk) * np * ln_pp(P.p);
@@ -408,7 +414,7 @@ const char *pfm_last_error(const pfm_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 int pfm_coeffs(int f, int m, int *n_terms, double *c_re, double *c_im, double *w_re, double *w_im,
                double *a0, int *order, int *is_pair) {
-  if (f != PFM_EXP && f != PFM_PHI1 && f != PFM_LOG1M) return PFM_ERR_INVALID;
+  if (f != PFM_EXP && f != PFM_PHI1 && f != PFM_LOG1M && f != PFM_PHI2) return PFM_ERR_INVALID;
   const PfmSetEntry *e = find_set(m, func_index(f));
   if (!e) return PFM_ERR_UNSUPPORTED;
   if (n_terms) *n_terms = e->nterms;
@@ -425,7 +431,7 @@ int pfm_coeffs(int f, int m, int *n_terms, double *c_re, double *c_im, double *w
 }
 
 int pfm_poly(int f, int m, double *d1, double *d2) {
-  if (f != PFM_EXP && f != PFM_PHI1 && f != PFM_LOG1M) return PFM_ERR_INVALID;
+  if (f != PFM_EXP && f != PFM_PHI1 && f != PFM_LOG1M && f != PFM_PHI2) return PFM_ERR_INVALID;
   const PfmSetEntry *e = find_set(m, func_index(f));
   if (!e) return PFM_ERR_UNSUPPORTED;
   if (d1) *d1 = e->poly[0];
@@ -441,14 +447,17 @@ int pfm_theta(int f, int m, double tol, double *theta) {
     *theta = theta_of(el, tol);
     return PFM_OK;
   }
-  if (f < 1 || f > 3) return PFM_ERR_INVALID;
+  if (!valid_mask(f)) return PFM_ERR_INVALID;
   // phi1 always carries the exponential approximant too (its doubling and its
-  // recurrence apply e^B), so its θ is the smaller of the two.
+  // recurrence apply e^B), and phi2 carries both (its doubling squares phi1),
+  // so θ is the smallest of those involved.
   const PfmSetEntry *ee = find_set(m, 0);
   const PfmSetEntry *ep = find_set(m, 1);
-  if (!ee || (!ep && (f & PFM_PHI1))) return PFM_ERR_UNSUPPORTED;
+  const PfmSetEntry *eq = find_set(m, 3);
+  if (!ee || (!ep && (f & (PFM_PHI1 | PFM_PHI2))) || (!eq && (f & PFM_PHI2))) return PFM_ERR_UNSUPPORTED;
   double th = theta_of(ee, tol);
-  if (f & PFM_PHI1) th = std::min(th, theta_of(ep, tol));
+  if (f & (PFM_PHI1 | PFM_PHI2)) th = std::min(th, theta_of(ep, tol));
+  if (f & PFM_PHI2) th = std::min(th, theta_of(eq, tol));
   *theta = th;
   return PFM_OK;
 }
@@ -502,6 +511,7 @@ int sparse_terms(pfm_ctx *ctx, const char *what, int f, int m, double tol, TriTe
 }
 
 int tri_validate(pfm_ctx *ctx, int f, double tol, int batch, const pfm_tri_problem *probs) {
+  if (f & PFM_PHI2) return set_err(ctx, PFM_ERR_UNSUPPORTED, "phi2 is provided for dense full matrices");
   if (f < 1 || f > 3) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
   if (!(tol > 0.0 && tol < 1.0)) return set_err(ctx, PFM_ERR_INVALID, "tol must lie in (0,1)");
   if (batch < 1 || !probs) return set_err(ctx, PFM_ERR_INVALID, "empty batch");
@@ -703,6 +713,7 @@ int pfm_tri_action_noalloc(pfm_ctx *ctx, int f, int m, double tol, int batch, co
 int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, const pfm_band_problem *probs,
                     pfm_info *info, int force_plan, pfm_stream_t stream_) {
   if (!ctx) return PFM_ERR_INVALID;
+  if (f & PFM_PHI2) return set_err(ctx, PFM_ERR_UNSUPPORTED, "phi2 is provided for dense full matrices");
   if (f < 1 || f > 3) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
   if (!(tol > 0.0 && tol < 1.0)) return set_err(ctx, PFM_ERR_INVALID, "tol must lie in (0,1)");
   if (b < 1 || b > PFM_BAND_MAX_B) return set_err(ctx, PFM_ERR_INVALID, "half-bandwidth b = %d not in [1, %d]", b,
@@ -857,7 +868,8 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
   const bool log1m = f == PFM_LOG1M;
   // a caller-given set: no scaling identity, r(A) itself (s = 0) or one step
   // of the action (N = 1)
-  if ((f < 1 || f > 3) && !log1m) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
+  if (!valid_mask(f)) return set_err(ctx, PFM_ERR_INVALID, "bad function mask %d", f);
+  const bool phi2 = !log1m && (f & PFM_PHI2);
   if (tols) {  // per-instance tolerances: the scalar is their minimum
     if (batch < 1) return set_err(ctx, PFM_ERR_INVALID, "empty batch");
     tol = tols[0];
@@ -880,9 +892,11 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
     const int64_t ocols = action ? P.p : P.n;
     if (P.ldf < ocols) return set_err(ctx, PFM_ERR_INVALID, "problem %d: ldf too small", i);
     if (((f & PFM_EXP) || log1m) && !P.F_exp) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_exp null", i);
-    if ((f & PFM_PHI1) && !P.F_phi1) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_phi1 null", i);
+    if ((f & PFM_PHI1) && !log1m && !P.F_phi1) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_phi1 null", i);
+    if (phi2 && !P.F_phi2) return set_err(ctx, PFM_ERR_INVALID, "problem %d: F_phi2 null", i);
     if (action && (!P.V || P.ldv < P.p)) return set_err(ctx, PFM_ERR_INVALID, "problem %d: bad V", i);
-    if (misaligned(P.A) || misaligned(P.V) || misaligned(P.F_exp) || misaligned(P.F_phi1))
+    if (misaligned(P.A) || misaligned(P.V) || misaligned(P.F_exp) || misaligned(P.F_phi1) ||
+        (phi2 && misaligned(P.F_phi2)))
       return set_err(ctx, PFM_ERR_INVALID, "problem %d: an array is not 8-byte aligned", i);
   }
   const PfmSetEntry *ee = nullptr, *ep = nullptr;
@@ -916,6 +930,17 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
   const bool cplx = dtype == PFM_C128;
   const int order_v = cs ? 0 : ee->order;
   const bool mixed = prec == PFM_MIXED;
+  const PfmSetEntry *eq = nullptr;
+  if (phi2) {
+    // phi2 with the squaring recurrence: real full matrices in binary64 on
+    // the single-workgroup routes, real shift sets
+    eq = cs ? nullptr : find_set(m, 3);
+    bool small = true;
+    for (int i = 0; i < batch; ++i) small &= probs[i].n <= 512;
+    if (!eq || hybrid || pairs || mixed || cplx || action || !small)
+      return set_err(ctx, PFM_ERR_UNSUPPORTED,
+                     "phi2 is provided for real full matrices up to n = 512 in binary64 with m = 4, 5 or 8");
+  }
   if (mixed && (cplx || pairs || action))
     return set_err(ctx, PFM_ERR_UNSUPPORTED,
                    "the mixed path is built for real full-matrix problems with real shift sets");
@@ -955,7 +980,8 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
   }
   for (int i = 0; i < (cs ? 0 : tols ? batch : 1); ++i) {
     const double ti = tols ? tols[i] : tol, th = thetas[i];
-    const double fl = std::max(rounding_floor(ee, th), T_want_phi(f) ? rounding_floor(ep, th) : 0.0);
+    const double fl = std::max({rounding_floor(ee, th), T_want_phi(f) ? rounding_floor(ep, th) : 0.0,
+                                phi2 ? rounding_floor(eq, th) : 0.0});
     if (ti < fl)
       return set_err(ctx, PFM_ERR_UNSUPPORTED, "tol %g is below the rounding floor %.2g of the m = %d set", ti, fl, m);
   }
@@ -966,9 +992,11 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
     T = cs->T;
   } else {
   T.want_exp = ((f & PFM_EXP) || log1m) ? 1 : 0;  // log(1 - A) runs in the exp slot
-  T.want_phi = (f & PFM_PHI1) ? 1 : 0;
+  T.want_phi = ((f & PFM_PHI1) && !log1m) || phi2 ? 1 : 0;  // phi2's doubling squares phi1
+  T.want_phi2 = phi2 ? 1 : 0;
   T.a0e = ee->a0;
   T.a0p = ep->a0;
+  T.a0q = phi2 ? eq->a0 : 0.0;
   T.d1e = ee->poly[0];
   T.d2e = ee->poly[1];
   if (!pairs) {
@@ -978,6 +1006,7 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
       T.c_re[k] = ee->c_re[k];
       T.we_re[k] = ee->w_re[k];
       T.wp_re[k] = ep->w_re[k];
+      T.wq_re[k] = phi2 ? eq->w_re[k] : 0.0;
     }
   } else {
     // one conjugate pair per function (the Padé poles of exp and phi1
@@ -1042,6 +1071,7 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
     D.V = (const double *)P.V;
     D.Fe = (double *)P.F_exp;
     D.Fp = (double *)P.F_phi1;
+    D.Fq = (double *)P.F_phi2;
     D.ldv = P.ldv;
     D.ldf = P.ldf;
     D.emb = emb ? 1 : 0;
@@ -1072,7 +1102,7 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
     if (!large) {
       D.dinv_off = dofs; dofs += align_up(nterms * 2 * (np / 16) * 256, 64);
     }
-    D.r_off = dofs;    dofs += align_up(4 * nn, 64);
+    D.r_off = dofs;    dofs += align_up((phi2 ? 6 : 4) * nn, 64);
     if (emb || mixed) {
       D.e_off = dofs;  dofs += align_up((int64_t)std::max(D.n, D.npad) * D.npad, 64);
     }
@@ -1148,6 +1178,7 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
   // reuses; per list one part per tile size (128 for npad >= 256, else 64).
   // All tiles of one instance go to one XCD.
   std::vector<SqTask> all;
+  const int nchains = 1 + T.want_phi + T.want_phi2;  // products per output tile and level: R, Phi, Phi2
   using LevelLists = std::array<std::pair<int64_t, int>, 2>;  // (offset, count) per tile size
   auto build = [&](const std::vector<int> &ids, int tc, bool all_cols) {
     std::vector<std::vector<SqTask>> qx(8);
@@ -1157,7 +1188,7 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
       if (tile_of(i) != tc) continue;
       const int tlm = (desc[i].npad + TL - 1) / TL;
       const int tln = ((all_cols ? desc[i].npad : desc[i].ncol) + TL - 1) / TL;
-      for (int w = 0; w < 1 + T.want_phi; ++w)
+      for (int w = 0; w < nchains; ++w)
         for (int tt = 0; tt < tlm * tln; ++tt) qx[x].push_back(SqTask{i, tt + (w << 20)});
       x = (x + 1) & 7;
     }
@@ -1337,11 +1368,11 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
     if ((LL)[0].second)                                                                             \
       hipLaunchKernelGGL((square_level_f64_kernel<MODE, 64>), dim3((LL)[0].second), dim3(256), 0, stream, \
                          d_desc, dt + (LL)[0].first, (LL)[0].second, LEVEL, wsd, d_plan, T.a0e, T.a0p, a1e,  \
-                         a1p);                                                                      \
+                         a1p, T.a0q);                                                               \
     if ((LL)[1].second)                                                                             \
       hipLaunchKernelGGL((square_level_f64_kernel<MODE, 128>), dim3((LL)[1].second), dim3(256), 0,  \
                          stream, d_desc, dt + (LL)[1].first, (LL)[1].second, LEVEL, wsd, d_plan, T.a0e,     \
-                         T.a0p, a1e, a1p);                                                          \
+                         T.a0p, a1e, a1p, T.a0q);                                                   \
   } while (0)
   // Everything from here on depends only on what the host has decided (the
   // descriptors, lists and task lists); a call that repeats all of it
@@ -1639,22 +1670,22 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
     if (!ng) continue;
     const int *gl = d_list + sq_off[g];
     hipLaunchKernelGGL(sq_queue_kernel, dim3(1), dim3(kQueueThreads), 0, stream, d_desc, d_plan, gl, ng,
-                       g ? 128 : 64, 1 + T.want_phi, pol_direct + 1, qp[g].q, qp[g].ord, qp[g].pre, qp[g].lstart,
+                       g ? 128 : 64, nchains, pol_direct + 1, qp[g].q, qp[g].ord, qp[g].pre, qp[g].lstart,
                        qp[g].done);
     const int grid = std::max(1, occ[g] * ctx->num_cu);
     if (g == 0)
       hipLaunchKernelGGL(sq_persist_kernel<64>, dim3(grid), dim3(256), 0, stream, d_desc, d_plan, gl,
-                         1 + T.want_phi, qp[g].q, qp[g].ord, qp[g].pre, qp[g].lstart, qp[g].done, wsd, ctx->d_err);
+                         nchains, qp[g].q, qp[g].ord, qp[g].pre, qp[g].lstart, qp[g].done, wsd, ctx->d_err);
     else
       hipLaunchKernelGGL(sq_persist_kernel<128>, dim3(grid), dim3(256), 0, stream, d_desc, d_plan, gl,
-                         1 + T.want_phi, qp[g].q, qp[g].ord, qp[g].pre, qp[g].lstart, qp[g].done, wsd, ctx->d_err);
+                         nchains, qp[g].q, qp[g].ord, qp[g].pre, qp[g].lstart, qp[g].done, wsd, ctx->d_err);
     ctx->cur_launches[2] += 2;
   }
   prof_mark(ctx, 3, stream);
   // 5. results to the caller's row-major buffers, then the info records
   const int tn = (maxc + 31) / 32;  // stores run over the caller's n
   hipLaunchKernelGGL(store_full_kernel, dim3(tn * tn, batch), dim3(256), 0, stream, d_desc, d_plan,
-                     wsd, T.want_exp, T.want_phi);
+                     wsd, T.want_exp, (f & PFM_PHI1) && !log1m ? 1 : 0, T.want_phi2);
   ctx->cur_launches[3]++;
   prof_mark(ctx, 4, stream);
   if (ctx->prof) ctx->prof_pending = true;

@@ -25,8 +25,9 @@ struct InstDesc {
   const double *A;   // row-major real matrix the kernels read (embedded if emb)
   const double *Ain; // caller's A (the norm is taken on it; complex: interleaved)
   const double *V;   // caller's V (action), else null
-  double *Fe;        // caller's outputs (row-major)
+  double *Fe;        // caller's outputs (row-major): exp, phi1, phi2
   double *Fp;
+  double *Fq;
   int64_t lda, ldv, ldf;
   int64_t ldin;      // leading dimension of Ain
   int32_t n, npad, p, cls;
@@ -36,7 +37,7 @@ struct InstDesc {
   int32_t ncol;      // columns of the result that are computed (n, or hn if emb)
   int64_t fac_off;   // nterms * npad^2 (complex: 2x) : LU factors, column-major
   int64_t dinv_off;  // nterms * 2 * (npad/16) * 256   : inverted 16x16 diagonal blocks of L and U
-  int64_t r_off;     // 4 * npad^2 : R ping-pong buffers, then phi1 ping-pong buffers
+  int64_t r_off;     // 4 (6 with phi2) * npad^2 : R, phi1 (and phi2) ping-pong buffers
   int64_t e_off;     // emb: the embedded matrix, row-major n x n
   double theta;      // admissible ||B||_1 for this instance's tolerance (§3)
   int64_t ln_off;    // large instances: nterms * ln_stride(npad) (colbuf, dinv)
@@ -79,12 +80,14 @@ __host__ __device__ inline bool on_route(const PlanRec &P, int r) { return P.rou
 struct Terms {
   int32_t nterms;
   int32_t pair_real;
-  int32_t want_exp, want_phi;
-  double a0e, a0p;
+  int32_t want_exp, want_phi;  // want_phi: the phi1 chain is computed (also for phi2)
+  int32_t want_phi2, pad_;
+  double a0e, a0p, a0q;         // a0q, wq_re: phi2 (real shift sets, no folding)
   double d1e, d2e;  // polynomial part d1 B + d2 B^2 of the hybrid set (exp), else 0
   double c_re[kMaxTerms], c_im[kMaxTerms];
   double we_re[kMaxTerms], we_im[kMaxTerms];
   double wp_re[kMaxTerms], wp_im[kMaxTerms];
+  double wq_re[kMaxTerms];
   int32_t fold[kMaxTerms];
   int32_t fn[kMaxTerms];
 };

@@ -434,6 +434,7 @@ int pfm_srv_submit(pfm_server *S, const pfm_problem *pr, int f, int m, double to
   if (!S || !pr || !ticket) return PFM_ERR_INVALID;
   if (pr->n < 1 || pr->p < 0 || !pr->A || pr->lda < pr->n || (pr->p > 0 && (!pr->V || pr->ldv < pr->p)))
     return PFM_ERR_INVALID;
+  if (f & PFM_PHI2) return PFM_ERR_UNSUPPORTED;  // served: exp and phi1
   if (f < 1 || f > 3 || !(tol > 0.0 && tol < 1.0)) return PFM_ERR_INVALID;
   if (prec != PFM_FP64 && prec != PFM_MIXED) return PFM_ERR_INVALID;
   if (dtype != PFM_R64 && dtype != PFM_C128) return PFM_ERR_INVALID;

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpfm.so")
 EXP = 1
 PHI1 = 2
 LOG1M = 4  # log(1 - A), on its own (its result goes to F_exp)
+PHI2 = 8   # phi2(A) (full real matrices up to n = 512, binary64, m = 4, 5, 8)
 R64 = 0
 C128 = 1
 FP64 = 0
@@ -47,7 +48,7 @@ class Problem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("lda", ctypes.c_int64), ("ldv", ctypes.c_int64), ("ldf", ctypes.c_int64),
                 ("A", ctypes.c_void_p), ("V", ctypes.c_void_p),
-                ("F_exp", ctypes.c_void_p), ("F_phi1", ctypes.c_void_p)]
+                ("F_exp", ctypes.c_void_p), ("F_phi1", ctypes.c_void_p), ("F_phi2", ctypes.c_void_p)]
 
 
 class TriProblem(ctypes.Structure):
@@ -339,7 +340,7 @@ def _stream_ptr(stream):
 def _fmask(funcs):
     m = 0
     for f in funcs:
-        m |= {"exp": EXP, "phi1": PHI1, "log1m": LOG1M}[f]
+        m |= {"exp": EXP, "phi1": PHI1, "log1m": LOG1M, "phi2": PHI2}[f]
     return m
 
 
@@ -389,11 +390,13 @@ def expm(A, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None
         # log(1 - A) is written to the F_exp slot
         fe = outs["exp"][i] if "exp" in funcs else (outs["log1m"][i] if "log1m" in funcs else None)
         fp = outs["phi1"][i] if "phi1" in funcs else None
-        _check_outputs(fe, fp, a.shape, a.dtype)
-        ldf = (fe if fe is not None else fp).stride(0)
+        fq = outs["phi2"][i] if "phi2" in funcs else None
+        _check_outputs(fe, fp, a.shape, a.dtype, fq)
+        ldf = next(o for o in (fe, fp, fq) if o is not None).stride(0)
         probs.append(Problem(a.shape[0], 0, a.stride(0), 0, ldf, a.data_ptr(), None,
                              fe.data_ptr() if fe is not None else None,
-                             fp.data_ptr() if fp is not None else None))
+                             fp.data_ptr() if fp is not None else None,
+                             fq.data_ptr() if fq is not None else None))
     ctx = ctx or default_context(mats[0].device.index or 0)
     info = _info_buffer(info_out, len(mats), mats[0].device)
     rc = ctx.eval_batched(probs, fm, m, tol, {"fp64": FP64, "mixed": MIXED}[prec],
@@ -403,18 +406,17 @@ def expm(A, funcs=("exp",), m=8, tol=1e-12, prec="fp64", force_plan=-1, ctx=None
     return out, _Info(info)
 
 
-def _check_outputs(fe, fp, shape, dtype):
+def _check_outputs(fe, fp, shape, dtype, fq=None):
     """The result tensors of one instance: on the GPU, of the instance's shape
-    and element type, unit column stride, and one row stride for both
-    functions (the library writes both with the same leading dimension)."""
-    for o in (fe, fp):
-        if o is None:
-            continue
+    and element type, unit column stride, and one row stride for all
+    functions (the library writes them with the same leading dimension)."""
+    present = [o for o in (fe, fp, fq) if o is not None]
+    for o in present:
         _require_gpu(o)
         if o.dtype != dtype or tuple(o.shape) != tuple(shape) or o.stride(1) != 1:
             raise ValueError("each output must be a %s tensor of shape %s with unit column stride"
                              % (dtype, tuple(shape)))
-    if fe is not None and fp is not None and fe.stride(0) != fp.stride(0):
+    if len({o.stride(0) for o in present}) > 1:
         raise ValueError("the outputs of one instance must share their row stride")
 
 

@@ -43,9 +43,9 @@ def test_version(L):
 
 
 @pytest.mark.parametrize("m", [4, 5, 8])
-@pytest.mark.parametrize("func", ["exp", "phi1"])
+@pytest.mark.parametrize("func", ["exp", "phi1", "phi2"])
 def test_coeffs_bitwise_equal_oracle(L, m, func):
-    c, w, a0, order, pair = pfm.coeffs(pfm.EXP if func == "exp" else pfm.PHI1, m)
+    c, w, a0, order, pair = pfm.coeffs({"exp": pfm.EXP, "phi1": pfm.PHI1, "phi2": pfm.PHI2}[func], m)
     a0o, terms = co.roundoff_terms(func, m)
     assert not pair
     assert a0 == a0o
@@ -68,7 +68,10 @@ def test_coeffs_pairs_match_oracle(L, func):
 @pytest.mark.parametrize("m", [1, 4, 5, 8])
 @pytest.mark.parametrize("tol", [2.0 ** -24, 1e-8, 1e-10, 1e-12])
 def test_theta_matches_oracle(L, m, tol):
-    for fm, funcs in ((pfm.EXP, ("exp",)), (pfm.EXP | pfm.PHI1, ("exp", "phi1"))):
+    cases = [(pfm.EXP, ("exp",)), (pfm.EXP | pfm.PHI1, ("exp", "phi1"))]
+    if m > 1:  # phi2 brings in the exponential's and phi1's bounds
+        cases += [(pfm.PHI2, ("exp", "phi1", "phi2")), (pfm.EXP | pfm.PHI2, ("exp", "phi1", "phi2"))]
+    for fm, funcs in cases:
         lib_t = pfm.theta(fm, m, tol)
         orc_t = min(th.theta_set(f, m, tol) for f in funcs)
         assert abs(lib_t - orc_t) <= 1e-13 * orc_t, (m, tol, lib_t, orc_t)
@@ -84,6 +87,11 @@ def test_invalid_arguments_rejected_on_host(L):
     n = ctypes.c_int()
     assert L.pfm_coeffs(3, 8, ctypes.byref(n), None, None, None, None, None, None, None) == pfm.ERR_INVALID
     assert L.pfm_coeffs(1, 7, ctypes.byref(n), None, None, None, None, None, None, None) == pfm.ERR_UNSUPPORTED
+    # phi2: no m = 1 Padé pair and no hybrid weights; 16 is not a function
+    assert L.pfm_coeffs(pfm.PHI2, 1, ctypes.byref(n), None, None, None, None, None, None, None) == pfm.ERR_UNSUPPORTED
+    assert L.pfm_theta(pfm.PHI2, 10, 1e-12, ctypes.byref(out)) == pfm.ERR_UNSUPPORTED
+    assert L.pfm_theta(16, 8, 1e-12, ctypes.byref(out)) == pfm.ERR_INVALID
+    assert L.pfm_theta(pfm.LOG1M | pfm.EXP, 5, 1e-12, ctypes.byref(out)) == pfm.ERR_INVALID
 
 
 def test_workspace_bytes_host(L):
