@@ -32,11 +32,21 @@ PEAK_HBM = 8.0e12     # bytes/s
 PROBLEM_DTYPE = None
 
 
+def problem_dtype(np):
+    """numpy record type of pfm_problem, checked against the binding's layout."""
+    import ctypes
+    from paper_2210_03714_amd.pfm import Problem
+    dt = np.dtype([("n", "<i4"), ("p", "<i4"), ("lda", "<i8"), ("ldv", "<i8"), ("ldf", "<i8"),
+                   ("A", "<u8"), ("V", "<u8"), ("F_exp", "<u8"), ("F_phi1", "<u8"), ("F_phi2", "<u8")])
+    assert dt.itemsize == ctypes.sizeof(Problem)
+    for name, _ in Problem._fields_:
+        assert dt.fields[name][1] == getattr(Problem, name).offset, name
+    return dt
+
+
 def _problem_array(np, A, outs, ldf):
     """pfm_problem records for a (batch, n, n) tensor A and output tensors."""
-    dt = np.dtype([("n", "<i4"), ("p", "<i4"), ("lda", "<i8"), ("ldv", "<i8"), ("ldf", "<i8"),
-                   ("A", "<u8"), ("V", "<u8"), ("F_exp", "<u8"), ("F_phi1", "<u8")])
-    assert dt.itemsize == 64
+    dt = problem_dtype(np)
     b, n = A.shape[0], A.shape[1]
     arr = np.zeros(b, dtype=dt)
     es = A.element_size()
