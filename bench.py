@@ -299,6 +299,9 @@ def tri_leg(batch, d, p, reps, cpu, hybrid=True):
     steps_ms = phases["solve_combine"][0] / max(1, calls)
     algo = colsteps * 16.0 * d
     achieved = algo / (steps_ms * 1e-3)
+    # d <= 1024 runs in the wave-per-column scan kernel, larger d in the
+    # lane-per-column kernel
+    kname = "tri_scan_kernel<8,false,false>" if d <= 1024 else "tri_steps_kernel<8,false,false>"
     res = {"metric": "tridiagonal exp(A)v columns/s", "value": round(batch * p / wall, 1), "unit": "columns/s",
            "ms_per_call": round(wall * 1e3, 3), "steps_kernel_ms": round(steps_ms, 3),
            "factor_kernel_ms": round(phases["lu"][0] / max(1, calls), 3),
@@ -307,9 +310,9 @@ def tri_leg(batch, d, p, reps, cpu, hybrid=True):
            "config": {"workload": "batch %d x tridiagonal d=%d, N(0,1) diagonals rescaled to ||A||_1~U[0.5,8], "
                                   "p=%d columns N(0,1), exp(A)V, m=8 (R8), tol 1e-12, FP64" % (batch, d, p),
                       "batch": batch, "d": d, "p": p},
-           "roofline": {"bound": "hbm", "kernel": "tri_steps_kernel<8,false,false>", "achieved": round(achieved / 1e9, 1),
+           "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved / 1e9, 1),
                         "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
-                        "traffic": traffic_from_profile("tri_steps_kernel<8,false,false>")}}
+                        "traffic": traffic_from_profile(kname)}}
     if hybrid:
         # R10' of §5: the hybrid set of §4.3 (m = 10) on the same batch
         F8 = F.clone()
@@ -594,6 +597,7 @@ def main():
     ap.add_argument("--no-config4", action="store_true", help="skip the uneven mixed-precision batch")
     ap.add_argument("--band-batch", type=int, default=4096)
     ap.add_argument("--band-only", action="store_true", help="run only the banded leg (profiling)")
+    ap.add_argument("--tri-only", action="store_true", help="run only the tridiagonal leg (profiling)")
     ap.add_argument("--tri-batch", type=int, default=4096)
     ap.add_argument("--tri-d", type=int, default=1024)
     ap.add_argument("--tri-p", type=int, default=64)
@@ -609,7 +613,7 @@ def main():
 
     # the oracle's worker processes start before anything touches the GPU
     cpu = None
-    if not args.no_cpu_baseline and not args.calib_copy and not args.band_only:
+    if not args.no_cpu_baseline and not args.calib_copy and not args.band_only and not args.tri_only:
         cpu = OracleBaseline(runs=args.cpu_runs, run_s=args.cpu_run_seconds)
 
     import numpy as np
@@ -626,6 +630,9 @@ def main():
 
     if args.band_only:
         print(json.dumps(band_leg(args.band_batch, args.tri_d, args.tri_p, 2, 3, None)))
+        return
+    if args.tri_only:
+        print(json.dumps(tri_leg(args.tri_batch, args.tri_d, args.tri_p, 3, None)))
         return
 
     from paper_2210_03714_amd import pfm

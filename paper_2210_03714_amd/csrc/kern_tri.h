@@ -34,6 +34,9 @@ namespace pfm {
 
 constexpr int kTriL = 8;         // rows per checkpoint chunk
 constexpr int kTriTerms = 10;    // most shifts in a real set (the hybrid set of §4.3)
+constexpr int kTsR = 16;         // tri_scan_kernel: rows per lane
+constexpr int kTsMaxD = 64 * kTsR;  // its largest d (one wave holds a column)
+constexpr int kTsW = 8;          // its waves (columns) per workgroup
 
 struct TriDesc {
   const double *dl, *dd, *du, *V;
@@ -45,8 +48,10 @@ struct TriDesc {
   int64_t f_off;  // factors: [k][l, ui, em][d]
   int64_t v_off;  // vectors: [slot][3][d][p]
   int64_t c_off;  // checkpoints: [slot][chunk][k][p]
-  int32_t wave0;   // first wave of this instance in the step launch
-  int32_t nwaves;  // its waves: functions x ceil(p / 64)
+  int32_t wave0;   // first wave of this instance in tri_steps_kernel's launch
+  int32_t nwaves;  // its waves: functions x ceil(p / 64) (0: tri_scan_kernel takes it)
+  int32_t sg0;     // first workgroup of this instance in tri_scan_kernel's launch
+  int32_t nsg;     // its workgroups: functions x ceil(p / kTsW) (0: tri_steps_kernel takes it)
 };
 
 struct TriTerms {
@@ -142,7 +147,7 @@ tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
   for (int r = 1; r < d; ++r) {
     const double mlo = -c * (D.dl[r - 1] / Nd);  // M[r][r-1]
     const double mup = -c * (D.du[r - 1] / Nd);  // M[r-1][r]
-    const double lr = mlo / u;
+    const double lr = mlo * uinv;  // tri_scan_kernel forms the same product from ui
     em[r - 1] = mup * uinv;
     u = (1.0 - c * (D.dd[r] / Nd)) - lr * mup;
     uinv = 1.0 / u;
@@ -476,6 +481,236 @@ tri_steps_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__r
       }
     }
     // block 0 is staged in buffer 0 again for the next step's pass 1
+  }
+}
+
+// One double through a DPP lane move (two 32-bit moves).  Lanes whose source
+// lies outside the pattern, and rows that RM leaves out, take `old`.
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ double dpp_f64(double src, double old) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(src), CTRL, RM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(src), CTRL, RM, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// The value entering lane L of the recurrence Z_L = g_L Z_{L-1} + h_L,
+// Z_{-1} = 0 (lane 0 gets 0): an inclusive scan of the maps (g, h) over the
+// wave, composed as (g, h) after (g', h') = (g g', g h' + h): shifts by 1, 2,
+// 4, 8 within each row of 16 lanes, then row 0's total into row 1 and row
+// 2's into row 3, then rows 0-1's into rows 2 and 3; the result moved up one
+// lane.  Lanes left without a source compose with the identity (1, 0).
+__device__ __forceinline__ double scan_in_fwd(double g, double h, int lane) {
+#define PFM_SCAN_LEVEL(CTRL, RM)                        \
+  {                                                     \
+    const double gp = dpp_f64<CTRL, RM>(g, 1.0);        \
+    const double hp = dpp_f64<CTRL, RM>(h, 0.0);        \
+    h = fma(g, hp, h);                                  \
+    g *= gp;                                            \
+  }
+  PFM_SCAN_LEVEL(0x111, 0xf)  // row_shr:1
+  PFM_SCAN_LEVEL(0x112, 0xf)  // row_shr:2
+  PFM_SCAN_LEVEL(0x114, 0xf)  // row_shr:4
+  PFM_SCAN_LEVEL(0x118, 0xf)  // row_shr:8
+  PFM_SCAN_LEVEL(0x142, 0xa)  // row_bcast:15 into rows 1 and 3
+  PFM_SCAN_LEVEL(0x143, 0xc)  // row_bcast:31 into rows 2 and 3
+#undef PFM_SCAN_LEVEL
+  (void)lane;
+  return dpp_f64<0x138>(h, 0.0);  // wave_shr:1
+}
+
+// The value entering lane L of X_L = G_L X_{L+1} + H_L, X_64 = 0 (lane 63
+// gets 0): shifts by 1, 2, 4, 8 towards lane 0 within each row, then each
+// row's map is applied to the value leaving the rows above it (the row
+// totals sit in lanes 16, 32, 48; wave-uniform), then moved down one lane.
+__device__ __forceinline__ double scan_in_bwd(double G, double H, int lane) {
+#define PFM_SCAN_LEVEL(CTRL)                          \
+  {                                                   \
+    const double Gp = dpp_f64<CTRL>(G, 1.0);          \
+    const double Hp = dpp_f64<CTRL>(H, 0.0);          \
+    H = fma(G, Hp, H);                                \
+    G *= Gp;                                          \
+  }
+  PFM_SCAN_LEVEL(0x101)  // row_shl:1
+  PFM_SCAN_LEVEL(0x102)  // row_shl:2
+  PFM_SCAN_LEVEL(0x104)  // row_shl:4
+  PFM_SCAN_LEVEL(0x108)  // row_shl:8
+#undef PFM_SCAN_LEVEL
+  const double s2 = readlane_f64(H, 48);                          // leaving row 2 upwards: row 3's total on 0
+  const double s1 = fma(readlane_f64(G, 32), s2, readlane_f64(H, 32));
+  const double s0 = fma(readlane_f64(G, 16), s1, readlane_f64(H, 16));
+  const int row = lane >> 4;
+  const double sin = row == 0 ? s0 : row == 1 ? s1 : row == 2 ? s2 : 0.0;
+  H = fma(G, sin, H);
+  return dpp_f64<0x130>(H, 0.0);  // wave_shl:1
+}
+
+// All N steps of the tridiagonal action with a wave per column: lane L holds
+// rows 16 L .. 16 L + 15 of the column, so the vector and every intermediate
+// stay in registers for the whole call (d <= kTsMaxD).  The sweeps of each
+// shifted system run as affine recurrences split at lane boundaries:
+//   forward  z_r = y_r - l_r z_{r-1}:  each lane composes its rows into one
+//            map Z_L = g_L Z_{L-1} + h_L, an inclusive scan over the lanes
+//            gives every lane the value entering its rows, and the lane then
+//            runs its rows again from that value;
+//   backward x_r = ui_r z_r - em_r x_{r+1}: the same with the maps composed
+//            from the last row up and the scan from lane 63 down.
+// A workgroup is kTsW columns of one function slot of one instance; it
+// stages the instance's B and 1/u of every shift in LDS once, transposed so
+// that the lanes' reads of one row index are consecutive, and forms l and em
+// from them as tri_factor_kernel does:
+//   l_r = (-c_k B[r][r-1]) ui_{r-1},   -em_r = (c_k B[r][r+1]) ui_r.
+// Rows past d are staged as zeros, so they hold y = z = x = 0.  Waves past p
+// repeat column p - 1 (same inputs, same arithmetic, same stores).  No
+// barrier follows the staging: each wave runs its column to the end.
+// NT, PHI and HYB as in tri_steps_kernel.
+template <int NT, bool PHI, bool HYB>
+__global__ void __launch_bounds__(64 * kTsW)
+tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
+                const double *__restrict__ fac) {
+  constexpr int NF = 3 + NT;  // staged fields: sub, dia, sup, then ui_k
+  constexpr int R = kTsR;
+  __shared__ double st[NF * kTsMaxD];  // field f, row r at f * kTsMaxD + (r % R) * 64 + r / R
+  const int t = threadIdx.x, lane = t & 63;
+  int lo = 0, hi = batch - 1;  // the instance whose workgroups contain this one
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].sg0 <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const int ii = lo;
+  if (plan[ii].status & 8) return;  // PFM_NOT_COMPUTED: uniform over the workgroup, before the barrier
+  const TriDesc D = desc[ii];
+  const int d = D.d, p = D.p;
+  const int cpg = (p + kTsW - 1) / kTsW;
+  const int wl = (int)blockIdx.x - D.sg0;
+  const int slot = wl / cpg;
+  int col = (wl - slot * cpg) * kTsW + (t >> 6);
+  if (col >= p) col = p - 1;
+  const int fn = slot == 0 ? T.fn[0] : T.fn[1];
+  const int N = plan[ii].s;
+
+  {
+    const double *bsrc = fac + D.b_off;  // sub, dia, sup: d each
+    const double *usrc = fac + D.f_off;  // per shift l, ui, em: d each
+    for (int idx = t; idx < NF * kTsMaxD; idx += 64 * kTsW) {
+      const int f = idx / kTsMaxD, r = idx - f * kTsMaxD;
+      double v = 0.0;
+      if (r < d) v = f < 3 ? bsrc[(int64_t)f * d + r] : usrc[(int64_t)(f - 3) * 3 * d + d + r];
+      st[f * kTsMaxD + (r % R) * 64 + r / R] = v;
+    }
+  }
+  __syncthreads();
+  const double *sl = st + lane;  // this lane's rows: sl[f * kTsMaxD + i * 64]
+  auto ld = [&](int f, int i) { return sl[f * kTsMaxD + i * 64]; };
+
+  const int r0 = lane * R;
+  double y[R];
+  {
+    const double *vp = D.V + col;
+#pragma unroll
+    for (int i = 0; i < R; ++i) y[i] = r0 + i < d ? vp[(int64_t)(r0 + i) * D.ldv] : 0.0;
+  }
+  double u1[PHI ? R : 1];
+#pragma unroll 1
+  for (int j = 0; j < N; ++j) {
+    // phi1's first step is u_1 = rho(B) V / N: the 1/N is folded into its weights
+    const bool first_phi = fn == 1 && j == 0;
+    const double a0 = first_phi ? T.a0p / (double)N : T.a0e;
+    // y <- B y's input; f = B y, acc = a0 y (+ u_1 or P)
+    double fv[R], acc[R];
+    {
+      double yup = __shfl_up(y[R - 1], 1), ydn = __shfl_down(y[0], 1);
+      if (lane == 0) yup = 0.0;
+      if (lane == 63) ydn = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const double ym = i > 0 ? y[i - 1] : yup, yp = i + 1 < R ? y[i + 1] : ydn;
+        fv[i] = fma(ld(2, i), yp, fma(ld(0, i), ym, ld(1, i) * y[i]));
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) acc[i] = a0 * y[i];
+      if constexpr (PHI) {
+        if (fn == 1 && j > 0) {
+#pragma unroll
+          for (int i = 0; i < R; ++i) acc[i] += u1[i];
+        }
+      }
+      if constexpr (HYB) {
+        // P = d1 f + d2 B f (the hybrid set's polynomial part, §4.3)
+        double fup = __shfl_up(fv[R - 1], 1), fdn = __shfl_down(fv[0], 1);
+        if (lane == 0) fup = 0.0;
+        if (lane == 63) fdn = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const double fm = i > 0 ? fv[i - 1] : fup, fp = i + 1 < R ? fv[i + 1] : fdn;
+          const double bf = fma(ld(2, i), fp, fma(ld(0, i), fm, ld(1, i) * fv[i]));
+          acc[i] += fma(T.d2, bf, T.d1 * fv[i]);
+        }
+      }
+    }
+#pragma unroll 1
+    for (int k = 0; k < NT; ++k) {
+      const double ck = T.c[k], nck = -ck;
+      const double wk = first_phi ? T.wp[k] / (double)N : T.we[k];
+      double A[R], z[R];
+      // B's rows are read again for every shift: held across the shifts
+      // they would take 64 more registers per lane
+      typedef const __attribute__((address_space(3))) double lds_double;
+      lds_double *sk = (lds_double *)sl;
+      asm volatile("" : "+v"(sk));
+      auto lk = [&](int f, int i) { return sk[f * kTsMaxD + i * 64]; };
+      // forward, this lane's rows from a zero start: z0 into z, and the
+      // products gamma_i = prod_{i' <= i} (-l_i') into A, so that
+      // z_i = z0_i + gamma_i z_in once the value entering the lane is known
+      double h = 0.0, g = 1.0;
+      double uprev = lane > 0 ? st[(3 + k) * kTsMaxD + (R - 1) * 64 + lane - 1] : 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const double ui = lk(3 + k, i);
+        const double l = (nck * lk(0, i)) * uprev;
+        h = fma(-l, h, fv[i]);
+        g *= -l;
+        z[i] = h;
+        A[i] = g;
+        uprev = ui;
+      }
+      const double zin = scan_in_fwd(g, h, lane);
+#pragma unroll
+      for (int i = 0; i < R; ++i) z[i] = fma(A[i], zin, z[i]);
+      // backward, from this lane's last row with a zero start: x0 into z,
+      // delta_i = prod_{i' >= i} (-em_i') into A; x_i = x0_i + delta_i x_in
+      double H = 0.0, G = 1.0;
+#pragma unroll
+      for (int i = R - 1; i >= 0; --i) {
+        const double ui = lk(3 + k, i);
+        const double e = (ck * lk(2, i)) * ui;
+        H = fma(e, H, ui * z[i]);
+        G *= e;
+        z[i] = H;
+        A[i] = G;
+      }
+      const double xin = scan_in_bwd(G, H, lane);
+#pragma unroll
+      for (int i = 0; i < R; ++i) acc[i] = fma(wk, fma(A[i], xin, z[i]), acc[i]);
+    }
+    if constexpr (PHI) {
+      if (first_phi && N > 1) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) u1[i] = acc[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) y[i] = acc[i];
+  }
+  {
+    double *fp = (fn ? D.Fp : D.Fe) + col;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (r0 + i < d) fp[(int64_t)(r0 + i) * D.ldf] = y[i];
   }
 }
 

@@ -531,11 +531,13 @@ int tri_validate(pfm_ctx *ctx, int f, double tol, int batch, const pfm_tri_probl
   return PFM_OK;
 }
 
-// Descriptor of one tridiagonal instance; its B, factors, vectors and
-// checkpoints take the next doubles of the workspace from *dofs, its waves
-// the next ones of the step launch from *waves.
+// Descriptor of one tridiagonal instance; its B and factors take the next
+// doubles of the workspace from *dofs.  d <= kTsMaxD: its steps run in
+// tri_scan_kernel, whose next workgroups (*sgs) it takes; else in
+// tri_steps_kernel, whose next waves (*waves) it takes, with its vectors and
+// checkpoints in the workspace as well.
 void tri_desc(const pfm_tri_problem &P, const TriTerms &T, double theta, int64_t *dofs, int64_t *waves,
-              TriDesc *D) {
+              int64_t *sgs, TriDesc *D) {
   memset(D, 0, sizeof *D);
   D->dl = P.dl;
   D->dd = P.dd;
@@ -551,9 +553,15 @@ void tri_desc(const pfm_tri_problem &P, const TriTerms &T, double theta, int64_t
   const int64_t d = P.d, p = P.p, nch = (d + kTriL - 1) / kTriL;
   D->b_off = *dofs; *dofs += align_up(3 * d, 64);
   D->f_off = *dofs; *dofs += align_up(3 * d * T.nterms, 64);
+  D->wave0 = (int32_t)*waves;
+  D->sg0 = (int32_t)*sgs;
+  if (d <= kTsMaxD) {
+    D->nsg = T.nf * (int32_t)((p + kTsW - 1) / kTsW);
+    *sgs += D->nsg;
+    return;
+  }
   D->v_off = *dofs; *dofs += align_up((int64_t)T.nf * 3 * d * p, 64);
   D->c_off = *dofs; *dofs += align_up((int64_t)T.nf * nch * T.nterms * p, 64);
-  D->wave0 = (int32_t)*waves;
   D->nwaves = T.nf * (int32_t)((p + 63) / 64);
   *waves += D->nwaves;
 }
@@ -561,7 +569,7 @@ void tri_desc(const pfm_tri_problem &P, const TriTerms &T, double theta, int64_t
 // Enqueue a tridiagonal call whose descriptors are (or will be, earlier on
 // the stream) at d_desc: plan, factorisations, the N steps, the info records.
 int tri_launch(pfm_ctx *ctx, const TriTerms &T, int order, int batch, const TriDesc *d_desc, PlanRec *d_plan,
-               double *wsd, int64_t waves, pfm_info *info, int force_plan, hipStream_t stream) {
+               double *wsd, int64_t waves, int64_t sgs, pfm_info *info, int force_plan, hipStream_t stream) {
   hipLaunchKernelGGL(tri_plan_kernel, dim3(batch), dim3(256), 0, stream, d_desc, d_plan, force_plan);
   HIP_TRY(ctx, hipGetLastError());
   {
@@ -577,8 +585,14 @@ int tri_launch(pfm_ctx *ctx, const TriTerms &T, int order, int batch, const TriD
   ctx->cur_launches[0]++;
   prof_mark(ctx, 1, stream);
 #define PFM_TRI_STEPS(NT, PHI, HYB)                                                                            \
-  hipLaunchKernelGGL((tri_steps_kernel<NT, PHI, HYB>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, batch, \
-                     d_plan, T, (const double *)wsd, wsd)
+  do {                                                                                                         \
+    if (sgs)                                                                                                   \
+      hipLaunchKernelGGL((tri_scan_kernel<NT, PHI, HYB>), dim3((unsigned)sgs), dim3(64 * kTsW), 0, stream,     \
+                         d_desc, batch, d_plan, T, (const double *)wsd);                                       \
+    if (waves)                                                                                                 \
+      hipLaunchKernelGGL((tri_steps_kernel<NT, PHI, HYB>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, \
+                         batch, d_plan, T, (const double *)wsd, wsd);                                          \
+  } while (0)
   const bool hybrid = T.d1 != 0.0 || T.d2 != 0.0;
   const bool tri_phi = T.fn[0] == 1 || (T.nf > 1 && T.fn[1] == 1);
   if (hybrid) {
@@ -655,10 +669,11 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
   if (rc) return rc;
   hipStream_t stream = (hipStream_t)stream_;
   std::vector<TriDesc> desc(batch);
-  int64_t dofs = 0, waves = 0;
+  int64_t dofs = 0, waves = 0, sgs = 0;
   for (int i = 0; i < batch; ++i) {
-    tri_desc(probs[i], T, theta, &dofs, &waves, &desc[i]);
-    if (waves > (int64_t)1 << 30) return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
+    tri_desc(probs[i], T, theta, &dofs, &waves, &sgs, &desc[i]);
+    if (waves > (int64_t)1 << 30 || sgs > (int64_t)1 << 30)
+      return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
   }
   const int64_t desc_bytes = align_up((int64_t)batch * sizeof(TriDesc), 256);
   const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
@@ -670,7 +685,7 @@ int pfm_tri_action(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_
   double *wsd = (double *)(base + desc_bytes + plan_bytes);
   rc = upload_desc(ctx, d_desc, desc.data(), batch * sizeof(TriDesc), stream);
   if (rc) return rc;
-  return tri_launch(ctx, T, order, batch, d_desc, d_plan, wsd, waves, info, force_plan, stream);
+  return tri_launch(ctx, T, order, batch, d_desc, d_plan, wsd, waves, sgs, info, force_plan, stream);
 }
 
 int pfm_tri_action_noalloc(pfm_ctx *ctx, int f, int m, double tol, int batch, const pfm_tri_problem *probs,
@@ -692,10 +707,11 @@ int pfm_tri_action_noalloc(pfm_ctx *ctx, int f, int m, double tol, int batch, co
   if (!base) return set_err(ctx, PFM_ERR_HIP, "the scratch array of device %d was not resolved", ctx->device);
   const int64_t desc_bytes = align_up((int64_t)batch * sizeof(TriDesc), 256);
   const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
-  int64_t dofs = 0, waves = 0;
+  int64_t dofs = 0, waves = 0, sgs = 0;
   for (int i = 0; i < batch; ++i) {
-    tri_desc(probs[i], T, theta, &dofs, &waves, &g_noalloc_desc[i]);
-    if (waves > (int64_t)1 << 30) return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
+    tri_desc(probs[i], T, theta, &dofs, &waves, &sgs, &g_noalloc_desc[i]);
+    if (waves > (int64_t)1 << 30 || sgs > (int64_t)1 << 30)
+      return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
   }
   const int64_t need = desc_bytes + plan_bytes + dofs * 8;
   if ((size_t)need > kScratchBytes)
@@ -707,7 +723,7 @@ int pfm_tri_action_noalloc(pfm_ctx *ctx, int f, int m, double tol, int batch, co
   PlanRec *d_plan = (PlanRec *)(base + desc_bytes);
   double *wsd = (double *)(base + desc_bytes + plan_bytes);
   HIP_TRY(ctx, hipMemcpyAsync(d_desc, g_noalloc_desc, batch * sizeof(TriDesc), hipMemcpyHostToDevice, stream));
-  return tri_launch(ctx, T, order, batch, d_desc, d_plan, wsd, waves, info, force_plan, stream);
+  return tri_launch(ctx, T, order, batch, d_desc, d_plan, wsd, waves, sgs, info, force_plan, stream);
 }
 
 int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, const pfm_band_problem *probs,

@@ -4,9 +4,11 @@ tridiagonal oracle (oracle/banded.py), through the C ABI.
 Bar: relative Frobenius error per instance and function <= 1e-12, with the
 oracle's own plan equal to the GPU's (N = ceil(eta / θ); the GPU's N is
 handed to the oracle only when eta / θ sits within 1e-12 of an integer), the
-same ||A||_1 bit for bit, and route 3.  Sizes span one and many 16-row
-checkpoint chunks with ragged tails, and one and several 64-column waves
-with ragged last waves."""
+same ||A||_1 bit for bit, and route 3.  Sizes up to d = 1024 run in the
+wave-per-column scan kernel (one and many 16-row lane blocks, ragged tails,
+ragged last workgroups of 8 columns); larger d in the lane-per-column kernel
+(8-row checkpoint chunks, 64-column waves); the uneven batch mixes both in
+one call."""
 
 import ctypes
 import sys
@@ -80,7 +82,7 @@ def _check(res, info, tris, vecs, funcs, m, tol, cols=None):
 def test_uneven_batch(torch_dev, m, funcs):
     """Several instances of different d and p in one call."""
     torch, dev = torch_dev
-    shapes = [(1, 1), (2, 3), (15, 2), (16, 1), (17, 5), (33, 64), (100, 65), (257, 7)]
+    shapes = [(1, 1), (2, 3), (15, 2), (16, 1), (17, 5), (33, 64), (1025, 2), (100, 65), (257, 7), (1500, 3)]
     tris = []
     vecs = []
     for j, (d, p) in enumerate(shapes):
