@@ -570,15 +570,29 @@ __device__ __forceinline__ double scan_in_bwd(double G, double H, int lane) {
 template <int NT, bool PHI, bool HYB>
 __global__ void __launch_bounds__(64 * kTsW)
 tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
-                const double *__restrict__ fac) {
-  constexpr int NF = 3 + NT;  // staged fields: sub, dia, sup, then ui_k
+                const double *__restrict__ fac, int nsg) {
+  // LST (up to 8 shifts, where it fits the 160 KiB of LDS): -l_k and ui_k
+  // of every shift are staged, and each lane's composed products
+  //   g_{k,L} = prod_i (-l_r),  G_{k,L} = prod_i (-em_r)  over its rows r
+  // are formed once per workgroup, so that a shift costs 8 FP64 operations
+  // per row: the lane's rows are swept from the value entering them, twice
+  // per direction.  Otherwise (the 10 shifts of the hybrid set) only ui_k is
+  // staged, l and em are formed per row, and the lane's sweeps keep the
+  // running products, 10 operations per row.
+  constexpr bool LST = NT <= 8;
+  constexpr int NF = LST ? 3 + 2 * NT : 3 + NT;  // sub, dia, sup, then (-l_k, ui_k) or ui_k
   constexpr int R = kTsR;
-  __shared__ double st[NF * kTsMaxD];  // field f, row r at f * kTsMaxD + (r % R) * 64 + r / R
+  constexpr int NTAB = LST ? 2 * NT * 64 : 0;  // g then G, [k][lane]
+  __shared__ double st[NF * kTsMaxD + NTAB];  // field f, row r at f * kTsMaxD + (r % R) * 64 + r / R
   const int t = threadIdx.x, lane = t & 63;
+  // workgroup b runs on XCD b mod 8: XCD x takes the x-th eighth of the
+  // workgroups in order, so the workgroups of one instance share an L2
+  const int sgw = (int)((blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3));
+  if (sgw >= nsg) return;  // grid padding: uniform over the workgroup, before the barrier
   int lo = 0, hi = batch - 1;  // the instance whose workgroups contain this one
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (desc[mid].sg0 <= (int)blockIdx.x) lo = mid;
+    if (desc[mid].sg0 <= sgw) lo = mid;
     else hi = mid - 1;
   }
   const int ii = lo;
@@ -586,7 +600,7 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
   const TriDesc D = desc[ii];
   const int d = D.d, p = D.p;
   const int cpg = (p + kTsW - 1) / kTsW;
-  const int wl = (int)blockIdx.x - D.sg0;
+  const int wl = sgw - D.sg0;
   const int slot = wl / cpg;
   int col = (wl - slot * cpg) * kTsW + (t >> 6);
   if (col >= p) col = p - 1;
@@ -596,16 +610,46 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
   {
     const double *bsrc = fac + D.b_off;  // sub, dia, sup: d each
     const double *usrc = fac + D.f_off;  // per shift l, ui, em: d each
-    for (int idx = t; idx < NF * kTsMaxD; idx += 64 * kTsW) {
-      const int f = idx / kTsMaxD, r = idx - f * kTsMaxD;
-      double v = 0.0;
-      if (r < d) v = f < 3 ? bsrc[(int64_t)f * d + r] : usrc[(int64_t)(f - 3) * 3 * d + d + r];
-      st[f * kTsMaxD + (r % R) * 64 + r / R] = v;
+    // a thread per (field, lane): the lane's R rows from global memory into
+    // registers, then into LDS, where the 64 lanes' writes are consecutive
+    for (int q = t; q < NF * 64; q += 64 * kTsW) {
+      const int f = q >> 6;  // uniform over the wave
+      const double *src;
+      double sg = 1.0;
+      if (f < 3) src = bsrc + (int64_t)f * d;
+      else if (LST) {
+        src = usrc + (int64_t)((f - 3) >> 1) * 3 * d + ((f - 3) & 1 ? d : 0);
+        if (!((f - 3) & 1)) sg = -1.0;
+      } else {
+        src = usrc + (int64_t)(f - 3) * 3 * d + d;
+      }
+      double v[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int r = lane * R + i;
+        v[i] = r < d ? sg * src[r] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) st[f * kTsMaxD + i * 64 + lane] = v[i];
     }
   }
   __syncthreads();
   const double *sl = st + lane;  // this lane's rows: sl[f * kTsMaxD + i * 64]
   auto ld = [&](int f, int i) { return sl[f * kTsMaxD + i * 64]; };
+  if constexpr (LST) {
+    // the lanes' products, one (shift, lane) per thread
+    for (int q = t; q < NT * 64; q += 64 * kTsW) {
+      const int k = q >> 6, L = q & 63;
+      const double *rw = st + L;
+      double g = 1.0, G = 1.0;
+      for (int i = 0; i < R; ++i) g *= rw[(3 + 2 * k) * kTsMaxD + i * 64];
+      for (int i = R - 1; i >= 0; --i)
+        G *= (T.c[k] * rw[2 * kTsMaxD + i * 64]) * rw[(4 + 2 * k) * kTsMaxD + i * 64];
+      st[NF * kTsMaxD + q] = g;
+      st[NF * kTsMaxD + NT * 64 + q] = G;
+    }
+    __syncthreads();
+  }
 
   const int r0 = lane * R;
   double y[R];
@@ -652,50 +696,122 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
         }
       }
     }
+    typedef const __attribute__((address_space(3))) double lds_double;
+    if constexpr (LST) {
+      // KP shifts at a time from k0, their chains side by side; the sum
+      // keeps the order k = 0, 1, ...
+      auto run_shifts = [&](auto kpc, int k0) {
+        constexpr int KP = decltype(kpc)::value;
+        double A[KP][R], z[KP][R], ck[KP], wk[KP];
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+          ck[j] = T.c[k0 + j];
+          wk[j] = first_phi ? T.wp[k0 + j] / (double)N : T.we[k0 + j];
+        }
+        // B's rows are read again for every shift pair: held across them
+        // they would take 64 more registers per lane
+        lds_double *sk = (lds_double *)sl;
+        asm volatile("" : "+v"(sk));
+        auto lk = [&](int f, int i) { return sk[f * kTsMaxD + i * 64]; };
+        // forward: the lane's rows from a zero start (its map's offset), the
+        // scan, then the rows again from the value entering them
+        double h[KP], zp[KP];
+#pragma unroll
+        for (int j = 0; j < KP; ++j) h[j] = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+#pragma unroll
+          for (int j = 0; j < KP; ++j) {
+            const double nl = lk(3 + 2 * (k0 + j), i);
+            A[j][i] = nl;
+            h[j] = fma(nl, h[j], fv[i]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < KP; ++j) zp[j] = scan_in_fwd(sk[NF * kTsMaxD + (k0 + j) * 64], h[j], lane);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+#pragma unroll
+          for (int j = 0; j < KP; ++j) {
+            zp[j] = fma(A[j][i], zp[j], fv[i]);
+            z[j][i] = zp[j];
+          }
+        }
+        // backward: z <- ui z, A <- -em, the same in the other direction
+#pragma unroll
+        for (int j = 0; j < KP; ++j) h[j] = 0.0;
+#pragma unroll
+        for (int i = R - 1; i >= 0; --i) {
+          const double sup = lk(2, i);
+#pragma unroll
+          for (int j = 0; j < KP; ++j) {
+            const double ui = lk(4 + 2 * (k0 + j), i);
+            const double e = (ck[j] * sup) * ui;
+            const double sv = ui * z[j][i];
+            A[j][i] = e;
+            z[j][i] = sv;
+            h[j] = fma(e, h[j], sv);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < KP; ++j) zp[j] = scan_in_bwd(sk[NF * kTsMaxD + (NT + k0 + j) * 64], h[j], lane);
+#pragma unroll
+        for (int i = R - 1; i >= 0; --i) {
+#pragma unroll
+          for (int j = 0; j < KP; ++j) {
+            zp[j] = fma(A[j][i], zp[j], z[j][i]);
+            acc[i] = fma(wk[j], zp[j], acc[i]);
+          }
+        }
+      };
 #pragma unroll 1
-    for (int k = 0; k < NT; ++k) {
-      const double ck = T.c[k], nck = -ck;
-      const double wk = first_phi ? T.wp[k] / (double)N : T.we[k];
-      double A[R], z[R];
-      // B's rows are read again for every shift: held across the shifts
-      // they would take 64 more registers per lane
-      typedef const __attribute__((address_space(3))) double lds_double;
-      lds_double *sk = (lds_double *)sl;
-      asm volatile("" : "+v"(sk));
-      auto lk = [&](int f, int i) { return sk[f * kTsMaxD + i * 64]; };
-      // forward, this lane's rows from a zero start: z0 into z, and the
-      // products gamma_i = prod_{i' <= i} (-l_i') into A, so that
-      // z_i = z0_i + gamma_i z_in once the value entering the lane is known
-      double h = 0.0, g = 1.0;
-      double uprev = lane > 0 ? st[(3 + k) * kTsMaxD + (R - 1) * 64 + lane - 1] : 0.0;
+      for (int k = 0; k + 2 <= NT; k += 2) run_shifts(std::integral_constant<int, 2>(), k);
+      if constexpr (NT & 1) run_shifts(std::integral_constant<int, 1>(), NT - 1);
+    } else {
+#pragma unroll 1
+      for (int k = 0; k < NT; ++k) {
+        const double ck = T.c[k], nck = -ck;
+        const double wk = first_phi ? T.wp[k] / (double)N : T.we[k];
+        double A[R], z[R];
+        // B's rows are read again for every shift: held across the shifts
+        // they would take 64 more registers per lane
+        lds_double *sk = (lds_double *)sl;
+        asm volatile("" : "+v"(sk));
+        auto lk = [&](int f, int i) { return sk[f * kTsMaxD + i * 64]; };
+        // forward, this lane's rows from a zero start: z0 into z, and the
+        // products gamma_i = prod_{i' <= i} (-l_i') into A, so that
+        // z_i = z0_i + gamma_i z_in once the value entering the lane is known
+        double h = 0.0, g = 1.0;
+        double uprev = lane > 0 ? st[(3 + k) * kTsMaxD + (R - 1) * 64 + lane - 1] : 0.0;
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const double ui = lk(3 + k, i);
-        const double l = (nck * lk(0, i)) * uprev;
-        h = fma(-l, h, fv[i]);
-        g *= -l;
-        z[i] = h;
-        A[i] = g;
-        uprev = ui;
+        for (int i = 0; i < R; ++i) {
+          const double ui = lk(3 + k, i);
+          const double l = (nck * lk(0, i)) * uprev;
+          h = fma(-l, h, fv[i]);
+          g *= -l;
+          z[i] = h;
+          A[i] = g;
+          uprev = ui;
+        }
+        const double zin = scan_in_fwd(g, h, lane);
+#pragma unroll
+        for (int i = 0; i < R; ++i) z[i] = fma(A[i], zin, z[i]);
+        // backward, from this lane's last row with a zero start: x0 into z,
+        // delta_i = prod_{i' >= i} (-em_i') into A; x_i = x0_i + delta_i x_in
+        double H = 0.0, G = 1.0;
+#pragma unroll
+        for (int i = R - 1; i >= 0; --i) {
+          const double ui = lk(3 + k, i);
+          const double e = (ck * lk(2, i)) * ui;
+          H = fma(e, H, ui * z[i]);
+          G *= e;
+          z[i] = H;
+          A[i] = G;
+        }
+        const double xin = scan_in_bwd(G, H, lane);
+#pragma unroll
+        for (int i = 0; i < R; ++i) acc[i] = fma(wk, fma(A[i], xin, z[i]), acc[i]);
       }
-      const double zin = scan_in_fwd(g, h, lane);
-#pragma unroll
-      for (int i = 0; i < R; ++i) z[i] = fma(A[i], zin, z[i]);
-      // backward, from this lane's last row with a zero start: x0 into z,
-      // delta_i = prod_{i' >= i} (-em_i') into A; x_i = x0_i + delta_i x_in
-      double H = 0.0, G = 1.0;
-#pragma unroll
-      for (int i = R - 1; i >= 0; --i) {
-        const double ui = lk(3 + k, i);
-        const double e = (ck * lk(2, i)) * ui;
-        H = fma(e, H, ui * z[i]);
-        G *= e;
-        z[i] = H;
-        A[i] = G;
-      }
-      const double xin = scan_in_bwd(G, H, lane);
-#pragma unroll
-      for (int i = 0; i < R; ++i) acc[i] = fma(wk, fma(A[i], xin, z[i]), acc[i]);
     }
     if constexpr (PHI) {
       if (first_phi && N > 1) {

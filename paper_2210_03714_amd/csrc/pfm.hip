@@ -587,8 +587,8 @@ int tri_launch(pfm_ctx *ctx, const TriTerms &T, int order, int batch, const TriD
 #define PFM_TRI_STEPS(NT, PHI, HYB)                                                                            \
   do {                                                                                                         \
     if (sgs)                                                                                                   \
-      hipLaunchKernelGGL((tri_scan_kernel<NT, PHI, HYB>), dim3((unsigned)sgs), dim3(64 * kTsW), 0, stream,     \
-                         d_desc, batch, d_plan, T, (const double *)wsd);                                       \
+      hipLaunchKernelGGL((tri_scan_kernel<NT, PHI, HYB>), dim3((unsigned)align_up(sgs, 8)), dim3(64 * kTsW), 0, \
+                         stream, d_desc, batch, d_plan, T, (const double *)wsd, (int)sgs);                      \
     if (waves)                                                                                                 \
       hipLaunchKernelGGL((tri_steps_kernel<NT, PHI, HYB>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, \
                          batch, d_plan, T, (const double *)wsd, wsd);                                          \
