@@ -547,6 +547,17 @@ int pfm_srv_poll(pfm_server *srv, uint64_t ticket, pfm_info *info, double *laten
  * and per-instance status.  Returns the count. */
 int pfm_srv_drain(pfm_server *srv, int max, uint64_t *tickets, double *latency_s, int32_t *status);
 
+/* Where a completed (or failed) request's latency went, in seconds, into
+ * parts[4]: [0] waiting for admission (its resident copies to fit the
+ * budget), [1] admitted and waiting for a lane, [2] the host enqueueing its
+ * batch (copies and pfm_eval_batched_tols on the lane stream), [3] from the
+ * end of the enqueue to the scheduler seeing the batch's completion event
+ * (device time, plus the earlier work on that stream).  The four add up to
+ * the latency that pfm_srv_poll and pfm_srv_drain report.  Returns 1 if the
+ * request is not finished, PFM_ERR_INVALID for an unknown (or released)
+ * ticket.  The request keeps its record until pfm_srv_release. */
+int pfm_srv_timing(pfm_server *srv, uint64_t ticket, double *parts);
+
 /* Copy a done request's result for function `which` (PFM_EXP or PFM_PHI1)
  * to the device buffer dst (row-major, leading dimension ldd, the request's
  * element type), synchronously.  The result stays until released. */

@@ -108,6 +108,7 @@ struct Req {
   void *rFe = nullptr, *rFp = nullptr;
   size_t ws = 0;                      // workspace estimate
   double t_submit = 0.0, t_done = 0.0;
+  double t_admit = 0.0, t_dispatch = 0.0, t_launched = 0.0;  // admitted, handed to a lane, enqueued
   pfm_info info{};
   bool reported = false;
 };
@@ -206,6 +207,7 @@ bool admit_one(pfm_server *S, Req &r) {
   S->resident += need;
   S->peak_resident = std::max(S->peak_resident, S->resident);
   r.state = kAdmitted;
+  r.t_admit = now_s();
   return true;
 }
 
@@ -275,6 +277,7 @@ void lane_main(pfm_server *S, Lane *L) {
     const double t1 = now_s();
     lk.lock();
     S->launch_s += t1 - t0;
+    for (Req *r : batch) r->t_launched = t1;
     L->has_todo = false;
     L->launch_rc = rc;
     L->launched = true;
@@ -329,6 +332,7 @@ void scheduler(pfm_server *S) {
       if (!hp) continue;
       std::vector<Req *> batch;
       const Req &head = *hp;
+      const double td = now_s();
       size_t ws = 0;
       std::deque<uint64_t> rest;
       for (uint64_t id : S->admitted) {
@@ -337,6 +341,7 @@ void scheduler(pfm_server *S) {
           batch.push_back(&r);
           ws += r.ws;
           r.state = kRunning;
+          r.t_dispatch = td;
           L.reqs.push_back(id);
         } else {
           rest.push_back(id);
@@ -498,6 +503,22 @@ int pfm_srv_drain(pfm_server *S, int max, uint64_t *tickets, double *latency, in
     }
   }
   return k;
+}
+
+int pfm_srv_timing(pfm_server *S, uint64_t ticket, double *parts) {
+  if (!S || !parts) return PFM_ERR_INVALID;
+  std::lock_guard<std::mutex> g(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return PFM_ERR_INVALID;
+  const Req &r = it->second;
+  if (r.state != kDone && r.state != kFailed) return 1;
+  parts[0] = r.t_admit - r.t_submit;
+  parts[1] = r.t_dispatch - r.t_admit;
+  // a batch whose launch failed is retired without a launch stamp
+  const double tl = r.t_launched > 0.0 ? r.t_launched : r.t_done;
+  parts[2] = tl - r.t_dispatch;
+  parts[3] = r.t_done - tl;
+  return PFM_OK;
 }
 
 int pfm_srv_fetch(pfm_server *S, uint64_t ticket, int which, void *dst, int64_t ldd) {

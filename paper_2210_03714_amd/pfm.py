@@ -114,6 +114,7 @@ def lib():
         L.pfm_srv_poll.argtypes = [vp, ctypes.c_uint64, vp, dp]
         L.pfm_srv_drain.argtypes = [vp, i32, u64p, dp, ip]
         L.pfm_srv_fetch.argtypes = [vp, ctypes.c_uint64, i32, vp, ctypes.c_int64]
+        L.pfm_srv_timing.argtypes = [vp, ctypes.c_uint64, dp]
         L.pfm_srv_release.argtypes = [vp, ctypes.c_uint64]
         L.pfm_srv_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p, dp]
         L.pfm_profile_read.argtypes = [vp, dp, ip, ip]
@@ -694,6 +695,16 @@ class Server:
         for t, _, _ in out:
             self._keep.pop(t, None)
         return out
+
+    def timing(self, ticket):
+        """Where a finished request's latency went, in seconds: (admission wait,
+        wait for a lane, host enqueue, enqueue end to completion seen); None
+        while it runs."""
+        parts = (ctypes.c_double * 4)()
+        rc = lib().pfm_srv_timing(self._h, ticket, parts)
+        if rc < 0:
+            raise PfmError(rc, "pfm_srv_timing")
+        return None if rc == 1 else tuple(parts)
 
     def fetch(self, ticket, func="exp"):
         """The result as a new CUDA tensor (the request keeps it until release)."""

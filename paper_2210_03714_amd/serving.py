@@ -27,6 +27,7 @@ def run_stream(srv, reqs, dpool, dvpool, keep=(), progress=None):
     lag = np.zeros(n)
     by_ticket = {}
     lat = np.full(n, np.nan)
+    parts = np.full((n, 4), np.nan)
     status = np.zeros(n, dtype=np.int64)
     done = 0
 
@@ -35,6 +36,7 @@ def run_stream(srv, reqs, dpool, dvpool, keep=(), progress=None):
         for t, l, s in srv.drain():
             i = by_ticket.pop(t)
             lat[i] = l + lag[i]
+            parts[i] = srv.timing(t)
             status[i] = s
             done += 1
             if i not in keep:
@@ -70,7 +72,7 @@ def run_stream(srv, reqs, dpool, dvpool, keep=(), progress=None):
             last_report = time.perf_counter()
             progress("draining: done %d/%d" % (done, n))
     t_end = time.perf_counter()
-    return {"latency": lat, "status": status, "tickets": tickets, "lag": lag,
+    return {"latency": lat, "status": status, "tickets": tickets, "lag": lag, "parts": parts,
             "wall": t_end - t0, "submit_wall": t_sub - t0}
 
 
@@ -85,4 +87,10 @@ def summarize(res, reqs):
         "max_submit_lag_ms": float(res["lag"].max() * 1e3),
         "failed": int((res["status"] != 0).sum()),
         "wall_s": res["wall"],
+        # where the latency went (library stamps; the submit lag is apart)
+        "breakdown_ms": {name: {"p50": round(float(np.percentile(res["parts"][:, j], 50) * 1e3), 3),
+                                "p99": round(float(np.percentile(res["parts"][:, j], 99) * 1e3), 3),
+                                "mean": round(float(res["parts"][:, j].mean() * 1e3), 3)}
+                         for j, name in enumerate(("admission_wait", "lane_wait", "host_enqueue",
+                                                   "device_to_completion_seen"))},
     }

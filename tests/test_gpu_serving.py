@@ -55,6 +55,13 @@ def test_mix_equals_alone_and_oracle(torch_dev):
     _say("  stats", st, "p99 ms %.2f" % (np.percentile(res["latency"], 99) * 1e3))
     assert st["error"] == 0 and st["done"] == len(reqs)
     assert (res["status"] == 0).all()
+    # the latency's parts (pfm_srv_timing) are ordered stamps and add up to it
+    parts = res["parts"]
+    assert np.isfinite(parts).all() and (parts >= 0.0).all()
+    assert np.allclose(parts.sum(axis=1), res["latency"] - res["lag"], rtol=0.0, atol=1e-9)
+    assert (parts[:, 3] > 0.0).all()  # every batch ran on the device
+    summ = serving.summarize(res, reqs)
+    assert set(summ["breakdown_ms"]) == {"admission_wait", "lane_wait", "host_enqueue", "device_to_completion_seen"}
     rng = np.random.default_rng(0)
     oracle_idx = set(rng.choice(len(reqs), 8, replace=False).tolist())
     for i, r in enumerate(reqs):
