@@ -548,6 +548,22 @@ __device__ __forceinline__ double scan_in_bwd(double G, double H, int lane) {
   return dpp_f64<0x130>(H, 0.0);  // wave_shl:1
 }
 
+// The same values when every lane's multiplier is at most 2^-30 in
+// magnitude: the value entering lane L is then h_{L-1} + g_{L-1} h_{L-2} up
+// to g_{L-1} g_{L-2} Z_{L-3}, below 2^-60 max|Z|, so two lanes' maps carry
+// every digit (the planned B makes |l_r|, |em_r| < 0.06, so a lane's
+// product of 16 is below 1e-19).
+__device__ __forceinline__ double scan_in_fwd2(double g, double h) {
+  const double h1 = dpp_f64<0x138>(h, 0.0), g1 = dpp_f64<0x138>(g, 0.0);  // wave_shr:1
+  const double h2 = dpp_f64<0x138>(h1, 0.0);
+  return fma(g1, h2, h1);
+}
+__device__ __forceinline__ double scan_in_bwd2(double G, double H) {
+  const double h1 = dpp_f64<0x130>(H, 0.0), g1 = dpp_f64<0x130>(G, 0.0);  // wave_shl:1
+  const double h2 = dpp_f64<0x130>(h1, 0.0);
+  return fma(g1, h2, h1);
+}
+
 // All N steps of the tridiagonal action with a wave per column: lane L holds
 // rows 16 L .. 16 L + 15 of the column, so the vector and every intermediate
 // stay in registers for the whole call (d <= kTsMaxD).  The sweeps of each
@@ -636,6 +652,7 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
   __syncthreads();
   const double *sl = st + lane;  // this lane's rows: sl[f * kTsMaxD + i * 64]
   auto ld = [&](int f, int i) { return sl[f * kTsMaxD + i * 64]; };
+  bool short_scan = false;  // every lane product at most 2^-30 (scan_in_fwd2)
   if constexpr (LST) {
     // the lanes' products, one (shift, lane) per thread
     for (int q = t; q < NT * 64; q += 64 * kTsW) {
@@ -649,6 +666,12 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
       st[NF * kTsMaxD + NT * 64 + q] = G;
     }
     __syncthreads();
+    // each wave (one column) decides for itself: the same tables, the same vote
+    int big = 0;
+    for (int k = 0; k < NT; ++k)
+      big |= !(fabs(st[NF * kTsMaxD + k * 64 + lane]) <= 0x1p-30 &&
+               fabs(st[NF * kTsMaxD + (NT + k) * 64 + lane]) <= 0x1p-30);  // (NaN too)
+    short_scan = !__any(big);
   }
 
   const int r0 = lane * R;
@@ -727,8 +750,13 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
             h[j] = fma(nl, h[j], fv[i]);
           }
         }
+        if (short_scan) {
 #pragma unroll
-        for (int j = 0; j < KP; ++j) zp[j] = scan_in_fwd(sk[NF * kTsMaxD + (k0 + j) * 64], h[j], lane);
+          for (int j = 0; j < KP; ++j) zp[j] = scan_in_fwd2(sk[NF * kTsMaxD + (k0 + j) * 64], h[j]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < KP; ++j) zp[j] = scan_in_fwd(sk[NF * kTsMaxD + (k0 + j) * 64], h[j], lane);
+        }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
 #pragma unroll
@@ -753,8 +781,13 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
             h[j] = fma(e, h[j], sv);
           }
         }
+        if (short_scan) {
 #pragma unroll
-        for (int j = 0; j < KP; ++j) zp[j] = scan_in_bwd(sk[NF * kTsMaxD + (NT + k0 + j) * 64], h[j], lane);
+          for (int j = 0; j < KP; ++j) zp[j] = scan_in_bwd2(sk[NF * kTsMaxD + (NT + k0 + j) * 64], h[j]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < KP; ++j) zp[j] = scan_in_bwd(sk[NF * kTsMaxD + (NT + k0 + j) * 64], h[j], lane);
+        }
 #pragma unroll
         for (int i = R - 1; i >= 0; --i) {
 #pragma unroll
@@ -793,7 +826,7 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
           A[i] = g;
           uprev = ui;
         }
-        const double zin = scan_in_fwd(g, h, lane);
+        const double zin = __any(!(fabs(g) <= 0x1p-30)) ? scan_in_fwd(g, h, lane) : scan_in_fwd2(g, h);
 #pragma unroll
         for (int i = 0; i < R; ++i) z[i] = fma(A[i], zin, z[i]);
         // backward, from this lane's last row with a zero start: x0 into z,
@@ -808,7 +841,7 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
           z[i] = H;
           A[i] = G;
         }
-        const double xin = scan_in_bwd(G, H, lane);
+        const double xin = __any(!(fabs(G) <= 0x1p-30)) ? scan_in_bwd(G, H, lane) : scan_in_bwd2(G, H);
 #pragma unroll
         for (int i = 0; i < R; ++i) acc[i] = fma(wk, fma(A[i], xin, z[i]), acc[i]);
       }

@@ -120,6 +120,63 @@ def test_force_plan(torch_dev):
             assert me.rel_fro(res[f][i].cpu().numpy(), own[f]) <= BAR
 
 
+def _lane_products(dl, dd, du, N, cs, rows=16):
+    """Largest |prod (-l_r)| and |prod (-em_r)| over 16-row lane blocks of
+    the LU of every I - c B, B = A / N (the multipliers of the scan kernel's
+    lane maps)."""
+    d = len(dd)
+    sub = np.concatenate([[0.0], dl / N]); dia = dd / N; sup = np.concatenate([du / N, [0.0]])
+    big = 0.0
+    for c in cs:
+        u = np.empty(d); l = np.zeros(d); em = np.zeros(d)
+        u[0] = 1.0 - c * dia[0]
+        for r in range(1, d):
+            l[r] = -c * sub[r] / u[r - 1]
+            u[r] = 1.0 - c * dia[r] - l[r] * (-c * sup[r - 1])
+        em[:] = -c * sup / u
+        for b0 in range(0, d, rows):
+            big = max(big, abs(np.prod(-l[b0:b0 + rows])), abs(np.prod(-em[b0:b0 + rows])))
+    return big
+
+
+def test_full_scan_path(torch_dev):
+    """A forced N = 1 on trid{a, eps, a} with a ~ 2 (|c_k| ||B||_1 up to
+    0.85: still diagonally dominant, |l_r| ~ 0.5 on every row) makes the
+    16-row lane products exceed 2^-30, so the scan kernel composes the lane
+    maps over the whole wave instead of two lanes; both functions against
+    the oracle on the same forced plan."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(wl.SEED_BASE + 615)
+    tris = []
+    for d in (300, 1024, 77):
+        dl = 2.0 * (1.0 + 0.05 * rng.standard_normal(d - 1))
+        du = 2.0 * (1.0 + 0.05 * rng.standard_normal(d - 1))
+        tris.append((dl, 0.05 * rng.standard_normal(d), du))
+    vecs = [wl.vectors(len(t[1]), 5, wl.SEED_BASE + 616 + i) for i, t in enumerate(tris)]
+    a0, terms = me.build_terms(("exp",), 8, False)
+    cs = [complex(c).real for c, _, _ in terms]
+    assert max(_lane_products(*t, 1, cs) for t in tris) > 2.0 ** -30
+    _say("case tri full scan path")
+    res, info = _run(torch, dev, tris, vecs, ("exp", "phi1"), 8, 1e-12, force_plan=1)
+    for i, ((dl, dd, du), V) in enumerate(zip(tris, vecs)):
+        assert info[i]["plan"] == 1 and info[i]["status"] == 0
+        own = bd.tri_action(dl, dd, du, V, ("exp", "phi1"), 8, 1e-12, force_plan=1)
+        for f in ("exp", "phi1"):
+            err = me.rel_fro(res[f][i].cpu().numpy(), own[f])
+            assert err <= BAR, (i, f, err)
+    # the hybrid set (m = 10, |c_k| <= 1/8): a ~ 2.2 gives |l_r| ~ 0.3
+    a0, terms = me.build_terms(("exp",), 10, False)
+    cs = [complex(c).real for c, _, _ in terms]
+    tris = [(1.1 * x[0], 1.1 * x[1], 1.1 * x[2]) for x in tris]
+    assert max(_lane_products(*t, 1, cs) for t in tris) > 2.0 ** -30
+    res, info = _run(torch, dev, tris, vecs, ("exp",), 10, 1e-12, force_plan=1)
+    for i, ((dl, dd, du), V) in enumerate(zip(tris, vecs)):
+        assert info[i]["plan"] == 1 and info[i]["status"] == 0
+        own = bd.tri_action(dl, dd, du, V, ("exp",), 10, 1e-12, force_plan=1)
+        err = me.rel_fro(res["exp"][i].cpu().numpy(), own["exp"])
+        assert err <= _hybrid_bar(1), (i, err)
+
+
 def test_headline_shape_sampled(torch_dev):
     """The benchmark's workload shape (d = 1024, p = 64, ||A||_1 in [0.5, 8]);
     sampled columns of sampled instances against the oracle (columns are
