@@ -28,6 +28,16 @@ sys.path.insert(0, ROOT)
 METRIC = "exp(A) evals/sec, batch n=256 at 1e-12 rel err (FP64 vs mixed); p99 latency"
 PEAK_FP64 = 78.6e12   # dense FP64 MFMA, FLOP/s
 PEAK_HBM = 8.0e12     # bytes/s
+PEAK_FP64_VEC = 78.6e12  # FP64 vector FMA: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+
+
+def paper_flops(colsteps, per_col_step, ms):
+    """The banded legs' arithmetic rate by the paper's own count (§2.1, §5.1:
+    flops per shifted solve and per product, per column-step) against the
+    FP64 vector peak."""
+    rate = colsteps * per_col_step / (ms * 1e-3)
+    return {"per_column_step": per_col_step, "achieved": round(rate / 1e12, 3), "peak": PEAK_FP64_VEC / 1e12,
+            "unit": "TFLOP/s", "frac": round(rate / PEAK_FP64_VEC, 4)}
 
 PROBLEM_DTYPE = None
 
@@ -312,7 +322,9 @@ def tri_leg(batch, d, p, reps, cpu, hybrid=True):
                       "batch": batch, "d": d, "p": p},
            "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved / 1e9, 1),
                         "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
-                        "traffic": traffic_from_profile(kname)}}
+                        "traffic": traffic_from_profile(kname)},
+           # m solves of 8 d flops and one product of 5 d per column-step (§2.1)
+           "paper_flops": paper_flops(colsteps, 8 * (8 * d) + 5 * d, steps_ms)}
     if hybrid:
         # R10' of §5: the hybrid set of §4.3 (m = 10) on the same batch
         F8 = F.clone()
@@ -404,6 +416,9 @@ def band_leg(batch, d, p, b, reps, cpu, hybrid=True):
            "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved / 1e9, 1),
                         "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
                         "traffic": traffic_from_profile(kname)}}
+    if b == 2:
+        # m pentadiagonal solves of 15 d flops and one product of 9 d per column-step (§5.1)
+        res["paper_flops"] = paper_flops(colsteps, 8 * (15 * d) + 9 * d, steps_ms)
     if hybrid:
         # R10' of §5 on the same batch: the hybrid set of §4.3 (m = 10)
         F8 = F.clone()
