@@ -203,10 +203,12 @@ int pfm_theta(int f, int m, double tol, double *theta);
 /* Evaluate a batch of problems.
  *   f          PFM_EXP, PFM_PHI1, PFM_PHI2 (any combination), or PFM_LOG1M
  *   m          number of shifted solves: 1, 4, 5 or 8; or 10, the hybrid set
- *              of §4.3, for PFM_EXP of real full matrices in binary64 on the
- *              Gauss-Jordan routes (every |c_k| ||B||_1 <= 1/2, which planned
- *              steps meet; PFM_ERR_UNSUPPORTED otherwise); or PFM_R10STAR,
- *              the other hybrid set, likewise
+ *              of §4.3, for PFM_EXP of real matrices in binary64: full
+ *              matrices on the Gauss-Jordan routes (every |c_k| ||B||_1 <=
+ *              1/2, which planned steps meet; PFM_ERR_UNSUPPORTED otherwise),
+ *              the action (p >= 1) on every route, each step adding
+ *              d1 B u + d2 B^2 u; or PFM_R10STAR, the other hybrid set,
+ *              likewise
  *   tol        target of the forward bound per scaled step, in (0, 1), and
  *              not below the set's rounding floor (sum_k |w_k| + |d1| + |d2|)
  *              θ(tol) 2^-53, which the round-off form cannot go under

@@ -5,6 +5,8 @@
 // i.e. one product Y = B u and then, for every shift, the solve with the
 // factors of I - c_k B computed once for all N steps (§5.1, first remark:
 // the LU factorisation is done only once).
+// With the hybrid set of §4.3 (exp only) the step adds d1 Y + d2 B Y, a
+// second product with the same B.
 //   exp:   u_0 = V, u_j = r(B) u_{j-1}, j = 1..N          -> e^A V
 //   phi1:  u_1 = (a0' V + sum_k w'_k Z_k(V)) / N,
 //          u_{j+1} = r(B) u_j + u_1                       -> phi1(A) V
@@ -159,12 +161,36 @@ action_f64_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ ili
     }
     __syncthreads();
 
-    // the m shifted solves on P_k^T Y, combined in the round-off form
+    // the m shifted solves on P_k^T Y, combined in the round-off form; the
+    // hybrid set starts the sum from its polynomial part d1 Y + d2 B Y
     const bool first_phi = PHI && step == 0;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) acc[rb][ct] = zero4();
+    if (T.d1e != 0.0 || T.d2e != 0.0) {  // (uniform: the call's set)
+#pragma unroll 2
+      for (int k0 = 0; k0 < np; k0 += 4) {
+        double bf[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) bf[ct] = Ybuf[(k0 + g) * SW + 16 * ct + i16];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const int bb = wave + 4 * rb;
+          if (bb < nblk) {
+            const double a = Bt[(16 * bb + ar) + (int64_t)(k0 + g) * np];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[rb][ct] = mfma16(a, bf[ct], acc[rb][ct]);
+          }
+        }
+      }
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[rb][ct][v] = fma(T.d2e, acc[rb][ct][v], T.d1e * Z[rb][ct][v]);
+    }
 #pragma unroll 1
     for (int k = 0; k < T.nterms; ++k) {
       const int fold = T.fold[k];

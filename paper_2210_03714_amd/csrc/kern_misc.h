@@ -220,7 +220,7 @@ route_kernel(const InstDesc *__restrict__ inst, PlanRec *__restrict__ plan, int 
   } else if ((D.rflags & kRfGj) && dom) {
     route = 1;
   }
-  if (hybrid && route == 0) P.status |= PFM_NOT_COMPUTED;
+  if (hybrid && route == 0 && !action) P.status |= PFM_NOT_COMPUTED;  // the action's LU route adds the polynomial
   if (action ? P.s > kNCap : P.s > kSCap) P.status |= PFM_NOT_COMPUTED;
   P.route = route;
   plan[i] = P;

@@ -934,9 +934,10 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
     hybrid = ee && (ee->poly[0] != 0.0 || ee->poly[1] != 0.0);
     if (!ee || (!ep && !hybrid)) return set_err(ctx, PFM_ERR_UNSUPPORTED, "no coefficient set for m = %d", m);
     if (hybrid) {
-      // the hybrid set of §4.3: the exponential of real matrices in binary64,
-      // on the Gauss-Jordan routes (checked after the plan)
-      if (f != PFM_EXP || prec != PFM_FP64 || dtype != PFM_R64 || action)
+      // the hybrid set of §4.3: the exponential of real matrices in binary64;
+      // full matrices on the Gauss-Jordan routes (checked after the plan),
+      // the action on every route
+      if (f != PFM_EXP || prec != PFM_FP64 || dtype != PFM_R64)
         return set_err(ctx, PFM_ERR_UNSUPPORTED,
                        "m = %d (the hybrid set) is provided for exp(A) of real matrices in binary64", m);
       ep = ee;  // no phi1 weights; never read (want_phi = 0)
@@ -1067,7 +1068,7 @@ int eval_impl(pfm_ctx *ctx, int f, int m, const double *tols, double tol, int pr
     }
   }
   const bool gj_call = pol_gj && !action && !emb && !mixed;
-  if (hybrid && !gj_call)
+  if (hybrid && !gj_call && !action)
     for (int i = 0; i < batch; ++i)
       if (probs[i].n <= 512)
         return set_err(ctx, PFM_ERR_UNSUPPORTED,

@@ -108,6 +108,35 @@ def test_headline_shape_sampled(torch_dev):
     _say("  worst err / bar %.2e" % w)
 
 
+def test_action_against_oracle(torch_dev):
+    """exp(A) V with the hybrid set on every action route: n = 17 and 100 on
+    the single-workgroup LU-factor route (the step adds d1 Y + d2 B Y to the
+    shifted solves), n = 200 and 600 on the multi-workgroup route (the
+    explicit r(B) = a0 I + (alpha1 + d1) B + B (T + d2 I) B).  Bar as for the
+    full matrix with the N steps' errors adding (N in place of 2^s)."""
+    torch, dev = torch_dev
+    from paper_2210_03714_amd import pfm
+    sizes, ps, norms = [17, 100, 200, 600], [1, 5, 16, 33], [1.0, 2.5, 3.0, 2.0]
+    mats = [wl.gaussian(n, t, wl.SEED_BASE + 740 + n) for n, t in zip(sizes, norms)]
+    vecs = [wl.vectors(n, p, wl.SEED_BASE + 750 + n) for n, p in zip(sizes, ps)]
+    At = [torch.from_numpy(a).to(dev) for a in mats]
+    Vt = [torch.from_numpy(v).to(dev) for v in vecs]
+    _say("case hybrid m=10 action")
+    res, info = pfm.action(At, Vt, ("exp",), m=10)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, (A, V) in enumerate(zip(mats, vecs)):
+        N = int(info[i]["plan"])
+        own = me.action(A, V, ("exp",), 10, 1e-12, force_plan=N)
+        assert info[i]["status"] == 0 and info[i]["order"] == 10
+        assert info[i]["route"] == (0 if sizes[i] <= 128 else 2), (i, info[i]["route"])
+        err = me.rel_fro(res["exp"][i].cpu().numpy(), own["exp"])
+        bar = _bar(A.shape[0], 0, own["theta"]) * N
+        worst = max(worst, err / bar)
+        assert err <= bar, (i, sizes[i], N, err, bar)
+    _say("  worst err / bar %.2e" % worst)
+
+
 def test_unsupported_combinations(torch_dev):
     torch, dev = torch_dev
     from paper_2210_03714_amd import pfm
@@ -119,7 +148,7 @@ def test_unsupported_combinations(torch_dev):
         pfm.expm([At], ("phi1",), m=10)
     assert e.value.code == pfm.ERR_UNSUPPORTED
     with pytest.raises(pfm.PfmError) as e:
-        pfm.action([At], [V], ("exp",), m=10)
+        pfm.action([At], [V], ("phi1",), m=10)
     assert e.value.code == pfm.ERR_UNSUPPORTED
     with pytest.raises(pfm.PfmError) as e:
         pfm.expm([At.to(torch.complex128)], ("exp",), m=10)
