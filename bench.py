@@ -405,7 +405,8 @@ def band_leg(batch, d, p, b, reps, cpu, hybrid=True):
     colsteps = float(Ns.sum()) * p
     steps_ms = phases["solve_combine"][0] / max(1, calls)
     achieved = colsteps * 16.0 * d / (steps_ms * 1e-3)
-    kname = "band_steps_kernel<%d,8>" % b
+    # b = 2 with d <= 1024 runs in the wave-per-shift scan kernel
+    kname = "band_scan_kernel<8,false>" if b == 2 and d <= 1024 else "band_steps_kernel<%d,8>" % b
     res = {"metric": "banded exp(A)v columns/s", "value": round(batch * p / wall, 1), "unit": "columns/s",
            "ms_per_call": round(wall * 1e3, 3), "steps_kernel_ms": round(steps_ms, 3),
            "factor_kernel_ms": round(phases["lu"][0] / max(1, calls), 3),

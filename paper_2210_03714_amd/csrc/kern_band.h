@@ -39,6 +39,7 @@
 namespace pfm {
 
 constexpr int kBandMaxB = 4;
+constexpr int kBsC = 16;  // band_scan_kernel: columns per workgroup, one after another
 constexpr int kBandCH = 8;  // forward pass: x rows read ahead
 // rows per checkpoint chunk: the backward pass holds the chunk's forward
 // values of every shift in registers (4 rows keep the kernel within the
@@ -55,8 +56,10 @@ struct BandDesc {
   int64_t f_off;  // factors: [d][k][2b + 1]
   int64_t v_off;  // vectors: [slot][3][d][p]
   int64_t z_off;  // checkpoints: [slot][chunk][k][b][p]
-  int32_t wave0;   // first wave of this instance in the step launch
-  int32_t nwaves;  // its waves: functions x ceil(p / 64)
+  int32_t wave0;   // first wave of this instance in band_steps_kernel's launch
+  int32_t nwaves;  // its waves: functions x ceil(p / 64) (0: band_scan_kernel takes it)
+  int32_t sg0;     // first workgroup of this instance in band_scan_kernel's launch
+  int32_t nsg;     // its workgroups: functions x ceil(p / kBsC) (0: band_steps_kernel takes it)
 };
 
 // ||A||_1 (column j adds |A[i][j]| for rows i = j - b .. j + b in increasing
@@ -451,6 +454,270 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
         }
       }
     }
+  }
+}
+
+// All N steps of the pentadiagonal action (b = 2, d <= kTsMaxD, up to 8
+// shifts), one column at a time per workgroup and a wave per shift.  Lane L
+// of wave k holds rows 16 L .. 16 L + 15 of shift k's factors (l_1, l_2,
+// 1/u, em_1, em_2) in registers for the whole launch; B, the column's y and
+// B y, and the shifts' w_k x_k live in LDS, transposed so that the lanes'
+// accesses to one row index are consecutive (row r at (r % 16) 64 + r / 16).
+// A step:
+//   f = B y                 (the workgroup, by rows)
+//   forward  z_r = f_r - l_1 z_{r-1} - l_2 z_{r-2}: each lane's 16 rows from
+//            a zero state give the state leaving them, h_L = (z_{14}, z_{15});
+//            with the lane's homogeneous 2 x 2 map M_L (formed once) the state
+//            entering lane L is h_{L-1} + M_{L-1} h_{L-2} when every map entry
+//            is at most 2^-30 (the rest, M_{L-1} M_{L-2} h_{L-3}, is below
+//            2^-58 of the largest state), else the maps are composed lane by
+//            lane; the lane then sweeps its rows again from that state
+//   backward x_r = ui_r z_r - em_1 x_{r+1} - em_2 x_{r+2}: the same from lane
+//            63 down, and w_k x_k into LDS
+//   y <- a0 y (+ u_1) + sum_k w_k x_k   (the workgroup, by rows, k in order)
+// Three barriers per step; the columns of a workgroup run one after another,
+// so the factors are loaded once for kBsC columns.
+__device__ __forceinline__ int bs_idx(int r) { return (r & 15) * 64 + (r >> 4); }
+
+template <int NT, bool PHI>
+__global__ void __launch_bounds__(64 * NT)
+band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
+                 const double *__restrict__ fac, int nsg) {
+  constexpr int R = 16, NTH = 64 * NT, MD = kTsMaxD;
+  __shared__ double Bs[5 * MD];   // B[r][r + o] at (o + 2) MD + bs_idx(r)
+  __shared__ double ys[MD];       // y
+  __shared__ double fs[MD];       // B y
+  __shared__ double part[NT * MD];  // w_k x_k
+  const int t = threadIdx.x, lane = t & 63, k = t >> 6;
+  // workgroup b runs on XCD b mod 8: XCD x takes the x-th eighth of the
+  // workgroups in order, so the workgroups of one instance share an L2
+  const int sgw = (int)((blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3));
+  if (sgw >= nsg) return;  // grid padding: uniform, before any barrier
+  int lo = 0, hi = batch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].sg0 <= sgw) lo = mid;
+    else hi = mid - 1;
+  }
+  const int ii = lo;
+  if (plan[ii].status & 8) return;  // PFM_NOT_COMPUTED: uniform, before any barrier
+  const BandDesc D = desc[ii];
+  const int d = D.d, p = D.p;
+  const int cpg = (p + kBsC - 1) / kBsC;
+  const int wl = sgw - D.sg0;
+  const int slot = wl / cpg;
+  const int c0 = (wl - slot * cpg) * kBsC;
+  const int fn = slot == 0 ? T.fn[0] : T.fn[1];
+  const int N = plan[ii].s;
+  const double *Bw = fac + D.b_off;  // [r][5]
+  const double *Fw = fac + D.f_off;  // [r][k][5]
+
+  // B into LDS: a thread per (diagonal, lane), its 16 rows
+  for (int q = t; q < 5 * 64; q += NTH) {
+    const int o = q >> 6, L = q & 63;
+    double v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = L * R + i;
+      v[i] = r < d ? Bw[(int64_t)r * 5 + o] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) Bs[o * MD + i * 64 + L] = v[i];
+  }
+  // this wave's shift, this lane's rows
+  double l1[R], l2[R], ui[R], e1[R], e2[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int r = lane * R + i;
+    const double *f = Fw + ((int64_t)r * NT + k) * 5;
+    const bool in = r < d;
+    l1[i] = in ? f[0] : 0.0;
+    l2[i] = in ? f[1] : 0.0;
+    ui[i] = in ? f[2] : 0.0;
+    e1[i] = in ? f[3] : 0.0;
+    e2[i] = in ? f[4] : 0.0;
+  }
+  // the lane's homogeneous maps: forward (z_{-2}, z_{-1}) -> (z_14, z_15),
+  // backward (x_16, x_17) -> (x_0, x_1), column by column
+  double M[2][2], G[2][2];
+#pragma unroll
+  for (int cidx = 0; cidx < 2; ++cidx) {
+    double zm2 = cidx == 0 ? 1.0 : 0.0, zm1 = cidx == 0 ? 0.0 : 1.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const double z = fma(-l1[i], zm1, -l2[i] * zm2);
+      zm2 = zm1;
+      zm1 = z;
+    }
+    M[0][cidx] = zm2;
+    M[1][cidx] = zm1;
+    double xp1 = cidx == 0 ? 1.0 : 0.0, xp2 = cidx == 0 ? 0.0 : 1.0;
+#pragma unroll
+    for (int i = R - 1; i >= 0; --i) {
+      const double x = fma(-e1[i], xp1, -e2[i] * xp2);
+      xp2 = xp1;
+      xp1 = x;
+    }
+    G[0][cidx] = xp1;
+    G[1][cidx] = xp2;
+  }
+  const double thr = 0x1p-30;
+  const bool short_scan = !__any(!(fabs(M[0][0]) <= thr && fabs(M[0][1]) <= thr && fabs(M[1][0]) <= thr &&
+                                   fabs(M[1][1]) <= thr && fabs(G[0][0]) <= thr && fabs(G[0][1]) <= thr &&
+                                   fabs(G[1][0]) <= thr && fabs(G[1][1]) <= thr));
+  __syncthreads();
+
+  constexpr int NQ = (16 + NT - 1) / NT;  // row indices i per thread in the by-rows phases
+#pragma unroll 1
+  for (int cc = 0; cc < kBsC; ++cc) {
+    const int col = c0 + cc;
+    if (col >= p) break;  // uniform over the workgroup
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = q * NT + k;
+      if (i < 16) {
+        const int r = lane * R + i;
+        ys[i * 64 + lane] = r < d ? D.V[(int64_t)r * D.ldv + col] : 0.0;
+      }
+    }
+    double u1[PHI ? NQ : 1];
+    __syncthreads();
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+      // phi1's first step is u_1 = rho(B) V / N: the 1/N is folded into its weights
+      const bool first_phi = fn == 1 && j == 0;
+      const double a0 = first_phi ? T.a0p / (double)N : T.a0e;
+      const double wk = first_phi ? T.wp[k] / (double)N : T.we[k];
+      // f = B y
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int i = q * NT + k;
+        if (i < 16) {
+          const int r = lane * R + i;
+          double f = 0.0;
+#pragma unroll
+          for (int o = -2; o <= 2; ++o) {
+            const int rr = r + o;
+            const double yv = (rr >= 0 && rr < MD) ? ys[bs_idx(rr)] : 0.0;
+            f = fma(Bs[(o + 2) * MD + i * 64 + lane], yv, f);
+          }
+          fs[i * 64 + lane] = f;
+        }
+      }
+      __syncthreads();
+      // forward: the state leaving this lane's rows from a zero state
+      double zm2 = 0.0, zm1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const double z = fma(-l1[i], zm1, fma(-l2[i], zm2, fs[i * 64 + lane]));
+        zm2 = zm1;
+        zm1 = z;
+      }
+      double s0, s1;  // the state entering this lane: (z_{-2}, z_{-1})
+      if (short_scan) {
+        const double h10 = dpp_f64<0x138>(zm2, 0.0), h11 = dpp_f64<0x138>(zm1, 0.0);  // wave_shr:1
+        const double h20 = dpp_f64<0x138>(h10, 0.0), h21 = dpp_f64<0x138>(h11, 0.0);
+        const double m00 = dpp_f64<0x138>(M[0][0], 0.0), m01 = dpp_f64<0x138>(M[0][1], 0.0);
+        const double m10 = dpp_f64<0x138>(M[1][0], 0.0), m11 = dpp_f64<0x138>(M[1][1], 0.0);
+        s0 = fma(m00, h20, fma(m01, h21, h10));
+        s1 = fma(m10, h20, fma(m11, h21, h11));
+      } else {
+        double a0s = 0.0, a1s = 0.0;
+        s0 = 0.0;
+        s1 = 0.0;
+        for (int L = 0; L < 64; ++L) {
+          if (lane == L) {
+            s0 = a0s;
+            s1 = a1s;
+          }
+          const double n0 = fma(readlane_f64(M[0][0], L), a0s, fma(readlane_f64(M[0][1], L), a1s, readlane_f64(zm2, L)));
+          const double n1 = fma(readlane_f64(M[1][0], L), a0s, fma(readlane_f64(M[1][1], L), a1s, readlane_f64(zm1, L)));
+          a0s = n0;
+          a1s = n1;
+        }
+      }
+      // the rows again from the entering state; keep ui z
+      double sv[R];
+      zm2 = s0;
+      zm1 = s1;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const double z = fma(-l1[i], zm1, fma(-l2[i], zm2, fs[i * 64 + lane]));
+        zm2 = zm1;
+        zm1 = z;
+        sv[i] = ui[i] * z;
+      }
+      // backward: the state leaving this lane upwards from a zero state
+      double xp1 = 0.0, xp2 = 0.0;
+#pragma unroll
+      for (int i = R - 1; i >= 0; --i) {
+        const double x = fma(-e1[i], xp1, fma(-e2[i], xp2, sv[i]));
+        xp2 = xp1;
+        xp1 = x;
+      }
+      double x0, x1;  // the state entering this lane from below: (x_16, x_17)
+      if (short_scan) {
+        const double h10 = dpp_f64<0x130>(xp1, 0.0), h11 = dpp_f64<0x130>(xp2, 0.0);  // wave_shl:1
+        const double h20 = dpp_f64<0x130>(h10, 0.0), h21 = dpp_f64<0x130>(h11, 0.0);
+        const double g00 = dpp_f64<0x130>(G[0][0], 0.0), g01 = dpp_f64<0x130>(G[0][1], 0.0);
+        const double g10 = dpp_f64<0x130>(G[1][0], 0.0), g11 = dpp_f64<0x130>(G[1][1], 0.0);
+        x0 = fma(g00, h20, fma(g01, h21, h10));
+        x1 = fma(g10, h20, fma(g11, h21, h11));
+      } else {
+        double a0s = 0.0, a1s = 0.0;
+        x0 = 0.0;
+        x1 = 0.0;
+        for (int L = 63; L >= 0; --L) {
+          if (lane == L) {
+            x0 = a0s;
+            x1 = a1s;
+          }
+          const double n0 = fma(readlane_f64(G[0][0], L), a0s, fma(readlane_f64(G[0][1], L), a1s, readlane_f64(xp1, L)));
+          const double n1 = fma(readlane_f64(G[1][0], L), a0s, fma(readlane_f64(G[1][1], L), a1s, readlane_f64(xp2, L)));
+          a0s = n0;
+          a1s = n1;
+        }
+      }
+      xp1 = x0;
+      xp2 = x1;
+#pragma unroll
+      for (int i = R - 1; i >= 0; --i) {
+        const double x = fma(-e1[i], xp1, fma(-e2[i], xp2, sv[i]));
+        xp2 = xp1;
+        xp1 = x;
+        part[k * MD + i * 64 + lane] = wk * x;
+      }
+      __syncthreads();
+      // y <- a0 y (+ u_1) + sum_k w_k x_k
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int i = q * NT + k;
+        if (i < 16) {
+          const int e = i * 64 + lane;
+          double a = a0 * ys[e];
+          if constexpr (PHI) {
+            if (fn == 1 && j > 0) a += u1[q];
+          }
+#pragma unroll
+          for (int kk = 0; kk < NT; ++kk) a += part[kk * MD + e];
+          if constexpr (PHI) {
+            if (first_phi && N > 1) u1[q] = a;
+          }
+          ys[e] = a;
+        }
+      }
+      __syncthreads();
+    }
+    double *F = (fn ? D.Fp : D.Fe) + col;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = q * NT + k;
+      if (i < 16) {
+        const int r = lane * R + i;
+        if (r < d) F[(int64_t)r * D.ldf] = ys[i * 64 + lane];
+      }
+    }
+    __syncthreads();  // the next column overwrites ys
   }
 }
 

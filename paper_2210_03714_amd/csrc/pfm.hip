@@ -754,7 +754,7 @@ int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, co
   hipStream_t stream = (hipStream_t)stream_;
   std::vector<BandDesc> desc(batch);
   int64_t dofs = 0;
-  int64_t waves = 0;
+  int64_t waves = 0, sgs = 0;
   for (int i = 0; i < batch; ++i) {
     const pfm_band_problem &P = probs[i];
     BandDesc &D = desc[i];
@@ -772,12 +772,20 @@ int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, co
     const int64_t d = P.d, p = P.p;
     D.b_off = dofs; dofs += align_up((2 * b + 1) * d, 64);
     D.f_off = dofs; dofs += align_up((int64_t)T.nterms * (2 * b + 1) * d, 64);
-    D.v_off = dofs; dofs += align_up((int64_t)T.nf * 3 * d * p, 64);
-    D.z_off = dofs; dofs += align_up((int64_t)T.nf * ((d + kBandL(b) - 1) / kBandL(b)) * T.nterms * b * p, 64);
     D.wave0 = (int32_t)waves;
-    D.nwaves = T.nf * (int32_t)((p + 63) / 64);
-    waves += D.nwaves;
-    if (waves > (int64_t)1 << 30) return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
+    D.sg0 = (int32_t)sgs;
+    if (b == 2 && T.nterms <= 8 && d <= kTsMaxD) {
+      // band_scan_kernel: the vector stays on chip, no vectors or checkpoints
+      D.nsg = T.nf * (int32_t)((p + kBsC - 1) / kBsC);
+      sgs += D.nsg;
+    } else {
+      D.v_off = dofs; dofs += align_up((int64_t)T.nf * 3 * d * p, 64);
+      D.z_off = dofs; dofs += align_up((int64_t)T.nf * ((d + kBandL(b) - 1) / kBandL(b)) * T.nterms * b * p, 64);
+      D.nwaves = T.nf * (int32_t)((p + 63) / 64);
+      waves += D.nwaves;
+    }
+    if (waves > (int64_t)1 << 30 || sgs > (int64_t)1 << 30)
+      return set_err(ctx, PFM_ERR_INVALID, "too many columns in one call");
   }
   const int64_t desc_bytes = align_up((int64_t)batch * sizeof(BandDesc), 256);
   const int64_t plan_bytes = align_up((int64_t)batch * sizeof(PlanRec), 256);
@@ -803,7 +811,25 @@ int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, co
                      wsd);
   ctx->cur_launches[0]++;
   prof_mark(ctx, 1, stream);
+  if (sgs) {
+    const bool band_phi = T.fn[0] == 1 || (T.nf > 1 && T.fn[1] == 1);
+    const dim3 gs((unsigned)align_up(sgs, 8));
+#define PFM_BAND_SCAN(NT)                                                                                        \
+  do {                                                                                                           \
+    if (band_phi)                                                                                                \
+      hipLaunchKernelGGL((band_scan_kernel<NT, true>), gs, dim3(64 * NT), 0, stream, d_desc, batch, d_plan, T,   \
+                         (const double *)wsd, (int)sgs);                                                         \
+    else                                                                                                         \
+      hipLaunchKernelGGL((band_scan_kernel<NT, false>), gs, dim3(64 * NT), 0, stream, d_desc, batch, d_plan, T,  \
+                         (const double *)wsd, (int)sgs);                                                         \
+  } while (0)
+    if (T.nterms == 4) PFM_BAND_SCAN(4);
+    else if (T.nterms == 5) PFM_BAND_SCAN(5);
+    else PFM_BAND_SCAN(8);
+#undef PFM_BAND_SCAN
+  }
 #define PFM_BAND_STEPS(BW, NT)                                                                                 \
+  if (waves)                                                                                                   \
   hipLaunchKernelGGL((band_steps_kernel<BW, NT>), dim3((unsigned)waves), dim3(64), 0, stream, d_desc, batch, d_plan, \
                      T, (const double *)wsd, wsd)
 #define PFM_BAND_NT(BW)                                   \

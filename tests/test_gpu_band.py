@@ -5,7 +5,10 @@ seeded inputs: relative Frobenius error <= 1e-12 per instance and function,
 the same N, the same ||A||_1 bit for bit, and route 4.  Half-bandwidths
 b = 1..4, uneven batches with ragged 64-column waves, d below and above b,
 and the entries of ``bands`` outside A set to NaN on the device (they must
-never be read)."""
+never be read).  At b = 2 with up to 8 shifts and d <= 1024 the steps run
+in the wave-per-shift scan kernel (ragged 16-column workgroups, d = 1024 at
+its limit); the uneven batch also holds d = 1100, which the lane-per-column
+kernel takes in the same call."""
 
 import ctypes
 import sys
@@ -83,7 +86,7 @@ def _check(res, info, bands, vecs, b, funcs, m, tol, bar=BAR, cols=None, idx=Non
     return worst
 
 
-SHAPES = [(1, 1), (2, 3), (5, 64), (37, 65), (130, 7)]
+SHAPES = [(1, 1), (2, 3), (5, 64), (37, 65), (1100, 2), (130, 7), (1024, 17)]
 
 
 @pytest.mark.parametrize("b", [1, 2, 3, 4])
@@ -147,6 +150,34 @@ def test_headline_shape_sampled(torch_dev):
     res, info = _run(torch, dev, bands, vecs, b, ("exp",), 8, 1e-12)
     w = _check(res, info, bands, vecs, b, ("exp",), 8, 1e-12, cols=[0, 31, 63], idx=[0, 17, 63])
     _say("  worst %.2e" % w)
+
+
+def test_full_scan_path(torch_dev):
+    """A forced N = 1 on a pentadiagonal A with off-diagonals ~1.6 and ~0.4
+    (|c_k| ||B||_1 up to 0.88: still diagonally dominant) makes the 16-row
+    lane maps of the scan kernel reach 3e-4, so it composes them lane by lane
+    instead of over two lanes; exp and phi1 against the oracle on the same
+    forced plan."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(wl.SEED_BASE + 985)
+    bands, vecs = [], []
+    for j, d in enumerate((300, 1024, 77)):
+        x = np.zeros((5, d))
+        x[1] = 1.6 * (1 + 0.05 * rng.standard_normal(d))
+        x[3] = 1.6 * (1 + 0.05 * rng.standard_normal(d))
+        x[0] = 0.4 * (1 + 0.05 * rng.standard_normal(d))
+        x[4] = 0.4 * (1 + 0.05 * rng.standard_normal(d))
+        x[2] = 0.05 * rng.standard_normal(d)
+        bands.append(x)
+        vecs.append(wl.vectors(d, 5 + 13 * j, wl.SEED_BASE + 986 + j))
+    _say("case band full scan path")
+    res, info = _run(torch, dev, bands, vecs, 2, ("exp", "phi1"), 8, 1e-12, force_plan=1)
+    for i in range(len(bands)):
+        assert info[i]["plan"] == 1 and info[i]["status"] == 0
+        own = bd.band_action(bands[i], 2, vecs[i], ("exp", "phi1"), 8, 1e-12, force_plan=1)
+        for f in ("exp", "phi1"):
+            err = me.rel_fro(res[f][i].cpu().numpy(), own[f])
+            assert err <= BAR, (i, f, err)
 
 
 def _hybrid_bar(N):
