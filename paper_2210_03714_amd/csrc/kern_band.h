@@ -118,57 +118,79 @@ band_plan_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
 }
 
 // B = A / N and the LU of M = I - c_k B for every (instance, shift): one
-// thread each, elimination down the band without interchanges.  The factor
-// rows first hold M (l_i[r] = M[r][r - i], ui[r] = M[r][r],
-// em_j[r] = M[r][r + j]); step q subtracts l M[q][.] from the b rows below
-// it and then normalises row q.  A zero or non-finite pivot sets
-// PFM_SINGULAR_SHIFT with the smallest such shift.
+// thread each, elimination down the band without interchanges.  The rows
+// q .. q + BW that elimination step q touches are held in registers (row
+// r's values: l_1..l_b, then the diagonal, then U[r][r + 1..b]; they start
+// as M's); step q subtracts l M[q][.] from the rows below it, normalises
+// row q (1/u, em_j = U[q][q + j] / U[q][q]) and stores it, and the next row
+// of M enters the window.  The instance's shifts share the writing of B.
+// A zero or non-finite pivot sets PFM_SINGULAR_SHIFT with the smallest such
+// shift.
+template <int BW>
 __global__ void __launch_bounds__(64)
 band_factor_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan, int batch, TriTerms T,
                    double *__restrict__ wsd) {
+  constexpr int W = 2 * BW + 1;
   const int gid = blockIdx.x * 64 + threadIdx.x;
   const int ii = gid / T.nterms, k = gid - ii * T.nterms;
   if (ii >= batch) return;
   if (plan[ii].status & 8) return;  // PFM_NOT_COMPUTED (too many steps)
   const BandDesc D = desc[ii];
-  const int d = D.d, b = D.b;
+  const int d = D.d, nt = T.nterms;
   const double Nd = (double)plan[ii].s;
   const double c = T.c[k];
-  const double *A = D.bands;
-  double *Bw = wsd + D.b_off;
-  const int nt = T.nterms, w = 2 * b + 1;
-  double *Fb = wsd + D.f_off;
-  // row r's value j (0..2b) of this shift
-  auto at = [&](int r, int j) -> double & { return Fb[((int64_t)r * nt + k) * w + j]; };
-  if (k == 0) {
-    for (int o = -b; o <= b; ++o)
-      for (int r = 0; r < d; ++r)
-        Bw[(int64_t)r * w + b + o] = (r + o >= 0 && r + o < d) ? A[(int64_t)(b + o) * d + r] / Nd : 0.0;
-  }
-  for (int r = 0; r < d; ++r) {
-    for (int i = 1; i <= b; ++i) at(r, i - 1) = r - i >= 0 ? -c * (A[(int64_t)(b - i) * d + r] / Nd) : 0.0;
-    at(r, b) = 1.0 - c * (A[(int64_t)b * d + r] / Nd);
-    for (int j = 1; j <= b; ++j) at(r, b + j) = r + j < d ? -c * (A[(int64_t)(b + j) * d + r] / Nd) : 0.0;
-  }
+  const double *__restrict__ A = D.bands;
+  double *__restrict__ Bw = wsd + D.b_off;
+  double *__restrict__ Fb = wsd + D.f_off;
+  for (int r = k; r < d; r += nt)
+#pragma unroll
+    for (int o = -BW; o <= BW; ++o)
+      Bw[(int64_t)r * W + BW + o] = (r + o >= 0 && r + o < d) ? A[(int64_t)(BW + o) * d + r] / Nd : 0.0;
+  // M's row r in the window's layout (zero past the matrix)
+  auto mrow = [&](int r, double *v) {
+#pragma unroll
+    for (int i = 1; i <= BW; ++i) v[i - 1] = (r < d && r - i >= 0) ? -c * (A[(int64_t)(BW - i) * d + r] / Nd) : 0.0;
+    v[BW] = r < d ? 1.0 - c * (A[(int64_t)BW * d + r] / Nd) : 1.0;
+#pragma unroll
+    for (int j = 1; j <= BW; ++j) v[BW + j] = r + j < d ? -c * (A[(int64_t)(BW + j) * d + r] / Nd) : 0.0;
+  };
+  double win[BW + 1][W];
+#pragma unroll
+  for (int r = 0; r <= BW; ++r) mrow(r, win[r]);
   bool bad = false;
+#pragma unroll 1
   for (int q = 0; q < d; ++q) {
-    const double piv = at(q, b);
+    const double piv = win[0][BW];
     bad |= !(piv != 0.0 && isfinite(piv));
-    for (int i = 1; i <= b && q + i < d; ++i) {
-      const int r = q + i;
-      const double lv = at(r, i - 1) / piv;  // M[r][q] / U[q][q]
-      at(r, i - 1) = lv;
-      for (int j = 1; j <= b && q + j < d; ++j) {
-        const double u = at(q, b + j);  // U[q][q + j], not yet normalised
-        const int off = j - i;          // column q + j relative to row r
-        if (off == 0) at(r, b) -= lv * u;
-        else if (off > 0) at(r, b + off) -= lv * u;
-        else at(r, -off - 1) -= lv * u;
+#pragma unroll
+    for (int i = 1; i <= BW; ++i) {
+      if (q + i < d) {
+        const double lv = win[i][i - 1] / piv;  // M[q + i][q] / U[q][q]
+        win[i][i - 1] = lv;
+#pragma unroll
+        for (int j = 1; j <= BW; ++j) {
+          if (q + j < d) {
+            const double u = win[0][BW + j];  // U[q][q + j], not yet normalised
+            const int off = j - i;            // column q + j relative to row q + i
+            if (off == 0) win[i][BW] -= lv * u;
+            else if (off > 0) win[i][BW + off] -= lv * u;
+            else win[i][-off - 1] -= lv * u;
+          }
+        }
       }
     }
     const double inv = 1.0 / piv;
-    at(q, b) = inv;
-    for (int j = 1; j <= b; ++j) at(q, b + j) *= inv;
+    win[0][BW] = inv;
+#pragma unroll
+    for (int j = 1; j <= BW; ++j) win[0][BW + j] *= inv;
+    double *out = Fb + ((int64_t)q * nt + k) * W;
+#pragma unroll
+    for (int j = 0; j < W; ++j) out[j] = win[0][j];
+#pragma unroll
+    for (int r = 0; r < BW; ++r)
+#pragma unroll
+      for (int j = 0; j < W; ++j) win[r][j] = win[r + 1][j];
+    mrow(q + BW + 1, win[BW]);
   }
   if (bad) {
     atomicOr(&plan[ii].status, 1);
@@ -477,17 +499,16 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
 //   y <- a0 y (+ u_1) + sum_k w_k x_k   (the workgroup, by rows, k in order)
 // Three barriers per step; the columns of a workgroup run one after another,
 // so the factors are loaded once for kBsC columns.
-__device__ __forceinline__ int bs_idx(int r) { return (r & 15) * 64 + (r >> 4); }
-
 template <int NT, bool PHI>
 __global__ void __launch_bounds__(64 * NT)
 band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
                  const double *__restrict__ fac, int nsg) {
   constexpr int R = 16, NTH = 64 * NT, MD = kTsMaxD;
-  __shared__ double Bs[5 * MD];   // B[r][r + o] at (o + 2) MD + bs_idx(r)
+  __shared__ double Bs[5 * MD];   // B[r][r + o] at (o + 2) MD + (r % 16) 64 + r / 16
   __shared__ double ys[MD];       // y
   __shared__ double fs[MD];       // B y
   __shared__ double part[NT * MD];  // w_k x_k
+  __shared__ double maps[NT * 64 * 8];  // per (shift, lane): M (row-major), then G
   const int t = threadIdx.x, lane = t & 63, k = t >> 6;
   // workgroup b runs on XCD b mod 8: XCD x takes the x-th eighth of the
   // workgroups in order, so the workgroups of one instance share an L2
@@ -565,6 +586,12 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
   const bool short_scan = !__any(!(fabs(M[0][0]) <= thr && fabs(M[0][1]) <= thr && fabs(M[1][0]) <= thr &&
                                    fabs(M[1][1]) <= thr && fabs(G[0][0]) <= thr && fabs(G[0][1]) <= thr &&
                                    fabs(G[1][0]) <= thr && fabs(G[1][1]) <= thr));
+  {
+    double *mp = maps + (k * 64 + lane) * 8;
+    mp[0] = M[0][0]; mp[1] = M[0][1]; mp[2] = M[1][0]; mp[3] = M[1][1];
+    mp[4] = G[0][0]; mp[5] = G[0][1]; mp[6] = G[1][0]; mp[7] = G[1][1];
+  }
+  const double *mk = maps + k * 64 * 8;  // this wave's maps, lane by lane
   __syncthreads();
 
   constexpr int NQ = (16 + NT - 1) / NT;  // row indices i per thread in the by-rows phases
@@ -593,12 +620,11 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
       for (int q = 0; q < NQ; ++q) {
         const int i = q * NT + k;
         if (i < 16) {
-          const int r = lane * R + i;
           double f = 0.0;
 #pragma unroll
           for (int o = -2; o <= 2; ++o) {
-            const int rr = r + o;
-            const double yv = (rr >= 0 && rr < MD) ? ys[bs_idx(rr)] : 0.0;
+            const int rr = lane * R + i + o;
+            const double yv = (rr >= 0 && rr < MD) ? ys[(rr & 15) * 64 + (rr >> 4)] : 0.0;
             f = fma(Bs[(o + 2) * MD + i * 64 + lane], yv, f);
           }
           fs[i * 64 + lane] = f;
@@ -606,10 +632,12 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
       }
       __syncthreads();
       // forward: the state leaving this lane's rows from a zero state
+      double fr[R];
       double zm2 = 0.0, zm1 = 0.0;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        const double z = fma(-l1[i], zm1, fma(-l2[i], zm2, fs[i * 64 + lane]));
+        fr[i] = fs[i * 64 + lane];
+        const double z = fma(-l1[i], zm1, fma(-l2[i], zm2, fr[i]));
         zm2 = zm1;
         zm1 = z;
       }
@@ -617,10 +645,9 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
       if (short_scan) {
         const double h10 = dpp_f64<0x138>(zm2, 0.0), h11 = dpp_f64<0x138>(zm1, 0.0);  // wave_shr:1
         const double h20 = dpp_f64<0x138>(h10, 0.0), h21 = dpp_f64<0x138>(h11, 0.0);
-        const double m00 = dpp_f64<0x138>(M[0][0], 0.0), m01 = dpp_f64<0x138>(M[0][1], 0.0);
-        const double m10 = dpp_f64<0x138>(M[1][0], 0.0), m11 = dpp_f64<0x138>(M[1][1], 0.0);
-        s0 = fma(m00, h20, fma(m01, h21, h10));
-        s1 = fma(m10, h20, fma(m11, h21, h11));
+        const double *m = mk + (lane > 0 ? lane - 1 : 0) * 8;  // M_{L-1} (lane 0: h1 = h2 = 0)
+        s0 = fma(m[0], h20, fma(m[1], h21, h10));
+        s1 = fma(m[2], h20, fma(m[3], h21, h11));
       } else {
         double a0s = 0.0, a1s = 0.0;
         s0 = 0.0;
@@ -630,8 +657,9 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
             s0 = a0s;
             s1 = a1s;
           }
-          const double n0 = fma(readlane_f64(M[0][0], L), a0s, fma(readlane_f64(M[0][1], L), a1s, readlane_f64(zm2, L)));
-          const double n1 = fma(readlane_f64(M[1][0], L), a0s, fma(readlane_f64(M[1][1], L), a1s, readlane_f64(zm1, L)));
+          const double *m = mk + L * 8;
+          const double n0 = fma(m[0], a0s, fma(m[1], a1s, readlane_f64(zm2, L)));
+          const double n1 = fma(m[2], a0s, fma(m[3], a1s, readlane_f64(zm1, L)));
           a0s = n0;
           a1s = n1;
         }
@@ -642,7 +670,7 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
       zm1 = s1;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        const double z = fma(-l1[i], zm1, fma(-l2[i], zm2, fs[i * 64 + lane]));
+        const double z = fma(-l1[i], zm1, fma(-l2[i], zm2, fr[i]));
         zm2 = zm1;
         zm1 = z;
         sv[i] = ui[i] * z;
@@ -659,10 +687,9 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
       if (short_scan) {
         const double h10 = dpp_f64<0x130>(xp1, 0.0), h11 = dpp_f64<0x130>(xp2, 0.0);  // wave_shl:1
         const double h20 = dpp_f64<0x130>(h10, 0.0), h21 = dpp_f64<0x130>(h11, 0.0);
-        const double g00 = dpp_f64<0x130>(G[0][0], 0.0), g01 = dpp_f64<0x130>(G[0][1], 0.0);
-        const double g10 = dpp_f64<0x130>(G[1][0], 0.0), g11 = dpp_f64<0x130>(G[1][1], 0.0);
-        x0 = fma(g00, h20, fma(g01, h21, h10));
-        x1 = fma(g10, h20, fma(g11, h21, h11));
+        const double *g = mk + (lane < 63 ? lane + 1 : 63) * 8 + 4;  // G_{L+1} (lane 63: h1 = h2 = 0)
+        x0 = fma(g[0], h20, fma(g[1], h21, h10));
+        x1 = fma(g[2], h20, fma(g[3], h21, h11));
       } else {
         double a0s = 0.0, a1s = 0.0;
         x0 = 0.0;
@@ -672,8 +699,9 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
             x0 = a0s;
             x1 = a1s;
           }
-          const double n0 = fma(readlane_f64(G[0][0], L), a0s, fma(readlane_f64(G[0][1], L), a1s, readlane_f64(xp1, L)));
-          const double n1 = fma(readlane_f64(G[1][0], L), a0s, fma(readlane_f64(G[1][1], L), a1s, readlane_f64(xp2, L)));
+          const double *g = mk + L * 8 + 4;
+          const double n0 = fma(g[0], a0s, fma(g[1], a1s, readlane_f64(xp1, L)));
+          const double n1 = fma(g[2], a0s, fma(g[3], a1s, readlane_f64(xp2, L)));
           a0s = n0;
           a1s = n1;
         }

@@ -807,8 +807,13 @@ int pfm_band_action(pfm_ctx *ctx, int f, int m, double tol, int b, int batch, co
   for (int ph = 0; ph < kNumPhases; ++ph) ctx->cur_launches[ph] = 0;
   prof_mark(ctx, 0, stream);
   const int nfac = batch * T.nterms;
-  hipLaunchKernelGGL(band_factor_kernel, dim3((nfac + 63) / 64), dim3(64), 0, stream, d_desc, d_plan, batch, T,
-                     wsd);
+  {
+    const dim3 gf((nfac + 63) / 64);
+    if (b == 1) hipLaunchKernelGGL(band_factor_kernel<1>, gf, dim3(64), 0, stream, d_desc, d_plan, batch, T, wsd);
+    else if (b == 2) hipLaunchKernelGGL(band_factor_kernel<2>, gf, dim3(64), 0, stream, d_desc, d_plan, batch, T, wsd);
+    else if (b == 3) hipLaunchKernelGGL(band_factor_kernel<3>, gf, dim3(64), 0, stream, d_desc, d_plan, batch, T, wsd);
+    else hipLaunchKernelGGL(band_factor_kernel<4>, gf, dim3(64), 0, stream, d_desc, d_plan, batch, T, wsd);
+  }
   ctx->cur_launches[0]++;
   prof_mark(ctx, 1, stream);
   if (sgs) {
