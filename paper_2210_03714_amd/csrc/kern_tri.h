@@ -129,27 +129,28 @@ tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
   const int d = D.d;
   const double Nd = (double)plan[ii].s;
   const double c = T.c[k];
-  double *sub = wsd + D.b_off, *dia = sub + d, *sup = dia + d;
-  double *l = wsd + D.f_off + (int64_t)k * 3 * d, *ui = l + d, *em = ui + d;
-  if (k == 0) {
-    for (int r = 0; r < d; ++r) {
-      sub[r] = r > 0 ? D.dl[r - 1] / Nd : 0.0;
-      dia[r] = D.dd[r] / Nd;
-      sup[r] = r + 1 < d ? D.du[r] / Nd : 0.0;
-    }
+  double *__restrict__ sub = wsd + D.b_off, *__restrict__ dia = sub + d, *__restrict__ sup = dia + d;
+  double *__restrict__ l = wsd + D.f_off + (int64_t)k * 3 * d, *__restrict__ ui = l + d, *__restrict__ em = ui + d;
+  const double *__restrict__ Al = D.dl, *__restrict__ Ad = D.dd, *__restrict__ Au = D.du;
+  // the instance's shifts share the writing of B
+  for (int r = k; r < d; r += T.nterms) {
+    sub[r] = r > 0 ? Al[r - 1] / Nd : 0.0;
+    dia[r] = Ad[r] / Nd;
+    sup[r] = r + 1 < d ? Au[r] / Nd : 0.0;
   }
   bool bad = false;
-  double u = 1.0 - c * (D.dd[0] / Nd);
+  double u = 1.0 - c * (Ad[0] / Nd);
   double uinv = 1.0 / u;
   bad |= !(u != 0.0 && isfinite(u));
   l[0] = 0.0;
   ui[0] = uinv;
+#pragma unroll 4
   for (int r = 1; r < d; ++r) {
-    const double mlo = -c * (D.dl[r - 1] / Nd);  // M[r][r-1]
-    const double mup = -c * (D.du[r - 1] / Nd);  // M[r-1][r]
+    const double mlo = -c * (Al[r - 1] / Nd);  // M[r][r-1]
+    const double mup = -c * (Au[r - 1] / Nd);  // M[r-1][r]
     const double lr = mlo * uinv;  // tri_scan_kernel forms the same product from ui
     em[r - 1] = mup * uinv;
-    u = (1.0 - c * (D.dd[r] / Nd)) - lr * mup;
+    u = (1.0 - c * (Ad[r] / Nd)) - lr * mup;
     uinv = 1.0 / u;
     bad |= !(u != 0.0 && isfinite(u));
     l[r] = lr;
