@@ -178,8 +178,8 @@ def _bar_set(m, n, s, theta):
 
 def test_r10star_full_and_tridiagonal(torch_dev):
     """R*10 (m = PFM_R10STAR, §4.3 eqs. Frac10ciNO-Frac10biNO) at tol 1e-8:
-    full matrices on the Gauss-Jordan route and the tridiagonal action
-    (R*10' of §5), against the oracle at the same plan, within the bars of
+    full matrices on the Gauss-Jordan route, the dense action on both of its
+    routes and the tridiagonal action (R*10' of §5), against the oracle at the same plan, within the bars of
     this module and of the tridiagonal tests (its weights, sum |w| ~ 1.3e6,
     set the rounding).  Below its rounding floor (tol 1e-12) it is refused."""
     torch, dev = torch_dev
@@ -217,6 +217,20 @@ def test_r10star_full_and_tridiagonal(torch_dev):
         own = bd.tri_action(a, b, c, V, ("exp",), 110, tol, force_plan=N)
         err = me.rel_fro(rt["exp"][i].cpu().numpy(), own["exp"])
         assert err <= 2 * 16 * N * amp * U, (i, N, err)
+    # the dense action on both routes (n = 60 single-workgroup, n = 200 multi-workgroup)
+    amats = [wl.gaussian(n, 2.0, wl.SEED_BASE + 740 + n) for n in (60, 200)]
+    avecs = [wl.vectors(n, p, wl.SEED_BASE + 750 + n) for n, p in ((60, 4), (200, 9))]
+    _say("case R*10 dense action")
+    ra, ia = pfm.action([torch.from_numpy(a).to(dev) for a in amats], [torch.from_numpy(v).to(dev) for v in avecs],
+                        ("exp",), m=m, tol=tol)
+    torch.cuda.synchronize()
+    for i, (A, V) in enumerate(zip(amats, avecs)):
+        N = int(ia[i]["plan"])
+        own = me.action(A, V, ("exp",), 110, tol, force_plan=N)
+        assert ia[i]["status"] == 0 and ia[i]["route"] == (0 if A.shape[0] <= 128 else 2)
+        err = me.rel_fro(ra["exp"][i].cpu().numpy(), own["exp"])
+        bar = _bar_set(110, A.shape[0], 0, own["theta"]) * N
+        assert err <= bar, (i, A.shape[0], N, err, bar)
     A0 = torch.from_numpy(mats[0]).to(dev)
     for t in (1e-12, 1e-10):
         with pytest.raises(pfm.PfmError) as e:
