@@ -7,8 +7,16 @@
 // strictly column diagonally dominant, so elimination without interchanges
 // is the partial-pivoting LU.
 //
-// Layout (one lane per column of V, a wave per 64 consecutive columns of one
-// instance, so every lane needs the same rows of B and of the factors):
+// Two step kernels share the factorisation:
+//   band_scan_kernel (b = 2, up to 8 shifts, d <= kTsMaxD): a wave per shift,
+//     one column at a time, the sweeps as 2-state affine maps scanned over
+//     the lanes, the vector in LDS for all N steps (described above the
+//     kernel);
+//   band_steps_kernel (the rest): a lane per column, a wave per 64
+//     consecutive columns of one instance (every lane needs the same rows of
+//     B and of the factors), the vector in memory between the passes of a
+//     step (below).
+// Layout:
 //   A:        bands[(b + o) d + i] = A[i][i + o], o = -b..b (caller's; the
 //             entries with i + o outside [0, d) are never read)
 //   B:        row-major, B[r][r + o] at r (2b + 1) + b + o (A / N, zero
@@ -19,11 +27,12 @@
 //             backward sweep is x_r = ui z_r - sum_j em_j x_{r+j}.  One row's
 //             values of all shifts are contiguous, so a block of rows is one
 //             contiguous range that the wave stages through LDS
+//   band_steps_kernel only:
 //   vectors:  per function slot, two ping-pong buffers and one for u_1 (φ1)
 //             or the hybrid set's polynomial part, d x p row-major
 //   checkpoints: per slot, the last b forward values of every shift at the
 //             end of each chunk of kBandL(b) rows, [chunk][k][b][p]
-// A step makes two passes over the column.  The forward pass forms y = B x
+// A band_steps_kernel step makes two passes over the column.  The forward pass forms y = B x
 // and runs the forward sweeps of all shifts, keeping only the checkpoints.
 // The backward pass walks the chunks from the last: it recomputes the
 // chunk's forward values from its checkpoint in registers (reading x again,

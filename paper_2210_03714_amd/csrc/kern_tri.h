@@ -8,23 +8,30 @@
 // (|c_k| ||B||_1 < 0.2 on the registered sets), so elimination without
 // interchanges is the partial-pivoting LU.
 //
-// Layout (one thread per column of V, a wave per 64 consecutive columns of
-// one instance, so every factor read is the same address in all lanes):
+// Two step kernels share the factorisation:
+//   tri_scan_kernel (d <= kTsMaxD): a wave per column, 16 rows per lane, the
+//     sweeps as affine maps scanned over the lanes; the vector stays in
+//     registers for all N steps (described above the kernel);
+//   tri_steps_kernel (larger d): a lane per column, a wave per 64 columns of
+//     one instance (every factor read is the same address in all lanes), the
+//     vector in memory between the passes of a step (below).
+// Workspace layout:
 //   B:        sub[r] = B[r][r-1] (sub[0] = 0), dia[r], sup[r] = B[r][r+1]
 //             (sup[d-1] = 0)
-//   factors:  per shift k, l[r] = M[r][r-1] / u[r-1] (l[0] = 0),
+//   factors:  per shift k, l[r] = M[r][r-1] (1 / u[r-1]) (l[0] = 0),
 //             ui[r] = 1 / u[r] and em[r] = M[r][r+1] / u[r] (em[d-1] = 0),
 //             M = I - c_k B = L U; the backward sweep is then
 //             x_r = ui[r] z_r - em[r] x_{r+1}
+//   tri_steps_kernel only:
 //   vectors:  per function slot, two ping-pong buffers and u_1 (phi1), each
 //             d x p row-major (lanes read consecutive addresses)
 //   checkpoints: the forward sweep's value at the end of every kTriL-row
 //             chunk, per shift, [chunk][k][column]
-// A step reads the input vector twice and writes the output once: the first
-// pass runs the forward sweeps of all shifts and keeps only the chunk-end
-// values; the second pass walks the chunks from the last, recomputes each
-// chunk's forward values from its checkpoint in registers, and runs the
-// backward sweep, accumulating a0 x + sum_k w_k x_k on the way.
+// A tri_steps_kernel step reads the input vector twice and writes the output
+// once: the first pass runs the forward sweeps of all shifts and keeps only
+// the chunk-end values; the second pass walks the chunks from the last,
+// recomputes each chunk's forward values from its checkpoint in registers,
+// and runs the backward sweep, accumulating a0 x + sum_k w_k x_k on the way.
 #pragma once
 #include <type_traits>
 
