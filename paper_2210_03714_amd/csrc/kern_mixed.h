@@ -63,21 +63,27 @@ solve_mixed_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ il
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) Ap[rb][ct] = zero4();
 
-  // B[:, slab] in natural row order and its largest entry
+  // element (rb, ct, v) of B[:, slab] in natural row order.  The base
+  // pointer is made opaque at every use, so that the addresses of these
+  // loads are formed where they are used rather than held in registers
+  // across the shifts (at npad = 512 that is 32 64-bit addresses a lane).
+  auto b_elem = [&](const double *Ab, int rb, int ct, int v) -> double {
+    const int b = wave + 4 * rb, col = c0 + 16 * ct + i16, r = 16 * b + 4 * g + v;
+    return (b < nblk && r < n && col < ncol) ? sc * Ab[(int64_t)r * D.lda + col] : 0.0;
+  };
+  auto opaque_a = [&]() {
+    const double *Ab = D.A;
+    asm volatile("" : "+v"(Ab));
+    return Ab;
+  };
   auto load_b = [&](v4d (&X)[RB][CT]) {
+    const double *Ab = opaque_a();
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int b = wave + 4 * rb;
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const int col = c0 + 16 * ct + i16;
+      for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = 16 * b + 4 * g + v;
-          X[rb][ct][v] = (b < nblk && r < n && col < ncol) ? sc * D.A[(int64_t)r * D.lda + col] : 0.0;
-        }
-      }
-    }
+        for (int v = 0; v < 4; ++v) X[rb][ct][v] = b_elem(Ab, rb, ct, v);
   };
   // workgroup-wide max |X| (all threads get the value)
   int par = 0;
@@ -131,14 +137,18 @@ solve_mixed_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ il
         }
       }
       __syncthreads();
+      {
+        const int *pk = perm;
+        asm volatile("" : "+v"(pk));  // (as for B's loads)
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int b = wave + 4 * rb;
+        for (int rb = 0; rb < RB; ++rb) {
+          const int b = wave + 4 * rb;
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
+          for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            Zf[rb][ct][v] = (b < nblk) ? (float)Ybuf[perm[16 * b + 4 * g + v] * SW + 16 * ct + i16] : 0.f;
+            for (int v = 0; v < 4; ++v)
+              Zf[rb][ct][v] = (b < nblk) ? (float)Ybuf[pk[16 * b + 4 * g + v] * SW + 16 * ct + i16] : 0.f;
+        }
       }
       __syncthreads();
       lu_solve_slab<RB, CT, SW, float>(Zf, Wf, dL, dU, S32, Tst32[wave], np, nblk, wave, ar32, g, i16);
@@ -162,11 +172,11 @@ solve_mixed_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ il
         }
       }
       __syncthreads();
-      v4d G[RB][CT];
+      // B Z accumulates in r's registers (r is formed again from B below)
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) G[rb][ct] = zero4();
+        for (int ct = 0; ct < CT; ++ct) Rd[rb][ct] = zero4();
 #pragma unroll 2
       for (int k0 = 0; k0 < np; k0 += 4) {
         double bf[CT];
@@ -178,18 +188,21 @@ solve_mixed_kernel(const InstDesc *__restrict__ inst, const int *__restrict__ il
           if (bb < nblk) {
             const double a = Bt[(16 * bb + ar64) + (int64_t)(k0 + g) * np];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) G[rb][ct] = mfma16(a, bf[ct], G[rb][ct]);
+            for (int ct = 0; ct < CT; ++ct) Rd[rb][ct] = mfma16(a, bf[ct], Rd[rb][ct]);
           }
         }
       }
       __syncthreads();
-      load_b(Rd);
+      {
+        const double *Ab = opaque_a();
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
+          for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Rd[rb][ct][v] = fma(ck, G[rb][ct][v], Rd[rb][ct][v] - Zd[rb][ct][v]);
+            for (int v = 0; v < 4; ++v)
+              Rd[rb][ct][v] = fma(ck, Rd[rb][ct][v], b_elem(Ab, rb, ct, v) - Zd[rb][ct][v]);
+      }
       const double rmax = wg_max(Rd);
       rrel = bmax > 0.0 ? rmax / bmax : 0.0;
       if (rrel <= irtol) break;
