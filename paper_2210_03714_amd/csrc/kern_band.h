@@ -495,19 +495,30 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
 // B y, and the shifts' w_k x_k live in LDS, transposed so that the lanes'
 // accesses to one row index are consecutive (row r at (r % 16) 64 + r / 16).
 // A step:
-//   f = B y                 (the workgroup, by rows)
+//   f = B y                 (the workgroup, a thread per pair of adjacent rows)
 //   forward  z_r = f_r - l_1 z_{r-1} - l_2 z_{r-2}: each lane's 16 rows from
 //            a zero state give the state leaving them, h_L = (z_{14}, z_{15});
 //            with the lane's homogeneous 2 x 2 map M_L (formed once) the state
 //            entering lane L is h_{L-1} + M_{L-1} h_{L-2} when every map entry
 //            is at most 2^-30 (the rest, M_{L-1} M_{L-2} h_{L-3}, is below
-//            2^-58 of the largest state), else the maps are composed lane by
-//            lane; the lane then sweeps its rows again from that state
+//            2^-58 of the largest state; lane L - 1 forms it with its own map
+//            and DPP moves it up), else the maps are composed lane by lane;
+//            the lane then sweeps its rows again from that state
 //   backward x_r = ui_r z_r - em_1 x_{r+1} - em_2 x_{r+2}: the same from lane
-//            63 down, and w_k x_k into LDS
+//            63 down, and w_k x_k into LDS (exp alone: w_k ui is held in place
+//            of ui, so the sweep gives w_k x_k itself)
 //   y <- a0 y (+ u_1) + sum_k w_k x_k   (the workgroup, by rows, k in order)
 // Three barriers per step; the columns of a workgroup run one after another,
 // so the factors are loaded once for kBsC columns.
+// A double moved by the DPP pattern CTRL, 0 in the lanes with no source lane
+// (bound control set), so no old value has to be written first.
+template <int CTRL>
+__device__ __forceinline__ double dpp0_f64(double src) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(src), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(src), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
 template <int NT, bool PHI>
 __global__ void __launch_bounds__(64 * NT)
 band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,
@@ -567,6 +578,13 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
     e1[i] = in ? f[3] : 0.0;
     e2[i] = in ? f[4] : 0.0;
   }
+  // exp alone: w_k is the same at every step, and w_k x obeys the backward
+  // recurrence with w_k ui in place of ui, so the weight is folded in here
+  if constexpr (!PHI) {
+    const double w = T.we[k];
+#pragma unroll
+    for (int i = 0; i < R; ++i) ui[i] *= w;
+  }
   // the lane's homogeneous maps: forward (z_{-2}, z_{-1}) -> (z_14, z_15),
   // backward (x_16, x_17) -> (x_0, x_1), column by column
   double M[2][2], G[2][2];
@@ -621,30 +639,41 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
 #pragma unroll 1
     for (int j = 0; j < N; ++j) {
       // phi1's first step is u_1 = rho(B) V / N: the 1/N is folded into its weights
-      const bool first_phi = fn == 1 && j == 0;
+      const bool first_phi = PHI && fn == 1 && j == 0;
       const double a0 = first_phi ? T.a0p / (double)N : T.a0e;
       const double wk = first_phi ? T.wp[k] / (double)N : T.we[k];
-      // f = B y
+      // f = B y: a thread takes NQ adjacent rows of its lane's block, so
+      // their y values are read once, NQ + 4 of them
+      {
+        const int i0 = k * NQ;
+        if (i0 < 16) {
+          double yw[NQ + 4];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int i = q * NT + k;
-        if (i < 16) {
-          double f = 0.0;
-#pragma unroll
-          for (int o = -2; o <= 2; ++o) {
-            const int rr = lane * R + i + o;
-            const double yv = (rr >= 0 && rr < MD) ? ys[(rr & 15) * 64 + (rr >> 4)] : 0.0;
-            f = fma(Bs[(o + 2) * MD + i * 64 + lane], yv, f);
+          for (int q = 0; q < NQ + 4; ++q) {
+            const int rr = lane * R + i0 + q - 2;
+            yw[q] = (rr >= 0 && rr < MD) ? ys[(rr & 15) * 64 + (rr >> 4)] : 0.0;
           }
-          fs[i * 64 + lane] = f;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const int i = i0 + q;
+            if (i < 16) {
+              double f = 0.0;
+#pragma unroll
+              for (int o = -2; o <= 2; ++o) f = fma(Bs[(o + 2) * MD + i * 64 + lane], yw[q + o + 2], f);
+              fs[i * 64 + lane] = f;
+            }
+          }
         }
       }
       __syncthreads();
-      // forward: the state leaving this lane's rows from a zero state
+      // forward: the state leaving this lane's rows from a zero state (its
+      // first two rows need no terms of the state)
       double fr[R];
-      double zm2 = 0.0, zm1 = 0.0;
+      fr[0] = fs[lane];
+      fr[1] = fs[64 + lane];
+      double zm2 = fr[0], zm1 = fma(-l1[1], fr[0], fr[1]);
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
+      for (int i = 2; i < R; ++i) {
         fr[i] = fs[i * 64 + lane];
         const double z = fma(-l1[i], zm1, fma(-l2[i], zm2, fr[i]));
         zm2 = zm1;
@@ -652,11 +681,21 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
       }
       double s0, s1;  // the state entering this lane: (z_{-2}, z_{-1})
       if (short_scan) {
-        const double h10 = dpp_f64<0x138>(zm2, 0.0), h11 = dpp_f64<0x138>(zm1, 0.0);  // wave_shr:1
-        const double h20 = dpp_f64<0x138>(h10, 0.0), h21 = dpp_f64<0x138>(h11, 0.0);
-        const double *m = mk + (lane > 0 ? lane - 1 : 0) * 8;  // M_{L-1} (lane 0: h1 = h2 = 0)
-        s0 = fma(m[0], h20, fma(m[1], h21, h10));
-        s1 = fma(m[2], h20, fma(m[3], h21, h11));
+        const double h10 = dpp0_f64<0x138>(zm2), h11 = dpp0_f64<0x138>(zm1);  // wave_shr:1
+        if constexpr (!PHI) {
+          // lane L forms h_L + M_L h_{L-1} with its own map (registers); one
+          // shift up gives lane L + 1 its entering state
+          const double c0 = fma(M[0][0], h10, fma(M[0][1], h11, zm2));
+          const double c1 = fma(M[1][0], h10, fma(M[1][1], h11, zm1));
+          s0 = dpp0_f64<0x138>(c0);
+          s1 = dpp0_f64<0x138>(c1);
+        } else {
+          // phi1 keeps u_1 too: the neighbour's map from LDS, so nothing spills
+          const double h20 = dpp0_f64<0x138>(h10), h21 = dpp0_f64<0x138>(h11);
+          const double *m = mk + (lane > 0 ? lane - 1 : 0) * 8;  // M_{L-1} (lane 0: h1 = h2 = 0)
+          s0 = fma(m[0], h20, fma(m[1], h21, h10));
+          s1 = fma(m[2], h20, fma(m[3], h21, h11));
+        }
       } else {
         double a0s = 0.0, a1s = 0.0;
         s0 = 0.0;
@@ -685,20 +724,27 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
         sv[i] = ui[i] * z;
       }
       // backward: the state leaving this lane upwards from a zero state
-      double xp1 = 0.0, xp2 = 0.0;
+      double xp2 = sv[R - 1], xp1 = fma(-e1[R - 2], sv[R - 1], sv[R - 2]);
 #pragma unroll
-      for (int i = R - 1; i >= 0; --i) {
+      for (int i = R - 3; i >= 0; --i) {
         const double x = fma(-e1[i], xp1, fma(-e2[i], xp2, sv[i]));
         xp2 = xp1;
         xp1 = x;
       }
       double x0, x1;  // the state entering this lane from below: (x_16, x_17)
       if (short_scan) {
-        const double h10 = dpp_f64<0x130>(xp1, 0.0), h11 = dpp_f64<0x130>(xp2, 0.0);  // wave_shl:1
-        const double h20 = dpp_f64<0x130>(h10, 0.0), h21 = dpp_f64<0x130>(h11, 0.0);
-        const double *g = mk + (lane < 63 ? lane + 1 : 63) * 8 + 4;  // G_{L+1} (lane 63: h1 = h2 = 0)
-        x0 = fma(g[0], h20, fma(g[1], h21, h10));
-        x1 = fma(g[2], h20, fma(g[3], h21, h11));
+        const double h10 = dpp0_f64<0x130>(xp1), h11 = dpp0_f64<0x130>(xp2);  // wave_shl:1
+        if constexpr (!PHI) {
+          const double c0 = fma(G[0][0], h10, fma(G[0][1], h11, xp1));
+          const double c1 = fma(G[1][0], h10, fma(G[1][1], h11, xp2));
+          x0 = dpp0_f64<0x130>(c0);
+          x1 = dpp0_f64<0x130>(c1);
+        } else {
+          const double h20 = dpp0_f64<0x130>(h10), h21 = dpp0_f64<0x130>(h11);
+          const double *g = mk + (lane < 63 ? lane + 1 : 63) * 8 + 4;  // G_{L+1} (lane 63: h1 = h2 = 0)
+          x0 = fma(g[0], h20, fma(g[1], h21, h10));
+          x1 = fma(g[2], h20, fma(g[3], h21, h11));
+        }
       } else {
         double a0s = 0.0, a1s = 0.0;
         x0 = 0.0;
@@ -722,7 +768,7 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
         const double x = fma(-e1[i], xp1, fma(-e2[i], xp2, sv[i]));
         xp2 = xp1;
         xp1 = x;
-        part[k * MD + i * 64 + lane] = wk * x;
+        part[k * MD + i * 64 + lane] = PHI ? wk * x : x;
       }
       __syncthreads();
       // y <- a0 y (+ u_1) + sum_k w_k x_k
