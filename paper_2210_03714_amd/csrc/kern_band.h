@@ -525,7 +525,7 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
                  const double *__restrict__ fac, int nsg) {
   constexpr int R = 16, NTH = 64 * NT, MD = kTsMaxD;
   __shared__ double Bs[5 * MD];   // B[r][r + o] at (o + 2) MD + (r % 16) 64 + r / 16
-  __shared__ double ys[MD];       // y
+  __shared__ double ys[16 * 65];  // y: row r at (r % 16) 65 + r / 16 + 1; column 0 is zero
   __shared__ double fs[MD];       // B y
   __shared__ double part[NT * MD];  // w_k x_k
   __shared__ double maps[NT * 64 * 8];  // per (shift, lane): M (row-major), then G
@@ -553,6 +553,7 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
   const double *Bw = fac + D.b_off;  // [r][5]
   const double *Fw = fac + D.f_off;  // [r][k][5]
 
+  if (t < 16) ys[t * 65] = 0.0;  // the zero column, never written again
   // B into LDS: a thread per (diagonal, lane), its 16 rows
   for (int q = t; q < 5 * 64; q += NTH) {
     const int o = q >> 6, L = q & 63;
@@ -631,7 +632,7 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
       const int i = q * NT + k;
       if (i < 16) {
         const int r = lane * R + i;
-        ys[i * 64 + lane] = r < d ? D.V[(int64_t)r * D.ldv + col] : 0.0;
+        ys[i * 65 + lane + 1] = r < d ? D.V[(int64_t)r * D.ldv + col] : 0.0;
       }
     }
     double u1[PHI ? NQ : 1];
@@ -651,7 +652,7 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
 #pragma unroll
           for (int q = 0; q < NQ + 4; ++q) {
             const int rr = lane * R + i0 + q - 2;
-            yw[q] = (rr >= 0 && rr < MD) ? ys[(rr & 15) * 64 + (rr >> 4)] : 0.0;
+            yw[q] = ys[(rr & 15) * 65 + (rr >> 4) + 1];  // rows -2, -1, MD, MD + 1: column 0
           }
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
@@ -777,7 +778,7 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
         const int i = q * NT + k;
         if (i < 16) {
           const int e = i * 64 + lane;
-          double a = a0 * ys[e];
+          double a = a0 * ys[e + i + 1];
           if constexpr (PHI) {
             if (fn == 1 && j > 0) a += u1[q];
           }
@@ -786,7 +787,7 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
           if constexpr (PHI) {
             if (first_phi && N > 1) u1[q] = a;
           }
-          ys[e] = a;
+          ys[e + i + 1] = a;
         }
       }
       __syncthreads();
@@ -797,7 +798,7 @@ band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__
       const int i = q * NT + k;
       if (i < 16) {
         const int r = lane * R + i;
-        if (r < d) F[(int64_t)r * D.ldf] = ys[i * 64 + lane];
+        if (r < d) F[(int64_t)r * D.ldf] = ys[i * 65 + lane + 1];
       }
     }
     __syncthreads();  // the next column overwrites ys
