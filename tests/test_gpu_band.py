@@ -90,7 +90,7 @@ SHAPES = [(1, 1), (2, 3), (5, 64), (37, 65), (1100, 2), (130, 7), (1024, 17)]
 
 
 @pytest.mark.parametrize("b", [1, 2, 3, 4])
-@pytest.mark.parametrize("funcs,m", [(("exp", "phi1"), 8), (("exp",), 4), (("phi1",), 5)])
+@pytest.mark.parametrize("funcs,m", [(("exp", "phi1"), 8), (("exp",), 8), (("exp",), 4), (("phi1",), 5)])
 def test_uneven_batch(torch_dev, b, funcs, m):
     torch, dev = torch_dev
     bands = [wl.band_gaussian_batch(1, d, b, 0.5, 8.0, wl.SEED_BASE + 900 + 7 * j + b)[0]
@@ -152,12 +152,13 @@ def test_headline_shape_sampled(torch_dev):
     _say("  worst %.2e" % w)
 
 
-def test_full_scan_path(torch_dev):
+@pytest.mark.parametrize("funcs", [("exp", "phi1"), ("exp",)])
+def test_full_scan_path(torch_dev, funcs):
     """A forced N = 1 on a pentadiagonal A with off-diagonals ~1.6 and ~0.4
     (|c_k| ||B||_1 up to 0.88: still diagonally dominant) makes the 16-row
     lane maps of the scan kernel reach 3e-4, so it composes them lane by lane
-    instead of over two lanes; exp and phi1 against the oracle on the same
-    forced plan."""
+    instead of over two lanes; against the oracle on the same forced plan,
+    in the kernel with phi1 and in the exp-only one."""
     torch, dev = torch_dev
     rng = np.random.default_rng(wl.SEED_BASE + 985)
     bands, vecs = [], []
@@ -170,12 +171,12 @@ def test_full_scan_path(torch_dev):
         x[2] = 0.05 * rng.standard_normal(d)
         bands.append(x)
         vecs.append(wl.vectors(d, 5 + 13 * j, wl.SEED_BASE + 986 + j))
-    _say("case band full scan path")
-    res, info = _run(torch, dev, bands, vecs, 2, ("exp", "phi1"), 8, 1e-12, force_plan=1)
+    _say("case band full scan path funcs=%s" % (funcs,))
+    res, info = _run(torch, dev, bands, vecs, 2, funcs, 8, 1e-12, force_plan=1)
     for i in range(len(bands)):
         assert info[i]["plan"] == 1 and info[i]["status"] == 0
-        own = bd.band_action(bands[i], 2, vecs[i], ("exp", "phi1"), 8, 1e-12, force_plan=1)
-        for f in ("exp", "phi1"):
+        own = bd.band_action(bands[i], 2, vecs[i], funcs, 8, 1e-12, force_plan=1)
+        for f in funcs:
             err = me.rel_fro(res[f][i].cpu().numpy(), own[f])
             assert err <= BAR, (i, f, err)
 
