@@ -510,15 +510,6 @@ band_steps_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *_
 //   y <- a0 y (+ u_1) + sum_k w_k x_k   (the workgroup, by rows, k in order)
 // Three barriers per step; the columns of a workgroup run one after another,
 // so the factors are loaded once for kBsC columns.
-// A double moved by the DPP pattern CTRL, 0 in the lanes with no source lane
-// (bound control set), so no old value has to be written first.
-template <int CTRL>
-__device__ __forceinline__ double dpp0_f64(double src) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(src), CTRL, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(src), CTRL, 0xf, 0xf, true);
-  return __hiloint2double(hi, lo);
-}
-
 template <int NT, bool PHI>
 __global__ void __launch_bounds__(64 * NT)
 band_scan_kernel(const BandDesc *__restrict__ desc, int batch, const PlanRec *__restrict__ plan, TriTerms T,

@@ -500,6 +500,14 @@ __device__ __forceinline__ double dpp_f64(double src, double old) {
   const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(src), CTRL, RM, 0xf, false);
   return __hiloint2double(hi, lo);
 }
+// A double moved by the DPP pattern CTRL, 0 in the lanes with no source lane
+// (bound control set), so no old value has to be written first.
+template <int CTRL>
+__device__ __forceinline__ double dpp0_f64(double src) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(src), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(src), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
                           __builtin_amdgcn_readlane(__double2loint(v), l));
@@ -561,15 +569,13 @@ __device__ __forceinline__ double scan_in_bwd(double G, double H, int lane) {
 // to g_{L-1} g_{L-2} Z_{L-3}, below 2^-60 max|Z|, so two lanes' maps carry
 // every digit (the planned B makes |l_r|, |em_r| < 0.06, so a lane's
 // product of 16 is below 1e-19).
+// Lane L - 1 forms h_{L-1} + g_{L-1} h_{L-2} with its own multiplier and one
+// move passes it to lane L (lane 0 gets 0).
 __device__ __forceinline__ double scan_in_fwd2(double g, double h) {
-  const double h1 = dpp_f64<0x138>(h, 0.0), g1 = dpp_f64<0x138>(g, 0.0);  // wave_shr:1
-  const double h2 = dpp_f64<0x138>(h1, 0.0);
-  return fma(g1, h2, h1);
+  return dpp0_f64<0x138>(fma(g, dpp0_f64<0x138>(h), h));  // wave_shr:1
 }
 __device__ __forceinline__ double scan_in_bwd2(double G, double H) {
-  const double h1 = dpp_f64<0x130>(H, 0.0), g1 = dpp_f64<0x130>(G, 0.0);  // wave_shl:1
-  const double h2 = dpp_f64<0x130>(h1, 0.0);
-  return fma(g1, h2, h1);
+  return dpp0_f64<0x130>(fma(G, dpp0_f64<0x130>(H), H));  // wave_shl:1
 }
 
 // All N steps of the tridiagonal action with a wave per column: lane L holds
