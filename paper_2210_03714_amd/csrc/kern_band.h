@@ -151,55 +151,90 @@ band_factor_kernel(const BandDesc *__restrict__ desc, PlanRec *__restrict__ plan
   const double *__restrict__ A = D.bands;
   double *__restrict__ Bw = wsd + D.b_off;
   double *__restrict__ Fb = wsd + D.f_off;
-  for (int r = k; r < d; r += nt)
+  // One thread per (instance, shift) leaves the chip's SIMDs mostly empty,
+  // so A's rows are loaded kFacPF at a time from clamped (in-bounds)
+  // addresses, and the conditions below select on the values.
+  // A's band entries at row r (clamped into the matrix), diagonal by diagonal
+  auto raw_row = [&](int r, double *v) {
+    const int rc = min(r, d - 1);
 #pragma unroll
-    for (int o = -BW; o <= BW; ++o)
-      Bw[(int64_t)r * W + BW + o] = (r + o >= 0 && r + o < d) ? A[(int64_t)(BW + o) * d + r] / Nd : 0.0;
-  // M's row r in the window's layout (zero past the matrix)
-  auto mrow = [&](int r, double *v) {
+    for (int o = 0; o < W; ++o) v[o] = A[(int64_t)o * d + rc];
+  };
+  for (int r0 = k; r0 < d; r0 += kFacPF * nt) {
+    double raw[kFacPF][W];
 #pragma unroll
-    for (int i = 1; i <= BW; ++i) v[i - 1] = (r < d && r - i >= 0) ? -c * (A[(int64_t)(BW - i) * d + r] / Nd) : 0.0;
-    v[BW] = r < d ? 1.0 - c * (A[(int64_t)BW * d + r] / Nd) : 1.0;
+    for (int q = 0; q < kFacPF; ++q) raw_row(r0 + q * nt, raw[q]);
 #pragma unroll
-    for (int j = 1; j <= BW; ++j) v[BW + j] = r + j < d ? -c * (A[(int64_t)(BW + j) * d + r] / Nd) : 0.0;
+    for (int q = 0; q < kFacPF; ++q) {
+      const int r = r0 + q * nt;
+      double v[W];
+#pragma unroll
+      for (int o = -BW; o <= BW; ++o) v[BW + o] = (r + o >= 0 && r + o < d) ? raw[q][BW + o] / Nd : 0.0;
+      if (r < d) {
+#pragma unroll
+        for (int o = 0; o < W; ++o) Bw[(int64_t)r * W + o] = v[o];
+      }
+    }
+  }
+  // M's row r in the window's layout (zero past the matrix) from its raw entries
+  auto mrow = [&](int r, const double *a, double *v) {
+#pragma unroll
+    for (int i = 1; i <= BW; ++i) v[i - 1] = (r < d && r - i >= 0) ? -c * (a[BW - i] / Nd) : 0.0;
+    v[BW] = r < d ? 1.0 - c * (a[BW] / Nd) : 1.0;
+#pragma unroll
+    for (int j = 1; j <= BW; ++j) v[BW + j] = r + j < d ? -c * (a[BW + j] / Nd) : 0.0;
   };
   double win[BW + 1][W];
 #pragma unroll
-  for (int r = 0; r <= BW; ++r) mrow(r, win[r]);
+  for (int r = 0; r <= BW; ++r) {
+    double a[W];
+    raw_row(r, a);
+    mrow(r, a, win[r]);
+  }
   bool bad = false;
 #pragma unroll 1
-  for (int q = 0; q < d; ++q) {
-    const double piv = win[0][BW];
-    bad |= !(piv != 0.0 && isfinite(piv));
+  for (int q0 = 0; q0 < d; q0 += kFacPF) {
+    // the rows that enter the window during this block
+    double raw[kFacPF][W];
 #pragma unroll
-    for (int i = 1; i <= BW; ++i) {
-      if (q + i < d) {
-        const double lv = win[i][i - 1] / piv;  // M[q + i][q] / U[q][q]
-        win[i][i - 1] = lv;
+    for (int s = 0; s < kFacPF; ++s) raw_row(q0 + s + BW + 1, raw[s]);
 #pragma unroll
-        for (int j = 1; j <= BW; ++j) {
-          if (q + j < d) {
-            const double u = win[0][BW + j];  // U[q][q + j], not yet normalised
-            const int off = j - i;            // column q + j relative to row q + i
-            if (off == 0) win[i][BW] -= lv * u;
-            else if (off > 0) win[i][BW + off] -= lv * u;
-            else win[i][-off - 1] -= lv * u;
+    for (int s = 0; s < kFacPF; ++s) {
+      const int q = q0 + s;
+      const double piv = win[0][BW];
+      bad |= q < d && !(piv != 0.0 && isfinite(piv));
+#pragma unroll
+      for (int i = 1; i <= BW; ++i) {
+        if (q + i < d) {
+          const double lv = win[i][i - 1] / piv;  // M[q + i][q] / U[q][q]
+          win[i][i - 1] = lv;
+#pragma unroll
+          for (int j = 1; j <= BW; ++j) {
+            if (q + j < d) {
+              const double u = win[0][BW + j];  // U[q][q + j], not yet normalised
+              const int off = j - i;            // column q + j relative to row q + i
+              if (off == 0) win[i][BW] -= lv * u;
+              else if (off > 0) win[i][BW + off] -= lv * u;
+              else win[i][-off - 1] -= lv * u;
+            }
           }
         }
       }
+      const double inv = 1.0 / piv;
+      win[0][BW] = inv;
+#pragma unroll
+      for (int j = 1; j <= BW; ++j) win[0][BW + j] *= inv;
+      if (q < d) {
+        double *out = Fb + ((int64_t)q * nt + k) * W;
+#pragma unroll
+        for (int j = 0; j < W; ++j) out[j] = win[0][j];
+      }
+#pragma unroll
+      for (int r = 0; r < BW; ++r)
+#pragma unroll
+        for (int j = 0; j < W; ++j) win[r][j] = win[r + 1][j];
+      mrow(q + BW + 1, raw[s], win[BW]);
     }
-    const double inv = 1.0 / piv;
-    win[0][BW] = inv;
-#pragma unroll
-    for (int j = 1; j <= BW; ++j) win[0][BW + j] *= inv;
-    double *out = Fb + ((int64_t)q * nt + k) * W;
-#pragma unroll
-    for (int j = 0; j < W; ++j) out[j] = win[0][j];
-#pragma unroll
-    for (int r = 0; r < BW; ++r)
-#pragma unroll
-      for (int j = 0; j < W; ++j) win[r][j] = win[r + 1][j];
-    mrow(q + BW + 1, win[BW]);
   }
   if (bad) {
     atomicOr(&plan[ii].status, 1);

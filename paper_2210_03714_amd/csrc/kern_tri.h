@@ -44,6 +44,7 @@ constexpr int kTriTerms = 10;    // most shifts in a real set (the hybrid set of
 constexpr int kTsR = 16;         // tri_scan_kernel: rows per lane
 constexpr int kTsMaxD = 64 * kTsR;  // its largest d (one wave holds a column)
 constexpr int kTsW = 8;          // its waves (columns) per workgroup
+constexpr int kFacPF = 16;       // factor kernels: rows whose loads are issued together
 
 struct TriDesc {
   const double *dl, *dd, *du, *V;
@@ -139,11 +140,31 @@ tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
   double *__restrict__ sub = wsd + D.b_off, *__restrict__ dia = sub + d, *__restrict__ sup = dia + d;
   double *__restrict__ l = wsd + D.f_off + (int64_t)k * 3 * d, *__restrict__ ui = l + d, *__restrict__ em = ui + d;
   const double *__restrict__ Al = D.dl, *__restrict__ Ad = D.dd, *__restrict__ Au = D.du;
+  // One thread per (instance, shift) leaves the chip's SIMDs mostly empty,
+  // so the loads are issued kFacPF rows at a time from clamped (in-bounds)
+  // addresses and waited for once per block; the off-diagonals exist only
+  // for d >= 2.
+  const int nt = T.nterms;
   // the instance's shifts share the writing of B
-  for (int r = k; r < d; r += T.nterms) {
-    sub[r] = r > 0 ? Al[r - 1] / Nd : 0.0;
-    dia[r] = Ad[r] / Nd;
-    sup[r] = r + 1 < d ? Au[r] / Nd : 0.0;
+  for (int r0 = k; r0 < d; r0 += kFacPF * nt) {
+    double vl[kFacPF], vd[kFacPF], vu[kFacPF];
+#pragma unroll
+    for (int q = 0; q < kFacPF; ++q) {
+      const int r = min(r0 + q * nt, d - 1);
+      vd[q] = Ad[r];
+      vl[q] = d > 1 ? Al[max(r - 1, 0)] : 0.0;
+      vu[q] = d > 1 ? Au[min(r, d - 2)] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kFacPF; ++q) {
+      const int r = r0 + q * nt;
+      const double bs = r > 0 ? vl[q] / Nd : 0.0, bd = vd[q] / Nd, bu = r + 1 < d ? vu[q] / Nd : 0.0;
+      if (r < d) {
+        sub[r] = bs;
+        dia[r] = bd;
+        sup[r] = bu;
+      }
+    }
   }
   bool bad = false;
   double u = 1.0 - c * (Ad[0] / Nd);
@@ -151,17 +172,33 @@ tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
   bad |= !(u != 0.0 && isfinite(u));
   l[0] = 0.0;
   ui[0] = uinv;
-#pragma unroll 4
-  for (int r = 1; r < d; ++r) {
-    const double mlo = -c * (Al[r - 1] / Nd);  // M[r][r-1]
-    const double mup = -c * (Au[r - 1] / Nd);  // M[r-1][r]
-    const double lr = mlo * uinv;  // tri_scan_kernel forms the same product from ui
-    em[r - 1] = mup * uinv;
-    u = (1.0 - c * (Ad[r] / Nd)) - lr * mup;
-    uinv = 1.0 / u;
-    bad |= !(u != 0.0 && isfinite(u));
-    l[r] = lr;
-    ui[r] = uinv;
+  for (int r0 = 1; r0 < d; r0 += kFacPF) {
+    double al[kFacPF], au[kFacPF], ad[kFacPF];
+#pragma unroll
+    for (int q = 0; q < kFacPF; ++q) {
+      const int r = min(r0 + q, d - 1);  // >= 1
+      al[q] = Al[r - 1];
+      au[q] = Au[r - 1];
+      ad[q] = Ad[r];
+    }
+#pragma unroll
+    for (int q = 0; q < kFacPF; ++q) {
+      const int r = r0 + q;
+      const double mlo = -c * (al[q] / Nd);  // M[r][r-1]
+      const double mup = -c * (au[q] / Nd);  // M[r-1][r]
+      const double lr = mlo * uinv;  // tri_scan_kernel forms the same product from ui
+      const double emr = mup * uinv;
+      const double un = (1.0 - c * (ad[q] / Nd)) - lr * mup;
+      const double unv = 1.0 / un;
+      if (r < d) {
+        u = un;
+        uinv = unv;
+        bad |= !(u != 0.0 && isfinite(u));
+        em[r - 1] = emr;
+        l[r] = lr;
+        ui[r] = uinv;
+      }
+    }
   }
   em[d - 1] = 0.0;
   if (bad) {
