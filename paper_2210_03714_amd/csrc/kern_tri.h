@@ -724,6 +724,18 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
                fabs(st[NF * kTsMaxD + (NT + k) * 64 + lane]) <= 0x1p-30);  // (NaN too)
     short_scan = !__any(big);
   }
+  // exp: the lane products of the next shift pair (forward, backward), read
+  // one pair ahead so that the scans do not wait for LDS
+  double gq[2] = {0.0, 0.0}, Gq[2] = {0.0, 0.0};
+  auto load_g = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int kk = min(k0 + j, NT - 1);
+      gq[j] = st[NF * kTsMaxD + kk * 64 + lane];
+      Gq[j] = st[NF * kTsMaxD + (NT + kk) * 64 + lane];
+    }
+  };
+  if constexpr (LST && !PHI) load_g(0);
 
   const int r0 = lane * R;
   double y[R];
@@ -787,6 +799,14 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
         lds_double *sk = (lds_double *)sl;
         asm volatile("" : "+v"(sk));
         auto lk = [&](int f, int i) { return sk[f * kTsMaxD + i * 64]; };
+        auto gfw = [&](int j) -> double {
+          if constexpr (PHI) return sk[NF * kTsMaxD + (k0 + j) * 64];
+          else return gq[j];
+        };
+        auto gbw = [&](int j) -> double {
+          if constexpr (PHI) return sk[NF * kTsMaxD + (NT + k0 + j) * 64];
+          else return Gq[j];
+        };
         // forward: the lane's rows from a zero start (its map's offset), the
         // scan, then the rows again from the value entering them
         double h[KP], zp[KP];
@@ -803,10 +823,10 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
         }
         if (short_scan) {
 #pragma unroll
-          for (int j = 0; j < KP; ++j) zp[j] = scan_in_fwd2(sk[NF * kTsMaxD + (k0 + j) * 64], h[j]);
+          for (int j = 0; j < KP; ++j) zp[j] = scan_in_fwd2(gfw(j), h[j]);
         } else {
 #pragma unroll
-          for (int j = 0; j < KP; ++j) zp[j] = scan_in_fwd(sk[NF * kTsMaxD + (k0 + j) * 64], h[j], lane);
+          for (int j = 0; j < KP; ++j) zp[j] = scan_in_fwd(gfw(j), h[j], lane);
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
@@ -834,11 +854,12 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
         }
         if (short_scan) {
 #pragma unroll
-          for (int j = 0; j < KP; ++j) zp[j] = scan_in_bwd2(sk[NF * kTsMaxD + (NT + k0 + j) * 64], h[j]);
+          for (int j = 0; j < KP; ++j) zp[j] = scan_in_bwd2(gbw(j), h[j]);
         } else {
 #pragma unroll
-          for (int j = 0; j < KP; ++j) zp[j] = scan_in_bwd(sk[NF * kTsMaxD + (NT + k0 + j) * 64], h[j], lane);
+          for (int j = 0; j < KP; ++j) zp[j] = scan_in_bwd(gbw(j), h[j], lane);
         }
+        if constexpr (!PHI) load_g(k0 + KP < NT ? k0 + KP : 0);  // the next pair's (or the next step's first)
 #pragma unroll
         for (int i = R - 1; i >= 0; --i) {
 #pragma unroll
