@@ -45,6 +45,7 @@ constexpr int kTsR = 16;         // tri_scan_kernel: rows per lane
 constexpr int kTsMaxD = 64 * kTsR;  // its largest d (one wave holds a column)
 constexpr int kTsW = 8;          // its waves (columns) per workgroup
 constexpr int kFacPF = 16;       // factor kernels: rows whose loads are issued together
+static_assert(kFacPF == 16, "tri_factor_kernel stores 4 runs of 16 rows per wave instruction");
 
 struct TriDesc {
   const double *dl, *dd, *du, *V;
@@ -126,26 +127,38 @@ tri_plan_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, in
 // B = A / N and the LU of I - c_k B for every (instance, shift): one thread
 // each, a sequential sweep down the diagonal.  A zero or non-finite pivot
 // sets PFM_SINGULAR_SHIFT with the smallest such shift.
+// One thread per (instance, shift) leaves the chip's SIMDs mostly empty, so
+// A's rows are loaded kFacPF at a time from clamped (in-bounds) addresses and
+// waited for once per block.  The workgroup is one wave; its 64 threads write
+// their factor rows of a block to LDS, and the wave then stores them as runs
+// of kFacPF consecutive rows (one thread's l, 1/u or em), so that a store
+// instruction touches a few cache lines instead of 64.
 __global__ void __launch_bounds__(64)
 tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, int batch, TriTerms T,
                   double *__restrict__ wsd) {
-  const int gid = blockIdx.x * 64 + threadIdx.x;
+  __shared__ double buf[3][64][kFacPF + 1];  // a block's l, 1/u, em of each thread
+  __shared__ double *dst[3][64];             // where each thread's rows go
+  __shared__ int dlen[64];                   // its d (0: nothing to store)
+  const int t = threadIdx.x;
+  const int gid = blockIdx.x * 64 + t;
   const int ii = gid / T.nterms, k = gid - ii * T.nterms;
-  if (ii >= batch) return;
-  if (plan[ii].status & 8) return;  // PFM_NOT_COMPUTED (too many steps)
-  const TriDesc D = desc[ii];
-  const int d = D.d;
-  const double Nd = (double)plan[ii].s;
+  // PFM_NOT_COMPUTED (too many steps) and the grid's padding: no rows
+  const bool active = ii < batch && !(plan[ii].status & 8);
+  TriDesc D{};
+  if (active) D = desc[ii];
+  const int d = active ? D.d : 0;
+  const double Nd = active ? (double)plan[ii].s : 1.0;
   const double c = T.c[k];
   double *__restrict__ sub = wsd + D.b_off, *__restrict__ dia = sub + d, *__restrict__ sup = dia + d;
   double *__restrict__ l = wsd + D.f_off + (int64_t)k * 3 * d, *__restrict__ ui = l + d, *__restrict__ em = ui + d;
   const double *__restrict__ Al = D.dl, *__restrict__ Ad = D.dd, *__restrict__ Au = D.du;
-  // One thread per (instance, shift) leaves the chip's SIMDs mostly empty,
-  // so the loads are issued kFacPF rows at a time from clamped (in-bounds)
-  // addresses and waited for once per block; the off-diagonals exist only
-  // for d >= 2.
+  dst[0][t] = l;
+  dst[1][t] = ui;
+  dst[2][t] = em;
+  dlen[t] = d;
   const int nt = T.nterms;
-  // the instance's shifts share the writing of B
+  // the instance's shifts share the writing of B (the off-diagonals exist
+  // only for d >= 2)
   for (int r0 = k; r0 < d; r0 += kFacPF * nt) {
     double vl[kFacPF], vd[kFacPF], vu[kFacPF];
 #pragma unroll
@@ -167,40 +180,74 @@ tri_factor_kernel(const TriDesc *__restrict__ desc, PlanRec *__restrict__ plan, 
     }
   }
   bool bad = false;
-  double u = 1.0 - c * (Ad[0] / Nd);
-  double uinv = 1.0 / u;
-  bad |= !(u != 0.0 && isfinite(u));
-  l[0] = 0.0;
-  ui[0] = uinv;
-  for (int r0 = 1; r0 < d; r0 += kFacPF) {
-    double al[kFacPF], au[kFacPF], ad[kFacPF];
+  double u = 1.0, uinv = 1.0;
+  if (d > 0) {
+    u = 1.0 - c * (Ad[0] / Nd);
+    uinv = 1.0 / u;
+    bad |= !(u != 0.0 && isfinite(u));
+    l[0] = 0.0;
+    ui[0] = uinv;
+  }
+  int dmax = d;  // the wave's largest d: the blocks below are uniform over the wave
 #pragma unroll
-    for (int q = 0; q < kFacPF; ++q) {
-      const int r = min(r0 + q, d - 1);  // >= 1
-      al[q] = Al[r - 1];
-      au[q] = Au[r - 1];
-      ad[q] = Ad[r];
-    }
+  for (int o = 32; o >= 1; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o));
+  // A's rows of a block, read one block ahead through global (not flat)
+  // loads, which the LDS accesses of the stores do not have to wait for
+  typedef const __attribute__((address_space(1))) double gdouble;
+  double al[kFacPF], au[kFacPF], ad[kFacPF];
+  auto load_rows = [&](int r0) {
+    if (r0 < d) {
 #pragma unroll
-    for (int q = 0; q < kFacPF; ++q) {
-      const int r = r0 + q;
-      const double mlo = -c * (al[q] / Nd);  // M[r][r-1]
-      const double mup = -c * (au[q] / Nd);  // M[r-1][r]
-      const double lr = mlo * uinv;  // tri_scan_kernel forms the same product from ui
-      const double emr = mup * uinv;
-      const double un = (1.0 - c * (ad[q] / Nd)) - lr * mup;
-      const double unv = 1.0 / un;
-      if (r < d) {
-        u = un;
-        uinv = unv;
-        bad |= !(u != 0.0 && isfinite(u));
-        em[r - 1] = emr;
-        l[r] = lr;
-        ui[r] = uinv;
+      for (int q = 0; q < kFacPF; ++q) {
+        const int r = min(r0 + q, d - 1);  // >= 1
+        al[q] = ((gdouble *)Al)[r - 1];
+        au[q] = ((gdouble *)Au)[r - 1];
+        ad[q] = ((gdouble *)Ad)[r];
       }
     }
+  };
+  load_rows(1);
+  for (int r0 = 1; r0 < dmax; r0 += kFacPF) {
+    double cl[kFacPF], cu[kFacPF], cd[kFacPF];
+#pragma unroll
+    for (int q = 0; q < kFacPF; ++q) {
+      cl[q] = al[q];
+      cu[q] = au[q];
+      cd[q] = ad[q];
+    }
+    load_rows(r0 + kFacPF);
+    if (r0 < d) {
+#pragma unroll
+      for (int q = 0; q < kFacPF; ++q) {
+        const int r = r0 + q;
+        const double mlo = -c * (cl[q] / Nd);  // M[r][r-1]
+        const double mup = -c * (cu[q] / Nd);  // M[r-1][r]
+        const double lr = mlo * uinv;  // tri_scan_kernel forms the same product from ui
+        const double emr = mup * uinv;
+        const double un = (1.0 - c * (cd[q] / Nd)) - lr * mup;
+        const double unv = 1.0 / un;
+        if (r < d) {
+          u = un;
+          uinv = unv;
+          bad |= !(u != 0.0 && isfinite(u));
+        }
+        buf[0][t][q] = lr;     // l[r]
+        buf[1][t][q] = uinv;   // ui[r]
+        buf[2][t][q] = emr;    // em[r - 1]
+      }
+    }
+    __syncthreads();
+    // run ru = (field, thread): 16 lanes store its rows r0 .. r0 + 15
+#pragma unroll 4
+    for (int it = 0; it < 3 * kFacPF; ++it) {
+      const int ru = it * 4 + (t >> 4), e = t & 15;
+      const int f = ru >> 6, tp = ru & 63;
+      const int r = r0 + e;
+      if (r < dlen[tp]) dst[f][tp][r - (f == 2)] = buf[f][tp][e];
+    }
+    __syncthreads();  // the next block overwrites buf
   }
-  em[d - 1] = 0.0;
+  if (d > 0) em[d - 1] = 0.0;
   if (bad) {
     atomicOr(&plan[ii].status, 1);
     atomicMin(&plan[ii].bad_shift, k);
