@@ -800,9 +800,8 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
     // y <- B y's input; f = B y, acc = a0 y (+ u_1 or P)
     double fv[R], acc[R];
     {
-      double yup = __shfl_up(y[R - 1], 1), ydn = __shfl_down(y[0], 1);
-      if (lane == 0) yup = 0.0;
-      if (lane == 63) ydn = 0.0;
+      // the neighbouring lanes' edge rows (0 past the wave's ends), by DPP
+      const double yup = dpp0_f64<0x138>(y[R - 1]), ydn = dpp0_f64<0x130>(y[0]);  // wave_shr:1, wave_shl:1
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const double ym = i > 0 ? y[i - 1] : yup, yp = i + 1 < R ? y[i + 1] : ydn;
@@ -818,9 +817,7 @@ tri_scan_kernel(const TriDesc *__restrict__ desc, int batch, const PlanRec *__re
       }
       if constexpr (HYB) {
         // P = d1 f + d2 B f (the hybrid set's polynomial part, §4.3)
-        double fup = __shfl_up(fv[R - 1], 1), fdn = __shfl_down(fv[0], 1);
-        if (lane == 0) fup = 0.0;
-        if (lane == 63) fdn = 0.0;
+        const double fup = dpp0_f64<0x138>(fv[R - 1]), fdn = dpp0_f64<0x130>(fv[0]);
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           const double fm = i > 0 ? fv[i - 1] : fup, fp = i + 1 < R ? fv[i + 1] : fdn;
